@@ -1,0 +1,190 @@
+/*
+ * airg.h -- C ABI of the MI355X AIRG reduction-multigrid solver.
+ *
+ * The library solves A x = b for a sparse nonsymmetric A (for example an
+ * upwind discretisation of v.grad(u) = 0, the paper's Eqs. advection and
+ * advection_bc) with FGMRES preconditioned by AIRG V-cycles:
+ *   - setup: PMISR DDC CF splitting (Sec. 2.1), GMRES-polynomial smoother
+ *     coefficients by Arnoldi (Sec. 2.2, Eq. gmres_poly), the fixed-sparsity
+ *     assembled inverse (Eq. fixed_sparsity), the approximate ideal restrictor
+ *     Z = -A_cf Ahat^{-1} (Eq. z), one-point prolongation, A_coarse = R A P with
+ *     relative drop and lumping, and automatic truncation with a high-order
+ *     Newton-form coarse polynomial (Sec. 2.3, 2.4);
+ *   - solve: V-cycles with only up F-point smoothing (Eq. f_point), the
+ *     polynomials applied matrix-free.
+ *
+ * Conventions
+ *   - Every function returns an int status: AIRG_OK (0), a warning (> 0) or an
+ *     error (< 0).  Nothing throws across the ABI.  airg_last_error() returns
+ *     the message of the most recent error on the calling thread.
+ *   - Matrices are CSR with int32 row pointers and column indices, the columns
+ *     of each row strictly ascending, every row holding a nonzero diagonal.
+ *   - Vectors are FP64.  Solve-phase vectors (b, x, w, lam) are DEVICE pointers
+ *     on the current HIP device; setup matrices may be host or device pointers
+ *     (flag on_device).
+ *   - All device work is enqueued on the hip_stream given at setup (NULL: the
+ *     null stream); a call returns after its results are complete.
+ *   - A handle is not re-entrant: calls on one handle must not overlap.
+ *     Separate handles are independent.
+ */
+#ifndef AIRG_H
+#define AIRG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AIRG_MAX_LEVELS 64
+
+enum airg_status {
+  AIRG_OK = 0,
+  AIRG_NOT_CONVERGED = 1,   /* max_it reached; x holds the last iterate */
+  AIRG_ERR_INVALID = -1,    /* bad shape, pointer, parameter or CSR structure */
+  AIRG_ERR_ZERO_DIAG = -2,  /* a level matrix has a zero or missing diagonal */
+  AIRG_ERR_NONFINITE = -3,  /* NaN or Inf in the matrix or a right-hand side */
+  AIRG_ERR_HIP = -4,        /* a HIP runtime call failed (code in the message) */
+  AIRG_ERR_NOMEM = -5,      /* device allocation failed */
+  AIRG_ERR_BREAKDOWN = -6,  /* unrecoverable Krylov breakdown */
+  AIRG_ERR_INTERNAL = -7
+};
+
+typedef enum { AIRG_FP64 = 0, AIRG_FP32 = 1, AIRG_BF16 = 2 } airg_precision;
+
+typedef struct airg_ctx* airg_handle;
+
+/* Solver options: one field per option of the paper's solver (Sec. 3 option
+ * set); airg_params_default() fills the defaults listed here. */
+typedef struct {
+  double strong_threshold;   /* theta_s of the strength test, 0.99 (Sec. 2.1) */
+  double ddc_fraction;       /* F points converted per DDC pass, 0.01 (Sec. 2.1) */
+  double a_drop;             /* relative drop on A_coarse, 1e-6 (Sec. 2) */
+  double r_drop;             /* relative drop on R, 0.01 (value not in the paper) */
+  double trunc_tol;          /* automatic truncation tolerance, 1e-2; <= 0 disables (Sec. 2.4) */
+  double rtol;               /* FGMRES relative tolerance on |b - A x|, 1e-10 */
+  uint64_t seed;             /* every random draw of the setup, 17517 */
+  int64_t min_coarse_rows;   /* a level this small is always the coarsest, 64 */
+  int32_t ddc_its;           /* DDC passes, 2 */
+  int32_t lump;              /* lump dropped A_coarse entries to the diagonal, 1 */
+  int32_t poly_order;        /* smoother polynomial degree d, 4 */
+  int32_t coarse_poly_order; /* Newton coarse polynomial degree, 20 */
+  int32_t trunc_start_level; /* first level tested for truncation, 1 */
+  int32_t max_levels;        /* <= AIRG_MAX_LEVELS, 64 */
+  int32_t added_roots;       /* extra copies of outlying Newton roots, 1 */
+  int32_t precision;         /* airg_precision of the V-cycle storage, AIRG_FP64 */
+  int32_t max_it;            /* FGMRES iteration cap (V-cycles), 500 */
+  int32_t restart;           /* FGMRES restart length, 30 */
+  int32_t keep_setup_data;   /* keep level data in setup numbering for export, 0 */
+  int32_t reserved;
+} airg_params;
+
+typedef struct {
+  int32_t iterations;        /* V-cycles applied */
+  int32_t converged;         /* 1 when the true relative residual <= rtol */
+  int32_t restarts;
+  int32_t reserved;
+  double rel_residual;       /* true |b - A x| / |b| at exit */
+  double rel_residual_estimate; /* Arnoldi estimate at exit */
+  double solve_ms;           /* device time of the solve */
+} airg_solve_info;
+
+typedef struct {
+  int32_t levels;
+  int32_t coarse_roots;                    /* Newton roots on the coarsest level */
+  int64_t n[AIRG_MAX_LEVELS];              /* rows of A_l */
+  int64_t nnz[AIRG_MAX_LEVELS];            /* nnz of A_l */
+  int64_t n_f[AIRG_MAX_LEVELS];            /* F points (0 on the coarsest) */
+  int64_t nnz_ff[AIRG_MAX_LEVELS];
+  int64_t nnz_fc[AIRG_MAX_LEVELS];
+  int64_t nnz_z[AIRG_MAX_LEVELS];          /* Z after the relative drop */
+  int32_t poly_degree[AIRG_MAX_LEVELS];    /* smoother degree actually used */
+  int32_t pmisr_rounds[AIRG_MAX_LEVELS];
+  double trunc_rel[AIRG_MAX_LEVELS];       /* truncation test result (NaN if not tested) */
+  double grid_complexity;                  /* sum n_l / n_0 */
+  double cycle_complexity;                 /* V-cycle FLOPs / FLOPs of one top-grid SpMV */
+  double storage_complexity;               /* nnz kept for the solve / nnz(A_0) */
+  double vcycle_bytes;                     /* algorithmic HBM bytes of one V-cycle */
+  double setup_ms;                         /* device+host time of airg_setup */
+  double setup_component_ms[8];            /* cf split, prolongator, gmres poly,
+                                              restrictor spgemm, coarse spgemm,
+                                              extract, drop, truncation */
+} airg_stats;
+
+/* Sizes of one level (for allocating export buffers). */
+typedef struct {
+  int64_t n, n_f, n_c;
+  int64_t nnz_a, nnz_ff, nnz_fc, nnz_z;
+  int32_t is_coarsest;
+  int32_t poly_len;      /* number of smoother coefficients (degree + 1) */
+  int32_t n_roots;       /* Newton roots (coarsest level) */
+  int32_t reserved;
+} airg_level_info;
+
+/* Host arrays of one level in setup numbering: F and C points in ascending
+ * level index, coarse index = rank among the C points.  Caller allocated from
+ * airg_level_info; a NULL pointer skips that array. */
+typedef struct {
+  int8_t* state;                                   /* n: 1 = F, 2 = C */
+  int32_t* a_rowptr; int32_t* a_col; double* a_val;     /* A_l */
+  int32_t* ff_rowptr; int32_t* ff_col; double* ff_val;  /* A_ff */
+  int32_t* fc_rowptr; int32_t* fc_col; double* fc_val;  /* A_fc */
+  int32_t* z_rowptr; int32_t* z_col; double* z_val;     /* Z (n_c x n_f) */
+  int32_t* cmap;                                   /* n_f: coarse index or -1 */
+  double* alpha;                                   /* poly_len smoother coefficients */
+  double* roots_re; double* roots_im;              /* n_roots, applied order */
+} airg_level_arrays;
+
+/* Fill *p with the defaults above. */
+int airg_params_default(airg_params* p);
+
+/* Build the hierarchy for the n x n CSR matrix (rowptr[n+1], colidx[nnz],
+ * vals[nnz]).  The arrays are read during the call only (the library copies A);
+ * on_device says whether they are device pointers.  On success *out owns all
+ * device memory of the solver until airg_destroy. */
+int airg_setup(airg_handle* out, int64_t n, int64_t nnz, const int32_t* rowptr,
+               const int32_t* colidx, const double* vals, int on_device,
+               const airg_params* p, void* hip_stream);
+
+/* Solve A x = b for nrhs right-hand sides: column k of b starts at b + k*ldb,
+ * of x at x + k*ldx (device pointers, FP64).  x is the initial guess when
+ * use_x_as_guess, else the guess is 0.  info (nrhs entries, may be NULL)
+ * receives per right-hand-side results.  Returns AIRG_NOT_CONVERGED if any
+ * column missed rtol within max_it. */
+int airg_solve(airg_handle h, int nrhs, const double* b, int64_t ldb, double* x,
+               int64_t ldx, int use_x_as_guess, airg_solve_info* info);
+
+/* Solve A^T lam = w (adjoint) with an AIRG hierarchy built on the explicit
+ * transpose, with the same parameters and seed; built on the first call and
+ * kept by the handle.  Pointers and layout as in airg_solve. */
+int airg_adjoint_solve(airg_handle h, int nrhs, const double* w, int64_t ldw,
+                       double* lam, int64_t ldl, int use_guess, airg_solve_info* info);
+
+/* Hierarchy statistics. */
+int airg_get_stats(airg_handle h, airg_stats* s);
+
+/* Level sizes and level arrays (the arrays need keep_setup_data = 1, except
+ * for the coarsest level's matrix and roots and every level's coefficients). */
+int airg_level_info_get(airg_handle h, int level, airg_level_info* out);
+int airg_export_level(airg_handle h, int level, airg_level_arrays* out);
+
+/* Build a solver from a given hierarchy (host arrays in setup numbering, as
+ * airg_export_level writes them): level 0's a_* arrays hold the top matrix,
+ * every non-coarsest level holds state, ff, fc, z, cmap and alpha, and the
+ * coarsest holds a_* and the roots in applied order. */
+int airg_import_hierarchy(airg_handle* out, int nlevels, const airg_level_info* infos,
+                          const airg_level_arrays* levels, const airg_params* p,
+                          void* hip_stream);
+
+/* Release the handle and all its device memory (NULL is a no-op). */
+void airg_destroy(airg_handle h);
+
+/* Static text for a status code; the last error message of this thread. */
+const char* airg_status_string(int code);
+const char* airg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AIRG_H */

@@ -1,0 +1,156 @@
+"""ctypes declarations of the C ABI in include/airg.h (argument marshalling only)."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libairg.so")
+HOST_LIB_PATH = os.path.join(HERE, "libairg_dense_host.so")
+MAX_LEVELS = 64
+
+c_i32, c_i64, c_u64, c_dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+P = ctypes.POINTER
+
+STATUS = {0: "AIRG_OK", 1: "AIRG_NOT_CONVERGED", -1: "AIRG_ERR_INVALID", -2: "AIRG_ERR_ZERO_DIAG",
+          -3: "AIRG_ERR_NONFINITE", -4: "AIRG_ERR_HIP", -5: "AIRG_ERR_NOMEM",
+          -6: "AIRG_ERR_BREAKDOWN", -7: "AIRG_ERR_INTERNAL"}
+FP64, FP32, BF16 = 0, 1, 2
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("strong_threshold", c_dbl), ("ddc_fraction", c_dbl), ("a_drop", c_dbl),
+                ("r_drop", c_dbl), ("trunc_tol", c_dbl), ("rtol", c_dbl), ("seed", c_u64),
+                ("min_coarse_rows", c_i64), ("ddc_its", c_i32), ("lump", c_i32),
+                ("poly_order", c_i32), ("coarse_poly_order", c_i32), ("trunc_start_level", c_i32),
+                ("max_levels", c_i32), ("added_roots", c_i32), ("precision", c_i32),
+                ("max_it", c_i32), ("restart", c_i32), ("keep_setup_data", c_i32),
+                ("reserved", c_i32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", c_i32), ("converged", c_i32), ("restarts", c_i32),
+                ("reserved", c_i32), ("rel_residual", c_dbl), ("rel_residual_estimate", c_dbl),
+                ("solve_ms", c_dbl)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("levels", c_i32), ("coarse_roots", c_i32),
+                ("n", c_i64 * MAX_LEVELS), ("nnz", c_i64 * MAX_LEVELS),
+                ("n_f", c_i64 * MAX_LEVELS), ("nnz_ff", c_i64 * MAX_LEVELS),
+                ("nnz_fc", c_i64 * MAX_LEVELS), ("nnz_z", c_i64 * MAX_LEVELS),
+                ("poly_degree", c_i32 * MAX_LEVELS), ("pmisr_rounds", c_i32 * MAX_LEVELS),
+                ("trunc_rel", c_dbl * MAX_LEVELS), ("grid_complexity", c_dbl),
+                ("cycle_complexity", c_dbl), ("storage_complexity", c_dbl),
+                ("vcycle_bytes", c_dbl), ("setup_ms", c_dbl), ("setup_component_ms", c_dbl * 8)]
+
+    def as_dict(self):
+        L = self.levels
+        out = {"levels": L, "coarse_roots": self.coarse_roots}
+        for k in ("n", "nnz", "n_f", "nnz_ff", "nnz_fc", "nnz_z", "poly_degree", "pmisr_rounds",
+                  "trunc_rel"):
+            out[k] = list(getattr(self, k))[:L]
+        for k in ("grid_complexity", "cycle_complexity", "storage_complexity", "vcycle_bytes",
+                  "setup_ms"):
+            out[k] = getattr(self, k)
+        names = ["cf_split", "prolongator", "gmres_poly", "restrictor_spgemm", "coarse_spgemm",
+                 "extract", "drop", "truncation"]
+        out["setup_component_ms"] = dict(zip(names, list(self.setup_component_ms)))
+        return out
+
+
+class LevelInfo(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("n_f", c_i64), ("n_c", c_i64), ("nnz_a", c_i64),
+                ("nnz_ff", c_i64), ("nnz_fc", c_i64), ("nnz_z", c_i64), ("is_coarsest", c_i32),
+                ("poly_len", c_i32), ("n_roots", c_i32), ("reserved", c_i32)]
+
+
+class LevelArrays(ctypes.Structure):
+    _fields_ = [("state", P(ctypes.c_int8)),
+                ("a_rowptr", P(c_i32)), ("a_col", P(c_i32)), ("a_val", P(c_dbl)),
+                ("ff_rowptr", P(c_i32)), ("ff_col", P(c_i32)), ("ff_val", P(c_dbl)),
+                ("fc_rowptr", P(c_i32)), ("fc_col", P(c_i32)), ("fc_val", P(c_dbl)),
+                ("z_rowptr", P(c_i32)), ("z_col", P(c_i32)), ("z_val", P(c_dbl)),
+                ("cmap", P(c_i32)), ("alpha", P(c_dbl)), ("roots_re", P(c_dbl)),
+                ("roots_im", P(c_dbl))]
+
+
+SYMBOLS = {
+    "airg_params_default": (c_i32, [P(Params)]),
+    "airg_setup": (c_i32, [P(ctypes.c_void_p), c_i64, c_i64, ctypes.c_void_p, ctypes.c_void_p,
+                           ctypes.c_void_p, ctypes.c_int, P(Params), ctypes.c_void_p]),
+    "airg_solve": (c_i32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, c_i64, ctypes.c_void_p,
+                           c_i64, ctypes.c_int, P(SolveInfo)]),
+    "airg_adjoint_solve": (c_i32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, c_i64,
+                                   ctypes.c_void_p, c_i64, ctypes.c_int, P(SolveInfo)]),
+    "airg_get_stats": (c_i32, [ctypes.c_void_p, P(Stats)]),
+    "airg_level_info_get": (c_i32, [ctypes.c_void_p, ctypes.c_int, P(LevelInfo)]),
+    "airg_export_level": (c_i32, [ctypes.c_void_p, ctypes.c_int, P(LevelArrays)]),
+    "airg_import_hierarchy": (c_i32, [P(ctypes.c_void_p), ctypes.c_int, P(LevelInfo),
+                                      P(LevelArrays), P(Params), ctypes.c_void_p]),
+    "airg_destroy": (None, [ctypes.c_void_p]),
+    "airg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "airg_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path=None):
+    """Load libairg.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          "`python -m paper_2508_17517_amd.build` (there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SYMBOLS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+class AirgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(code, lib=None):
+    lib = lib or load()
+    if code < 0:
+        raise AirgError(code, lib.airg_last_error().decode())
+    return code
+
+
+def default_params(**overrides):
+    p = Params()
+    check(load().airg_params_default(ctypes.byref(p)))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def load_host_dense():
+    """Host-only build of the library's dense routines (CPU tests)."""
+    if not os.path.exists(HOST_LIB_PATH):
+        raise ImportError(f"{HOST_LIB_PATH} is missing: run the build")
+    lib = ctypes.CDLL(HOST_LIB_PATH)
+    dp, ip = P(c_dbl), ctypes.c_int
+    lib.airg_host_gmres_poly.argtypes = [dp, ip, ip, c_dbl, dp]
+    lib.airg_host_gmres_poly.restype = ip
+    lib.airg_host_hessenberg_eig.argtypes = [dp, ip, dp, dp]
+    lib.airg_host_hessenberg_eig.restype = ip
+    lib.airg_host_newton_roots.argtypes = [dp, ip, ip, ip, dp, dp, ip]
+    lib.airg_host_newton_roots.restype = ip
+    lib.airg_host_numerical_rank.argtypes = [dp, ip, ip, c_dbl]
+    lib.airg_host_numerical_rank.restype = ip
+    return lib

@@ -1,0 +1,306 @@
+// C ABI of the AIRG library (declared in include/airg.h).  Every entry point
+// catches the library's exceptions and turns them into status codes.
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "airg.h"
+#include "hierarchy.hpp"
+#include "kernels.hpp"
+#include "solve.hpp"
+
+using namespace airg;
+
+struct airg_ctx {
+  Hierarchy H;
+  Workspace W;
+  std::unique_ptr<Hierarchy> Ht;  // adjoint hierarchy (built on A^T on first use)
+  std::unique_ptr<Workspace> Wt;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <class F>
+int guard(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return AIRG_ERR_NOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return AIRG_ERR_INTERNAL;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return AIRG_ERR_INTERNAL;
+  }
+}
+
+void check_params(const airg_params& p) {
+  auto bad = [](const char* what) { fail(AIRG_ERR_INVALID, std::string("invalid parameter: ") + what); };
+  if (!(p.strong_threshold >= 0.0 && p.strong_threshold <= 1.0)) bad("strong_threshold");
+  if (!(p.ddc_fraction >= 0.0 && p.ddc_fraction <= 1.0)) bad("ddc_fraction");
+  if (p.ddc_its < 0 || p.ddc_its > 1000) bad("ddc_its");
+  if (!(p.a_drop >= 0.0 && p.a_drop < 1.0)) bad("a_drop");
+  if (!(p.r_drop >= 0.0 && p.r_drop <= 1.0)) bad("r_drop");
+  if (p.poly_order < 0 || p.poly_order > 64) bad("poly_order");
+  if (p.coarse_poly_order < 0 || p.coarse_poly_order > 4096) bad("coarse_poly_order");
+  if (!std::isfinite(p.trunc_tol)) bad("trunc_tol");
+  if (p.trunc_start_level < 0) bad("trunc_start_level");
+  if (p.max_levels < 1 || p.max_levels > AIRG_MAX_LEVELS) bad("max_levels");
+  if (p.min_coarse_rows < 1) bad("min_coarse_rows");
+  if (p.precision != AIRG_FP64 && p.precision != AIRG_FP32 && p.precision != AIRG_BF16) bad("precision");
+  if (!(p.rtol > 0.0 && p.rtol < 1.0)) bad("rtol");
+  if (p.max_it < 0) bad("max_it");
+  if (p.restart < 1 || p.restart > 512) bad("restart");
+}
+
+// Copy the caller's CSR (host or device) into library memory.
+void load_csr(CSR& A, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+              const double* val, int on_device, hipStream_t s) {
+  if (n <= 0 || nnz < n || nnz > 2147483647ll) fail(AIRG_ERR_INVALID, "bad matrix size");
+  if (!rowptr || !col || !val) fail(AIRG_ERR_INVALID, "null matrix pointer");
+  A.alloc(n, n, nnz, s);
+  hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  AIRG_HIP(hipMemcpyAsync(A.rowptr.get(), rowptr, (n + 1) * sizeof(int32_t), k, s));
+  AIRG_HIP(hipMemcpyAsync(A.col.get(), col, nnz * sizeof(int32_t), k, s));
+  AIRG_HIP(hipMemcpyAsync(A.val.get(), val, nnz * sizeof(double), k, s));
+  int32_t ends[2];
+  AIRG_HIP(hipMemcpyAsync(&ends[0], A.rowptr.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  AIRG_HIP(hipMemcpyAsync(&ends[1], A.rowptr.get() + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  AIRG_HIP(hipStreamSynchronize(s));
+  if (ends[0] != 0 || ends[1] != nnz) fail(AIRG_ERR_INVALID, "rowptr must start at 0 and end at nnz");
+  DBuf<double> diag(n, s);
+  validate_csr(A, diag, s, true);
+}
+
+int solve_columns(Hierarchy& H, Workspace& W, int nrhs, const double* b, int64_t ldb, double* x,
+                  int64_t ldx, int guess, airg_solve_info* info) {
+  if (nrhs < 0) fail(AIRG_ERR_INVALID, "nrhs must be >= 0");
+  if (nrhs > 0 && (!b || !x)) fail(AIRG_ERR_INVALID, "null vector pointer");
+  if (nrhs > 1 && (ldb < H.n0 || ldx < H.n0)) fail(AIRG_ERR_INVALID, "leading dimension < n");
+  int status = AIRG_OK;
+  for (int k = 0; k < nrhs; ++k) {
+    int st = fgmres_solve(H, W, b + (int64_t)k * ldb, x + (int64_t)k * ldx, guess != 0,
+                          info ? info + k : nullptr);
+    if (st != AIRG_OK) status = st;
+  }
+  return status;
+}
+
+airg_ctx* handle_of(airg_handle h) {
+  if (!h) fail(AIRG_ERR_INVALID, "null handle");
+  return h;
+}
+
+const CSR* level_matrix(const airg_ctx* c, int l) {
+  const Level& L = c->H.levels[l];
+  if (l == 0) return &c->H.A0;
+  if (L.A.rows > 0 || L.coarsest) return &L.A;
+  return nullptr;
+}
+
+template <class T>
+void copy_out(T* dst, const DBuf<T>& src, int64_t n, hipStream_t s, const char* what) {
+  if (!dst) return;
+  if (n > 0 && !src.get()) fail(AIRG_ERR_INVALID, std::string(what) + " was not kept (keep_setup_data = 0)");
+  src.to_host(dst, n);
+}
+
+void copy_csr_out(int32_t* rp, int32_t* col, double* val, const CSR* A, hipStream_t s,
+                  const char* what) {
+  if (!rp && !col && !val) return;
+  if (!A || !A->rowptr.get()) fail(AIRG_ERR_INVALID, std::string(what) + " was not kept (keep_setup_data = 0)");
+  copy_out(rp, A->rowptr, A->rows + 1, s, what);
+  copy_out(col, A->col, A->nnz, s, what);
+  copy_out(val, A->val, A->nnz, s, what);
+}
+
+}  // namespace
+
+extern "C" {
+
+int airg_params_default(airg_params* p) {
+  if (!p) return AIRG_ERR_INVALID;
+  std::memset(p, 0, sizeof(*p));
+  p->strong_threshold = 0.99;
+  p->ddc_fraction = 0.01;
+  p->a_drop = 1e-6;
+  p->r_drop = 0.01;
+  p->trunc_tol = 1e-2;
+  p->rtol = 1e-10;
+  p->seed = 17517;
+  p->min_coarse_rows = 64;
+  p->ddc_its = 2;
+  p->lump = 1;
+  p->poly_order = 4;
+  p->coarse_poly_order = 20;
+  p->trunc_start_level = 1;
+  p->max_levels = AIRG_MAX_LEVELS;
+  p->added_roots = 1;
+  p->precision = AIRG_FP64;
+  p->max_it = 500;
+  p->restart = 30;
+  p->keep_setup_data = 0;
+  return AIRG_OK;
+}
+
+int airg_setup(airg_handle* out, int64_t n, int64_t nnz, const int32_t* rowptr,
+               const int32_t* colidx, const double* vals, int on_device, const airg_params* p,
+               void* hip_stream) {
+  return guard([&]() {
+    if (!out) fail(AIRG_ERR_INVALID, "null output handle");
+    *out = nullptr;
+    airg_params prm;
+    if (p) prm = *p;
+    else airg_params_default(&prm);
+    check_params(prm);
+    std::unique_ptr<airg_ctx> c(new airg_ctx());
+    c->H.p = prm;
+    c->H.s = (hipStream_t)hip_stream;
+    CSR A;
+    load_csr(A, n, nnz, rowptr, colidx, vals, on_device, c->H.s);
+    build_hierarchy(c->H, std::move(A));
+    workspace_init(c->H, c->W);
+    AIRG_HIP(hipStreamSynchronize(c->H.s));
+    *out = c.release();
+    return (int)AIRG_OK;
+  });
+}
+
+int airg_solve(airg_handle h, int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
+               int use_x_as_guess, airg_solve_info* info) {
+  return guard([&]() {
+    airg_ctx* c = handle_of(h);
+    return solve_columns(c->H, c->W, nrhs, b, ldb, x, ldx, use_x_as_guess, info);
+  });
+}
+
+int airg_adjoint_solve(airg_handle h, int nrhs, const double* w, int64_t ldw, double* lam,
+                       int64_t ldl, int use_guess, airg_solve_info* info) {
+  return guard([&]() {
+    airg_ctx* c = handle_of(h);
+    if (!c->Ht) {
+      std::unique_ptr<Hierarchy> Ht(new Hierarchy());
+      Ht->p = c->H.p;
+      Ht->s = c->H.s;
+      CSR At;
+      transpose(c->H.A0, At, c->H.s);
+      build_hierarchy(*Ht, std::move(At));
+      std::unique_ptr<Workspace> Wt(new Workspace());
+      workspace_init(*Ht, *Wt);
+      c->Ht = std::move(Ht);
+      c->Wt = std::move(Wt);
+    }
+    return solve_columns(*c->Ht, *c->Wt, nrhs, w, ldw, lam, ldl, use_guess, info);
+  });
+}
+
+int airg_get_stats(airg_handle h, airg_stats* s) {
+  return guard([&]() {
+    airg_ctx* c = handle_of(h);
+    if (!s) fail(AIRG_ERR_INVALID, "null stats");
+    hierarchy_stats(c->H, s);
+    return (int)AIRG_OK;
+  });
+}
+
+int airg_level_info_get(airg_handle h, int level, airg_level_info* out) {
+  return guard([&]() {
+    airg_ctx* c = handle_of(h);
+    if (!out || level < 0 || level >= (int)c->H.levels.size()) fail(AIRG_ERR_INVALID, "bad level");
+    const Level& L = c->H.levels[level];
+    std::memset(out, 0, sizeof(*out));
+    out->n = L.n;
+    out->n_f = L.nF;
+    out->n_c = L.nC;
+    out->nnz_a = L.nnz_a;
+    out->nnz_ff = L.Aff.nnz;
+    out->nnz_fc = L.coarsest ? 0 : (L.Afc_nat.rowptr.get() ? L.Afc_nat.nnz : L.Afc.nnz);
+    out->nnz_z = L.coarsest ? 0 : (L.Z_nat.rowptr.get() ? L.Z_nat.nnz : L.Z.nnz);
+    out->is_coarsest = L.coarsest ? 1 : 0;
+    out->poly_len = (int32_t)L.alpha.size();
+    out->n_roots = (int32_t)L.roots.size();
+    return (int)AIRG_OK;
+  });
+}
+
+int airg_export_level(airg_handle h, int level, airg_level_arrays* o) {
+  return guard([&]() {
+    airg_ctx* c = handle_of(h);
+    if (!o || level < 0 || level >= (int)c->H.levels.size()) fail(AIRG_ERR_INVALID, "bad level");
+    const Level& L = c->H.levels[level];
+    hipStream_t s = c->H.s;
+    copy_out(o->state, L.state, L.coarsest ? 0 : L.n, s, "state");
+    copy_csr_out(o->a_rowptr, o->a_col, o->a_val, level_matrix(c, level), s, "level matrix");
+    if (!L.coarsest) {
+      copy_csr_out(o->ff_rowptr, o->ff_col, o->ff_val, &L.Aff, s, "A_ff");
+      copy_csr_out(o->fc_rowptr, o->fc_col, o->fc_val, &L.Afc_nat, s, "A_fc");
+      copy_csr_out(o->z_rowptr, o->z_col, o->z_val, &L.Z_nat, s, "Z");
+      copy_out(o->cmap, L.cmap_nat, L.nF, s, "cmap");
+    }
+    AIRG_HIP(hipStreamSynchronize(s));
+    if (o->alpha)
+      for (size_t k = 0; k < L.alpha.size(); ++k) o->alpha[k] = L.alpha[k];
+    for (size_t k = 0; k < L.roots.size(); ++k) {
+      if (o->roots_re) o->roots_re[k] = L.roots[k].real();
+      if (o->roots_im) o->roots_im[k] = L.roots[k].imag();
+    }
+    return (int)AIRG_OK;
+  });
+}
+
+int airg_import_hierarchy(airg_handle* out, int nlevels, const airg_level_info* infos,
+                          const airg_level_arrays* levels, const airg_params* p, void* hip_stream) {
+  return guard([&]() {
+    if (!out || !infos || !levels || nlevels < 1 || nlevels > AIRG_MAX_LEVELS)
+      fail(AIRG_ERR_INVALID, "bad import arguments");
+    *out = nullptr;
+    airg_params prm;
+    if (p) prm = *p;
+    else airg_params_default(&prm);
+    check_params(prm);
+    std::unique_ptr<airg_ctx> c(new airg_ctx());
+    c->H.p = prm;
+    c->H.s = (hipStream_t)hip_stream;
+    import_hierarchy(c->H, nlevels, infos, levels);
+    workspace_init(c->H, c->W);
+    AIRG_HIP(hipStreamSynchronize(c->H.s));
+    *out = c.release();
+    return (int)AIRG_OK;
+  });
+}
+
+void airg_destroy(airg_handle h) {
+  if (!h) return;
+  hipStream_t s = h->H.s;
+  (void)hipStreamSynchronize(s);
+  delete h;
+  (void)hipStreamSynchronize(s);
+}
+
+const char* airg_status_string(int code) {
+  switch (code) {
+    case AIRG_OK: return "ok";
+    case AIRG_NOT_CONVERGED: return "not converged";
+    case AIRG_ERR_INVALID: return "invalid argument";
+    case AIRG_ERR_ZERO_DIAG: return "zero or missing diagonal";
+    case AIRG_ERR_NONFINITE: return "non-finite value";
+    case AIRG_ERR_HIP: return "HIP runtime error";
+    case AIRG_ERR_NOMEM: return "out of device memory";
+    case AIRG_ERR_BREAKDOWN: return "Krylov breakdown";
+    case AIRG_ERR_INTERNAL: return "internal error";
+    default: return "unknown status";
+  }
+}
+
+const char* airg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

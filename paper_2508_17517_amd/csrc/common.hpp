@@ -1,0 +1,123 @@
+// Shared host-side definitions of the AIRG library: error type, device
+// buffers, CSR matrices and the launch helpers every translation unit uses.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "airg.h"
+#include "error.hpp"
+
+namespace airg {
+
+#define AIRG_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      ::airg::fail(e_ == hipErrorOutOfMemory ? AIRG_ERR_NOMEM : AIRG_ERR_HIP,       \
+                   std::string(#call) + ": " + hipGetErrorString(e_) + " (" +       \
+                       std::to_string((int)e_) + ")");                              \
+  } while (0)
+
+#define AIRG_CHECK_LAUNCH() AIRG_HIP(hipGetLastError())
+
+void launch_zero_bytes(void* p, size_t bytes, hipStream_t s);
+
+// Stream-ordered device buffer (hipMallocAsync / hipFreeAsync).
+template <class T>
+class DBuf {
+ public:
+  DBuf() = default;
+  DBuf(size_t n, hipStream_t s) { alloc(n, s); }
+  ~DBuf() { release(); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept { *this = std::move(o); }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p_ = o.p_; n_ = o.n_; s_ = o.s_;
+      o.p_ = nullptr; o.n_ = 0;
+    }
+    return *this;
+  }
+  void alloc(size_t n, hipStream_t s) {
+    release();
+    s_ = s;
+    n_ = n;
+    if (n) AIRG_HIP(hipMallocAsync((void**)&p_, n * sizeof(T) + 256, s));
+  }
+  void release() {
+    if (p_) (void)hipFreeAsync(p_, s_);
+    p_ = nullptr;
+    n_ = 0;
+  }
+  T* get() const { return p_; }
+  size_t size() const { return n_; }
+  // cleared by a fill kernel (no memset nodes in code a caller may capture)
+  void zero() { if (n_) launch_zero_bytes(p_, n_ * sizeof(T), s_); }
+  void to_host(T* dst, size_t n) const {
+    if (n) AIRG_HIP(hipMemcpyAsync(dst, p_, n * sizeof(T), hipMemcpyDeviceToHost, s_));
+  }
+  std::vector<T> host(size_t n) const {
+    std::vector<T> v(n);
+    to_host(v.data(), n);
+    AIRG_HIP(hipStreamSynchronize(s_));
+    return v;
+  }
+  void from_host(const T* src, size_t n) {
+    if (n) AIRG_HIP(hipMemcpyAsync(p_, src, n * sizeof(T), hipMemcpyHostToDevice, s_));
+  }
+  hipStream_t stream() const { return s_; }
+
+ private:
+  T* p_ = nullptr;
+  size_t n_ = 0;
+  hipStream_t s_ = nullptr;
+};
+
+// Device CSR matrix, int32 row pointers and columns.
+struct CSR {
+  int64_t rows = 0, cols = 0, nnz = 0;
+  DBuf<int32_t> rowptr, col;
+  DBuf<double> val;
+  void alloc(int64_t r, int64_t c, int64_t nz, hipStream_t s) {
+    rows = r; cols = c; nnz = nz;
+    rowptr.alloc(r + 1, s);
+    col.alloc(nz, s);
+    val.alloc(nz, s);
+  }
+};
+
+// Read-only view passed to kernels.
+struct CSRView {
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* val;
+  int64_t rows;
+};
+inline CSRView view(const CSR& A) { return {A.rowptr.get(), A.col.get(), A.val.get(), A.rows}; }
+
+inline unsigned blocks_for(int64_t n, int per_block) {
+  int64_t b = (n + per_block - 1) / per_block;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+// Host scalar fetched from device memory (synchronises the stream).
+template <class T>
+T fetch(const T* dptr, hipStream_t s) {
+  T v;
+  AIRG_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+  AIRG_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+constexpr int kBlock = 256;
+
+}  // namespace airg

@@ -1,0 +1,594 @@
+// AIRG setup on the device, level by level (paper Sec. 2):
+//   truncation test (Sec. 2.4) -> strength, PMISR, DDC (Sec. 2.1) -> A_ff, A_fc,
+//   A_cf (Eq. air_two) -> smoother coefficients by Arnoldi (Eq. gmres_poly) ->
+//   Ahat^{-1} (Eq. fixed_sparsity) -> Z = -A_cf Ahat^{-1} with relative drop
+//   (Eq. z) -> one-point W -> A_{l+1} = R (A P), dropped and lumped.
+// Small dense problems (least squares, harmonic Ritz values) run on the host.
+#include "hierarchy.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace airg {
+
+namespace {
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Wall time of a setup component, measured to the end of its device work.
+struct Section {
+  double& acc;
+  hipStream_t s;
+  double t0;
+  Section(double& a, hipStream_t st) : acc(a), s(st), t0(now_ms()) {}
+  ~Section() {
+    (void)hipStreamSynchronize(s);
+    acc += now_ms() - t0;
+  }
+};
+
+enum { C_CF = 0, C_PROLONG, C_POLY, C_RSPGEMM, C_ASPGEMM, C_EXTRACT, C_DROP, C_TRUNC };
+
+// Dot products in tree order, any number of vectors (chunks of 64).
+void dots_dev(const double* V, int64_t ld, int nv, const double* w, int64_t n, double* out,
+              DBuf<double>& work, hipStream_t s) {
+  for (int k0 = 0; k0 < nv; k0 += 64) {
+    int cnt = std::min(64, nv - k0);
+    launch_tree_dots(V + (int64_t)k0 * ld, ld, cnt, w, n, out + k0, work.get(), s);
+  }
+}
+
+double dot1(const double* x, const double* y, int64_t n, DBuf<double>& work, DBuf<double>& res,
+            hipStream_t s) {
+  launch_tree_dots(x, 0, 1, y, n, res.get(), work.get(), s);
+  return fetch(res.get(), s);
+}
+
+struct ArnoldiOut {
+  std::vector<double> H;  // (m+1) x m row-major
+  int m = 0, steps = 0;
+  double beta = 0.0;
+};
+
+// m steps of Arnoldi on K(A, b) with classical Gram-Schmidt applied twice, in
+// the operation order of a sequential implementation: the Hessenberg matrix
+// comes out bit for bit the same as the CPU reference's.
+ArnoldiOut arnoldi_dev(const CSR& A, const double* b, int m, hipStream_t s) {
+  const int64_t n = A.rows;
+  const int64_t ld = (n + 63) / 64 * 64;
+  ArnoldiOut R;
+  R.m = m;
+  R.steps = m;
+  R.H.assign((size_t)(m + 1) * m, 0.0);
+  DBuf<double> V((size_t)m * ld, s), w(n, s), hd(m + 1, s), res(1, s);
+  DBuf<double> work(dot_work_size(n, 64), s);
+  R.beta = std::sqrt(dot1(b, b, n, work, res, s));
+  launch_divide(V.get(), b, R.beta, n, s);
+  std::vector<double> h(m + 1);
+  for (int j = 0; j < m; ++j) {
+    spmv_seq(A, V.get() + (int64_t)j * ld, w.get(), s);
+    const double w0 = std::sqrt(dot1(w.get(), w.get(), n, work, res, s));
+    for (int pass = 0; pass < 2; ++pass) {
+      dots_dev(V.get(), ld, j + 1, w.get(), n, hd.get(), work, s);
+      hd.to_host(h.data(), j + 1);
+      AIRG_HIP(hipStreamSynchronize(s));
+      launch_cgs_update(w.get(), V.get(), ld, hd.get(), j + 1, n, s);
+      for (int k = 0; k <= j; ++k) R.H[(size_t)k * m + j] = R.H[(size_t)k * m + j] + h[k];
+    }
+    const double hn = std::sqrt(dot1(w.get(), w.get(), n, work, res, s));
+    R.H[(size_t)(j + 1) * m + j] = hn;
+    if (hn <= 1e-14 * w0) {
+      R.steps = j + 1;
+      break;
+    }
+    if (j + 1 < m) launch_divide(V.get() + (int64_t)(j + 1) * ld, w.get(), hn, n, s);
+  }
+  AIRG_HIP(hipStreamSynchronize(s));
+  return R;
+}
+
+std::vector<cplx> coarse_roots(const CSR& A, int level, const airg_params& p, hipStream_t s) {
+  const int64_t n = A.rows;
+  DBuf<double> b(n, s);
+  launch_uniform(b.get(), n, p.seed, RNG_COARSE_RHS, level, s);
+  int m = (int)std::min<int64_t>((int64_t)p.coarse_poly_order + 1, n);
+  ArnoldiOut ar = arnoldi_dev(A, b.get(), m, s);
+  return newton_roots(ar.H, ar.m, ar.steps, p.added_roots != 0);
+}
+
+double truncation_test(const CSR& A, const std::vector<cplx>& roots, int level,
+                       const airg_params& p, hipStream_t s) {
+  const int64_t n = A.rows;
+  DBuf<double> b(n, s), x(n, s), w0(n, s), w1(n, s), t(n, s), r(n, s), res(1, s);
+  DBuf<double> work(dot_work_size(n, 1), s);
+  launch_uniform(b.get(), n, p.seed, RNG_TRUNC_RHS, level, s);
+  newton_apply_dev(A, pick_tpr(A.rows, A.nnz), roots, b.get(), x.get(), w0.get(), w1.get(),
+                   t.get(), s);
+  spmv_seq(A, x.get(), r.get(), s);
+  launch_sub(r.get(), b.get(), r.get(), n, s);
+  double rn = std::sqrt(dot1(r.get(), r.get(), n, work, res, s));
+  double bn = std::sqrt(dot1(b.get(), b.get(), n, work, res, s));
+  return rn / bn;
+}
+
+// Exclusive scan of 0/1 flags: idx[i] = rank of i among the flagged points,
+// returns the count.
+int64_t flag_scan(const DBuf<int8_t>& state, int64_t n, int which, DBuf<int64_t>& idx,
+                  hipStream_t s) {
+  idx.alloc(n + 1, s);
+  DBuf<int64_t> work(scan_work_size(n), s);
+  launch_flag(state.get(), n, which, idx.get(), s);
+  launch_scan_i64(idx.get(), idx.get(), n, work.get(), s);
+  return fetch(idx.get() + n, s);
+}
+
+void extract(const CSR& A, const DBuf<int8_t>& state, int rs, int cs, const DBuf<int64_t>& fidx,
+             const DBuf<int64_t>& cidx, int64_t nrows, int64_t ncols, CSR& out, hipStream_t s) {
+  DBuf<int64_t> cnt(nrows, s), off(nrows + 1, s), work(scan_work_size(nrows), s);
+  launch_extract_count(A, state.get(), rs, cs, cnt.get(), rs == 1 ? fidx.get() : cidx.get(), s);
+  launch_scan_i64(cnt.get(), off.get(), nrows, work.get(), s);
+  out.rows = nrows;
+  out.cols = ncols;
+  out.rowptr.alloc(nrows + 1, s);
+  DBuf<int32_t> ovf(1, s);
+  launch_fill_i32(ovf.get(), 1, 0, s);
+  launch_offsets_to_i32(off.get(), out.rowptr.get(), nrows + 1, ovf.get(), s);
+  out.nnz = fetch(off.get() + nrows, s);
+  out.col.alloc(out.nnz, s);
+  out.val.alloc(out.nnz, s);
+  launch_extract_fill(A, state.get(), rs, cs, fidx.get(), cidx.get(), out.rowptr.get(),
+                      out.col.get(), out.val.get(), s);
+}
+
+// CF splitting of one level: strength, PMISR rounds, DDC passes.
+void cf_split(const CSR& A, const DBuf<double>& diag, int level, const airg_params& p,
+              DBuf<int8_t>& state, int& rounds, hipStream_t s) {
+  const int64_t n = A.rows;
+  DBuf<int8_t> mask(A.nnz, s);
+  launch_strength(A, p.strong_threshold, mask.get(), nullptr, s);
+  DBuf<int64_t> colcount(n, s), st_off(n + 1, s), cursor(n, s), work(scan_work_size(n), s);
+  colcount.zero();
+  launch_pattern_transpose_count(A, mask.get(), colcount.get(), s);
+  launch_scan_i64(colcount.get(), st_off.get(), n, work.get(), s);
+  int64_t nst = fetch(st_off.get() + n, s);
+  DBuf<int32_t> st_col(nst, s);
+  cursor.zero();
+  launch_pattern_transpose_fill(A, mask.get(), st_off.get(), cursor.get(), st_col.get(), s);
+
+  state.alloc(n, s);
+  state.zero();
+  DBuf<int32_t> und(1, s);
+  rounds = 0;
+  for (;;) {
+    ++rounds;
+    launch_pmisr_select(A, mask.get(), st_off.get(), st_col.get(), state.get(), p.seed, level, s);
+    launch_pmisr_neighbours(A, mask.get(), st_off.get(), st_col.get(), state.get(), s);
+    launch_fill_i32(und.get(), 1, 0, s);
+    launch_pmisr_finalize(state.get(), n, und.get(), s);
+    if (fetch(und.get(), s) == 0) break;
+    if (rounds > 100000) fail(AIRG_ERR_INTERNAL, "PMISR did not terminate");
+  }
+
+  DBuf<double> r(n, s);
+  DBuf<unsigned long long> rmax(1, s);
+  DBuf<int32_t> nf(1, s), counts(1000, s);
+  std::vector<int32_t> hc(1000);
+  for (int it = 0; it < p.ddc_its; ++it) {
+    rmax.zero();
+    launch_fill_i32(nf.get(), 1, 0, s);
+    launch_ddc_ratio(A, state.get(), diag.get(), r.get(), rmax.get(), nf.get(), s);
+    int32_t nF = fetch(nf.get(), s);
+    unsigned long long bits = fetch(rmax.get(), s);
+    double rm;
+    std::memcpy(&rm, &bits, sizeof(double));
+    if (nF == 0 || rm == 0.0) break;
+    const int64_t k = (int64_t)std::ceil(p.ddc_fraction * (double)nF);
+    counts.zero();
+    launch_ddc_hist(r.get(), state.get(), n, rm, counts.get(), s);
+    counts.to_host(hc.data(), 1000);
+    AIRG_HIP(hipStreamSynchronize(s));
+    // the bin boundary whose conversion count is closest to k (a tie converts more)
+    int64_t cum = 0;
+    int bstar = 0;
+    for (int b = 999; b >= 0; --b) {
+      cum += hc[b];
+      if (cum >= k) {
+        bstar = b;
+        break;
+      }
+    }
+    int64_t above = cum - hc[bstar];
+    int edge = (cum - k) <= (k - above) ? bstar : bstar + 1;
+    launch_ddc_convert(r.get(), state.get(), n, rm, edge, s);
+  }
+}
+
+std::vector<double> smoother_coeffs(const CSR& Aff, int level, const airg_params& p,
+                                    hipStream_t s) {
+  const int64_t nf = Aff.rows;
+  DBuf<double> b(nf, s);
+  launch_uniform(b.get(), nf, p.seed, RNG_POLY_RHS, level, s);
+  int m = (int)std::min<int64_t>((int64_t)p.poly_order + 1, nf);
+  ArnoldiOut ar = arnoldi_dev(Aff, b.get(), m, s);
+  return gmres_poly_coeffs(ar.H, ar.m, ar.steps, ar.beta);
+}
+
+// Steps 2-8 on level `lvl`; returns false when the level cannot coarsen (no C
+// or no F points).  On success L holds the level operators in setup numbering
+// and Anext the coarse matrix.
+bool coarsen(Hierarchy& H, int lvl, const CSR& A, Level& L, CSR& Anext) {
+  hipStream_t s = H.s;
+  const airg_params& p = H.p;
+  const int64_t n = A.rows;
+  DBuf<double> diag(n, s);
+  validate_csr(A, diag, s, false);
+  {
+    Section t(H.comp_ms[C_CF], s);
+    cf_split(A, diag, lvl, p, L.state, L.pmisr_rounds, s);
+  }
+  L.nF = flag_scan(L.state, n, 1, L.fidx, s);
+  L.nC = flag_scan(L.state, n, 2, L.cidx, s);
+  if (L.nF == 0 || L.nC == 0) return false;
+  CSR Acf;
+  {
+    Section t(H.comp_ms[C_EXTRACT], s);
+    extract(A, L.state, 1, 1, L.fidx, L.cidx, L.nF, L.nF, L.Aff, s);
+    extract(A, L.state, 1, 2, L.fidx, L.cidx, L.nF, L.nC, L.Afc_nat, s);
+    extract(A, L.state, 2, 1, L.fidx, L.cidx, L.nC, L.nF, Acf, s);
+  }
+  {
+    Section t(H.comp_ms[C_POLY], s);
+    L.alpha = smoother_coeffs(L.Aff, lvl, p, s);
+  }
+  {
+    Section t(H.comp_ms[C_RSPGEMM], s);
+    CSR Ahat, Zfull;
+    fixed_sparsity_inverse(L.Aff, L.alpha, Ahat, s);
+    spgemm(Acf, Ahat, Zfull, s);
+    restrictor_drop(Zfull, p.r_drop, true, L.Z_nat, s);
+  }
+  {
+    Section t(H.comp_ms[C_PROLONG], s);
+    L.cmap_nat.alloc(L.nF, s);
+    launch_one_point(A, L.state.get(), L.fidx.get(), L.cidx.get(), L.cmap_nat.get(), s);
+  }
+  CSR RAP;
+  {
+    Section t(H.comp_ms[C_ASPGEMM], s);
+    DBuf<int64_t> flist(L.nF, s), clist(L.nC, s);
+    launch_inverse_map(L.state.get(), n, 1, L.fidx.get(), flist.get(), s);
+    launch_inverse_map(L.state.get(), n, 2, L.cidx.get(), clist.get(), s);
+    CSR R, P, AP;
+    build_r(L.Z_nat, flist.get(), clist.get(), n, R, s);
+    build_p(L.state.get(), L.fidx.get(), L.cidx.get(), L.cmap_nat.get(), n, L.nC, P, s);
+    spgemm(A, P, AP, s);
+    spgemm(R, AP, RAP, s);
+  }
+  {
+    Section t(H.comp_ms[C_DROP], s);
+    DBuf<int32_t> bad(1, s);
+    launch_fill_i32(bad.get(), 1, 0, s);
+    drop_lump(RAP, p.a_drop, p.lump != 0, Anext, bad.get(), s);
+    if (fetch(bad.get(), s))
+      fail(AIRG_ERR_ZERO_DIAG, "coarse matrix on level " + std::to_string(lvl + 1) +
+                                   " has a zero or missing diagonal");
+  }
+  return true;
+}
+
+}  // namespace
+
+void validate_csr(const CSR& A, DBuf<double>& diag, hipStream_t s, bool top) {
+  DBuf<int32_t> flags(1, s);
+  launch_fill_i32(flags.get(), 1, 0, s);
+  launch_validate(A, diag.get(), flags.get(), s);
+  int32_t f = fetch(flags.get(), s);
+  const char* where = top ? "input matrix" : "level matrix";
+  if (f & 1) fail(AIRG_ERR_INVALID, std::string(where) + ": CSR columns must be ascending and in range");
+  if (f & 2) fail(AIRG_ERR_NONFINITE, std::string(where) + ": non-finite value");
+  if (f & 4) fail(AIRG_ERR_ZERO_DIAG, std::string(where) + ": zero or missing diagonal");
+}
+
+void newton_apply_dev(const CSR& A, int tpr, const std::vector<cplx>& roots, const double* r,
+                      double* x, double* w0, double* w1, double* t, hipStream_t s) {
+  const int64_t n = A.rows;
+  const int m = (int)roots.size();
+  if (m == 0) fail(AIRG_ERR_INTERNAL, "no coarse roots");
+  const double* w = r;
+  double* bufs[2] = {w0, w1};
+  int nb = 0;
+  bool first = true;
+  int i = 0;
+  while (i < m) {
+    const cplx z = roots[i];
+    if (z.imag() == 0.0) {
+      const double inv = 1.0 / z.real();
+      if (i == m - 1) {  // last root: no product with A
+        axpy_first(x, w, inv, first, n, s);
+        return;
+      }
+      double inv_last = 0.0;
+      int skip = 0;
+      if (i + 1 == m - 1 && roots[i + 1].imag() == 0.0) {
+        inv_last = 1.0 / roots[i + 1].real();
+        skip = 1;
+      }
+      double* wn = bufs[nb];
+      newton_real(A, tpr, w, wn, x, inv, first, inv_last, s);
+      first = false;
+      w = wn;
+      nb ^= 1;
+      i += 1 + skip;
+    } else {
+      const double a = z.real(), b = z.imag();
+      const double mod2 = a * a + b * b;
+      const double c1 = 2.0 * a / mod2, c2 = 1.0 / mod2;
+      newton_pair1(A, tpr, w, t, x, c1, c2, first, s);
+      first = false;
+      if (i + 1 == m - 1) return;  // last pair
+      double inv_last = 0.0;
+      int skip = 0;
+      if (i + 2 == m - 1 && roots[i + 2].imag() == 0.0) {
+        inv_last = 1.0 / roots[i + 2].real();
+        skip = 1;
+      }
+      double* wn = bufs[nb];
+      newton_pair2(A, tpr, w, t, wn, x, c1, c2, inv_last, s);
+      w = wn;
+      nb ^= 1;
+      i += 2 + skip;
+    }
+  }
+}
+
+void build_hierarchy(Hierarchy& H, CSR&& Ain) {
+  const double t0 = now_ms();
+  hipStream_t s = H.s;
+  const airg_params& p = H.p;
+  H.A0 = std::move(Ain);
+  H.n0 = H.A0.rows;
+  H.nnz0 = H.A0.nnz;
+  H.levels.clear();
+  H.levels.reserve(p.max_levels);
+  CSR cur;  // level matrix for lvl >= 1
+  for (int lvl = 0; lvl < p.max_levels; ++lvl) {
+    const CSR& A = lvl == 0 ? H.A0 : cur;
+    const int64_t n = A.rows;
+    H.levels.emplace_back();
+    Level& L = H.levels.back();
+    L.n = n;
+    L.nnz_a = A.nnz;
+    bool last = n <= p.min_coarse_rows || lvl == p.max_levels - 1;
+    std::vector<cplx> roots;
+    if (!last && p.trunc_tol > 0 && lvl >= p.trunc_start_level) {
+      Section t(H.comp_ms[C_TRUNC], s);
+      roots = coarse_roots(A, lvl, p, s);
+      L.trunc_rel = truncation_test(A, roots, lvl, p, s);
+      last = L.trunc_rel <= p.trunc_tol;
+    }
+    if (!last) {
+      CSR next;
+      if (coarsen(H, lvl, A, L, next)) {
+        if (p.keep_setup_data && lvl > 0) L.A = std::move(cur);
+        cur = std::move(next);
+        continue;
+      }
+      // cannot coarsen: this level becomes the coarsest
+      L.state.release();
+      L.fidx.release();
+      L.cidx.release();
+      L.Aff = CSR();
+      L.Afc_nat = CSR();
+      L.nF = L.nC = 0;
+    }
+    if (roots.empty()) {
+      Section t(H.comp_ms[C_TRUNC], s);
+      roots = coarse_roots(A, lvl, p, s);
+    }
+    L.coarsest = true;
+    L.roots = std::move(roots);
+    if (lvl == 0) copy_csr(H.A0, L.A, s);
+    else L.A = std::move(cur);
+    L.tpr_a = pick_tpr(L.A.rows, L.A.nnz);
+    break;
+  }
+  finalize_hierarchy(H);
+  AIRG_HIP(hipStreamSynchronize(s));
+  H.setup_ms = now_ms() - t0;
+}
+
+void finalize_hierarchy(Hierarchy& H) {
+  hipStream_t s = H.s;
+  const int nl = (int)H.levels.size();
+  Level& Lc = H.levels.back();
+  Lc.pos.alloc(Lc.n, s);
+  launch_iota(Lc.pos.get(), Lc.n, s);
+  for (int l = nl - 2; l >= 0; --l) {
+    Level& L = H.levels[l];
+    Level& N = H.levels[l + 1];
+    L.pos.alloc(L.n, s);
+    launch_nested_pos(L.state.get(), L.fidx.get(), L.cidx.get(), L.nF, N.pos.get(), L.n,
+                      L.pos.get(), s);
+    permute_rows(L.Afc_nat, nullptr, N.pos.get(), L.nC, L.Afc, s);
+    permute_rows(L.Z_nat, N.pos.get(), nullptr, L.nF, L.Z, s);
+    L.cmap.alloc(L.nF, s);
+    launch_remap(L.cmap_nat.get(), N.pos.get(), L.nF, L.cmap.get(), s);
+    L.tpr_ff = pick_tpr(L.Aff.rows, L.Aff.nnz);
+    L.tpr_fc = pick_tpr(L.Afc.rows, L.Afc.nnz + L.Aff.nnz);
+    L.tpr_z = pick_tpr(L.Z.rows, L.Z.nnz);
+  }
+  int64_t off = 0;
+  for (Level& L : H.levels) {
+    L.off = off;
+    off += L.nF;
+  }
+  permute_rows(H.A0, H.levels[0].pos.get(), H.levels[0].pos.get(), H.n0, H.Aperm, s);
+  H.tpr_top = pick_tpr(H.Aperm.rows, H.Aperm.nnz);
+  // every solve-phase operator is checked once, so an inconsistent hierarchy
+  // (for example a bad import) fails here instead of in a kernel
+  {
+    DBuf<int32_t> flags(1, s);
+    launch_fill_i32(flags.get(), 1, 0, s);
+    launch_check_csr(H.Aperm, flags.get(), s);
+    for (int l = 0; l < nl; ++l) {
+      const Level& L = H.levels[l];
+      if (L.coarsest) {
+        launch_check_csr(L.A, flags.get(), s);
+        continue;
+      }
+      launch_check_csr(L.Aff, flags.get(), s);
+      launch_check_csr(L.Afc, flags.get(), s);
+      launch_check_csr(L.Z, flags.get(), s);
+      launch_check_map(L.cmap.get(), L.nF, -1, L.nC, flags.get(), s);
+      launch_check_map(L.pos.get(), L.n, 0, L.n, flags.get(), s);
+      if (L.Aff.rows != L.nF || L.Aff.cols != L.nF || L.Afc.rows != L.nF || L.Afc.cols != L.nC ||
+          L.Z.rows != L.nC || L.Z.cols != L.nF || H.levels[l + 1].n != L.nC)
+        fail(AIRG_ERR_INVALID, "inconsistent operator shapes on level " + std::to_string(l));
+    }
+    if (H.levels.back().A.rows != H.levels.back().n)
+      fail(AIRG_ERR_INVALID, "coarsest matrix does not match its level size");
+    if (fetch(flags.get(), s)) fail(AIRG_ERR_INVALID, "hierarchy operators fail the index check");
+  }
+  if (!H.p.keep_setup_data) {
+    for (int l = 0; l < nl; ++l) {
+      Level& L = H.levels[l];
+      if (!L.coarsest) L.A = CSR();
+      L.state.release();
+      L.fidx.release();
+      L.cidx.release();
+      L.Afc_nat = CSR();
+      L.Z_nat = CSR();
+      L.cmap_nat.release();
+    }
+  }
+  AIRG_HIP(hipStreamSynchronize(s));
+}
+
+void upload_csr(CSR& out, int64_t rows, int64_t cols, int64_t nnz, const int32_t* rowptr,
+                const int32_t* col, const double* val, hipStream_t s) {
+  if (!rowptr || (nnz > 0 && (!col || !val))) fail(AIRG_ERR_INVALID, "missing CSR array");
+  out.alloc(rows, cols, nnz, s);
+  out.rowptr.from_host(rowptr, rows + 1);
+  out.col.from_host(col, nnz);
+  out.val.from_host(val, nnz);
+  AIRG_HIP(hipStreamSynchronize(s));
+}
+
+void import_hierarchy(Hierarchy& H, int nlevels, const airg_level_info* infos,
+                      const airg_level_arrays* arr) {
+  hipStream_t s = H.s;
+  H.levels.clear();
+  H.levels.resize(nlevels);
+  const airg_level_info& i0 = infos[0];
+  upload_csr(H.A0, i0.n, i0.n, i0.nnz_a, arr[0].a_rowptr, arr[0].a_col, arr[0].a_val, s);
+  {
+    DBuf<double> diag(i0.n, s);
+    validate_csr(H.A0, diag, s, true);
+  }
+  H.n0 = i0.n;
+  H.nnz0 = i0.nnz_a;
+  for (int l = 0; l < nlevels; ++l) {
+    const airg_level_info& in = infos[l];
+    const airg_level_arrays& a = arr[l];
+    Level& L = H.levels[l];
+    L.n = in.n;
+    L.nnz_a = in.nnz_a;
+    if (l == nlevels - 1) {
+      if (!in.is_coarsest || in.n_roots <= 0 || !a.roots_re || !a.roots_im)
+        fail(AIRG_ERR_INVALID, "the last level must be the coarsest, with roots");
+      L.coarsest = true;
+      if (l == 0) copy_csr(H.A0, L.A, s);
+      else upload_csr(L.A, in.n, in.n, in.nnz_a, a.a_rowptr, a.a_col, a.a_val, s);
+      for (int k = 0; k < in.n_roots; ++k) L.roots.emplace_back(a.roots_re[k], a.roots_im[k]);
+      L.tpr_a = pick_tpr(L.A.rows, L.A.nnz);
+      continue;
+    }
+    if (in.is_coarsest || !a.state || !a.cmap || !a.alpha || in.poly_len <= 0)
+      fail(AIRG_ERR_INVALID, "level " + std::to_string(l) + " lacks state, cmap or alpha");
+    L.state.alloc(in.n, s);
+    L.state.from_host(a.state, in.n);
+    L.nF = flag_scan(L.state, in.n, 1, L.fidx, s);
+    L.nC = flag_scan(L.state, in.n, 2, L.cidx, s);
+    if (L.nF != in.n_f || L.nC != in.n_c || L.nF + L.nC != in.n || L.nC != infos[l + 1].n)
+      fail(AIRG_ERR_INVALID, "level " + std::to_string(l) + ": inconsistent F/C sizes");
+    upload_csr(L.Aff, in.n_f, in.n_f, in.nnz_ff, a.ff_rowptr, a.ff_col, a.ff_val, s);
+    upload_csr(L.Afc_nat, in.n_f, in.n_c, in.nnz_fc, a.fc_rowptr, a.fc_col, a.fc_val, s);
+    upload_csr(L.Z_nat, in.n_c, in.n_f, in.nnz_z, a.z_rowptr, a.z_col, a.z_val, s);
+    L.cmap_nat.alloc(in.n_f, s);
+    L.cmap_nat.from_host(a.cmap, in.n_f);
+    L.alpha.assign(a.alpha, a.alpha + in.poly_len);
+    // imported indices are checked before finalize indexes through them
+    DBuf<int32_t> flags(1, s);
+    launch_fill_i32(flags.get(), 1, 0, s);
+    launch_check_csr(L.Aff, flags.get(), s);
+    launch_check_csr(L.Afc_nat, flags.get(), s);
+    launch_check_csr(L.Z_nat, flags.get(), s);
+    launch_check_map(L.cmap_nat.get(), L.nF, -1, L.nC, flags.get(), s);
+    if (fetch(flags.get(), s))
+      fail(AIRG_ERR_INVALID, "level " + std::to_string(l) + ": index out of range");
+  }
+  {
+    Level& Lc = H.levels.back();
+    DBuf<int32_t> flags(1, s);
+    launch_fill_i32(flags.get(), 1, 0, s);
+    launch_check_csr(Lc.A, flags.get(), s);
+    if (fetch(flags.get(), s) || Lc.A.rows != Lc.n)
+      fail(AIRG_ERR_INVALID, "coarsest matrix: index out of range");
+  }
+  finalize_hierarchy(H);
+}
+
+void hierarchy_stats(const Hierarchy& H, airg_stats* st) {
+  std::memset(st, 0, sizeof(*st));
+  const int nl = (int)H.levels.size();
+  st->levels = nl;
+  double grid = 0, cyc = 0, sto = 0, bytes = 0;
+  const double nnz0 = (double)H.nnz0;
+  auto csr_bytes = [](double rows, double nnz) { return 12.0 * nnz + 4.0 * (rows + 1); };
+  for (int l = 0; l < nl && l < AIRG_MAX_LEVELS; ++l) {
+    const Level& L = H.levels[l];
+    st->n[l] = L.n;
+    st->nnz[l] = L.nnz_a;
+    st->n_f[l] = L.nF;
+    st->nnz_ff[l] = L.Aff.nnz;
+    st->nnz_fc[l] = L.Afc.nnz;
+    st->nnz_z[l] = L.Z.nnz;
+    st->poly_degree[l] = L.coarsest ? 0 : (int)L.alpha.size() - 1;
+    st->pmisr_rounds[l] = L.pmisr_rounds;
+    st->trunc_rel[l] = L.trunc_rel;
+    grid += (double)L.n;
+    if (L.coarsest) {
+      const double spmvs = (double)L.roots.size() - 1.0;
+      cyc += spmvs * (double)L.A.nnz;
+      sto += (double)L.A.nnz;
+      // per product: the matrix, w gathered, wn written, x read and written
+      bytes += spmvs * (csr_bytes((double)L.n, (double)L.A.nnz) + 8.0 * 4 * L.n);
+      st->coarse_roots = (int)L.roots.size();
+    } else {
+      const int d = (int)L.alpha.size() - 1;
+      cyc += (double)L.Z.nnz + (double)L.Afc.nnz + (double)L.Aff.nnz * (1 + d);
+      sto += (double)L.Z.nnz + (double)L.Afc.nnz + (double)L.Aff.nnz;
+      // restriction: Z, r_f gathered, r_c read, r_c' written
+      bytes += csr_bytes((double)L.nC, (double)L.Z.nnz) + 8.0 * (L.nF + 2 * L.nC);
+      // residual: A_ff, A_fc, cmap, e_c gathered, r_f read, e_f and s written
+      bytes += csr_bytes((double)L.nF, (double)L.Aff.nnz) + csr_bytes((double)L.nF, (double)L.Afc.nnz) +
+               4.0 * L.nF + 8.0 * (L.nC + 3 * L.nF);
+      // d Horner steps: A_ff, y gathered, s read, out written (+ e_f read on the last)
+      bytes += d * (csr_bytes((double)L.nF, (double)L.Aff.nnz) + 8.0 * 3 * L.nF) + 8.0 * L.nF;
+    }
+  }
+  st->grid_complexity = grid / (double)H.n0;
+  st->cycle_complexity = cyc / nnz0;
+  st->storage_complexity = sto / nnz0;
+  st->vcycle_bytes = bytes;
+  st->setup_ms = H.setup_ms;
+  for (int i = 0; i < 8; ++i) st->setup_component_ms[i] = H.comp_ms[i];
+}
+
+}  // namespace airg

@@ -1,0 +1,83 @@
+// AIRG hierarchy: per-level operators in two numberings.
+//
+// Setup numbering: the natural order of level l (F and C points in ascending
+// level index, coarse index = rank among the C points).  All setup decisions
+// are taken here.
+//
+// Solve numbering ("nested"): every level orders its unknowns F first, then
+// its C points in the nested order of level l+1.  Level l's vector is then
+// the suffix of the top-level vector starting at off_l = n_F(0) + ... +
+// n_F(l-1), so restriction, prolongation and smoothing touch contiguous
+// ranges and the V-cycle needs no gathers between levels.
+#pragma once
+
+#include <cmath>
+#include <complex>
+#include <limits>
+#include <vector>
+
+#include "common.hpp"
+#include "dense.hpp"
+
+namespace airg {
+
+struct Level {
+  int64_t n = 0, nF = 0, nC = 0;
+  int64_t off = 0;
+  bool coarsest = false;
+
+  // setup numbering (freed after finalize unless keep_setup_data)
+  CSR A;                    // level matrix (kept on the coarsest level)
+  DBuf<int8_t> state;       // 1 = F, 2 = C
+  DBuf<int64_t> fidx, cidx; // exclusive scans of the F / C flags
+  CSR Afc_nat, Z_nat;
+  DBuf<int32_t> cmap_nat;
+
+  // solve numbering
+  CSR Aff, Afc, Z;          // Afc columns and Z rows in level l+1's nested order
+  DBuf<int32_t> cmap;       // nested position on level l+1, or -1
+  DBuf<int32_t> pos;        // setup index -> nested position on this level
+  std::vector<double> alpha;
+  std::vector<cplx> roots;
+  int tpr_ff = 1, tpr_fc = 1, tpr_z = 1, tpr_a = 1;
+
+  // statistics
+  int64_t nnz_a = 0;
+  int pmisr_rounds = 0;
+  double trunc_rel = std::numeric_limits<double>::quiet_NaN();
+};
+
+struct Hierarchy {
+  airg_params p{};
+  hipStream_t s = nullptr;
+  int64_t n0 = 0, nnz0 = 0;
+  CSR A0;                   // top matrix, setup numbering
+  CSR Aperm;                // top matrix, nested numbering
+  int tpr_top = 1;
+  std::vector<Level> levels;
+  double setup_ms = 0.0;
+  double comp_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+// Build the hierarchy for A (device CSR, validated) with parameters p.
+void build_hierarchy(Hierarchy& H, CSR&& A);
+// Nested numbering and solve-form operators; frees setup data unless kept.
+void finalize_hierarchy(Hierarchy& H);
+// Build from host arrays in setup numbering (see airg_import_hierarchy).
+void import_hierarchy(Hierarchy& H, int nlevels, const airg_level_info* infos,
+                      const airg_level_arrays* arr);
+// Upload a host CSR.
+void upload_csr(CSR& out, int64_t rows, int64_t cols, int64_t nnz, const int32_t* rowptr,
+                const int32_t* col, const double* val, hipStream_t s);
+// Statistics.
+void hierarchy_stats(const Hierarchy& H, airg_stats* st);
+
+// Coarse solver: x = q(A) r with the Newton roots (r, x device vectors of
+// length A.rows; w0, w1, t scratch of the same length).
+void newton_apply_dev(const CSR& A, int tpr, const std::vector<cplx>& roots, const double* r,
+                      double* x, double* w0, double* w1, double* t, hipStream_t s);
+
+// Validates a device CSR and returns its diagonal; throws on error.
+void validate_csr(const CSR& A, DBuf<double>& diag, hipStream_t s, bool top);
+
+}  // namespace airg

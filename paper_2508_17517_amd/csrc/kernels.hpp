@@ -1,0 +1,162 @@
+// Host launchers of the HIP kernels (vec.hip, spmv.hip, cf.hip, spgemm.hip).
+// Every launcher enqueues on the given stream and returns without syncing.
+#pragma once
+
+#include "common.hpp"
+
+namespace airg {
+
+// ---------------------------------------------------------------- vec.hip
+// Random draws of the setup: U[0,1) from counter-based SplitMix64, element i
+// of stream (purpose, level) being output c + 1 of `seed`, c = purpose << 56 |
+// level << 40 | i.
+enum RngPurpose { RNG_PMISR = 1, RNG_POLY_RHS = 2, RNG_COARSE_RHS = 3, RNG_TRUNC_RHS = 4 };
+void launch_uniform(double* out, int64_t n, uint64_t seed, int purpose, int level, hipStream_t s);
+
+void launch_fill(double* x, int64_t n, double v, hipStream_t s);
+void launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s);
+void launch_zero_bytes(void* p, size_t bytes, hipStream_t s);
+void launch_copy(double* y, const double* x, int64_t n, hipStream_t s);
+void launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t s);   // y = a x
+void launch_divide(double* y, const double* x, double d, int64_t n, hipStream_t s);  // y = x / d
+void launch_divide_dev(double* y, const double* x, const double* d, int64_t n, hipStream_t s);
+void launch_sub(double* z, const double* x, const double* y, int64_t n, hipStream_t s);  // z = x - y
+// w = w - h[0] V_0 - h[1] V_1 - ... (k sequential per element; V_k = V + k ldv)
+void launch_cgs_update(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                       int64_t n, hipStream_t s);
+// x = x + sum_k y[k] Z_k (y on device)
+void launch_basis_combine(double* x, const double* Z, int64_t ldz, const double* y, int nv,
+                          int64_t n, hipStream_t s);
+
+// Dot products by the perfect binary tree over the index range (adjacent pairs
+// first, zero padded): out[k] = V_k . w for k < nv.  `work` needs
+// dot_work_size(n, nv) doubles.
+size_t dot_work_size(int64_t n, int nv);
+void launch_tree_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
+                      double* out, double* work, hipStream_t s);
+// out[0] = sqrt(out[0]) on the device
+void launch_sqrt_inplace(double* v, hipStream_t s);
+
+// Permutations: y[perm[i]] = x[i] (scatter) and y[i] = x[perm[i]] (gather).
+void launch_scatter(double* y, const double* x, const int32_t* perm, int64_t n, hipStream_t s);
+void launch_gather(double* y, const double* x, const int32_t* perm, int64_t n, hipStream_t s);
+
+// Exclusive scan of int64 counts: out[i] = sum_{j<i} in[j], out[n] = total.
+// `work` needs scan_work_size(n) int64s.  in and out may alias.
+size_t scan_work_size(int64_t n);
+void launch_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* work, hipStream_t s);
+// rowptr (int32) from int64 offsets; sets *overflow = 1 if any exceeds int32.
+void launch_offsets_to_i32(const int64_t* off, int32_t* rowptr, int64_t n1, int32_t* overflow,
+                           hipStream_t s);
+
+// ---------------------------------------------------------------- spmv.hip
+// Rows-per-thread-group shape of a CSR kernel (lanes per row, power of 2).
+int pick_tpr(int64_t rows, int64_t nnz);
+// y = A x, every row summed left to right from 0.0 by one lane (setup order).
+void spmv_seq(const CSR& A, const double* x, double* y, hipStream_t s);
+// y = A x with `tpr` lanes per row.
+void spmv(const CSR& A, int tpr, const double* x, double* y, hipStream_t s);
+// Horner step of the smoother: out = (acc ? out : 0) + a (A y) + b s
+void spmv_horner(const CSR& A, int tpr, const double* y, const double* sv, double* out, double a,
+                 double b, bool acc, hipStream_t st);
+// Restriction: dst[p] = src[p] + (Z r_f)[p]   (src may alias dst)
+void spmv_restrict(const CSR& Z, int tpr, const double* rf, const double* src, double* dst,
+                   hipStream_t s);
+// F-point residual with fused one-point prolongation:
+//   ef[i] = W e_c, s[i] = r_f[i] - (A_fc e_c)[i] - (A_ff W e_c)[i]
+void residual_fpoint(const CSR& Aff, const CSR& Afc, const int32_t* cmap, int tpr,
+                     const double* rf, const double* ec, double* ef, double* sv, hipStream_t s);
+// Newton steps of the coarse solver (see solve.cpp).
+void newton_real(const CSR& A, int tpr, const double* w, double* wn, double* x, double inv,
+                 bool first, double inv_last, hipStream_t s);
+void newton_pair1(const CSR& A, int tpr, const double* w, double* t, double* x, double c1,
+                  double c2, bool first, hipStream_t s);
+void newton_pair2(const CSR& A, int tpr, const double* w, const double* t, double* wn, double* x,
+                  double c1, double c2, double inv_last, hipStream_t s);
+// x = (first ? 0 : x) + a w
+void axpy_first(double* x, const double* w, double a, bool first, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------- cf.hip
+// Validates CSR structure (monotone rowptr, strictly ascending in-range
+// columns, finite values, nonzero diagonal present) and extracts the diagonal.
+// flags: bit0 structure, bit1 nonfinite, bit2 zero/missing diagonal.
+void launch_validate(const CSR& A, double* diag, int32_t* flags, hipStream_t s);
+// Structural checks of constructed operators (flags bit0: CSR, bit1: map).
+void launch_check_csr(const CSR& A, int32_t* flags, hipStream_t s);
+void launch_check_map(const int32_t* m, int64_t n, int64_t lo, int64_t hi, int32_t* flags,
+                      hipStream_t s);
+// Strength: mask[p] = 1 iff entry p is a strong off-diagonal connection.
+void launch_strength(const CSR& A, double theta, int8_t* mask, int64_t* row_count,
+                     hipStream_t s);
+// Transpose of the strong pattern: ST (rowptr/col) from mask.
+void launch_pattern_transpose_count(const CSR& A, const int8_t* mask, int64_t* colcount,
+                                    hipStream_t s);
+void launch_pattern_transpose_fill(const CSR& A, const int8_t* mask, const int64_t* off,
+                                   int64_t* cursor, int32_t* st_col, hipStream_t s);
+// PMISR round on G = S + S^T (S from A/mask, S^T from st_off/st_col).
+void launch_pmisr_select(const CSR& A, const int8_t* mask, const int64_t* st_off,
+                         const int32_t* st_col, int8_t* state, uint64_t seed, int level,
+                         hipStream_t s);
+void launch_pmisr_neighbours(const CSR& A, const int8_t* mask, const int64_t* st_off,
+                             const int32_t* st_col, int8_t* state, hipStream_t s);
+void launch_pmisr_finalize(int8_t* state, int64_t n, int32_t* undecided, hipStream_t s);
+// DDC: ratios of F rows, max and F count; histogram; conversion.
+void launch_ddc_ratio(const CSR& A, const int8_t* state, const double* diag, double* r,
+                      unsigned long long* rmax_bits, int32_t* nf, hipStream_t s);
+void launch_ddc_hist(const double* r, const int8_t* state, int64_t n, double rmax,
+                     int32_t* counts, hipStream_t s);
+void launch_ddc_convert(const double* r, int8_t* state, int64_t n, double rmax, int edge,
+                        hipStream_t s);
+// F/C flags -> int64 flags for scanning (which: 1 = F, 2 = C)
+void launch_flag(const int8_t* state, int64_t n, int which, int64_t* out, hipStream_t s);
+// Sub-block extraction (rows with state rs, columns with state cs, columns
+// renumbered through idx (F index or C index)).
+void launch_extract_count(const CSR& A, const int8_t* state, int rs, int cs, int64_t* count,
+                          const int64_t* rowidx, hipStream_t s);
+void launch_extract_fill(const CSR& A, const int8_t* state, int rs, int cs,
+                         const int64_t* fidx, const int64_t* cidx, const int32_t* rowptr_out,
+                         int32_t* col_out, double* val_out, hipStream_t s);
+// list[idx[i]] = i for the points with state == which (F or C index -> level index).
+void launch_inverse_map(const int8_t* state, int64_t n, int which, const int64_t* idx,
+                        int64_t* list, hipStream_t s);
+// Nested positions: pos[i] = fidx[i] for F points, nF + pos_next[cidx[i]] for C points.
+void launch_nested_pos(const int8_t* state, const int64_t* fidx, const int64_t* cidx, int64_t nF,
+                       const int32_t* pos_next, int64_t n, int32_t* pos, hipStream_t s);
+// out[f] = pos_next[cmap[f]] (or -1)
+void launch_remap(const int32_t* cmap, const int32_t* pos_next, int64_t nf, int32_t* out,
+                  hipStream_t s);
+void launch_iota(int32_t* x, int64_t n, hipStream_t s);
+// One-point prolongation: cmap[f] = coarse index of the strongest C column.
+void launch_one_point(const CSR& A, const int8_t* state, const int64_t* fidx,
+                      const int64_t* cidx, int32_t* cmap, hipStream_t s);
+
+// ---------------------------------------------------------------- spgemm.hip
+// C = A B with c_ij accumulated over k ascending from 0.0, exact zeros dropped.
+void spgemm(const CSR& A, const CSR& B, CSR& C, hipStream_t s);
+// Masked powers and the fixed-sparsity inverse on the pattern of Aff:
+//   out = alpha_0 I + alpha_1 A + alpha_2 A~^2 + ..., zeros dropped.
+void fixed_sparsity_inverse(const CSR& Aff, const std::vector<double>& alpha, CSR& out,
+                            hipStream_t s);
+// Drop |z| < tol * max_j |z_ij| per row (no lumping), optionally negating.
+void restrictor_drop(const CSR& Zin, double tol, bool negate, CSR& Z, hipStream_t s);
+// Relative off-diagonal drop with lumping to the diagonal; sets *bad_diag if a
+// row ends with a zero or missing diagonal.
+void drop_lump(const CSR& Ain, double tol, bool lump, CSR& Aout, int32_t* bad_diag,
+               hipStream_t s);
+// R = [Z I] in level numbering (rows n_c, columns n).
+void build_r(const CSR& Z, const int64_t* fpos, const int64_t* cpos, int64_t n, CSR& R,
+             hipStream_t s);
+// P = [W; I] in level numbering (rows n, columns n_c).
+void build_p(const int8_t* state, const int64_t* fidx, const int64_t* cidx, const int32_t* cmap,
+             int64_t n, int64_t nc, CSR& P, hipStream_t s);
+// Row permutation + column renumbering: out row newrow[i] = row i of A with
+// columns mapped through colmap (either map NULL: identity).  Column order within a row
+// is preserved.
+void permute_rows(const CSR& A, const int32_t* newrow, const int32_t* colmap, int64_t out_cols,
+                  CSR& out, hipStream_t s);
+// Explicit transpose with ascending columns.
+void transpose(const CSR& A, CSR& At, hipStream_t s);
+// Deep copy of a device CSR.
+void copy_csr(const CSR& A, CSR& out, hipStream_t s);
+
+}  // namespace airg

@@ -1,0 +1,571 @@
+// Sparse products and structural kernels of the setup (paper Eqs. z,
+// fixed_sparsity, prolong and the coarse product R A P).
+//
+// C = A B is formed row by row with a k-way merge of the sorted rows of B
+// selected by row i of A: one thread walks the merge, so every c_ij is
+// accumulated over k in ascending order starting from 0.0 and the result does
+// not depend on scheduling.  Exact zeros are dropped afterwards.
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace airg {
+
+static void scan_counts(const DBuf<int64_t>& cnt, int64_t n, DBuf<int64_t>& off, hipStream_t s) {
+  off.alloc(n + 1, s);
+  DBuf<int64_t> work(scan_work_size(n), s);
+  launch_scan_i64(cnt.get(), off.get(), n, work.get(), s);
+}
+
+// int32 rowptr from int64 offsets, failing on overflow.
+static int64_t offsets_to_rowptr(const DBuf<int64_t>& off, int64_t n, DBuf<int32_t>& rowptr,
+                                 hipStream_t s) {
+  rowptr.alloc(n + 1, s);
+  DBuf<int32_t> ovf(1, s);
+  launch_fill_i32(ovf.get(), 1, 0, s);
+  launch_offsets_to_i32(off.get(), rowptr.get(), n + 1, ovf.get(), s);
+  int64_t total = fetch(off.get() + n, s);
+  if (fetch(ovf.get(), s) || total > 2147483647ll)
+    fail(AIRG_ERR_NOMEM, "sparse matrix exceeds 2^31 nonzeros");
+  return total;
+}
+
+// ------------------------------------------------------------------ k-way merge product
+__global__ void merge_init_kernel(CSRView A, CSRView B, int32_t* cur) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.rows) return;
+  for (int p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) cur[p] = B.rowptr[A.col[p]];
+}
+
+__global__ void merge_count_kernel(CSRView A, CSRView B, int32_t* cur, int64_t* count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.rows) return;
+  const int s = A.rowptr[i], e = A.rowptr[i + 1];
+  int64_t c = 0;
+  for (;;) {
+    int mn = 0x7fffffff;
+    for (int p = s; p < e; ++p) {
+      int q = cur[p];
+      if (q < B.rowptr[A.col[p] + 1]) mn = min(mn, B.col[q]);
+    }
+    if (mn == 0x7fffffff) break;
+    ++c;
+    for (int p = s; p < e; ++p) {
+      int q = cur[p];
+      if (q < B.rowptr[A.col[p] + 1] && B.col[q] == mn) cur[p] = q + 1;
+    }
+  }
+  count[i] = c;
+}
+
+__global__ void merge_numeric_kernel(CSRView A, CSRView B, int32_t* cur, const int32_t* rowptr,
+                                     int32_t* col, double* val) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.rows) return;
+  const int s = A.rowptr[i], e = A.rowptr[i + 1];
+  int64_t o = rowptr[i];
+  for (;;) {
+    int mn = 0x7fffffff;
+    for (int p = s; p < e; ++p) {
+      int q = cur[p];
+      if (q < B.rowptr[A.col[p] + 1]) mn = min(mn, B.col[q]);
+    }
+    if (mn == 0x7fffffff) break;
+    double acc = 0.0;
+    for (int p = s; p < e; ++p) {  // ascending k
+      int q = cur[p];
+      if (q < B.rowptr[A.col[p] + 1] && B.col[q] == mn) {
+        acc = acc + A.val[p] * B.val[q];
+        cur[p] = q + 1;
+      }
+    }
+    col[o] = mn;
+    val[o] = acc;
+    ++o;
+  }
+}
+
+__global__ void nonzero_count_kernel(CSRView A, int64_t* count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.rows) return;
+  int64_t c = 0;
+  for (int p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) c += (A.val[p] != 0.0);
+  count[i] = c;
+}
+__global__ void nonzero_fill_kernel(CSRView A, const int32_t* rowptr, int32_t* col, double* val) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.rows) return;
+  int64_t o = rowptr[i];
+  for (int p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p)
+    if (A.val[p] != 0.0) {
+      col[o] = A.col[p];
+      val[o] = A.val[p];
+      ++o;
+    }
+}
+
+// Drop the explicit zeros of `in` into `out`.
+static void drop_zeros(const CSR& in, CSR& out, hipStream_t s) {
+  const int64_t n = in.rows;
+  DBuf<int64_t> cnt(n, s), off;
+  unsigned nb = blocks_for(n, kBlock);
+  if (n > 0) {
+    nonzero_count_kernel<<<nb, kBlock, 0, s>>>(view(in), cnt.get());
+    AIRG_CHECK_LAUNCH();
+  }
+  scan_counts(cnt, n, off, s);
+  out.rows = n;
+  out.cols = in.cols;
+  out.nnz = offsets_to_rowptr(off, n, out.rowptr, s);
+  out.col.alloc(out.nnz, s);
+  out.val.alloc(out.nnz, s);
+  if (n > 0) {
+    nonzero_fill_kernel<<<nb, kBlock, 0, s>>>(view(in), out.rowptr.get(), out.col.get(),
+                                              out.val.get());
+    AIRG_CHECK_LAUNCH();
+  }
+}
+
+void spgemm(const CSR& A, const CSR& B, CSR& C, hipStream_t s) {
+  if (A.cols != B.rows) fail(AIRG_ERR_INTERNAL, "spgemm shape mismatch");
+  const int64_t n = A.rows;
+  unsigned nb = blocks_for(n, kBlock);
+  DBuf<int32_t> cur(A.nnz, s);
+  DBuf<int64_t> cnt(n, s), off;
+  if (n > 0) {
+    merge_init_kernel<<<nb, kBlock, 0, s>>>(view(A), view(B), cur.get());
+    AIRG_CHECK_LAUNCH();
+    merge_count_kernel<<<nb, kBlock, 0, s>>>(view(A), view(B), cur.get(), cnt.get());
+    AIRG_CHECK_LAUNCH();
+  }
+  scan_counts(cnt, n, off, s);
+  CSR full;
+  full.rows = n;
+  full.cols = B.cols;
+  full.nnz = offsets_to_rowptr(off, n, full.rowptr, s);
+  full.col.alloc(full.nnz, s);
+  full.val.alloc(full.nnz, s);
+  if (n > 0) {
+    merge_init_kernel<<<nb, kBlock, 0, s>>>(view(A), view(B), cur.get());
+    AIRG_CHECK_LAUNCH();
+    merge_numeric_kernel<<<nb, kBlock, 0, s>>>(view(A), view(B), cur.get(), full.rowptr.get(),
+                                               full.col.get(), full.val.get());
+    AIRG_CHECK_LAUNCH();
+  }
+  drop_zeros(full, C, s);
+}
+
+// ------------------------------------------------------------------ fixed sparsity
+// T_out[p] = sum over q in row i (ascending) of T_in[q] * Aff[col(q), col(p)],
+// i.e. (T_in Aff) restricted to the pattern of Aff.
+__device__ __forceinline__ int find_col(const int32_t* col, int lo, int hi, int j) {
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    int c = col[mid];
+    if (c == j) return mid;
+    if (c < j) lo = mid + 1;
+    else hi = mid;
+  }
+  return -1;
+}
+
+__global__ void masked_power_kernel(CSRView Aff, const double* tin, double* tout) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Aff.rows) return;
+  const int s = Aff.rowptr[i], e = Aff.rowptr[i + 1];
+  for (int p = s; p < e; ++p) {
+    const int j = Aff.col[p];
+    double acc = 0.0;
+    for (int q = s; q < e; ++q) {
+      const int k = Aff.col[q];
+      int r = find_col(Aff.col, Aff.rowptr[k], Aff.rowptr[k + 1], j);
+      if (r >= 0) acc = acc + tin[q] * Aff.val[r];
+    }
+    tout[p] = acc;
+  }
+}
+
+// v = alpha_0 [i == j]; v = v + alpha_k T_k  (k = 1..d, left to right)
+__global__ void poly_init_kernel(CSRView Aff, double a0, double a1, int has_a1, double* v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Aff.rows) return;
+  for (int p = Aff.rowptr[i]; p < Aff.rowptr[i + 1]; ++p) {
+    double x = (Aff.col[p] == i) ? a0 : 0.0;
+    if (has_a1) x = x + a1 * Aff.val[p];
+    v[p] = x;
+  }
+}
+__global__ void poly_add_kernel(int64_t nnz, double a, const double* t, double* v) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nnz) v[p] = v[p] + a * t[p];
+}
+
+void fixed_sparsity_inverse(const CSR& Aff, const std::vector<double>& alpha, CSR& out,
+                            hipStream_t s) {
+  const int64_t n = Aff.rows;
+  if (alpha.empty()) fail(AIRG_ERR_INTERNAL, "empty polynomial");
+  CSR full;
+  full.rows = n;
+  full.cols = Aff.cols;
+  full.nnz = Aff.nnz;
+  full.rowptr.alloc(n + 1, s);
+  full.col.alloc(Aff.nnz, s);
+  full.val.alloc(Aff.nnz, s);
+  AIRG_HIP(hipMemcpyAsync(full.rowptr.get(), Aff.rowptr.get(), (n + 1) * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, s));
+  AIRG_HIP(hipMemcpyAsync(full.col.get(), Aff.col.get(), Aff.nnz * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, s));
+  unsigned nb = blocks_for(n, kBlock);
+  if (n > 0) {
+    poly_init_kernel<<<nb, kBlock, 0, s>>>(view(Aff), alpha[0], alpha.size() > 1 ? alpha[1] : 0.0,
+                                           alpha.size() > 1 ? 1 : 0, full.val.get());
+    AIRG_CHECK_LAUNCH();
+  }
+  if (alpha.size() > 2) {
+    DBuf<double> ta(Aff.nnz, s), tb(Aff.nnz, s);
+    AIRG_HIP(hipMemcpyAsync(ta.get(), Aff.val.get(), Aff.nnz * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+    for (size_t k = 2; k < alpha.size(); ++k) {
+      masked_power_kernel<<<nb, kBlock, 0, s>>>(view(Aff), ta.get(), tb.get());
+      AIRG_CHECK_LAUNCH();
+      poly_add_kernel<<<blocks_for(Aff.nnz, kBlock), kBlock, 0, s>>>(Aff.nnz, alpha[k], tb.get(),
+                                                                     full.val.get());
+      AIRG_CHECK_LAUNCH();
+      std::swap(ta, tb);
+    }
+  }
+  drop_zeros(full, out, s);
+}
+
+// ------------------------------------------------------------------ drops
+__global__ void rdrop_count_kernel(CSRView Z, double tol, int64_t* count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Z.rows) return;
+  double m = 0.0;
+  for (int p = Z.rowptr[i]; p < Z.rowptr[i + 1]; ++p) m = fmax(m, fabs(Z.val[p]));
+  const double thr = tol * m;
+  int64_t c = 0;
+  for (int p = Z.rowptr[i]; p < Z.rowptr[i + 1]; ++p) c += (fabs(Z.val[p]) >= thr);
+  count[i] = c;
+}
+__global__ void rdrop_fill_kernel(CSRView Z, double tol, double sign, const int32_t* rowptr,
+                                  int32_t* col, double* val) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Z.rows) return;
+  double m = 0.0;
+  for (int p = Z.rowptr[i]; p < Z.rowptr[i + 1]; ++p) m = fmax(m, fabs(Z.val[p]));
+  const double thr = tol * m;
+  int64_t o = rowptr[i];
+  for (int p = Z.rowptr[i]; p < Z.rowptr[i + 1]; ++p)
+    if (fabs(Z.val[p]) >= thr) {
+      col[o] = Z.col[p];
+      val[o] = sign * Z.val[p];
+      ++o;
+    }
+}
+
+void restrictor_drop(const CSR& Zin, double tol, bool negate, CSR& Z, hipStream_t s) {
+  const int64_t n = Zin.rows;
+  DBuf<int64_t> cnt(n, s), off;
+  unsigned nb = blocks_for(n, kBlock);
+  if (n > 0) {
+    rdrop_count_kernel<<<nb, kBlock, 0, s>>>(view(Zin), tol, cnt.get());
+    AIRG_CHECK_LAUNCH();
+  }
+  scan_counts(cnt, n, off, s);
+  Z.rows = n;
+  Z.cols = Zin.cols;
+  Z.nnz = offsets_to_rowptr(off, n, Z.rowptr, s);
+  Z.col.alloc(Z.nnz, s);
+  Z.val.alloc(Z.nnz, s);
+  if (n > 0) {
+    rdrop_fill_kernel<<<nb, kBlock, 0, s>>>(view(Zin), tol, negate ? -1.0 : 1.0, Z.rowptr.get(),
+                                            Z.col.get(), Z.val.get());
+    AIRG_CHECK_LAUNCH();
+  }
+}
+
+// Off-diagonal relative drop; dropped values lumped to the diagonal as
+// d + l_1 + l_2 + ... in ascending column order.
+__global__ void adrop_count_kernel(CSRView A, double tol, int lump, int64_t* count, int32_t* bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.rows) return;
+  double m = 0.0;
+  bool has_diag = false;
+  for (int p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) {
+    if (A.col[p] != i) m = fmax(m, fabs(A.val[p]));
+    else has_diag = true;
+  }
+  const double thr = tol * m;
+  int64_t c = 0;
+  bool dropped = false;
+  for (int p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) {
+    bool drop = A.col[p] != i && fabs(A.val[p]) < thr;
+    c += !drop;
+    dropped |= drop;
+  }
+  if (!has_diag || (lump && dropped && !has_diag)) atomicOr(bad, 1);
+  count[i] = c;
+}
+__global__ void adrop_fill_kernel(CSRView A, double tol, int lump, const int32_t* rowptr,
+                                  int32_t* col, double* val, int32_t* bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.rows) return;
+  const int s = A.rowptr[i], e = A.rowptr[i + 1];
+  double m = 0.0;
+  double d = 0.0;
+  for (int p = s; p < e; ++p) {
+    if (A.col[p] != i) m = fmax(m, fabs(A.val[p]));
+    else d = A.val[p];
+  }
+  const double thr = tol * m;
+  if (lump)
+    for (int p = s; p < e; ++p)
+      if (A.col[p] != i && fabs(A.val[p]) < thr) d = d + A.val[p];
+  int64_t o = rowptr[i];
+  for (int p = s; p < e; ++p) {
+    const int j = A.col[p];
+    if (j != i && fabs(A.val[p]) < thr) continue;
+    col[o] = j;
+    val[o] = (j == i) ? d : A.val[p];
+    ++o;
+  }
+  if (d == 0.0 || !isfinite(d)) atomicOr(bad, 1);
+}
+
+void drop_lump(const CSR& Ain, double tol, bool lump, CSR& Aout, int32_t* bad_diag,
+               hipStream_t s) {
+  const int64_t n = Ain.rows;
+  DBuf<int64_t> cnt(n, s), off;
+  unsigned nb = blocks_for(n, kBlock);
+  if (n > 0) {
+    adrop_count_kernel<<<nb, kBlock, 0, s>>>(view(Ain), tol, lump ? 1 : 0, cnt.get(), bad_diag);
+    AIRG_CHECK_LAUNCH();
+  }
+  scan_counts(cnt, n, off, s);
+  Aout.rows = n;
+  Aout.cols = Ain.cols;
+  Aout.nnz = offsets_to_rowptr(off, n, Aout.rowptr, s);
+  Aout.col.alloc(Aout.nnz, s);
+  Aout.val.alloc(Aout.nnz, s);
+  if (n > 0) {
+    adrop_fill_kernel<<<nb, kBlock, 0, s>>>(view(Ain), tol, lump ? 1 : 0, Aout.rowptr.get(),
+                                            Aout.col.get(), Aout.val.get(), bad_diag);
+    AIRG_CHECK_LAUNCH();
+  }
+}
+
+// ------------------------------------------------------------------ R and P
+// R row c: Z row c with F columns mapped to level indices (fpos, ascending),
+// plus 1.0 at level index cpos[c], merged in column order.
+__global__ void build_r_kernel(CSRView Z, const int64_t* fpos, const int64_t* cpos,
+                               const int32_t* rowptr, int32_t* col, double* val) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Z.rows) return;
+  const int32_t me = (int32_t)cpos[c];
+  int64_t o = rowptr[c];
+  bool placed = false;
+  for (int p = Z.rowptr[c]; p < Z.rowptr[c + 1]; ++p) {
+    int32_t j = (int32_t)fpos[Z.col[p]];
+    if (!placed && me < j) {
+      col[o] = me;
+      val[o] = 1.0;
+      ++o;
+      placed = true;
+    }
+    col[o] = j;
+    val[o] = Z.val[p];
+    ++o;
+  }
+  if (!placed) {
+    col[o] = me;
+    val[o] = 1.0;
+  }
+}
+__global__ void rowlen_plus_one_kernel(CSRView Z, int64_t* cnt) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < Z.rows) cnt[c] = (int64_t)(Z.rowptr[c + 1] - Z.rowptr[c]) + 1;
+}
+
+void build_r(const CSR& Z, const int64_t* fpos, const int64_t* cpos, int64_t n, CSR& R,
+             hipStream_t s) {
+  const int64_t nc = Z.rows;
+  DBuf<int64_t> cnt(nc, s), off;
+  unsigned nb = blocks_for(nc, kBlock);
+  if (nc > 0) {
+    rowlen_plus_one_kernel<<<nb, kBlock, 0, s>>>(view(Z), cnt.get());
+    AIRG_CHECK_LAUNCH();
+  }
+  scan_counts(cnt, nc, off, s);
+  R.rows = nc;
+  R.cols = n;
+  R.nnz = offsets_to_rowptr(off, nc, R.rowptr, s);
+  R.col.alloc(R.nnz, s);
+  R.val.alloc(R.nnz, s);
+  if (nc > 0) {
+    build_r_kernel<<<nb, kBlock, 0, s>>>(view(Z), fpos, cpos, R.rowptr.get(), R.col.get(),
+                                         R.val.get());
+    AIRG_CHECK_LAUNCH();
+  }
+}
+
+__global__ void p_count_kernel(const int8_t* state, const int64_t* fidx, const int32_t* cmap,
+                               int64_t n, int64_t* cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cnt[i] = (state[i] == 2) ? 1 : (cmap[fidx[i]] >= 0 ? 1 : 0);
+}
+__global__ void p_fill_kernel(const int8_t* state, const int64_t* fidx, const int64_t* cidx,
+                              const int32_t* cmap, int64_t n, const int32_t* rowptr, int32_t* col,
+                              double* val) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t o = rowptr[i];
+  if (state[i] == 2) {
+    col[o] = (int32_t)cidx[i];
+    val[o] = 1.0;
+  } else {
+    int32_t c = cmap[fidx[i]];
+    if (c >= 0) {
+      col[o] = c;
+      val[o] = 1.0;
+    }
+  }
+}
+
+void build_p(const int8_t* state, const int64_t* fidx, const int64_t* cidx, const int32_t* cmap,
+             int64_t n, int64_t nc, CSR& P, hipStream_t s) {
+  DBuf<int64_t> cnt(n, s), off;
+  unsigned nb = blocks_for(n, kBlock);
+  if (n > 0) {
+    p_count_kernel<<<nb, kBlock, 0, s>>>(state, fidx, cmap, n, cnt.get());
+    AIRG_CHECK_LAUNCH();
+  }
+  scan_counts(cnt, n, off, s);
+  P.rows = n;
+  P.cols = nc;
+  P.nnz = offsets_to_rowptr(off, n, P.rowptr, s);
+  P.col.alloc(P.nnz, s);
+  P.val.alloc(P.nnz, s);
+  if (n > 0) {
+    p_fill_kernel<<<nb, kBlock, 0, s>>>(state, fidx, cidx, cmap, n, P.rowptr.get(), P.col.get(),
+                                        P.val.get());
+    AIRG_CHECK_LAUNCH();
+  }
+}
+
+// ------------------------------------------------------------------ permutation / transpose
+__global__ void perm_count_kernel(CSRView A, const int32_t* newrow, int64_t* cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < A.rows) cnt[newrow ? newrow[i] : i] = A.rowptr[i + 1] - A.rowptr[i];
+}
+__global__ void perm_fill_kernel(CSRView A, const int32_t* newrow, const int32_t* colmap,
+                                 const int32_t* rowptr, int32_t* col, double* val) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.rows) return;
+  int64_t o = rowptr[newrow ? newrow[i] : i];
+  for (int p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p, ++o) {
+    int j = A.col[p];
+    col[o] = colmap ? colmap[j] : j;
+    val[o] = A.val[p];
+  }
+}
+
+void permute_rows(const CSR& A, const int32_t* newrow, const int32_t* colmap, int64_t out_cols,
+                  CSR& out, hipStream_t s) {
+  const int64_t n = A.rows;
+  DBuf<int64_t> cnt(n, s), off;
+  unsigned nb = blocks_for(n, kBlock);
+  if (n > 0) {
+    perm_count_kernel<<<nb, kBlock, 0, s>>>(view(A), newrow, cnt.get());
+    AIRG_CHECK_LAUNCH();
+  }
+  scan_counts(cnt, n, off, s);
+  out.rows = n;
+  out.cols = out_cols;
+  out.nnz = offsets_to_rowptr(off, n, out.rowptr, s);
+  out.col.alloc(out.nnz, s);
+  out.val.alloc(out.nnz, s);
+  if (n > 0) {
+    perm_fill_kernel<<<nb, kBlock, 0, s>>>(view(A), newrow, colmap, out.rowptr.get(),
+                                           out.col.get(), out.val.get());
+    AIRG_CHECK_LAUNCH();
+  }
+}
+
+__global__ void tcount_kernel(CSRView A, unsigned long long* cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.rows) return;
+  for (int p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) atomicAdd(&cnt[A.col[p]], 1ull);
+}
+__global__ void tfill_kernel(CSRView A, const int32_t* rowptr, unsigned long long* cursor,
+                             int32_t* col, double* val) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.rows) return;
+  for (int p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) {
+    int j = A.col[p];
+    unsigned long long k = atomicAdd(&cursor[j], 1ull);
+    col[rowptr[j] + (int64_t)k] = (int32_t)i;
+    val[rowptr[j] + (int64_t)k] = A.val[p];
+  }
+}
+__global__ void row_sort_kernel(int64_t rows, const int32_t* rowptr, int32_t* col, double* val) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  const int s = rowptr[i], e = rowptr[i + 1];
+  for (int p = s + 1; p < e; ++p) {
+    int c = col[p];
+    double v = val[p];
+    int q = p - 1;
+    while (q >= s && col[q] > c) {
+      col[q + 1] = col[q];
+      val[q + 1] = val[q];
+      --q;
+    }
+    col[q + 1] = c;
+    val[q + 1] = v;
+  }
+}
+
+void transpose(const CSR& A, CSR& At, hipStream_t s) {
+  const int64_t m = A.cols;
+  DBuf<int64_t> cnt(m, s), off;
+  launch_zero_bytes(cnt.get(), m * sizeof(int64_t), s);
+  unsigned nb = blocks_for(A.rows, kBlock);
+  if (A.rows > 0) {
+    tcount_kernel<<<nb, kBlock, 0, s>>>(view(A), (unsigned long long*)cnt.get());
+    AIRG_CHECK_LAUNCH();
+  }
+  scan_counts(cnt, m, off, s);
+  At.rows = m;
+  At.cols = A.rows;
+  At.nnz = offsets_to_rowptr(off, m, At.rowptr, s);
+  At.col.alloc(At.nnz, s);
+  At.val.alloc(At.nnz, s);
+  DBuf<int64_t> cursor(m, s);
+  launch_zero_bytes(cursor.get(), m * sizeof(int64_t), s);
+  if (A.rows > 0) {
+    tfill_kernel<<<nb, kBlock, 0, s>>>(view(A), At.rowptr.get(), (unsigned long long*)cursor.get(),
+                                       At.col.get(), At.val.get());
+    AIRG_CHECK_LAUNCH();
+  }
+  if (m > 0) {
+    row_sort_kernel<<<blocks_for(m, kBlock), kBlock, 0, s>>>(m, At.rowptr.get(), At.col.get(),
+                                                              At.val.get());
+    AIRG_CHECK_LAUNCH();
+  }
+}
+
+void copy_csr(const CSR& A, CSR& out, hipStream_t s) {
+  out.alloc(A.rows, A.cols, A.nnz, s);
+  AIRG_HIP(hipMemcpyAsync(out.rowptr.get(), A.rowptr.get(), (A.rows + 1) * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, s));
+  if (A.nnz) {
+    AIRG_HIP(hipMemcpyAsync(out.col.get(), A.col.get(), A.nnz * sizeof(int32_t),
+                            hipMemcpyDeviceToDevice, s));
+    AIRG_HIP(hipMemcpyAsync(out.val.get(), A.val.get(), A.nnz * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+  }
+}
+
+}  // namespace airg

@@ -1,0 +1,365 @@
+// Vector kernels: counter-based random draws, elementwise updates, dot
+// products in a fixed binary-tree order, permutations and prefix scans.
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace airg {
+
+// ------------------------------------------------------------------ RNG
+// SplitMix64 (Steele, Lea & Flood 2014): output k of seed s is mix64(s + k g)
+// with the golden gamma g; used here as a counter-based generator.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void uniform_kernel(double* out, int64_t n, uint64_t seed, uint64_t base) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t c = base + (uint64_t)i;
+  uint64_t z = mix64(seed + (c + 1ull) * 0x9E3779B97F4A7C15ull);
+  out[i] = (double)(z >> 11) * 0x1.0p-53;
+}
+
+void launch_uniform(double* out, int64_t n, uint64_t seed, int purpose, int level, hipStream_t s) {
+  if (n <= 0) return;
+  uint64_t base = ((uint64_t)purpose << 56) | ((uint64_t)level << 40);
+  uniform_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(out, n, seed, base);
+  AIRG_CHECK_LAUNCH();
+}
+
+// ------------------------------------------------------------------ elementwise
+__global__ void fill_kernel(double* x, int64_t n, double v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+__global__ void fill_i32_kernel(int32_t* x, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+__global__ void zero_bytes_kernel(uint8_t* p, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+__global__ void copy_kernel(double* y, const double* x, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+__global__ void scale_kernel(double* y, const double* x, double a, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i];
+}
+__global__ void divide_kernel(double* y, const double* x, double d, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i] / d;
+}
+__global__ void divide_dev_kernel(double* y, const double* x, const double* d, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i] / d[0];
+}
+__global__ void sub_kernel(double* z, const double* x, const double* y, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = x[i] - y[i];
+}
+
+void launch_fill(double* x, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  fill_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(x, n, v);
+  AIRG_CHECK_LAUNCH();
+}
+void launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return;
+  fill_i32_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(x, n, v);
+  AIRG_CHECK_LAUNCH();
+}
+void launch_zero_bytes(void* p, size_t bytes, hipStream_t s) {
+  if (!bytes) return;
+  zero_bytes_kernel<<<blocks_for((int64_t)bytes, kBlock), kBlock, 0, s>>>((uint8_t*)p, bytes);
+  AIRG_CHECK_LAUNCH();
+}
+void launch_copy(double* y, const double* x, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  copy_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, n);
+  AIRG_CHECK_LAUNCH();
+}
+void launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  scale_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, a, n);
+  AIRG_CHECK_LAUNCH();
+}
+void launch_divide(double* y, const double* x, double d, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  divide_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, d, n);
+  AIRG_CHECK_LAUNCH();
+}
+void launch_divide_dev(double* y, const double* x, const double* d, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  divide_dev_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, d, n);
+  AIRG_CHECK_LAUNCH();
+}
+void launch_sub(double* z, const double* x, const double* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  sub_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(z, x, y, n);
+  AIRG_CHECK_LAUNCH();
+}
+
+__global__ void cgs_update_kernel(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                                  int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = w[i];
+  for (int k = 0; k < nv; ++k) acc = acc - h[k] * V[(int64_t)k * ldv + i];
+  w[i] = acc;
+}
+void launch_cgs_update(double* w, const double* V, int64_t ldv, const double* h, int nv, int64_t n,
+                       hipStream_t s) {
+  if (n <= 0 || nv <= 0) return;
+  cgs_update_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(w, V, ldv, h, nv, n);
+  AIRG_CHECK_LAUNCH();
+}
+
+__global__ void basis_combine_kernel(double* x, const double* Z, int64_t ldz, const double* y,
+                                     int nv, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = x[i];
+  for (int k = 0; k < nv; ++k) acc = acc + y[k] * Z[(int64_t)k * ldz + i];
+  x[i] = acc;
+}
+void launch_basis_combine(double* x, const double* Z, int64_t ldz, const double* y, int nv,
+                          int64_t n, hipStream_t s) {
+  if (n <= 0 || nv <= 0) return;
+  basis_combine_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(x, Z, ldz, y, nv, n);
+  AIRG_CHECK_LAUNCH();
+}
+
+// ------------------------------------------------------------------ tree dots
+// A block reduces an aligned chunk of 1024 consecutive leaves: each of the 256
+// threads sums 4 adjacent leaves as (l0 + l1) + (l2 + l3); lanes then pair up
+// with offsets 1, 2, ..., 32 (lane L adds lane L + o when L is a multiple of
+// 2o) and the four waves combine as (w0 + w1) + (w2 + w3).  Every partial is
+// therefore an aligned subtree of the perfect binary tree over the zero-padded
+// index range, and later stages repeat the scheme on the partials.
+constexpr int kDotChunk = 1024;
+constexpr int kMaxDotVecs = 64;
+
+__device__ __forceinline__ double wave_tree(double v) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    double u = __shfl_down(v, o, 64);
+    v = v + u;
+  }
+  return v;  // valid in lane 0
+}
+
+__global__ __launch_bounds__(256) void tree_dot_stage1(const double* __restrict__ V, int64_t ldv,
+                                                       int nv, const double* __restrict__ w,
+                                                       int64_t n, double* __restrict__ part,
+                                                       int64_t nb) {
+  __shared__ double red[kMaxDotVecs][4];
+  const int t = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * kDotChunk + 4 * t;
+  double w4[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) w4[q] = (i0 + q < n) ? w[i0 + q] : 0.0;
+  const int lane = t & 63, wave = t >> 6;
+  for (int k = 0; k < nv; ++k) {
+    const double* v = V + (int64_t)k * ldv;
+    double p[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[q] = (i0 + q < n) ? v[i0 + q] * w4[q] : 0.0;
+    double local = (p[0] + p[1]) + (p[2] + p[3]);
+    double ws = wave_tree(local);
+    if (lane == 0) red[k][wave] = ws;
+  }
+  __syncthreads();
+  if (t < nv) part[(int64_t)t * nb + blockIdx.x] = (red[t][0] + red[t][1]) + (red[t][2] + red[t][3]);
+}
+
+__global__ __launch_bounds__(256) void tree_sum_stage(const double* __restrict__ in, int64_t m,
+                                                      int64_t in_stride, double* __restrict__ out,
+                                                      int64_t out_stride) {
+  __shared__ double red[4];
+  const int t = threadIdx.x;
+  const int k = blockIdx.y;
+  const double* src = in + (int64_t)k * in_stride;
+  const int64_t i0 = (int64_t)blockIdx.x * kDotChunk + 4 * t;
+  double p[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) p[q] = (i0 + q < m) ? src[i0 + q] : 0.0;
+  double local = (p[0] + p[1]) + (p[2] + p[3]);
+  double ws = wave_tree(local);
+  if ((t & 63) == 0) red[t >> 6] = ws;
+  __syncthreads();
+  if (t == 0) out[(int64_t)k * out_stride + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+size_t dot_work_size(int64_t n, int nv) {
+  int64_t nb = (n + kDotChunk - 1) / kDotChunk;
+  if (nb < 1) nb = 1;
+  int64_t nb2 = (nb + kDotChunk - 1) / kDotChunk;
+  return (size_t)nv * (size_t)(nb + nb2 + 2);
+}
+
+void launch_tree_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* out,
+                      double* work, hipStream_t s) {
+  if (nv <= 0) return;
+  if (nv > kMaxDotVecs) fail(AIRG_ERR_INVALID, "too many vectors in one dot launch");
+  int64_t nb = (n + kDotChunk - 1) / kDotChunk;
+  if (nb < 1) nb = 1;
+  double* a = work;
+  double* b = work + (size_t)nv * nb;
+  tree_dot_stage1<<<(unsigned)nb, 256, 0, s>>>(V, ldv, nv, w, n, a, nb);
+  AIRG_CHECK_LAUNCH();
+  int64_t m = nb;
+  int64_t stride = nb;
+  for (;;) {
+    // always at least one stage: a single partial is copied through as p + 0
+    int64_t mb = (m + kDotChunk - 1) / kDotChunk;
+    double* dst = (mb == 1) ? out : b;
+    int64_t dstride = (mb == 1) ? 1 : mb;
+    tree_sum_stage<<<dim3((unsigned)mb, (unsigned)nv), 256, 0, s>>>(a, m, stride, dst, dstride);
+    AIRG_CHECK_LAUNCH();
+    if (mb == 1) return;
+    std::swap(a, b);
+    m = mb;
+    stride = dstride;
+  }
+}
+
+__global__ void sqrt_kernel(double* v) { v[0] = sqrt(v[0]); }
+void launch_sqrt_inplace(double* v, hipStream_t s) {
+  sqrt_kernel<<<1, 1, 0, s>>>(v);
+  AIRG_CHECK_LAUNCH();
+}
+
+// ------------------------------------------------------------------ permutations
+__global__ void scatter_kernel(double* y, const double* x, const int32_t* perm, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[perm[i]] = x[i];
+}
+__global__ void gather_kernel(double* y, const double* x, const int32_t* perm, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[perm[i]];
+}
+void launch_scatter(double* y, const double* x, const int32_t* perm, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  scatter_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, perm, n);
+  AIRG_CHECK_LAUNCH();
+}
+void launch_gather(double* y, const double* x, const int32_t* perm, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  gather_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, perm, n);
+  AIRG_CHECK_LAUNCH();
+}
+
+// ------------------------------------------------------------------ scans
+// Three phases over chunks of 1024: chunk totals, a single-block exclusive scan
+// of the totals, then per-chunk exclusive scans offset by the chunk prefix.
+constexpr int kScanChunk = 1024;
+
+__device__ int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t* total) {
+  // 256 threads: Hillis-Steele inclusive scan in LDS
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    int64_t a = (t >= o) ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  int64_t incl = sh[t];
+  if (total) *total = sh[255];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(256) void scan_totals_kernel(const int64_t* in, int64_t n,
+                                                          int64_t* totals) {
+  __shared__ int64_t sh[256];
+  const int64_t i0 = (int64_t)blockIdx.x * kScanChunk + 4 * threadIdx.x;
+  int64_t v = 0;
+  for (int q = 0; q < 4; ++q)
+    if (i0 + q < n) v += in[i0 + q];
+  int64_t tot;
+  block_exclusive_scan(v, sh, &tot);
+  if (threadIdx.x == 0) totals[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void scan_single_kernel(int64_t* a, int64_t m) {
+  // exclusive scan of a[0..m) in place by one block; a[m] = total
+  __shared__ int64_t sh[256];
+  const int t = threadIdx.x;
+  const int64_t per = (m + 255) / 256;
+  const int64_t lo = t * per, hi = (lo + per < m) ? lo + per : m;
+  int64_t v = 0;
+  for (int64_t i = lo; i < hi; ++i) v += a[i];
+  int64_t tot;
+  int64_t base = block_exclusive_scan(v, sh, &tot);
+  for (int64_t i = lo; i < hi; ++i) {
+    int64_t x = a[i];
+    a[i] = base;
+    base += x;
+  }
+  if (t == 0) a[m] = tot;
+}
+
+__global__ __launch_bounds__(256) void scan_apply_kernel(const int64_t* in, int64_t* out, int64_t n,
+                                                         const int64_t* prefix) {
+  __shared__ int64_t sh[256];
+  const int64_t i0 = (int64_t)blockIdx.x * kScanChunk + 4 * threadIdx.x;
+  int64_t v[4];
+  int64_t tsum = 0;
+  for (int q = 0; q < 4; ++q) {
+    v[q] = (i0 + q < n) ? in[i0 + q] : 0;
+    tsum += v[q];
+  }
+  __syncthreads();  // in and out may alias: every read of this block is done
+  int64_t base = block_exclusive_scan(tsum, sh, nullptr) + prefix[blockIdx.x];
+  for (int q = 0; q < 4; ++q) {
+    if (i0 + q < n) out[i0 + q] = base;
+    base += v[q];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = prefix[gridDim.x];
+}
+
+size_t scan_work_size(int64_t n) {
+  int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+  return (size_t)(nb + 2);
+}
+
+void launch_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* work, hipStream_t s) {
+  if (n <= 0) {
+    launch_zero_bytes(out, sizeof(int64_t), s);
+    return;
+  }
+  int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+  scan_totals_kernel<<<(unsigned)nb, 256, 0, s>>>(in, n, work);
+  AIRG_CHECK_LAUNCH();
+  scan_single_kernel<<<1, 256, 0, s>>>(work, nb);
+  AIRG_CHECK_LAUNCH();
+  scan_apply_kernel<<<(unsigned)nb, 256, 0, s>>>(in, out, n, work);
+  AIRG_CHECK_LAUNCH();
+}
+
+__global__ void offsets_to_i32_kernel(const int64_t* off, int32_t* rp, int64_t n1, int32_t* ovf) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n1) return;
+  int64_t v = off[i];
+  if (v > 2147483647ll) {
+    atomicOr(ovf, 1);
+    v = 0;
+  }
+  rp[i] = (int32_t)v;
+}
+void launch_offsets_to_i32(const int64_t* off, int32_t* rowptr, int64_t n1, int32_t* overflow,
+                           hipStream_t s) {
+  if (n1 <= 0) return;
+  offsets_to_i32_kernel<<<blocks_for(n1, kBlock), kBlock, 0, s>>>(off, rowptr, n1, overflow);
+  AIRG_CHECK_LAUNCH();
+}
+
+}  // namespace airg

@@ -1,0 +1,282 @@
+"""GPU path vs the CPU oracle, through the C ABI (needs an MI355X).
+
+The setup follows the same summation orders as the oracle, so every discrete
+decision (CF split, prolongator, drops) and every assembled operator is
+compared bit for bit level by level; the Newton roots come from different
+eigenvalue codes and are compared to a tolerance.  Solutions must agree with
+the oracle's to a relative 1e-10 with the same FGMRES iteration count.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from airg_inputs import workloads, fv_advection
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _needs_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _solver(p, **kw):
+    from paper_2508_17517_amd import Solver
+    return Solver(p.indptr, p.indices, p.data, **kw)
+
+
+CASES = {
+    "fv64": lambda: workloads.fv64(),
+    "fv48_perm": lambda: workloads.fv_random(48, 0.3, True),
+    "fv128_perm": lambda: workloads.fv_random(128, 0.3, True),
+    "fv100_theta1": lambda: workloads.fv_random(100, 1.0, True),
+    "fv80x40_rect": lambda: workloads.fv_random(80, 0.7, True, ny=40),
+}
+
+
+def _csr_equal(name, got, want, l):
+    rp, col, val = got
+    want = sp.csr_matrix(want)
+    want.sort_indices()
+    assert np.array_equal(rp, want.indptr), f"level {l} {name}: row pointers differ"
+    assert np.array_equal(col, want.indices), f"level {l} {name}: columns differ"
+    if not np.array_equal(val, want.data):
+        d = np.abs(val - want.data).max() / np.abs(want.data).max()
+        raise AssertionError(f"level {l} {name}: values differ (max rel {d:.3e})")
+
+
+def compare_hierarchy(s, levels):
+    st = s.stats()
+    assert st["levels"] == len(levels), (st["levels"], len(levels))
+    for l, L in enumerate(levels):
+        g = s.export_level(l)
+        assert g["n"] == L.A.shape[0]
+        if l > 0 or L.coarsest:
+            _csr_equal("A", g["a"], L.A, l)
+        if L.coarsest:
+            assert g["is_coarsest"]
+            want = np.array(L.roots)
+            got = g["roots"]
+            assert len(got) == len(want), f"coarsest: {len(got)} roots vs {len(want)}"
+            assert np.allclose(np.sort_complex(got), np.sort_complex(want), rtol=1e-9, atol=1e-12)
+            continue
+        assert np.array_equal(g["state"], L.state), f"level {l}: CF split differs"
+        _csr_equal("A_ff", g["ff"], L.Aff, l)
+        _csr_equal("A_fc", g["fc"], L.Afc, l)
+        assert np.array_equal(g["alpha"], L.alpha), f"level {l}: smoother coefficients differ"
+        _csr_equal("Z", g["z"], L.Z, l)
+        assert np.array_equal(g["cmap"], L.cmap), f"level {l}: prolongator differs"
+        if L.trunc_rel is not None:
+            assert st["trunc_rel"][l] == pytest.approx(L.trunc_rel, rel=1e-8)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_hierarchy_is_the_oracles_level_by_level(case):
+    _needs_gpu()
+    p = CASES[case]()
+    print(f"case {case} n={p.n}", flush=True)
+    levels = oracle.setup(p.scipy())
+    s = _solver(p, keep_setup_data=1)
+    compare_hierarchy(s, levels)
+    s.close()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_solve_matches_oracle(case):
+    _needs_gpu()
+    p = CASES[case]()
+    print(f"case {case} n={p.n}", flush=True)
+    xo, its, rel, levels, _ = oracle.solve(p.scipy(), p.b)
+    s = _solver(p)
+    x, info = s.solve(torch.from_numpy(p.b).cuda())
+    xg = x.cpu().numpy()
+    assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
+    assert info["iterations"] == its
+    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+    # against the exact discrete solution too
+    u = oracle.sweep_solve(p.scipy(), p.b, p.level)
+    assert np.linalg.norm(xg - u) <= 1e-8 * np.linalg.norm(u)
+    s.close()
+
+
+def test_imported_oracle_hierarchy_solves_like_the_oracle():
+    _needs_gpu()
+    from paper_2508_17517_amd import Solver
+    p = workloads.fv_random(96, 0.3, True)
+    A = p.scipy()
+    xo, its, rel, levels, _ = oracle.solve(A, p.b)
+
+    def trip(M):
+        M = sp.csr_matrix(M)
+        M.sort_indices()
+        return (M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data)
+
+    lv = []
+    for l, L in enumerate(levels):
+        d = {}
+        if l == 0 or L.coarsest:
+            d["a"] = trip(L.A)
+        if L.coarsest:
+            d["roots"] = np.array(L.roots)
+        else:
+            d.update(state=L.state, ff=trip(L.Aff), fc=trip(L.Afc), z=trip(L.Z),
+                     cmap=L.cmap.astype(np.int32), alpha=L.alpha)
+        lv.append(d)
+    s = Solver.from_hierarchy(lv)
+    x, info = s.solve(torch.from_numpy(p.b).cuda())
+    assert info["iterations"] == its
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    s.close()
+
+
+def test_import_rejects_out_of_range_indices():
+    _needs_gpu()
+    from paper_2508_17517_amd import Solver, AirgError
+    p = workloads.fv_random(32, 0.3, True)
+    levels = oracle.setup(p.scipy())
+    L0, Lc = levels[0], levels[-1]
+    if len(levels) < 2:
+        pytest.skip("single level")
+    trip = lambda M: (M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data)
+    cm = L0.cmap.astype(np.int32).copy()
+    cm[0] = 10 ** 6
+    lv = [dict(a=trip(L0.A), state=L0.state, ff=trip(L0.Aff), fc=trip(L0.Afc), z=trip(L0.Z),
+               cmap=cm, alpha=L0.alpha)]
+    lv.append(dict(a=trip(levels[1].A), roots=np.array(levels[1].roots if levels[1].coarsest
+                                                         else oracle.hierarchy.newton_for_level(
+                                                             levels[1].A, 1, oracle.Params()))))
+    with pytest.raises(AirgError):
+        Solver.from_hierarchy(lv)
+
+
+def test_adjoint_solve_matches_oracle_and_sweep():
+    _needs_gpu()
+    p = workloads.fv_random(64, 0.3, True)
+    A = p.scipy()
+    w = np.random.default_rng(3).standard_normal(p.n)
+    lo, its, rel, _, _ = oracle.adjoint_solve(A, w)
+    s = _solver(p)
+    lam, info = s.adjoint_solve(torch.from_numpy(w).cuda())
+    lg = lam.cpu().numpy()
+    assert info["converged"] == 1 and info["iterations"] == its
+    assert np.linalg.norm(lg - lo) <= 1e-10 * np.linalg.norm(lo)
+    ls = oracle.sweep_solve(A, w, p.level, transpose=True)
+    assert np.linalg.norm(lg - ls) <= 1e-8 * np.linalg.norm(ls)
+    s.close()
+
+
+def test_several_right_hand_sides_and_initial_guess():
+    _needs_gpu()
+    p = workloads.fv_random(64, 0.5, True)
+    B = workloads.rhs_batch(p, 3)
+    s = _solver(p)
+    X, infos = s.solve(torch.from_numpy(B).cuda())
+    for k in range(3):
+        u = oracle.sweep_solve(p.scipy(), B[k], p.level)
+        assert infos[k]["converged"] == 1
+        assert np.linalg.norm(X[k].cpu().numpy() - u) <= 1e-8 * np.linalg.norm(u)
+    # restarting from the converged solution needs no iteration
+    x2, info2 = s.solve(torch.from_numpy(B[0]).cuda(), x=X[0].clone(), guess=True)
+    assert info2["iterations"] == 0 and info2["converged"] == 1
+    # a zero right-hand side gives zero
+    xz, infz = s.solve(torch.zeros(p.n, dtype=torch.float64, device="cuda"))
+    assert infz["iterations"] == 0 and float(xz.abs().max()) == 0.0
+    s.close()
+
+
+def test_setup_is_deterministic_run_to_run():
+    _needs_gpu()
+    p = workloads.fv_random(128, 1.2, True)
+    s1 = _solver(p, keep_setup_data=1)
+    s2 = _solver(p, keep_setup_data=1)
+    st1, st2 = s1.stats(), s2.stats()
+    assert st1["levels"] == st2["levels"]
+    for l in range(st1["levels"]):
+        a, b = s1.export_level(l), s2.export_level(l)
+        for k in a:
+            if isinstance(a[k], tuple):
+                for u, v in zip(a[k], b[k]):
+                    assert np.array_equal(u, v)
+            elif isinstance(a[k], np.ndarray):
+                assert np.array_equal(a[k], b[k])
+    x1, i1 = s1.solve(torch.from_numpy(p.b).cuda())
+    x2, i2 = s2.solve(torch.from_numpy(p.b).cuda())
+    assert i1["iterations"] == i2["iterations"]
+    assert torch.equal(x1, x2)
+    s1.close()
+    s2.close()
+
+
+def test_error_codes():
+    _needs_gpu()
+    from paper_2508_17517_amd import Solver, AirgError
+    p = workloads.fv_random(16, 0.3, False)
+    bad = p.data.copy()
+    bad[p.indptr[5] + 0] = np.nan
+    with pytest.raises(AirgError) as e:
+        Solver(p.indptr, p.indices, bad)
+    assert e.value.code == -3
+    # zero diagonal: the last entry of each FV row is its diagonal
+    z = p.data.copy()
+    z[p.indptr[8] - 1] = 0.0
+    with pytest.raises(AirgError) as e:
+        Solver(p.indptr, p.indices, z)
+    assert e.value.code == -2
+    # unsorted columns
+    ix = p.indices.copy()
+    r = 20
+    a, b = p.indptr[r], p.indptr[r + 1]
+    ix[a:b] = ix[a:b][::-1].copy()
+    with pytest.raises(AirgError) as e:
+        Solver(p.indptr, ix, p.data)
+    assert e.value.code == -1
+    # a parameter out of range
+    with pytest.raises(AirgError) as e:
+        Solver(p.indptr, p.indices, p.data, strong_threshold=1.5)
+    assert e.value.code == -1
+    # non-finite right-hand side
+    s = Solver(p.indptr, p.indices, p.data)
+    bb = torch.from_numpy(p.b).cuda()
+    bb[3] = float("inf")
+    with pytest.raises(AirgError) as e:
+        s.solve(bb)
+    assert e.value.code == -3
+    # an iteration cap that cannot be met reports not-converged with the iterate
+    s2 = Solver(p.indptr, p.indices, p.data, max_it=1)
+    x, info = s2.solve(torch.from_numpy(p.b).cuda())
+    assert info["converged"] == 0 and info["iterations"] == 1
+    s.close()
+    s2.close()
+
+
+def test_stats_are_consistent():
+    _needs_gpu()
+    p = workloads.fv_random(128, 0.3, True)
+    s = _solver(p)
+    st = s.stats()
+    levels = oracle.setup(p.scipy())
+    assert st["n"] == [L.A.shape[0] for L in levels]
+    assert st["nnz"] == [L.A.nnz for L in levels]
+    assert st["grid_complexity"] == pytest.approx(sum(L.A.shape[0] for L in levels) / p.n)
+    assert st["cycle_complexity"] > 1 and st["storage_complexity"] > 1
+    assert st["coarse_roots"] == len(levels[-1].roots)
+    s.close()
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.5 * math.pi])
+def test_grid_aligned_flow(theta):
+    # grid-aligned directions decouple into 1D lines (paper Sec. 3.4)
+    _needs_gpu()
+    gw, gs = workloads.inflow_values(1, 40)
+    p = fv_advection(40, theta, gw, gs, perm_seed=9)
+    xo, its, rel, levels, _ = oracle.solve(p.scipy(), p.b)
+    s = _solver(p)
+    x, info = s.solve(torch.from_numpy(p.b).cuda())
+    assert info["iterations"] == its
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    s.close()
