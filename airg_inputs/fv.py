@@ -57,36 +57,27 @@ class FVProblem:
         return sp.csr_matrix((self.data, self.indices, self.indptr), shape=(self.n, self.n))
 
 
-def _grid_csr(nx, ny, vx, vy, dvx, dvy):
-    """Natural-order CSR (cols south, west, diag) plus the d/dtheta values."""
+def _grid_slots(nx, ny, vx, vy, dvx, dvy):
+    """Natural-order stencil in three slots per row (south, west, diagonal):
+    columns, values, d/dtheta values and a mask of the entries that exist."""
     n = nx * ny
     k = np.arange(n, dtype=np.int64)
     i = k % nx
     j = k // nx
-    has_s = (j > 0) & (vy != 0.0)
-    has_w = (i > 0) & (vx != 0.0)
-    cnt = 1 + has_s.astype(np.int64) + has_w.astype(np.int64)
-    indptr = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(cnt, out=indptr[1:])
-    nnz = int(indptr[-1])
-    indices = np.empty(nnz, dtype=np.int64)
-    data = np.empty(nnz, dtype=np.float64)
-    ddata = np.empty(nnz, dtype=np.float64)
-    pos = indptr[:-1].copy()
-    s = pos[has_s]
-    indices[s] = k[has_s] - nx
-    data[s] = -vy
-    ddata[s] = -dvy
-    pos[has_s] += 1
-    w = pos[has_w]
-    indices[w] = k[has_w] - 1
-    data[w] = -vx
-    ddata[w] = -dvx
-    pos[has_w] += 1
-    indices[pos] = k
-    data[pos] = vx + vy
-    ddata[pos] = dvx + dvy
-    return indptr, indices, data, ddata, i, j
+    cols = np.stack([k - nx, k - 1, k], axis=1)
+    mask = np.stack([(j > 0) & (vy != 0.0), (i > 0) & (vx != 0.0), np.ones(n, dtype=bool)], axis=1)
+    vals = np.empty((n, 3))
+    vals[:, 0], vals[:, 1], vals[:, 2] = -vy, -vx, vx + vy
+    dvals = np.empty((n, 3))
+    dvals[:, 0], dvals[:, 1], dvals[:, 2] = -dvy, -dvx, dvx + dvy
+    return cols, vals, dvals, mask, i, j
+
+
+def _compress(cols, vals, dvals, mask):
+    """CSR arrays from the slot layout (slots already ascending in each row)."""
+    indptr = np.zeros(cols.shape[0] + 1, dtype=np.int64)
+    np.cumsum(mask.sum(axis=1), out=indptr[1:])
+    return indptr, cols[mask], vals[mask], dvals[mask]
 
 
 def fv_advection(nx, theta, g_west, g_south, perm_seed=None, ny=None):
@@ -104,7 +95,7 @@ def fv_advection(nx, theta, g_west, g_south, perm_seed=None, ny=None):
     g_west = np.broadcast_to(np.asarray(g_west, dtype=np.float64), (ny,)).copy()
     g_south = np.broadcast_to(np.asarray(g_south, dtype=np.float64), (nx,)).copy()
     n = nx * ny
-    indptr, indices, data, ddata, ci, cj = _grid_csr(nx, ny, vx, vy, dvx, dvy)
+    cols, vals, dvals, mask, ci, cj = _grid_slots(nx, ny, vx, vy, dvx, dvy)
 
     west_rows = np.arange(ny, dtype=np.int64) * nx
     south_rows = np.arange(nx, dtype=np.int64)
@@ -126,23 +117,22 @@ def fv_advection(nx, theta, g_west, g_south, perm_seed=None, ny=None):
         order = np.argsort(keys, kind="stable").astype(np.int64)
         inv = np.empty(n, dtype=np.int64)
         inv[order] = np.arange(n, dtype=np.int64)
-        lens = np.diff(indptr)[order]
-        new_ptr = np.zeros(n + 1, dtype=np.int64)
-        np.cumsum(lens, out=new_ptr[1:])
-        src = np.repeat(indptr[order], lens) + (np.arange(new_ptr[-1]) - np.repeat(new_ptr[:-1], lens))
-        rows = np.repeat(np.arange(n, dtype=np.int64), lens)
-        cols = inv[indices[src]]
-        perm_sort = np.lexsort((cols, rows))
-        indices = cols[perm_sort]
-        data = data[src][perm_sort]
-        ddata = ddata[src][perm_sort]
-        indptr = new_ptr
+        # row p of the permuted system is grid row order[p]; relabel its columns
+        # and sort each row's (at most three) slots, absent slots last
+        cols, vals, dvals, mask = cols[order], vals[order], dvals[order], mask[order]
+        cols = np.where(mask, inv[np.where(mask, cols, 0)], np.iinfo(np.int64).max)
+        srt = np.argsort(cols, axis=1, kind="stable")
+        cols = np.take_along_axis(cols, srt, axis=1)
+        vals = np.take_along_axis(vals, srt, axis=1)
+        dvals = np.take_along_axis(dvals, srt, axis=1)
+        mask = np.take_along_axis(mask, srt, axis=1)
         b = b[order]
         db = db[order]
         level = level[order]
         west_rows = inv[west_rows]
         south_rows = inv[south_rows]
         outflow = inv[outflow]
+    indptr, indices, data, ddata = _compress(cols, vals, dvals, mask)
 
     return FVProblem(nx=nx, ny=ny, theta=float(theta),
                      indptr=indptr.astype(np.int32), indices=indices.astype(np.int32),

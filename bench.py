@@ -17,12 +17,15 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E, published peak
+
 WORKLOADS = {
     # name: (grid side, theta, permuted)
     "fv2048": (2048, 0.3, True),
     "fv1024": (1024, 0.3, False),
     "fv8192": (8192, 0.3, True),
     "fv512": (512, 0.3, True),
+    "fv1024p": (1024, 0.3, True),
 }
 
 
@@ -52,6 +55,8 @@ def main():
     ap.add_argument("--workload", default="fv2048", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=512)
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--no-mixed", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the solver has no multi-GPU "
@@ -79,6 +84,11 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     st = s.stats()
+    for l in range(st["levels"]):
+        print(f"bench: level {l}: n {st['n'][l]} nnz {st['nnz'][l]} nF {st['n_f'][l]} "
+              f"nnz_ff {st['nnz_ff'][l]} nnz_fc {st['nnz_fc'][l]} nnz_z {st['nnz_z'][l]} "
+              f"d {st['poly_degree'][l]}", file=sys.stderr)
+    print(f"bench: setup {setup_s:.3f} s {st['setup_component_ms']}", file=sys.stderr, flush=True)
     x = torch.zeros_like(b)
     for w in range(a.warmup):
         x, info = s.solve(b, x)
@@ -121,6 +131,51 @@ def main():
         "roofline": None,
         "cpu_baseline": None,
     }
+    # per-class kernel timing (HIP events on the library's stream), right after
+    # the timed region on the same hierarchy
+    classes = {}
+    for cls in ("poly", "horner", "newton", "residual", "restrict", "top_spmv"):
+        kt = s.time_kernels(cls, reps=a.kernel_reps)
+        kt["gbps"] = kt["bytes_per_launch"] / (kt["avg_launch_ms"] * 1e-3) / 1e9
+        classes[cls] = kt
+        print(f"bench: {cls:9s} launches/V-cycle {kt['launches']:4d}  avg {1e3 * kt['avg_launch_ms']:8.2f} us"
+              f"  {kt['bytes_per_launch'] / 1e6:8.3f} MB/launch  {kt['gbps']:8.1f} GB/s",
+              file=sys.stderr, flush=True)
+    dom = classes["poly"]
+    out["roofline"] = {"bound": "hbm", "kernel": "poly-SpMV (Horner smoother steps + Newton "
+                                                 "coarse steps, one V-cycle's launches)",
+                       "achieved": dom["gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                       "frac": dom["gbps"] / HBM_PEAK_GBPS, "traffic": None,
+                       "avg_launch_us": 1e3 * dom["avg_launch_ms"],
+                       "bytes_per_launch": dom["bytes_per_launch"],
+                       "launches_per_vcycle": dom["launches"]}
+    out["kernel_classes_gbps"] = {k: round(v["gbps"], 1) for k, v in classes.items()}
+    # mixed precision: FP32 / BF16 storage in the V-cycle inside FP64 FGMRES,
+    # the same 1e-10 true FP64 residual
+    if not a.no_mixed:
+        out["mixed"] = {}
+        xref = x.clone()
+        for name, prec in (("fp32", binding.FP32), ("bf16", binding.BF16)):
+            sm = Solver(ip, ix, dv, precision=prec)
+            xm = torch.zeros_like(b)
+            for w in range(a.warmup):
+                xm, _ = sm.solve(b, xm)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(a.steps):
+                xm, im = sm.solve(b, xm)
+                assert im["converged"] == 1 and im["rel_residual"] <= 1e-10, im
+            torch.cuda.synchronize()
+            dtm = time.perf_counter() - t0
+            err = float(torch.linalg.norm(xm - xref) / torch.linalg.norm(xref))
+            ktm = sm.time_kernels("poly", reps=a.kernel_reps)
+            out["mixed"][name] = {"value": p.n * a.steps / dtm, "ms_per_step": 1000.0 * dtm / a.steps,
+                                  "iterations": im["iterations"], "rel_residual": im["rel_residual"],
+                                  "rel_diff_vs_fp64_solution": err,
+                                  "speedup_vs_fp64": (p.n * a.steps / dtm) / value,
+                                  "poly_gbps": ktm["bytes_per_launch"] / (ktm["avg_launch_ms"] * 1e-3) / 1e9}
+            print(f"bench: {name}: {out['mixed'][name]}", file=sys.stderr, flush=True)
+            sm.close()
     if not a.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.cpu_sample)

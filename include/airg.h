@@ -76,7 +76,9 @@ typedef struct {
   int32_t max_it;            /* FGMRES iteration cap (V-cycles), 500 */
   int32_t restart;           /* FGMRES restart length, 30 */
   int32_t keep_setup_data;   /* keep level data in setup numbering for export, 0 */
-  int32_t reserved;
+  int32_t locality_order;    /* order each level's F points in the solve numbering by
+                                breadth-first distance on A + A^T (cache locality of the
+                                SpMV gathers; the hierarchy itself is unchanged), 1 */
 } airg_params;
 
 typedef struct {
@@ -175,6 +177,33 @@ int airg_export_level(airg_handle h, int level, airg_level_arrays* out);
 int airg_import_hierarchy(airg_handle* out, int nlevels, const airg_level_info* infos,
                           const airg_level_arrays* levels, const airg_params* p,
                           void* hip_stream);
+
+/* Kernel classes of the solve, for airg_time_kernels. */
+enum airg_kernel_class {
+  AIRG_K_POLY = 0,      /* every polynomial SpMV of a V-cycle: Horner smoother steps on
+                           all levels and the Newton steps of the coarse solve */
+  AIRG_K_HORNER = 1,    /* smoother steps only (Sec. 2.2) */
+  AIRG_K_NEWTON = 2,    /* coarse Newton steps only (Sec. 2.3) */
+  AIRG_K_RESIDUAL = 3,  /* F-point residual with fused one-point prolongation (Eq. f_point) */
+  AIRG_K_RESTRICT = 4,  /* restriction r_c + Z r_f */
+  AIRG_K_TOP_SPMV = 5   /* top-level y = A x of the outer loop */
+};
+
+typedef struct {
+  int32_t launches;          /* launches of the class in one V-cycle (1 for AIRG_K_TOP_SPMV) */
+  int32_t reserved;
+  double avg_launch_ms;      /* device time per launch, HIP events around reps passes */
+  double bytes_per_launch;   /* algorithmic HBM bytes per launch: each matrix entry and
+                                each vector element read or written once */
+  double flops_per_launch;   /* 2 per matrix entry plus the vector updates */
+} airg_kernel_timing;
+
+/* Diagnostics for benchmarks: enqueue `reps` passes of exactly the launches
+ * one V-cycle makes of kernel class `cls` (same operators, same launch
+ * shapes, on the handle's scratch vectors) between two HIP events on the
+ * handle's stream, and report the average launch time and the algorithmic
+ * bytes and flops per launch.  Does not change the solver's state. */
+int airg_time_kernels(airg_handle h, int cls, int reps, airg_kernel_timing* out);
 
 /* Release the handle and all its device memory (NULL is a no-op). */
 void airg_destroy(airg_handle h);

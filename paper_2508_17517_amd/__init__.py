@@ -110,6 +110,14 @@ class Solver:
         binding.check(self.lib.airg_get_stats(self.h, ctypes.byref(s)), self.lib)
         return s.as_dict()
 
+    def time_kernels(self, cls="poly", reps=20):
+        """Average launch time and algorithmic bytes of one kernel class of the
+        V-cycle (see airg_time_kernels)."""
+        kt = binding.KernelTiming()
+        code = self.lib.airg_time_kernels(self.h, binding.KERNEL_CLASSES[cls], reps, ctypes.byref(kt))
+        binding.check(code, self.lib)
+        return kt.as_dict()
+
     def level_info(self, level):
         li = binding.LevelInfo()
         binding.check(self.lib.airg_level_info_get(self.h, level, ctypes.byref(li)), self.lib)

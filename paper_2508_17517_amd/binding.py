@@ -23,7 +23,7 @@ class Params(ctypes.Structure):
                 ("poly_order", c_i32), ("coarse_poly_order", c_i32), ("trunc_start_level", c_i32),
                 ("max_levels", c_i32), ("added_roots", c_i32), ("precision", c_i32),
                 ("max_it", c_i32), ("restart", c_i32), ("keep_setup_data", c_i32),
-                ("reserved", c_i32)]
+                ("locality_order", c_i32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -76,6 +76,16 @@ class LevelArrays(ctypes.Structure):
                 ("roots_im", P(c_dbl))]
 
 
+class KernelTiming(ctypes.Structure):
+    _fields_ = [("launches", c_i32), ("reserved", c_i32), ("avg_launch_ms", c_dbl),
+                ("bytes_per_launch", c_dbl), ("flops_per_launch", c_dbl)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+KERNEL_CLASSES = {"poly": 0, "horner": 1, "newton": 2, "residual": 3, "restrict": 4, "top_spmv": 5}
+
 SYMBOLS = {
     "airg_params_default": (c_i32, [P(Params)]),
     "airg_setup": (c_i32, [P(ctypes.c_void_p), c_i64, c_i64, ctypes.c_void_p, ctypes.c_void_p,
@@ -89,6 +99,7 @@ SYMBOLS = {
     "airg_export_level": (c_i32, [ctypes.c_void_p, ctypes.c_int, P(LevelArrays)]),
     "airg_import_hierarchy": (c_i32, [P(ctypes.c_void_p), ctypes.c_int, P(LevelInfo),
                                       P(LevelArrays), P(Params), ctypes.c_void_p]),
+    "airg_time_kernels": (c_i32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, P(KernelTiming)]),
     "airg_destroy": (None, [ctypes.c_void_p]),
     "airg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "airg_last_error": (ctypes.c_char_p, []),

@@ -149,6 +149,7 @@ int airg_params_default(airg_params* p) {
   p->max_it = 500;
   p->restart = 30;
   p->keep_setup_data = 0;
+  p->locality_order = 1;
   return AIRG_OK;
 }
 
@@ -241,7 +242,10 @@ int airg_export_level(airg_handle h, int level, airg_level_arrays* o) {
     copy_out(o->state, L.state, L.coarsest ? 0 : L.n, s, "state");
     copy_csr_out(o->a_rowptr, o->a_col, o->a_val, level_matrix(c, level), s, "level matrix");
     if (!L.coarsest) {
-      copy_csr_out(o->ff_rowptr, o->ff_col, o->ff_val, &L.Aff, s, "A_ff");
+      // A_ff in setup numbering: the solve copy unless the solve order differs
+      const CSR* ff = L.Aff_nat.rowptr.get() ? &L.Aff_nat
+                      : (c->H.p.locality_order ? nullptr : &L.Aff);
+      copy_csr_out(o->ff_rowptr, o->ff_col, o->ff_val, ff, s, "A_ff");
       copy_csr_out(o->fc_rowptr, o->fc_col, o->fc_val, &L.Afc_nat, s, "A_fc");
       copy_csr_out(o->z_rowptr, o->z_col, o->z_val, &L.Z_nat, s, "Z");
       copy_out(o->cmap, L.cmap_nat, L.nF, s, "cmap");
@@ -275,6 +279,14 @@ int airg_import_hierarchy(airg_handle* out, int nlevels, const airg_level_info* 
     AIRG_HIP(hipStreamSynchronize(c->H.s));
     *out = c.release();
     return (int)AIRG_OK;
+  });
+}
+
+int airg_time_kernels(airg_handle h, int cls, int reps, airg_kernel_timing* out) {
+  return guard([&]() {
+    airg_ctx* c = handle_of(h);
+    if (!out) fail(AIRG_ERR_INVALID, "null output");
+    return time_kernels(c->H, c->W, cls, reps, out);
   });
 }
 

@@ -95,6 +95,25 @@ struct CSR {
   }
 };
 
+// Matrix value storage of a solve-phase operator.
+enum ValType { VT_F64 = 0, VT_F32 = 1, VT_BF16 = 2 };
+struct bf16 {
+  uint16_t bits;
+};
+
+// Operator view for the solve kernels: structure plus values of type vt.
+struct OpView {
+  const int32_t* rowptr;
+  const int32_t* col;
+  const void* val;
+  ValType vt;
+  int64_t rows;
+  int64_t nnz;
+};
+inline OpView opview(const CSR& A) {
+  return {A.rowptr.get(), A.col.get(), A.val.get(), VT_F64, A.rows, A.nnz};
+}
+
 // Read-only view passed to kernels.
 struct CSRView {
   const int32_t* rowptr;

@@ -295,13 +295,32 @@ void validate_csr(const CSR& A, DBuf<double>& diag, hipStream_t s, bool top) {
   if (f & 4) fail(AIRG_ERR_ZERO_DIAG, std::string(where) + ": zero or missing diagonal");
 }
 
-void newton_apply_dev(const CSR& A, int tpr, const std::vector<cplx>& roots, const double* r,
-                      double* x, double* w0, double* w1, double* t, hipStream_t s) {
+OpView op_view(const CSR& A, const DBuf<float>& v32, const DBuf<bf16>& v16, int prec) {
+  OpView v = opview(A);
+  if (prec == AIRG_FP32) {
+    v.val = v32.get();
+    v.vt = VT_F32;
+  } else if (prec == AIRG_BF16) {
+    v.val = v16.get();
+    v.vt = VT_BF16;
+  }
+  return v;
+}
+
+template <class X>
+void newton_apply_t(const OpView& A, int tpr, const std::vector<cplx>& roots, const X* r, X* x,
+                    X* w0, X* w1, X* t, hipStream_t s, LaunchTally* tally) {
   const int64_t n = A.rows;
+  const double xb = (double)sizeof(X);
+  const double vb = A.vt == VT_F64 ? 8.0 : A.vt == VT_F32 ? 4.0 : 2.0;
+  const double mb = csr_bytes(n, A.nnz, vb), mf = 2.0 * (double)A.nnz;
+  auto count = [&](double vecs, double vec_flops) {
+    if (tally) tally->add(mb + xb * n * vecs, mf + vec_flops);
+  };
   const int m = (int)roots.size();
   if (m == 0) fail(AIRG_ERR_INTERNAL, "no coarse roots");
-  const double* w = r;
-  double* bufs[2] = {w0, w1};
+  const X* w = r;
+  X* bufs[2] = {w0, w1};
   int nb = 0;
   bool first = true;
   int i = 0;
@@ -310,7 +329,8 @@ void newton_apply_dev(const CSR& A, int tpr, const std::vector<cplx>& roots, con
     if (z.imag() == 0.0) {
       const double inv = 1.0 / z.real();
       if (i == m - 1) {  // last root: no product with A
-        axpy_first(x, w, inv, first, n, s);
+        axpy_first_t<X>(x, w, inv, first, n, s);
+        if (tally) tally->add(xb * n * (first ? 2 : 3), 2.0 * n);
         return;
       }
       double inv_last = 0.0;
@@ -319,8 +339,10 @@ void newton_apply_dev(const CSR& A, int tpr, const std::vector<cplx>& roots, con
         inv_last = 1.0 / roots[i + 1].real();
         skip = 1;
       }
-      double* wn = bufs[nb];
-      newton_real(A, tpr, w, wn, x, inv, first, inv_last, s);
+      X* wn = bufs[nb];
+      newton_real_t<X>(A, tpr, w, wn, x, inv, first, inv_last, s);
+      // w gathered, wn written, x written (and read unless first)
+      count(first ? 3 : 4, (inv_last != 0.0 ? 6.0 : 4.0) * n);
       first = false;
       w = wn;
       nb ^= 1;
@@ -329,7 +351,9 @@ void newton_apply_dev(const CSR& A, int tpr, const std::vector<cplx>& roots, con
       const double a = z.real(), b = z.imag();
       const double mod2 = a * a + b * b;
       const double c1 = 2.0 * a / mod2, c2 = 1.0 / mod2;
-      newton_pair1(A, tpr, w, t, x, c1, c2, first, s);
+      newton_pair1_t<X>(A, tpr, w, t, x, c1, c2, first, s);
+      // w gathered, t written, x written (and read unless first)
+      count(first ? 3 : 4, 4.0 * n);
       first = false;
       if (i + 1 == m - 1) return;  // last pair
       double inv_last = 0.0;
@@ -338,14 +362,20 @@ void newton_apply_dev(const CSR& A, int tpr, const std::vector<cplx>& roots, con
         inv_last = 1.0 / roots[i + 2].real();
         skip = 1;
       }
-      double* wn = bufs[nb];
-      newton_pair2(A, tpr, w, t, wn, x, c1, c2, inv_last, s);
+      X* wn = bufs[nb];
+      newton_pair2_t<X>(A, tpr, w, t, wn, x, c1, c2, inv_last, s);
+      // t gathered, w read, wn written (x read and written when fused)
+      count(inv_last != 0.0 ? 5 : 3, (inv_last != 0.0 ? 6.0 : 4.0) * n);
       w = wn;
       nb ^= 1;
       i += 2 + skip;
     }
   }
 }
+template void newton_apply_t<double>(const OpView&, int, const std::vector<cplx>&, const double*,
+                                     double*, double*, double*, double*, hipStream_t, LaunchTally*);
+template void newton_apply_t<float>(const OpView&, int, const std::vector<cplx>&, const float*,
+                                    float*, float*, float*, float*, hipStream_t, LaunchTally*);
 
 void build_hierarchy(Hierarchy& H, CSR&& Ain) {
   const double t0 = now_ms();
@@ -406,6 +436,25 @@ void build_hierarchy(Hierarchy& H, CSR&& Ain) {
 void finalize_hierarchy(Hierarchy& H) {
   hipStream_t s = H.s;
   const int nl = (int)H.levels.size();
+  const bool order = H.p.locality_order != 0;
+  // locality keys, top down: breadth-first distance on A_0 + A_0^T from a far
+  // node, inherited by the coarse points
+  std::vector<DBuf<int32_t>> key(nl);
+  if (order && nl > 1) {
+    key[0].alloc(H.n0, s);
+    CSR At;
+    transpose(H.A0, At, s);
+    bfs_levels(H.A0, At, 0, key[0].get(), s);
+    const int64_t src = far_node(key[0].get(), H.n0, s);
+    bfs_levels(H.A0, At, src, key[0].get(), s);
+    for (int l = 0; l + 1 < nl; ++l) {
+      Level& L = H.levels[l];
+      DBuf<int64_t> clist(L.nC, s);
+      launch_inverse_map(L.state.get(), L.n, 2, L.cidx.get(), clist.get(), s);
+      key[l + 1].alloc(L.nC, s);
+      inherit_keys(key[l].get(), clist.get(), L.nC, key[l + 1].get(), s);
+    }
+  }
   Level& Lc = H.levels.back();
   Lc.pos.alloc(Lc.n, s);
   launch_iota(Lc.pos.get(), Lc.n, s);
@@ -413,12 +462,26 @@ void finalize_hierarchy(Hierarchy& H) {
     Level& L = H.levels[l];
     Level& N = H.levels[l + 1];
     L.pos.alloc(L.n, s);
-    launch_nested_pos(L.state.get(), L.fidx.get(), L.cidx.get(), L.nF, N.pos.get(), L.n,
-                      L.pos.get(), s);
-    permute_rows(L.Afc_nat, nullptr, N.pos.get(), L.nC, L.Afc, s);
-    permute_rows(L.Z_nat, N.pos.get(), nullptr, L.nF, L.Z, s);
     L.cmap.alloc(L.nF, s);
-    launch_remap(L.cmap_nat.get(), N.pos.get(), L.nF, L.cmap.get(), s);
+    if (order) {
+      DBuf<int32_t> frank(L.nF, s);
+      rank_f_points(L.state.get(), L.fidx.get(), key[l].get(), L.n, L.nF, frank.get(), s);
+      launch_nested_pos_ranked(L.state.get(), L.fidx.get(), L.cidx.get(), frank.get(), L.nF,
+                               N.pos.get(), L.n, L.pos.get(), s);
+      CSR Aff;
+      permute_rows(L.Aff, frank.get(), frank.get(), L.nF, Aff, s);
+      if (H.p.keep_setup_data) L.Aff_nat = std::move(L.Aff);
+      L.Aff = std::move(Aff);
+      permute_rows(L.Afc_nat, frank.get(), N.pos.get(), L.nC, L.Afc, s);
+      permute_rows(L.Z_nat, N.pos.get(), frank.get(), L.nF, L.Z, s);
+      launch_remap_ranked(L.cmap_nat.get(), N.pos.get(), frank.get(), L.nF, L.cmap.get(), s);
+    } else {
+      launch_nested_pos(L.state.get(), L.fidx.get(), L.cidx.get(), L.nF, N.pos.get(), L.n,
+                        L.pos.get(), s);
+      permute_rows(L.Afc_nat, nullptr, N.pos.get(), L.nC, L.Afc, s);
+      permute_rows(L.Z_nat, N.pos.get(), nullptr, L.nF, L.Z, s);
+      launch_remap(L.cmap_nat.get(), N.pos.get(), L.nF, L.cmap.get(), s);
+    }
     L.tpr_ff = pick_tpr(L.Aff.rows, L.Aff.nnz);
     L.tpr_fc = pick_tpr(L.Afc.rows, L.Afc.nnz + L.Aff.nnz);
     L.tpr_z = pick_tpr(L.Z.rows, L.Z.nnz);
@@ -430,6 +493,28 @@ void finalize_hierarchy(Hierarchy& H) {
   }
   permute_rows(H.A0, H.levels[0].pos.get(), H.levels[0].pos.get(), H.n0, H.Aperm, s);
   H.tpr_top = pick_tpr(H.Aperm.rows, H.Aperm.nnz);
+  // value copies in the storage precision of the mixed-precision V-cycle
+  if (H.p.precision != AIRG_FP64) {
+    const bool bf = H.p.precision == AIRG_BF16;
+    auto lower = [&](const CSR& A, DBuf<float>& v32, DBuf<bf16>& v16) {
+      if (bf) {
+        v16.alloc(A.nnz, s);
+        convert_d2bf(v16.get(), A.val.get(), A.nnz, s);
+      } else {
+        v32.alloc(A.nnz, s);
+        convert_d2f(v32.get(), A.val.get(), A.nnz, s);
+      }
+    };
+    for (Level& L : H.levels) {
+      if (L.coarsest) {
+        lower(L.A, L.a32, L.a16);
+        continue;
+      }
+      lower(L.Aff, L.ff32, L.ff16);
+      lower(L.Afc, L.fc32, L.fc16);
+      lower(L.Z, L.z32, L.z16);
+    }
+  }
   // every solve-phase operator is checked once, so an inconsistent hierarchy
   // (for example a bad import) fails here instead of in a kernel
   {

@@ -31,6 +31,7 @@ struct Level {
   DBuf<int8_t> state;       // 1 = F, 2 = C
   DBuf<int64_t> fidx, cidx; // exclusive scans of the F / C flags
   CSR Afc_nat, Z_nat;
+  CSR Aff_nat;              // A_ff in setup numbering when the solve order differs
   DBuf<int32_t> cmap_nat;
 
   // solve numbering
@@ -40,6 +41,10 @@ struct Level {
   std::vector<double> alpha;
   std::vector<cplx> roots;
   int tpr_ff = 1, tpr_fc = 1, tpr_z = 1, tpr_a = 1;
+
+  // low-precision copies of the solve operators' values (FP32 or BF16 storage)
+  DBuf<float> ff32, fc32, z32, a32;
+  DBuf<bf16> ff16, fc16, z16, a16;
 
   // statistics
   int64_t nnz_a = 0;
@@ -72,10 +77,38 @@ void upload_csr(CSR& out, int64_t rows, int64_t cols, int64_t nnz, const int32_t
 // Statistics.
 void hierarchy_stats(const Hierarchy& H, airg_stats* st);
 
+// Launch count and algorithmic traffic of a sequence of kernel launches: each
+// matrix entry (12 bytes with its column), row pointer and vector element read
+// or written once; flops count 2 per matrix entry plus the vector updates.
+struct LaunchTally {
+  int launches = 0;
+  double bytes = 0.0, flops = 0.0;
+  void add(double b, double f) {
+    ++launches;
+    bytes += b;
+    flops += f;
+  }
+};
+inline double csr_bytes(int64_t rows, int64_t nnz, double vbytes = 8.0) {
+  return (4.0 + vbytes) * nnz + 4.0 * (rows + 1);
+}
+
+// Operator view of A in the storage precision prec (airg_precision): FP64
+// values, or the FP32 / BF16 copy.
+OpView op_view(const CSR& A, const DBuf<float>& v32, const DBuf<bf16>& v16, int prec);
+// Bytes of one stored matrix value in precision prec.
+inline double value_bytes(int prec) { return prec == AIRG_FP64 ? 8.0 : prec == AIRG_FP32 ? 4.0 : 2.0; }
+
 // Coarse solver: x = q(A) r with the Newton roots (r, x device vectors of
-// length A.rows; w0, w1, t scratch of the same length).
-void newton_apply_dev(const CSR& A, int tpr, const std::vector<cplx>& roots, const double* r,
-                      double* x, double* w0, double* w1, double* t, hipStream_t s);
+// length A.rows; w0, w1, t scratch of the same length).  X is the vector type.
+template <class X>
+void newton_apply_t(const OpView& A, int tpr, const std::vector<cplx>& roots, const X* r, X* x,
+                    X* w0, X* w1, X* t, hipStream_t s, LaunchTally* tally = nullptr);
+inline void newton_apply_dev(const CSR& A, int tpr, const std::vector<cplx>& roots, const double* r,
+                             double* x, double* w0, double* w1, double* t, hipStream_t s,
+                             LaunchTally* tally = nullptr) {
+  newton_apply_t<double>(opview(A), tpr, roots, r, x, w0, w1, t, s, tally);
+}
 
 // Validates a device CSR and returns its diagonal; throws on error.
 void validate_csr(const CSR& A, DBuf<double>& diag, hipStream_t s, bool top);

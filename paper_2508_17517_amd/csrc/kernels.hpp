@@ -56,25 +56,41 @@ int pick_tpr(int64_t rows, int64_t nnz);
 void spmv_seq(const CSR& A, const double* x, double* y, hipStream_t s);
 // y = A x with `tpr` lanes per row.
 void spmv(const CSR& A, int tpr, const double* x, double* y, hipStream_t s);
+
+// Solve-phase kernels, generic over the matrix storage (OpView::vt) and the
+// vector type X (double or float; rows accumulate in X).
+template <class X>
+void spmv_t(const OpView& A, int tpr, const X* x, X* y, hipStream_t s);
 // Horner step of the smoother: out = (acc ? out : 0) + a (A y) + b s
-void spmv_horner(const CSR& A, int tpr, const double* y, const double* sv, double* out, double a,
-                 double b, bool acc, hipStream_t st);
+template <class X>
+void spmv_horner_t(const OpView& A, int tpr, const X* y, const X* sv, X* out, double a, double b,
+                   bool acc, hipStream_t st);
 // Restriction: dst[p] = src[p] + (Z r_f)[p]   (src may alias dst)
-void spmv_restrict(const CSR& Z, int tpr, const double* rf, const double* src, double* dst,
-                   hipStream_t s);
+template <class X>
+void spmv_restrict_t(const OpView& Z, int tpr, const X* rf, const X* src, X* dst, hipStream_t s);
 // F-point residual with fused one-point prolongation:
 //   ef[i] = W e_c, s[i] = r_f[i] - (A_fc e_c)[i] - (A_ff W e_c)[i]
-void residual_fpoint(const CSR& Aff, const CSR& Afc, const int32_t* cmap, int tpr,
-                     const double* rf, const double* ec, double* ef, double* sv, hipStream_t s);
-// Newton steps of the coarse solver (see solve.cpp).
-void newton_real(const CSR& A, int tpr, const double* w, double* wn, double* x, double inv,
-                 bool first, double inv_last, hipStream_t s);
-void newton_pair1(const CSR& A, int tpr, const double* w, double* t, double* x, double c1,
-                  double c2, bool first, hipStream_t s);
-void newton_pair2(const CSR& A, int tpr, const double* w, const double* t, double* wn, double* x,
-                  double c1, double c2, double inv_last, hipStream_t s);
+template <class X>
+void residual_fpoint_t(const OpView& Aff, const OpView& Afc, const int32_t* cmap, int tpr,
+                       const X* rf, const X* ec, X* ef, X* sv, hipStream_t s);
+// Newton steps of the coarse solver (see newton_apply_dev).
+template <class X>
+void newton_real_t(const OpView& A, int tpr, const X* w, X* wn, X* x, double inv, bool first,
+                   double inv_last, hipStream_t s);
+template <class X>
+void newton_pair1_t(const OpView& A, int tpr, const X* w, X* t, X* x, double c1, double c2,
+                    bool first, hipStream_t s);
+template <class X>
+void newton_pair2_t(const OpView& A, int tpr, const X* w, const X* t, X* wn, X* x, double c1,
+                    double c2, double inv_last, hipStream_t s);
 // x = (first ? 0 : x) + a w
-void axpy_first(double* x, const double* w, double a, bool first, int64_t n, hipStream_t s);
+template <class X>
+void axpy_first_t(X* x, const X* w, double a, bool first, int64_t n, hipStream_t s);
+
+// Precision conversions (BF16: round to nearest even of the FP32 value).
+void convert_d2f(float* y, const double* x, int64_t n, hipStream_t s);
+void convert_f2d(double* y, const float* x, int64_t n, hipStream_t s);
+void convert_d2bf(bf16* y, const double* x, int64_t n, hipStream_t s);
 
 // ---------------------------------------------------------------- cf.hip
 // Validates CSR structure (monotone rowptr, strictly ascending in-range
@@ -129,6 +145,25 @@ void launch_iota(int32_t* x, int64_t n, hipStream_t s);
 // One-point prolongation: cmap[f] = coarse index of the strongest C column.
 void launch_one_point(const CSR& A, const int8_t* state, const int64_t* fidx,
                       const int64_t* cidx, int32_t* cmap, hipStream_t s);
+
+// ---------------------------------------------------------------- order.hip
+// Breadth-first levels of the graph of A + A^T from src (level[i] >= 0 for
+// every i; unreached components restart at the next level).
+void bfs_levels(const CSR& A, const CSR& At, int64_t src, int32_t* level, hipStream_t s);
+// The node of largest level (ties: smallest index).
+int64_t far_node(const int32_t* level, int64_t n, hipStream_t s);
+// rank[f] = position of F point f ordered by (key, F index).
+void rank_f_points(const int8_t* state, const int64_t* fidx, const int32_t* key, int64_t n,
+                   int64_t nf, int32_t* rank, hipStream_t s);
+// out[c] = key[clist[c]]
+void inherit_keys(const int32_t* key, const int64_t* clist, int64_t nc, int32_t* out, hipStream_t s);
+// pos[i] = frank[fidx[i]] for F points, nF + pos_next[cidx[i]] for C points.
+void launch_nested_pos_ranked(const int8_t* state, const int64_t* fidx, const int64_t* cidx,
+                              const int32_t* frank, int64_t nF, const int32_t* pos_next, int64_t n,
+                              int32_t* pos, hipStream_t s);
+// out[frank[f]] = pos_next[cmap[f]] (or -1)
+void launch_remap_ranked(const int32_t* cmap, const int32_t* pos_next, const int32_t* frank,
+                         int64_t nf, int32_t* out, hipStream_t s);
 
 // ---------------------------------------------------------------- spgemm.hip
 // C = A B with c_ij accumulated over k ascending from 0.0, exact zeros dropped.

@@ -1,0 +1,197 @@
+// Locality order of the solve numbering.
+//
+// The hierarchy is built in the input's numbering (which may be a random
+// permutation).  For the solve only the block structure [F_l | C_l] of the
+// nested numbering matters, so the F points of every level may be placed in
+// any order; placing them by breadth-first distance on the graph of A + A^T
+// (ties by index) turns the gathers of every SpMV into accesses within a few
+// BFS bands, which stay in cache.  Coarse points inherit the distance of the
+// fine point they are.
+#include "kernels.hpp"
+
+namespace airg {
+
+__global__ void bfs_step_kernel(CSRView A, CSRView At, int32_t* level, int32_t d,
+                                int32_t* changed) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.rows || level[i] != d) return;
+  bool ch = false;
+  for (int p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) {
+    int j = A.col[p];
+    if (level[j] < 0) {
+      level[j] = d + 1;  // every writer stores the same value
+      ch = true;
+    }
+  }
+  for (int p = At.rowptr[i]; p < At.rowptr[i + 1]; ++p) {
+    int j = At.col[p];
+    if (level[j] < 0) {
+      level[j] = d + 1;
+      ch = true;
+    }
+  }
+  if (ch) *changed = 1;
+}
+
+// Largest level, ties to the smallest index, packed as level << 32 | ~index.
+__global__ void far_node_kernel(const int32_t* level, int64_t n, unsigned long long* best) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t l = level[i];
+  if (l < 0) return;
+  unsigned long long k = ((unsigned long long)(uint32_t)l << 32) | (0xffffffffull - (uint64_t)i);
+  atomicMax(best, k);
+}
+
+// Smallest index not reached yet.
+__global__ void first_unvisited_kernel(const int32_t* level, int64_t n, unsigned long long* first) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && level[i] < 0) atomicMin(first, (unsigned long long)i);
+}
+
+__global__ void set_level_kernel(int32_t* level, int64_t i, int32_t v) { level[i] = v; }
+
+// Breadth-first levels of the graph of A + A^T from src; unreached
+// components restart from their smallest index at the next level.
+void bfs_levels(const CSR& A, const CSR& At, int64_t src, int32_t* level, hipStream_t s) {
+  const int64_t n = A.rows;
+  launch_fill_i32(level, n, -1, s);
+  DBuf<int32_t> changed(1, s);
+  DBuf<unsigned long long> red(1, s);
+  const unsigned nb = blocks_for(n, kBlock);
+  int32_t d = 0;
+  set_level_kernel<<<1, 1, 0, s>>>(level, src, 0);
+  AIRG_CHECK_LAUNCH();
+  for (;;) {
+    // a batch of steps between host checks; steps past the end do nothing
+    launch_fill_i32(changed.get(), 1, 0, s);
+    const int batch = 32;
+    for (int k = 0; k < batch; ++k, ++d) {
+      bfs_step_kernel<<<nb, kBlock, 0, s>>>(view(A), view(At), level, d, changed.get());
+      AIRG_CHECK_LAUNCH();
+    }
+    if (fetch(changed.get(), s)) continue;
+    // no growth in the whole batch: every component reached so far is done
+    unsigned long long first = ~0ull;
+    red.from_host(&first, 1);
+    first_unvisited_kernel<<<nb, kBlock, 0, s>>>(level, n, red.get());
+    AIRG_CHECK_LAUNCH();
+    first = fetch(red.get(), s);
+    if (first == ~0ull) break;
+    unsigned long long zero = 0;
+    red.from_host(&zero, 1);
+    far_node_kernel<<<nb, kBlock, 0, s>>>(level, n, red.get());
+    AIRG_CHECK_LAUNCH();
+    int32_t dmax = (int32_t)(fetch(red.get(), s) >> 32);
+    d = dmax + 1;
+    set_level_kernel<<<1, 1, 0, s>>>(level, (int64_t)first, d);
+    AIRG_CHECK_LAUNCH();
+  }
+}
+
+int64_t far_node(const int32_t* level, int64_t n, hipStream_t s) {
+  DBuf<unsigned long long> red(1, s);
+  unsigned long long zero = 0;
+  red.from_host(&zero, 1);
+  far_node_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(level, n, red.get());
+  AIRG_CHECK_LAUNCH();
+  unsigned long long k = fetch(red.get(), s);
+  return (int64_t)(0xffffffffull - (k & 0xffffffffull));
+}
+
+// ------------------------------------------------------------------ ranking
+__global__ void make_keys_kernel(const int8_t* state, const int64_t* fidx, const int32_t* key,
+                                 int64_t n, uint64_t* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && state[i] == 1)
+    out[fidx[i]] = ((uint64_t)(uint32_t)key[i] << 32) | (uint64_t)fidx[i];
+}
+__global__ void pad_keys_kernel(uint64_t* k, int64_t from, int64_t to) {
+  int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < to) k[i] = ~0ull;
+}
+__global__ void bitonic_step_kernel(uint64_t* keys, int64_t P, int64_t j, int64_t k) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  int64_t l = i ^ j;
+  if (l <= i) return;
+  const bool asc = (i & k) == 0;
+  uint64_t a = keys[i], b = keys[l];
+  if ((a > b) == asc) {
+    keys[i] = b;
+    keys[l] = a;
+  }
+}
+__global__ void rank_kernel(const uint64_t* sorted, int64_t nf, int32_t* rank) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nf) rank[sorted[r] & 0xffffffffull] = (int32_t)r;
+}
+
+// rank[f] = position of F point f when the F points are ordered by
+// (key, F index); keys are unique, so any correct sort gives the same ranks.
+void rank_f_points(const int8_t* state, const int64_t* fidx, const int32_t* key, int64_t n,
+                   int64_t nf, int32_t* rank, hipStream_t s) {
+  if (nf <= 0) return;
+  int64_t P = 1;
+  while (P < nf) P <<= 1;
+  DBuf<uint64_t> keys(P, s);
+  make_keys_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(state, fidx, key, n, keys.get());
+  AIRG_CHECK_LAUNCH();
+  if (P > nf) {
+    pad_keys_kernel<<<blocks_for(P - nf, kBlock), kBlock, 0, s>>>(keys.get(), nf, P);
+    AIRG_CHECK_LAUNCH();
+  }
+  const unsigned nb = blocks_for(P, kBlock);
+  for (int64_t k = 2; k <= P; k <<= 1)
+    for (int64_t j = k >> 1; j > 0; j >>= 1) {
+      bitonic_step_kernel<<<nb, kBlock, 0, s>>>(keys.get(), P, j, k);
+      AIRG_CHECK_LAUNCH();
+    }
+  rank_kernel<<<blocks_for(nf, kBlock), kBlock, 0, s>>>(keys.get(), nf, rank);
+  AIRG_CHECK_LAUNCH();
+}
+
+// key_next[c] = key[clist[c]]
+__global__ void inherit_key_kernel(const int32_t* key, const int64_t* clist, int64_t nc,
+                                   int32_t* out) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < nc) out[c] = key[clist[c]];
+}
+void inherit_keys(const int32_t* key, const int64_t* clist, int64_t nc, int32_t* out,
+                  hipStream_t s) {
+  if (nc <= 0) return;
+  inherit_key_kernel<<<blocks_for(nc, kBlock), kBlock, 0, s>>>(key, clist, nc, out);
+  AIRG_CHECK_LAUNCH();
+}
+
+// Nested positions with ordered F points, and the permuted prolongation map.
+__global__ void nested_pos_ranked_kernel(const int8_t* state, const int64_t* fidx,
+                                         const int64_t* cidx, const int32_t* frank, int64_t nF,
+                                         const int32_t* pos_next, int64_t n, int32_t* pos) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  pos[i] = state[i] == 1 ? frank[fidx[i]] : (int32_t)(nF + pos_next[cidx[i]]);
+}
+void launch_nested_pos_ranked(const int8_t* state, const int64_t* fidx, const int64_t* cidx,
+                              const int32_t* frank, int64_t nF, const int32_t* pos_next, int64_t n,
+                              int32_t* pos, hipStream_t s) {
+  if (n <= 0) return;
+  nested_pos_ranked_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(state, fidx, cidx, frank, nF,
+                                                                    pos_next, n, pos);
+  AIRG_CHECK_LAUNCH();
+}
+__global__ void remap_ranked_kernel(const int32_t* cmap, const int32_t* pos_next,
+                                    const int32_t* frank, int64_t nf, int32_t* out) {
+  int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  int32_t c = cmap[f];
+  out[frank[f]] = c >= 0 ? pos_next[c] : -1;
+}
+void launch_remap_ranked(const int32_t* cmap, const int32_t* pos_next, const int32_t* frank,
+                         int64_t nf, int32_t* out, hipStream_t s) {
+  if (nf <= 0) return;
+  remap_ranked_kernel<<<blocks_for(nf, kBlock), kBlock, 0, s>>>(cmap, pos_next, frank, nf, out);
+  AIRG_CHECK_LAUNCH();
+}
+
+}  // namespace airg

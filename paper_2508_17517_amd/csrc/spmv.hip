@@ -3,22 +3,39 @@
 // then combine with a shuffle tree inside the group.  The row result goes to a
 // fused epilogue (Horner step, restriction, Newton step, ...), so every
 // smoother and coarse-solver step is one pass over its matrix.  With TPR = 1 a
-// row is summed left to right from 0.0, the order the setup relies on.
+// row is summed left to right from 0, the order the setup relies on.
+//
+// The kernels are generic over the matrix value storage (FP64, FP32 or BF16)
+// and the vector type (FP64 or FP32); a row is accumulated in the vector type,
+// so the mixed-precision V-cycle stores matrices in FP32 or BF16 and
+// accumulates in FP32.
 #include "kernels.hpp"
 
 namespace airg {
 
-struct GatherX {
-  const double* __restrict__ x;
-  __device__ __forceinline__ double operator()(int j) const { return x[j]; }
+__device__ __forceinline__ double ldv(double v) { return v; }
+__device__ __forceinline__ float ldv(float v) { return v; }
+__device__ __forceinline__ float ldv(bf16 v) { return __uint_as_float((uint32_t)v.bits << 16); }
+
+template <class MV>
+struct CSRT {
+  const int32_t* __restrict__ rowptr;
+  const int32_t* __restrict__ col;
+  const MV* __restrict__ val;
+  int64_t rows;
 };
 
-template <int TPR, class Gather>
-__device__ __forceinline__ double row_dot(const CSRView& A, int64_t row, int lane, const Gather& g) {
-  double sum = 0.0;
+template <class MV>
+static CSRT<MV> csr_t(const OpView& A) {
+  return {A.rowptr, A.col, (const MV*)A.val, A.rows};
+}
+
+template <int TPR, class MV, class X>
+__device__ __forceinline__ X row_dot(const CSRT<MV>& A, int64_t row, int lane, const X* __restrict__ x) {
+  X sum = 0;
   if (row < A.rows) {
     const int s = A.rowptr[row], e = A.rowptr[row + 1];
-    for (int p = s + lane; p < e; p += TPR) sum = sum + A.val[p] * g(A.col[p]);
+    for (int p = s + lane; p < e; p += TPR) sum = sum + (X)ldv(A.val[p]) * x[A.col[p]];
   }
   if constexpr (TPR > 1) {
 #pragma unroll
@@ -27,31 +44,41 @@ __device__ __forceinline__ double row_dot(const CSRView& A, int64_t row, int lan
   return sum;
 }
 
-template <int TPR, class Epi>
-__global__ __launch_bounds__(256) void spmv_kernel(CSRView A, GatherX g, Epi epi) {
+template <int TPR, class MV, class X, class Epi>
+__global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV> A, const X* __restrict__ x, Epi epi) {
   const int lane = threadIdx.x & (TPR - 1);
   const int64_t row = (int64_t)blockIdx.x * (256 / TPR) + threadIdx.x / TPR;
-  double sum = row_dot<TPR>(A, row, lane, g);
+  X sum = row_dot<TPR>(A, row, lane, x);
   if (lane == 0 && row < A.rows) epi(row, sum);
 }
 
-template <class Epi>
-static void launch_spmv(const CSR& A, int tpr, const double* x, Epi epi, hipStream_t s) {
-  if (A.rows <= 0) return;
-  CSRView v = view(A);
-  GatherX g{x};
-  unsigned nb = blocks_for(A.rows, 256 / tpr);
+template <class MV, class X, class Epi>
+static void launch_spmv_t(const OpView& Av, int tpr, const X* x, Epi epi, hipStream_t s) {
+  if (Av.rows <= 0) return;
+  CSRT<MV> A = csr_t<MV>(Av);
+  unsigned nb = blocks_for(Av.rows, 256 / tpr);
   switch (tpr) {
-    case 1: spmv_kernel<1, Epi><<<nb, 256, 0, s>>>(v, g, epi); break;
-    case 2: spmv_kernel<2, Epi><<<nb, 256, 0, s>>>(v, g, epi); break;
-    case 4: spmv_kernel<4, Epi><<<nb, 256, 0, s>>>(v, g, epi); break;
-    case 8: spmv_kernel<8, Epi><<<nb, 256, 0, s>>>(v, g, epi); break;
-    case 16: spmv_kernel<16, Epi><<<nb, 256, 0, s>>>(v, g, epi); break;
-    case 32: spmv_kernel<32, Epi><<<nb, 256, 0, s>>>(v, g, epi); break;
-    case 64: spmv_kernel<64, Epi><<<nb, 256, 0, s>>>(v, g, epi); break;
+    case 1: spmv_kernel<1, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+    case 2: spmv_kernel<2, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+    case 4: spmv_kernel<4, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+    case 8: spmv_kernel<8, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+    case 16: spmv_kernel<16, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+    case 32: spmv_kernel<32, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+    case 64: spmv_kernel<64, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
     default: fail(AIRG_ERR_INTERNAL, "bad lanes-per-row");
   }
   AIRG_CHECK_LAUNCH();
+}
+
+// dispatch on the matrix storage type
+template <class X, class Epi>
+static void launch_spmv(const OpView& A, int tpr, const X* x, Epi epi, hipStream_t s) {
+  switch (A.vt) {
+    case VT_F64: launch_spmv_t<double>(A, tpr, x, epi, s); break;
+    case VT_F32: launch_spmv_t<float>(A, tpr, x, epi, s); break;
+    case VT_BF16: launch_spmv_t<bf16>(A, tpr, x, epi, s); break;
+    default: fail(AIRG_ERR_INTERNAL, "bad value type");
+  }
 }
 
 int pick_tpr(int64_t rows, int64_t nnz) {
@@ -65,121 +92,130 @@ int pick_tpr(int64_t rows, int64_t nnz) {
 }
 
 // ------------------------------------------------------------------ epilogues
+template <class X>
 struct EpiStore {
-  double* y;
-  __device__ void operator()(int64_t i, double t) const { y[i] = t; }
+  X* y;
+  __device__ void operator()(int64_t i, X t) const { y[i] = t; }
 };
+template <class X>
 struct EpiHorner {
-  double* out;
-  const double* sv;
-  double a, b;
+  X* out;
+  const X* sv;
+  X a, b;
   int acc;
-  __device__ void operator()(int64_t i, double t) const {
-    double v = a * t + b * sv[i];
+  __device__ void operator()(int64_t i, X t) const {
+    X v = a * t + b * sv[i];
     out[i] = acc ? out[i] + v : v;
   }
 };
+template <class X>
 struct EpiRestrict {
-  const double* src;
-  double* dst;
-  __device__ void operator()(int64_t i, double t) const { dst[i] = src[i] + t; }
+  const X* src;
+  X* dst;
+  __device__ void operator()(int64_t i, X t) const { dst[i] = src[i] + t; }
 };
+template <class X>
 struct EpiNewtonReal {
-  const double* w;
-  double* wn;
-  double* x;
-  double inv, inv_last;
+  const X* w;
+  X* wn;
+  X* x;
+  X inv, inv_last;
   int first;
-  __device__ void operator()(int64_t i, double t) const {
-    double wi = w[i];
-    double xi = (first ? 0.0 : x[i]) + wi * inv;
-    double wni = wi - t * inv;
+  __device__ void operator()(int64_t i, X t) const {
+    X wi = w[i];
+    X xi = (first ? X(0) : x[i]) + wi * inv;
+    X wni = wi - t * inv;
     wn[i] = wni;
-    if (inv_last != 0.0) xi = xi + wni * inv_last;
+    if (inv_last != X(0)) xi = xi + wni * inv_last;
     x[i] = xi;
   }
 };
+template <class X>
 struct EpiNewtonPair1 {
-  const double* w;
-  double* tv;
-  double* x;
-  double c1, c2;
+  const X* w;
+  X* tv;
+  X* x;
+  X c1, c2;
   int first;
-  __device__ void operator()(int64_t i, double t) const {
+  __device__ void operator()(int64_t i, X t) const {
     tv[i] = t;
-    x[i] = (first ? 0.0 : x[i]) + (c1 * w[i] - c2 * t);
+    x[i] = (first ? X(0) : x[i]) + (c1 * w[i] - c2 * t);
   }
 };
+template <class X>
 struct EpiNewtonPair2 {
-  const double* w;
-  const double* tv;
-  double* wn;
-  double* x;
-  double c1, c2, inv_last;
-  __device__ void operator()(int64_t i, double u) const {
-    double wni = w[i] - c1 * tv[i] + c2 * u;
+  const X* w;
+  const X* tv;
+  X* wn;
+  X* x;
+  X c1, c2, inv_last;
+  __device__ void operator()(int64_t i, X u) const {
+    X wni = w[i] - c1 * tv[i] + c2 * u;
     wn[i] = wni;
-    if (inv_last != 0.0) x[i] = x[i] + wni * inv_last;
+    if (inv_last != X(0)) x[i] = x[i] + wni * inv_last;
   }
 };
 
-void spmv_seq(const CSR& A, const double* x, double* y, hipStream_t s) {
-  launch_spmv(A, 1, x, EpiStore{y}, s);
+template <class X>
+void spmv_t(const OpView& A, int tpr, const X* x, X* y, hipStream_t s) {
+  launch_spmv(A, tpr, x, EpiStore<X>{y}, s);
 }
-void spmv(const CSR& A, int tpr, const double* x, double* y, hipStream_t s) {
-  launch_spmv(A, tpr, x, EpiStore{y}, s);
+template <class X>
+void spmv_horner_t(const OpView& A, int tpr, const X* y, const X* sv, X* out, double a, double b,
+                   bool acc, hipStream_t st) {
+  launch_spmv(A, tpr, y, EpiHorner<X>{out, sv, (X)a, (X)b, acc ? 1 : 0}, st);
 }
-void spmv_horner(const CSR& A, int tpr, const double* y, const double* sv, double* out, double a,
-                 double b, bool acc, hipStream_t st) {
-  launch_spmv(A, tpr, y, EpiHorner{out, sv, a, b, acc ? 1 : 0}, st);
+template <class X>
+void spmv_restrict_t(const OpView& Z, int tpr, const X* rf, const X* src, X* dst, hipStream_t s) {
+  launch_spmv(Z, tpr, rf, EpiRestrict<X>{src, dst}, s);
 }
-void spmv_restrict(const CSR& Z, int tpr, const double* rf, const double* src, double* dst,
-                   hipStream_t s) {
-  launch_spmv(Z, tpr, rf, EpiRestrict{src, dst}, s);
+template <class X>
+void newton_real_t(const OpView& A, int tpr, const X* w, X* wn, X* x, double inv, bool first,
+                   double inv_last, hipStream_t s) {
+  launch_spmv(A, tpr, w, EpiNewtonReal<X>{w, wn, x, (X)inv, (X)inv_last, first ? 1 : 0}, s);
 }
-void newton_real(const CSR& A, int tpr, const double* w, double* wn, double* x, double inv,
-                 bool first, double inv_last, hipStream_t s) {
-  launch_spmv(A, tpr, w, EpiNewtonReal{w, wn, x, inv, inv_last, first ? 1 : 0}, s);
+template <class X>
+void newton_pair1_t(const OpView& A, int tpr, const X* w, X* t, X* x, double c1, double c2,
+                    bool first, hipStream_t s) {
+  launch_spmv(A, tpr, w, EpiNewtonPair1<X>{w, t, x, (X)c1, (X)c2, first ? 1 : 0}, s);
 }
-void newton_pair1(const CSR& A, int tpr, const double* w, double* t, double* x, double c1,
-                  double c2, bool first, hipStream_t s) {
-  launch_spmv(A, tpr, w, EpiNewtonPair1{w, t, x, c1, c2, first ? 1 : 0}, s);
-}
-void newton_pair2(const CSR& A, int tpr, const double* w, const double* t, double* wn, double* x,
-                  double c1, double c2, double inv_last, hipStream_t s) {
-  launch_spmv(A, tpr, t, EpiNewtonPair2{w, t, wn, x, c1, c2, inv_last}, s);
+template <class X>
+void newton_pair2_t(const OpView& A, int tpr, const X* w, const X* t, X* wn, X* x, double c1,
+                    double c2, double inv_last, hipStream_t s) {
+  launch_spmv(A, tpr, t, EpiNewtonPair2<X>{w, t, wn, x, (X)c1, (X)c2, (X)inv_last}, s);
 }
 
-__global__ void axpy_first_kernel(double* x, const double* w, double a, int first, int64_t n) {
+template <class X>
+__global__ void axpy_first_kernel(X* x, const X* w, X a, int first, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] = (first ? 0.0 : x[i]) + a * w[i];
+  if (i < n) x[i] = (first ? X(0) : x[i]) + a * w[i];
 }
-void axpy_first(double* x, const double* w, double a, bool first, int64_t n, hipStream_t s) {
+template <class X>
+void axpy_first_t(X* x, const X* w, double a, bool first, int64_t n, hipStream_t s) {
   if (n <= 0) return;
-  axpy_first_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(x, w, a, first ? 1 : 0, n);
+  axpy_first_kernel<X><<<blocks_for(n, kBlock), kBlock, 0, s>>>(x, w, (X)a, first ? 1 : 0, n);
   AIRG_CHECK_LAUNCH();
 }
 
 // ------------------------------------------------------------------ F-point residual
 // s_i = r_i - sum_j Afc_ij e_c[j] - sum_j Aff_ij e_c[cmap[j]], ef_i = e_c[cmap[i]]
-template <int TPR>
-__global__ __launch_bounds__(256) void residual_kernel(CSRView Aff, CSRView Afc,
+template <int TPR, class MV, class X>
+__global__ __launch_bounds__(256) void residual_kernel(CSRT<MV> Aff, CSRT<MV> Afc,
                                                        const int32_t* __restrict__ cmap,
-                                                       const double* __restrict__ rf,
-                                                       const double* __restrict__ ec,
-                                                       double* __restrict__ ef,
-                                                       double* __restrict__ sv) {
+                                                       const X* __restrict__ rf,
+                                                       const X* __restrict__ ec,
+                                                       X* __restrict__ ef, X* __restrict__ sv) {
   const int lane = threadIdx.x & (TPR - 1);
   const int64_t row = (int64_t)blockIdx.x * (256 / TPR) + threadIdx.x / TPR;
-  double sum = 0.0;
+  X sum = 0;
   if (row < Aff.rows) {
     int s = Afc.rowptr[row], e = Afc.rowptr[row + 1];
-    for (int p = s + lane; p < e; p += TPR) sum = sum + Afc.val[p] * ec[Afc.col[p]];
+    for (int p = s + lane; p < e; p += TPR) sum = sum + (X)ldv(Afc.val[p]) * ec[Afc.col[p]];
     s = Aff.rowptr[row];
     e = Aff.rowptr[row + 1];
     for (int p = s + lane; p < e; p += TPR) {
       int c = cmap[Aff.col[p]];
-      if (c >= 0) sum = sum + Aff.val[p] * ec[c];
+      if (c >= 0) sum = sum + (X)ldv(Aff.val[p]) * ec[c];
     }
   }
   if constexpr (TPR > 1) {
@@ -188,26 +224,98 @@ __global__ __launch_bounds__(256) void residual_kernel(CSRView Aff, CSRView Afc,
   }
   if (lane == 0 && row < Aff.rows) {
     int c = cmap[row];
-    ef[row] = c >= 0 ? ec[c] : 0.0;
+    ef[row] = c >= 0 ? ec[c] : X(0);
     sv[row] = rf[row] - sum;
   }
 }
 
-void residual_fpoint(const CSR& Aff, const CSR& Afc, const int32_t* cmap, int tpr,
-                     const double* rf, const double* ec, double* ef, double* sv, hipStream_t s) {
-  if (Aff.rows <= 0) return;
-  CSRView a = view(Aff), b = view(Afc);
-  unsigned nb = blocks_for(Aff.rows, 256 / tpr);
+template <class MV, class X>
+static void residual_t(const OpView& Affv, const OpView& Afcv, const int32_t* cmap, int tpr,
+                       const X* rf, const X* ec, X* ef, X* sv, hipStream_t s) {
+  CSRT<MV> a = csr_t<MV>(Affv), b = csr_t<MV>(Afcv);
+  unsigned nb = blocks_for(Affv.rows, 256 / tpr);
   switch (tpr) {
-    case 1: residual_kernel<1><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-    case 2: residual_kernel<2><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-    case 4: residual_kernel<4><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-    case 8: residual_kernel<8><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-    case 16: residual_kernel<16><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-    case 32: residual_kernel<32><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-    case 64: residual_kernel<64><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+    case 1: residual_kernel<1, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+    case 2: residual_kernel<2, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+    case 4: residual_kernel<4, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+    case 8: residual_kernel<8, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+    case 16: residual_kernel<16, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+    case 32: residual_kernel<32, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+    case 64: residual_kernel<64, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
     default: fail(AIRG_ERR_INTERNAL, "bad lanes-per-row");
   }
+  AIRG_CHECK_LAUNCH();
+}
+
+template <class X>
+void residual_fpoint_t(const OpView& Aff, const OpView& Afc, const int32_t* cmap, int tpr,
+                       const X* rf, const X* ec, X* ef, X* sv, hipStream_t s) {
+  if (Aff.rows <= 0) return;
+  if (Aff.vt != Afc.vt) fail(AIRG_ERR_INTERNAL, "mixed value types in the residual");
+  switch (Aff.vt) {
+    case VT_F64: residual_t<double>(Aff, Afc, cmap, tpr, rf, ec, ef, sv, s); break;
+    case VT_F32: residual_t<float>(Aff, Afc, cmap, tpr, rf, ec, ef, sv, s); break;
+    case VT_BF16: residual_t<bf16>(Aff, Afc, cmap, tpr, rf, ec, ef, sv, s); break;
+    default: fail(AIRG_ERR_INTERNAL, "bad value type");
+  }
+}
+
+#define AIRG_INSTANTIATE(X)                                                                      \
+  template void spmv_t<X>(const OpView&, int, const X*, X*, hipStream_t);                        \
+  template void spmv_horner_t<X>(const OpView&, int, const X*, const X*, X*, double, double, bool, \
+                                 hipStream_t);                                                   \
+  template void spmv_restrict_t<X>(const OpView&, int, const X*, const X*, X*, hipStream_t);     \
+  template void newton_real_t<X>(const OpView&, int, const X*, X*, X*, double, bool, double,     \
+                                 hipStream_t);                                                   \
+  template void newton_pair1_t<X>(const OpView&, int, const X*, X*, X*, double, double, bool,    \
+                                  hipStream_t);                                                  \
+  template void newton_pair2_t<X>(const OpView&, int, const X*, const X*, X*, X*, double, double, \
+                                  double, hipStream_t);                                          \
+  template void axpy_first_t<X>(X*, const X*, double, bool, int64_t, hipStream_t);               \
+  template void residual_fpoint_t<X>(const OpView&, const OpView&, const int32_t*, int, const X*,  \
+                                     const X*, X*, X*, hipStream_t);
+AIRG_INSTANTIATE(double)
+AIRG_INSTANTIATE(float)
+#undef AIRG_INSTANTIATE
+
+// ------------------------------------------------------------------ FP64 wrappers
+void spmv_seq(const CSR& A, const double* x, double* y, hipStream_t s) { spmv_t(opview(A), 1, x, y, s); }
+void spmv(const CSR& A, int tpr, const double* x, double* y, hipStream_t s) {
+  spmv_t(opview(A), tpr, x, y, s);
+}
+
+// ------------------------------------------------------------------ conversions
+__global__ void d2f_kernel(float* y, const double* x, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+__global__ void f2d_kernel(double* y, const float* x, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (double)x[i];
+}
+// round to nearest even from FP32 (values are finite)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  uint32_t r = 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)((u + r) >> 16);
+}
+__global__ void d2bf_kernel(bf16* y, const double* x, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i].bits = f2bf((float)x[i]);
+}
+void convert_d2f(float* y, const double* x, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  d2f_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, n);
+  AIRG_CHECK_LAUNCH();
+}
+void convert_f2d(double* y, const float* x, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  f2d_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, n);
+  AIRG_CHECK_LAUNCH();
+}
+void convert_d2bf(bf16* y, const double* x, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  d2bf_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, n);
   AIRG_CHECK_LAUNCH();
 }
 

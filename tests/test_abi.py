@@ -35,7 +35,7 @@ def test_status_strings_and_defaults_without_gpu():
     p = binding.default_params()
     assert p.strong_threshold == 0.99 and p.ddc_its == 2 and p.poly_order == 4
     assert p.coarse_poly_order == 20 and p.trunc_tol == 1e-2 and p.rtol == 1e-10
-    assert p.seed == 17517 and p.restart == 30
+    assert p.seed == 17517 and p.restart == 30 and p.locality_order == 1
 
 
 def test_struct_sizes_match_the_header():

@@ -280,3 +280,43 @@ def test_grid_aligned_flow(theta):
     assert info["iterations"] == its
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
     s.close()
+
+
+@pytest.mark.parametrize("prec,name", [(1, "fp32"), (2, "bf16")])
+def test_mixed_precision_reaches_the_fp64_tolerance(prec, name):
+    # FP32 / BF16 storage in the V-cycle, FP64 outer FGMRES: the true FP64
+    # residual still reaches 1e-10 and the solution matches the FP64 oracle's
+    _needs_gpu()
+    p = workloads.fv_random(128, 0.3, True)
+    xo, its, rel, _, _ = oracle.solve(p.scipy(), p.b)
+    s = _solver(p, precision=prec)
+    x, info = s.solve(torch.from_numpy(p.b).cuda())
+    xg = x.cpu().numpy()
+    err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    print(f"{name}: iterations {info['iterations']} (fp64 oracle {its}), rel err vs oracle {err:.2e}")
+    assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
+    assert err <= 1e-8
+    assert info["iterations"] <= its + 6
+    s.close()
+
+
+def test_locality_order_changes_only_the_summation_order():
+    # the F points of every level are re-ordered for the solve; the hierarchy
+    # (exported in setup numbering) and the iteration count stay the same
+    _needs_gpu()
+    p = workloads.fv_random(128, 0.8, True)
+    s0 = _solver(p, locality_order=0, keep_setup_data=1)
+    s1 = _solver(p, locality_order=1, keep_setup_data=1)
+    for l in range(s0.stats()["levels"] - 1):
+        a, b = s0.export_level(l), s1.export_level(l)
+        assert np.array_equal(a["state"], b["state"])
+        for k in ("ff", "fc", "z"):
+            for u, v in zip(a[k], b[k]):
+                assert np.array_equal(u, v), (l, k)
+    bt = torch.from_numpy(p.b).cuda()
+    x0, i0 = s0.solve(bt)
+    x1, i1 = s1.solve(bt)
+    assert i0["iterations"] == i1["iterations"]
+    assert float(torch.linalg.norm(x0 - x1) / torch.linalg.norm(x0)) <= 1e-11
+    s0.close()
+    s1.close()
