@@ -152,9 +152,29 @@ int airg_setup(airg_handle* out, int64_t n, int64_t nnz, const int32_t* rowptr,
  * of x at x + k*ldx (device pointers, FP64).  x is the initial guess when
  * use_x_as_guess, else the guess is 0.  info (nrhs entries, may be NULL)
  * receives per right-hand-side results.  Returns AIRG_NOT_CONVERGED if any
- * column missed rtol within max_it. */
+ * column missed rtol within max_it.
+ * Several columns are solved together, up to 64 at a time: every V-cycle
+ * kernel then reads each matrix entry once for all columns (SpMM on
+ * interleaved columns) and one FGMRES process runs over the stacked columns,
+ * stopped only when every column has |b_k - A x_k| <= rtol |b_k|.  The
+ * Krylov bases then hold (2 restart + 1) vectors of n * 64 doubles. */
 int airg_solve(airg_handle h, int nrhs, const double* b, int64_t ldb, double* x,
                int64_t ldx, int use_x_as_guess, airg_solve_info* info);
+
+/* A batch of nprob independent systems (problem p: n[p] rows, nnz[p]
+ * entries, CSR arrays rowptr[p], colidx[p], vals[p]) set up as one
+ * block-diagonal matrix: every setup kernel and every V-cycle launch covers
+ * all problems at once.  on_device as in airg_setup. */
+int airg_setup_batch(airg_handle* out, int nprob, const int64_t* n, const int64_t* nnz,
+                     const int32_t* const* rowptr, const int32_t* const* colidx,
+                     const double* const* vals, int on_device, const airg_params* p,
+                     void* hip_stream);
+
+/* Solve every problem of a batch handle: b[p], x[p] device pointers of n[p]
+ * doubles.  One FGMRES process runs over the block-diagonal system until
+ * every problem has |b_p - A_p x_p| <= rtol |b_p|; info has nprob entries. */
+int airg_solve_batch(airg_handle h, const double* const* b, double* const* x,
+                     int use_x_as_guess, airg_solve_info* info);
 
 /* Solve A^T lam = w (adjoint) with an AIRG hierarchy built on the explicit
  * transpose, with the same parameters and seed; built on the first call and
@@ -204,6 +224,33 @@ typedef struct {
  * handle's stream, and report the average launch time and the algorithmic
  * bytes and flops per launch.  Does not change the solver's state. */
 int airg_time_kernels(airg_handle h, int cls, int reps, airg_kernel_timing* out);
+
+/* ---- differentiable advection solve -------------------------------------
+ * The upwind finite-volume system of v.grad(u) = 0 with inflow values g
+ * (paper Eqs. advection and advection_bc) on an nx x ny grid of square cells,
+ * v = (cos theta, sin theta), theta in [0, pi/2]: fluxes are divided by the
+ * cell size, inflow faces (west, south) move to the right-hand side.  Unknown
+ * k = j nx + i; row k holds -vy at k - nx (j > 0), -vx at k - 1 (i > 0) and
+ * vx + vy on the diagonal; b_k = vx g_west[j] (i = 0) + vy g_south[i] (j = 0).
+ * All pointers are device pointers. */
+
+/* Number of stored entries of the system. */
+int airg_fv_nnz(int64_t nx, int64_t ny, double theta, int64_t* nnz);
+
+/* Assemble rowptr[n+1], col[nnz], val[nnz], b[n] (n = nx ny); if not NULL,
+ * dval_dtheta[nnz] and db_dtheta[n] receive the derivatives in theta. */
+int airg_fv_assemble(int64_t nx, int64_t ny, double theta, const double* g_west,
+                     const double* g_south, int32_t* rowptr, int32_t* col, double* val,
+                     double* b, double* dval_dtheta, double* db_dtheta, void* hip_stream);
+
+/* Gradients of a loss L(u) with u = A^{-1} b, given the adjoint solution
+ * lam = A^{-T} dL/du: dg_west[ny] = vx lam at the west inflow cells,
+ * dg_south[nx] = vy lam at the south inflow cells and
+ * *dtheta = lam^T (db/dtheta - dA/dtheta u) (one device double). */
+int airg_fv_gradients(int64_t nx, int64_t ny, double theta, const int32_t* rowptr,
+                      const int32_t* col, const double* dval_dtheta, const double* db_dtheta,
+                      const double* u, const double* lam, double* dg_west, double* dg_south,
+                      double* dtheta, void* hip_stream);
 
 /* Release the handle and all its device memory (NULL is a no-op). */
 void airg_destroy(airg_handle h);

@@ -16,7 +16,7 @@ import numpy as np
 from . import binding
 from .binding import AirgError, FP64, FP32, BF16, default_params  # noqa: F401
 
-__all__ = ["Solver", "AirgError", "default_params", "FP64", "FP32", "BF16"]
+__all__ = ["Solver", "BatchSolver", "AirgError", "default_params", "FP64", "FP32", "BF16"]
 
 
 def _torch():
@@ -250,3 +250,57 @@ class Solver:
 
     def __exit__(self, *a):
         self.close()
+
+
+class BatchSolver(Solver):
+    """Many independent problems in one AIRG hierarchy (block-diagonal setup):
+    `problems` is a list of (indptr, indices, data) triples.  solve() takes a
+    list of right-hand sides, one per problem, and returns (xs, infos)."""
+
+    def __init__(self, problems, params=None, stream=None, **overrides):
+        self.lib = binding.load()
+        self.params = params if params is not None else default_params(**overrides)
+        if params is not None:
+            for k, v in overrides.items():
+                setattr(self.params, k, v)
+        self.stream = stream
+        self.h = ctypes.c_void_p()
+        torch = _torch()
+        np_ = len(problems)
+        if np_ < 1:
+            raise ValueError("empty batch")
+        mats = [(_as_device(a, torch.int32), _as_device(b, torch.int32),
+                 _as_device(c, torch.float64)) for a, b, c in problems]
+        self._sizes = [m[0].numel() - 1 for m in mats]
+        n = (ctypes.c_int64 * np_)(*self._sizes)
+        nnz = (ctypes.c_int64 * np_)(*[m[1].numel() for m in mats])
+        vp = ctypes.c_void_p * np_
+        rp = vp(*[m[0].data_ptr() for m in mats])
+        cp = vp(*[m[1].data_ptr() for m in mats])
+        dp = vp(*[m[2].data_ptr() for m in mats])
+        code = self.lib.airg_setup_batch(ctypes.byref(self.h), np_, n, nnz, rp, cp, dp, 1,
+                                         ctypes.byref(self.params), _stream_ptr(stream))
+        binding.check(code, self.lib)
+        st = self.stats()
+        self.n = st["n"][0]
+
+    def solve(self, bs, xs=None, guess=False):
+        torch = _torch()
+        np_ = len(self._sizes)
+        if len(bs) != np_:
+            raise ValueError(f"expected {np_} right-hand sides")
+        bs = [_as_device(b, torch.float64) for b in bs]
+        for b, m in zip(bs, self._sizes):
+            if b.numel() != m:
+                raise ValueError("right-hand side size does not match its problem")
+        if xs is None:
+            xs = [torch.zeros_like(b) for b in bs]
+        vp = ctypes.c_void_p * np_
+        infos = (binding.SolveInfo * np_)()
+        code = self.lib.airg_solve_batch(self.h, vp(*[b.data_ptr() for b in bs]),
+                                         vp(*[x.data_ptr() for x in xs]), 1 if guess else 0, infos)
+        binding.check(code, self.lib)
+        return xs, [i.as_dict() for i in infos]
+
+    def adjoint_solve(self, w, lam=None, guess=False):
+        raise NotImplementedError("adjoint solves take a single-problem Solver")

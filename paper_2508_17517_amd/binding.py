@@ -92,6 +92,11 @@ SYMBOLS = {
                            ctypes.c_void_p, ctypes.c_int, P(Params), ctypes.c_void_p]),
     "airg_solve": (c_i32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, c_i64, ctypes.c_void_p,
                            c_i64, ctypes.c_int, P(SolveInfo)]),
+    "airg_setup_batch": (c_i32, [P(ctypes.c_void_p), ctypes.c_int, P(c_i64), P(c_i64),
+                                 P(ctypes.c_void_p), P(ctypes.c_void_p), P(ctypes.c_void_p),
+                                 ctypes.c_int, P(Params), ctypes.c_void_p]),
+    "airg_solve_batch": (c_i32, [ctypes.c_void_p, P(ctypes.c_void_p), P(ctypes.c_void_p),
+                                 ctypes.c_int, P(SolveInfo)]),
     "airg_adjoint_solve": (c_i32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, c_i64,
                                    ctypes.c_void_p, c_i64, ctypes.c_int, P(SolveInfo)]),
     "airg_get_stats": (c_i32, [ctypes.c_void_p, P(Stats)]),
@@ -100,6 +105,9 @@ SYMBOLS = {
     "airg_import_hierarchy": (c_i32, [P(ctypes.c_void_p), ctypes.c_int, P(LevelInfo),
                                       P(LevelArrays), P(Params), ctypes.c_void_p]),
     "airg_time_kernels": (c_i32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, P(KernelTiming)]),
+    "airg_fv_nnz": (c_i32, [c_i64, c_i64, c_dbl, P(c_i64)]),
+    "airg_fv_assemble": (c_i32, [c_i64, c_i64, c_dbl] + [ctypes.c_void_p] * 9),
+    "airg_fv_gradients": (c_i32, [c_i64, c_i64, c_dbl] + [ctypes.c_void_p] * 10),
     "airg_destroy": (None, [ctypes.c_void_p]),
     "airg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "airg_last_error": (ctypes.c_char_p, []),

@@ -2,6 +2,7 @@
 // catches the library's exceptions and turns them into status codes.
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <new>
 #include <string>
@@ -16,8 +17,10 @@ using namespace airg;
 struct airg_ctx {
   Hierarchy H;
   Workspace W;
+  std::map<int, std::unique_ptr<Workspace>> Wk;   // K-column workspaces, made on first use
   std::unique_ptr<Hierarchy> Ht;  // adjoint hierarchy (built on A^T on first use)
   std::unique_ptr<Workspace> Wt;
+  std::map<int, std::unique_ptr<Workspace>> Wtk;
 };
 
 namespace {
@@ -81,16 +84,34 @@ void load_csr(CSR& A, int64_t n, int64_t nnz, const int32_t* rowptr, const int32
   validate_csr(A, diag, s, true);
 }
 
-int solve_columns(Hierarchy& H, Workspace& W, int nrhs, const double* b, int64_t ldb, double* x,
-                  int64_t ldx, int guess, airg_solve_info* info) {
+// Up to 64 columns are solved together as K interleaved columns, K the next
+// power of two (padding columns are zero).
+int solve_columns(Hierarchy& H, Workspace& W, std::map<int, std::unique_ptr<Workspace>>& Wk,
+                  int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, int guess,
+                  airg_solve_info* info) {
   if (nrhs < 0) fail(AIRG_ERR_INVALID, "nrhs must be >= 0");
   if (nrhs > 0 && (!b || !x)) fail(AIRG_ERR_INVALID, "null vector pointer");
   if (nrhs > 1 && (ldb < H.n0 || ldx < H.n0)) fail(AIRG_ERR_INVALID, "leading dimension < n");
+  if (nrhs > 1 && !H.seg.empty()) fail(AIRG_ERR_INVALID, "a batch handle solves one column per problem");
   int status = AIRG_OK;
-  for (int k = 0; k < nrhs; ++k) {
-    int st = fgmres_solve(H, W, b + (int64_t)k * ldb, x + (int64_t)k * ldx, guess != 0,
-                          info ? info + k : nullptr);
+  for (int k0 = 0; k0 < nrhs;) {
+    const int cnt = std::min(64, nrhs - k0);
+    int K = 1;
+    while (K < cnt) K <<= 1;
+    Workspace* ws = &W;
+    if (K > 1) {
+      auto it = Wk.find(K);
+      if (it == Wk.end()) {
+        std::unique_ptr<Workspace> w(new Workspace());
+        workspace_init(H, *w, K);
+        it = Wk.emplace(K, std::move(w)).first;
+      }
+      ws = it->second.get();
+    }
+    int st = fgmres_solve(H, *ws, b + (int64_t)k0 * ldb, ldb, x + (int64_t)k0 * ldx, ldx, cnt,
+                          guess != 0, info ? info + k0 : nullptr);
     if (st != AIRG_OK) status = st;
+    k0 += cnt;
   }
   return status;
 }
@@ -180,7 +201,84 @@ int airg_solve(airg_handle h, int nrhs, const double* b, int64_t ldb, double* x,
                int use_x_as_guess, airg_solve_info* info) {
   return guard([&]() {
     airg_ctx* c = handle_of(h);
-    return solve_columns(c->H, c->W, nrhs, b, ldb, x, ldx, use_x_as_guess, info);
+    return solve_columns(c->H, c->W, c->Wk, nrhs, b, ldb, x, ldx, use_x_as_guess, info);
+  });
+}
+
+int airg_setup_batch(airg_handle* out, int nprob, const int64_t* n, const int64_t* nnz,
+                     const int32_t* const* rowptr, const int32_t* const* colidx,
+                     const double* const* vals, int on_device, const airg_params* p,
+                     void* hip_stream) {
+  return guard([&]() {
+    if (!out || nprob < 1 || !n || !nnz || !rowptr || !colidx || !vals)
+      fail(AIRG_ERR_INVALID, "bad batch arguments");
+    *out = nullptr;
+    airg_params prm;
+    if (p) prm = *p;
+    else airg_params_default(&prm);
+    check_params(prm);
+    std::unique_ptr<airg_ctx> c(new airg_ctx());
+    c->H.p = prm;
+    hipStream_t s = (hipStream_t)hip_stream;
+    c->H.s = s;
+    int64_t N = 0, NZ = 0;
+    std::vector<int64_t> seg(1, 0);
+    for (int q = 0; q < nprob; ++q) {
+      if (n[q] <= 0 || nnz[q] < n[q]) fail(AIRG_ERR_INVALID, "bad problem size in the batch");
+      N += n[q];
+      NZ += nnz[q];
+      seg.push_back(N);
+    }
+    if (NZ > 2147483647ll || N > 2147483647ll) fail(AIRG_ERR_INVALID, "batch too large");
+    // block-diagonal concatenation: problem q's rows and columns shift by seg[q]
+    CSR A;
+    A.alloc(N, N, NZ, s);
+    int64_t zoff = 0;
+    for (int q = 0; q < nprob; ++q) {
+      CSR Aq;
+      load_csr(Aq, n[q], nnz[q], rowptr[q], colidx[q], vals[q], on_device, s);
+      launch_offset_copy_i32(A.rowptr.get() + seg[q], Aq.rowptr.get(), n[q] + 1, zoff, s);
+      launch_offset_copy_i32(A.col.get() + zoff, Aq.col.get(), nnz[q], seg[q], s);
+      AIRG_HIP(hipMemcpyAsync(A.val.get() + zoff, Aq.val.get(), nnz[q] * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+      zoff += nnz[q];
+      AIRG_HIP(hipStreamSynchronize(s));
+    }
+    DBuf<double> diag(N, s);
+    validate_csr(A, diag, s, true);
+    c->H.seg = seg;
+    build_hierarchy(c->H, std::move(A));
+    workspace_init(c->H, c->W);
+    AIRG_HIP(hipStreamSynchronize(s));
+    *out = c.release();
+    return (int)AIRG_OK;
+  });
+}
+
+int airg_solve_batch(airg_handle h, const double* const* b, double* const* x,
+                     int use_x_as_guess, airg_solve_info* info) {
+  return guard([&]() {
+    airg_ctx* c = handle_of(h);
+    const std::vector<int64_t>& seg = c->H.seg;
+    if (seg.empty()) fail(AIRG_ERR_INVALID, "not a batch handle");
+    if (!b || !x) fail(AIRG_ERR_INVALID, "null pointer array");
+    hipStream_t s = c->H.s;
+    const int np = (int)seg.size() - 1;
+    DBuf<double> bc(c->H.n0, s), xc(c->H.n0, s);
+    for (int q = 0; q < np; ++q) {
+      if (!b[q] || !x[q]) fail(AIRG_ERR_INVALID, "null vector pointer");
+      const size_t bytes = (seg[q + 1] - seg[q]) * sizeof(double);
+      AIRG_HIP(hipMemcpyAsync(bc.get() + seg[q], b[q], bytes, hipMemcpyDeviceToDevice, s));
+      if (use_x_as_guess)
+        AIRG_HIP(hipMemcpyAsync(xc.get() + seg[q], x[q], bytes, hipMemcpyDeviceToDevice, s));
+    }
+    int st = fgmres_solve(c->H, c->W, bc.get(), c->H.n0, xc.get(), c->H.n0, 1,
+                          use_x_as_guess != 0, info);
+    for (int q = 0; q < np; ++q)
+      AIRG_HIP(hipMemcpyAsync(x[q], xc.get() + seg[q], (seg[q + 1] - seg[q]) * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+    AIRG_HIP(hipStreamSynchronize(s));
+    return st;
   });
 }
 
@@ -200,7 +298,7 @@ int airg_adjoint_solve(airg_handle h, int nrhs, const double* w, int64_t ldw, do
       c->Ht = std::move(Ht);
       c->Wt = std::move(Wt);
     }
-    return solve_columns(*c->Ht, *c->Wt, nrhs, w, ldw, lam, ldl, use_guess, info);
+    return solve_columns(*c->Ht, *c->Wt, c->Wtk, nrhs, w, ldw, lam, ldl, use_guess, info);
   });
 }
 
@@ -287,6 +385,45 @@ int airg_time_kernels(airg_handle h, int cls, int reps, airg_kernel_timing* out)
     airg_ctx* c = handle_of(h);
     if (!out) fail(AIRG_ERR_INVALID, "null output");
     return time_kernels(c->H, c->W, cls, reps, out);
+  });
+}
+
+int airg_fv_nnz(int64_t nx, int64_t ny, double theta, int64_t* nnz) {
+  return guard([&]() {
+    if (nx < 1 || ny < 1 || !nnz || !(theta >= 0.0 && theta <= 1.5707963267948966))
+      fail(AIRG_ERR_INVALID, "bad grid or angle");
+    *nnz = fv_nnz(nx, ny, theta);
+    return (int)AIRG_OK;
+  });
+}
+
+int airg_fv_assemble(int64_t nx, int64_t ny, double theta, const double* g_west,
+                     const double* g_south, int32_t* rowptr, int32_t* col, double* val, double* b,
+                     double* dval_dtheta, double* db_dtheta, void* hip_stream) {
+  return guard([&]() {
+    if (nx < 1 || ny < 1 || !(theta >= 0.0 && theta <= 1.5707963267948966))
+      fail(AIRG_ERR_INVALID, "bad grid or angle");
+    if (!g_west || !g_south || !rowptr || !col || !val || !b) fail(AIRG_ERR_INVALID, "null pointer");
+    if (fv_nnz(nx, ny, theta) > 2147483647ll) fail(AIRG_ERR_INVALID, "grid too large");
+    hipStream_t s = (hipStream_t)hip_stream;
+    fv_assemble(nx, ny, theta, g_west, g_south, rowptr, col, val, b, dval_dtheta, db_dtheta, s);
+    AIRG_HIP(hipStreamSynchronize(s));
+    return (int)AIRG_OK;
+  });
+}
+
+int airg_fv_gradients(int64_t nx, int64_t ny, double theta, const int32_t* rowptr,
+                      const int32_t* col, const double* dval_dtheta, const double* db_dtheta,
+                      const double* u, const double* lam, double* dg_west, double* dg_south,
+                      double* dtheta, void* hip_stream) {
+  return guard([&]() {
+    if (nx < 1 || ny < 1) fail(AIRG_ERR_INVALID, "bad grid");
+    if (!rowptr || !col || !dval_dtheta || !db_dtheta || !u || !lam || !dg_west || !dg_south ||
+        !dtheta)
+      fail(AIRG_ERR_INVALID, "null pointer");
+    fv_gradients(nx, ny, theta, rowptr, col, dval_dtheta, db_dtheta, u, lam, dg_west, dg_south,
+                 dtheta, (hipStream_t)hip_stream);
+    return (int)AIRG_OK;
   });
 }
 

@@ -308,12 +308,12 @@ OpView op_view(const CSR& A, const DBuf<float>& v32, const DBuf<bf16>& v16, int 
 }
 
 template <class X>
-void newton_apply_t(const OpView& A, int tpr, const std::vector<cplx>& roots, const X* r, X* x,
-                    X* w0, X* w1, X* t, hipStream_t s, LaunchTally* tally) {
-  const int64_t n = A.rows;
+void newton_apply_t(const OpView& A, int tpr, int K, const std::vector<cplx>& roots, const X* r,
+                    X* x, X* w0, X* w1, X* t, hipStream_t s, LaunchTally* tally) {
+  const int64_t n = A.rows * K;  // vector elements; the matrix is read once per launch
   const double xb = (double)sizeof(X);
   const double vb = A.vt == VT_F64 ? 8.0 : A.vt == VT_F32 ? 4.0 : 2.0;
-  const double mb = csr_bytes(n, A.nnz, vb), mf = 2.0 * (double)A.nnz;
+  const double mb = csr_bytes(A.rows, A.nnz, vb), mf = 2.0 * (double)A.nnz * K;
   auto count = [&](double vecs, double vec_flops) {
     if (tally) tally->add(mb + xb * n * vecs, mf + vec_flops);
   };
@@ -340,7 +340,7 @@ void newton_apply_t(const OpView& A, int tpr, const std::vector<cplx>& roots, co
         skip = 1;
       }
       X* wn = bufs[nb];
-      newton_real_t<X>(A, tpr, w, wn, x, inv, first, inv_last, s);
+      newton_real_t<X>(A, tpr, K, w, wn, x, inv, first, inv_last, s);
       // w gathered, wn written, x written (and read unless first)
       count(first ? 3 : 4, (inv_last != 0.0 ? 6.0 : 4.0) * n);
       first = false;
@@ -351,7 +351,7 @@ void newton_apply_t(const OpView& A, int tpr, const std::vector<cplx>& roots, co
       const double a = z.real(), b = z.imag();
       const double mod2 = a * a + b * b;
       const double c1 = 2.0 * a / mod2, c2 = 1.0 / mod2;
-      newton_pair1_t<X>(A, tpr, w, t, x, c1, c2, first, s);
+      newton_pair1_t<X>(A, tpr, K, w, t, x, c1, c2, first, s);
       // w gathered, t written, x written (and read unless first)
       count(first ? 3 : 4, 4.0 * n);
       first = false;
@@ -363,7 +363,7 @@ void newton_apply_t(const OpView& A, int tpr, const std::vector<cplx>& roots, co
         skip = 1;
       }
       X* wn = bufs[nb];
-      newton_pair2_t<X>(A, tpr, w, t, wn, x, c1, c2, inv_last, s);
+      newton_pair2_t<X>(A, tpr, K, w, t, wn, x, c1, c2, inv_last, s);
       // t gathered, w read, wn written (x read and written when fused)
       count(inv_last != 0.0 ? 5 : 3, (inv_last != 0.0 ? 6.0 : 4.0) * n);
       w = wn;
@@ -372,9 +372,9 @@ void newton_apply_t(const OpView& A, int tpr, const std::vector<cplx>& roots, co
     }
   }
 }
-template void newton_apply_t<double>(const OpView&, int, const std::vector<cplx>&, const double*,
+template void newton_apply_t<double>(const OpView&, int, int, const std::vector<cplx>&, const double*,
                                      double*, double*, double*, double*, hipStream_t, LaunchTally*);
-template void newton_apply_t<float>(const OpView&, int, const std::vector<cplx>&, const float*,
+template void newton_apply_t<float>(const OpView&, int, int, const std::vector<cplx>&, const float*,
                                     float*, float*, float*, float*, hipStream_t, LaunchTally*);
 
 void build_hierarchy(Hierarchy& H, CSR&& Ain) {

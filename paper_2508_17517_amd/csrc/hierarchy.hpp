@@ -62,6 +62,9 @@ struct Hierarchy {
   std::vector<Level> levels;
   double setup_ms = 0.0;
   double comp_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // a block-diagonal batch of problems: block p holds setup-numbering rows
+  // seg[p] .. seg[p+1]-1 (empty for a single problem)
+  std::vector<int64_t> seg;
 };
 
 // Build the hierarchy for A (device CSR, validated) with parameters p.
@@ -100,14 +103,15 @@ OpView op_view(const CSR& A, const DBuf<float>& v32, const DBuf<bf16>& v16, int 
 inline double value_bytes(int prec) { return prec == AIRG_FP64 ? 8.0 : prec == AIRG_FP32 ? 4.0 : 2.0; }
 
 // Coarse solver: x = q(A) r with the Newton roots (r, x device vectors of
-// length A.rows; w0, w1, t scratch of the same length).  X is the vector type.
+// A.rows x K interleaved columns; w0, w1, t scratch of the same size).  X is
+// the vector type.
 template <class X>
-void newton_apply_t(const OpView& A, int tpr, const std::vector<cplx>& roots, const X* r, X* x,
-                    X* w0, X* w1, X* t, hipStream_t s, LaunchTally* tally = nullptr);
+void newton_apply_t(const OpView& A, int tpr, int K, const std::vector<cplx>& roots, const X* r,
+                    X* x, X* w0, X* w1, X* t, hipStream_t s, LaunchTally* tally = nullptr);
 inline void newton_apply_dev(const CSR& A, int tpr, const std::vector<cplx>& roots, const double* r,
                              double* x, double* w0, double* w1, double* t, hipStream_t s,
                              LaunchTally* tally = nullptr) {
-  newton_apply_t<double>(opview(A), tpr, roots, r, x, w0, w1, t, s, tally);
+  newton_apply_t<double>(opview(A), tpr, 1, roots, r, x, w0, w1, t, s, tally);
 }
 
 // Validates a device CSR and returns its diagonal; throws on error.

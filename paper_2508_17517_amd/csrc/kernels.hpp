@@ -41,6 +41,20 @@ void launch_sqrt_inplace(double* v, hipStream_t s);
 void launch_scatter(double* y, const double* x, const int32_t* perm, int64_t n, hipStream_t s);
 void launch_gather(double* y, const double* x, const int32_t* perm, int64_t n, hipStream_t s);
 
+// K interleaved columns: ys[pos[i] K + c] = b[c ldb + i] and x[c ldx + i] = xs[pos[i] K + c];
+// columns c >= kv are padding (zero in ys, not written to x).
+void launch_scatter_cols(double* ys, const double* b, int64_t ldb, const int32_t* pos, int64_t n,
+                         int K, int kv, hipStream_t s);
+void launch_gather_cols(double* x, int64_t ldx, const double* xs, const int32_t* pos, int64_t n,
+                        int K, int kv, hipStream_t s);
+// out[c] = sum_i x[i K + c]^2 in a fixed order; `work` needs col_sumsq_work_size(n, K).
+size_t col_sumsq_work_size(int64_t n, int K);
+void launch_col_sumsq(const double* x, int64_t n, int K, double* out, double* work, hipStream_t s);
+
+// dst[i] = src[i] + add
+void launch_offset_copy_i32(int32_t* dst, const int32_t* src, int64_t n, int64_t add,
+                            hipStream_t s);
+
 // Exclusive scan of int64 counts: out[i] = sum_{j<i} in[j], out[n] = total.
 // `work` needs scan_work_size(n) int64s.  in and out may alias.
 size_t scan_work_size(int64_t n);
@@ -57,32 +71,34 @@ void spmv_seq(const CSR& A, const double* x, double* y, hipStream_t s);
 // y = A x with `tpr` lanes per row.
 void spmv(const CSR& A, int tpr, const double* x, double* y, hipStream_t s);
 
-// Solve-phase kernels, generic over the matrix storage (OpView::vt) and the
-// vector type X (double or float; rows accumulate in X).
+// Solve-phase kernels, generic over the matrix storage (OpView::vt), the
+// vector type X (double or float; rows accumulate in X) and the number K of
+// interleaved columns (element (row, c) at row * K + c; K a power of two <= 64).
 template <class X>
-void spmv_t(const OpView& A, int tpr, const X* x, X* y, hipStream_t s);
+void spmv_t(const OpView& A, int tpr, int K, const X* x, X* y, hipStream_t s);
 // Horner step of the smoother: out = (acc ? out : 0) + a (A y) + b s
 template <class X>
-void spmv_horner_t(const OpView& A, int tpr, const X* y, const X* sv, X* out, double a, double b,
-                   bool acc, hipStream_t st);
+void spmv_horner_t(const OpView& A, int tpr, int K, const X* y, const X* sv, X* out, double a,
+                   double b, bool acc, hipStream_t st);
 // Restriction: dst[p] = src[p] + (Z r_f)[p]   (src may alias dst)
 template <class X>
-void spmv_restrict_t(const OpView& Z, int tpr, const X* rf, const X* src, X* dst, hipStream_t s);
+void spmv_restrict_t(const OpView& Z, int tpr, int K, const X* rf, const X* src, X* dst,
+                     hipStream_t s);
 // F-point residual with fused one-point prolongation:
 //   ef[i] = W e_c, s[i] = r_f[i] - (A_fc e_c)[i] - (A_ff W e_c)[i]
 template <class X>
-void residual_fpoint_t(const OpView& Aff, const OpView& Afc, const int32_t* cmap, int tpr,
+void residual_fpoint_t(const OpView& Aff, const OpView& Afc, const int32_t* cmap, int tpr, int K,
                        const X* rf, const X* ec, X* ef, X* sv, hipStream_t s);
-// Newton steps of the coarse solver (see newton_apply_dev).
+// Newton steps of the coarse solver (see newton_apply_t).
 template <class X>
-void newton_real_t(const OpView& A, int tpr, const X* w, X* wn, X* x, double inv, bool first,
-                   double inv_last, hipStream_t s);
+void newton_real_t(const OpView& A, int tpr, int K, const X* w, X* wn, X* x, double inv,
+                   bool first, double inv_last, hipStream_t s);
 template <class X>
-void newton_pair1_t(const OpView& A, int tpr, const X* w, X* t, X* x, double c1, double c2,
+void newton_pair1_t(const OpView& A, int tpr, int K, const X* w, X* t, X* x, double c1, double c2,
                     bool first, hipStream_t s);
 template <class X>
-void newton_pair2_t(const OpView& A, int tpr, const X* w, const X* t, X* wn, X* x, double c1,
-                    double c2, double inv_last, hipStream_t s);
+void newton_pair2_t(const OpView& A, int tpr, int K, const X* w, const X* t, X* wn, X* x,
+                    double c1, double c2, double inv_last, hipStream_t s);
 // x = (first ? 0 : x) + a w
 template <class X>
 void axpy_first_t(X* x, const X* w, double a, bool first, int64_t n, hipStream_t s);
@@ -164,6 +180,15 @@ void launch_nested_pos_ranked(const int8_t* state, const int64_t* fidx, const in
 // out[frank[f]] = pos_next[cmap[f]] (or -1)
 void launch_remap_ranked(const int32_t* cmap, const int32_t* pos_next, const int32_t* frank,
                          int64_t nf, int32_t* out, hipStream_t s);
+
+// ---------------------------------------------------------------- fv.hip
+int64_t fv_nnz(int64_t nx, int64_t ny, double theta);
+void fv_assemble(int64_t nx, int64_t ny, double theta, const double* gw, const double* gs,
+                 int32_t* rowptr, int32_t* col, double* val, double* b, double* dval, double* db,
+                 hipStream_t s);
+void fv_gradients(int64_t nx, int64_t ny, double theta, const int32_t* rowptr, const int32_t* col,
+                  const double* dval, const double* db, const double* u, const double* lam,
+                  double* dgw, double* dgs, double* dtheta, hipStream_t s);
 
 // ---------------------------------------------------------------- spgemm.hip
 // C = A B with c_ij accumulated over k ascending from 0.0, exact zeros dropped.

@@ -5,6 +5,13 @@
 // right-preconditioned FGMRES(restart) with classical Gram-Schmidt applied
 // twice; the Hessenberg column comes to the host once per iteration.
 //
+// Many right-hand sides are solved together as K interleaved columns: every
+// V-cycle kernel is then an SpMM that reads each matrix entry once for all
+// columns, and one Krylov process runs over the stacked columns (its
+// stopping test is tightened so that every column reaches the tolerance on
+// its own).  A block-diagonal batch of problems is solved the same way, each
+// problem being a convergence group.
+//
 // Mixed precision: with FP32 or BF16 storage the V-cycle runs on FP32 vectors
 // (matrices in the storage type, rows accumulated in FP32) between a
 // conversion of its FP64 input and of its output back to FP64; the outer
@@ -25,9 +32,10 @@ Workspace::~Workspace() {
   if (ev1) (void)hipEventDestroy(ev1);
 }
 
-void workspace_init(const Hierarchy& H, Workspace& W) {
+void workspace_init(const Hierarchy& H, Workspace& W, int K) {
   hipStream_t s = H.s;
-  const int64_t n = H.n0;
+  const int64_t n = H.n0 * K;
+  W.K = K;
   W.ld = (n + 63) / 64 * 64;
   W.restart = H.p.restart;
   W.V.alloc((size_t)(W.restart + 1) * W.ld, s);
@@ -35,7 +43,8 @@ void workspace_init(const Hierarchy& H, Workspace& W) {
   W.w.alloc(n, s);
   int64_t maxf = 1;
   for (const Level& L : H.levels) maxf = std::max(maxf, L.nF);
-  const int64_t nc = std::max<int64_t>(1, H.levels.back().n);
+  maxf *= K;
+  const int64_t nc = std::max<int64_t>(1, H.levels.back().n) * K;
   if (H.p.precision == AIRG_FP64) {
     W.rr.alloc(n, s);
     W.sv.alloc(maxf, s);
@@ -57,16 +66,20 @@ void workspace_init(const Hierarchy& H, Workspace& W) {
   }
   W.bperm.alloc(n, s);
   W.xperm.alloc(n, s);
+  if (!H.seg.empty()) W.nat.alloc(H.n0, s);
   W.hbuf.alloc(2 * (W.restart + 1) + 2, s);
   W.ybuf.alloc(W.restart + 1, s);
+  const size_t ng = std::max<size_t>((size_t)K, H.seg.empty() ? 1 : H.seg.size());
+  W.gbuf.alloc(ng + 1, s);
   W.dot_work.alloc(dot_work_size(n, 64), s);
+  W.col_work.alloc(col_sumsq_work_size(H.n0, K), s);
   AIRG_HIP(hipEventCreate(&W.ev0));
   AIRG_HIP(hipEventCreate(&W.ev1));
 }
 
 namespace {
 
-// Vectors of one V-cycle in vector type X (nested numbering).
+// Vectors of one V-cycle in vector type X (nested numbering, K columns).
 template <class X>
 struct VecSet {
   const X* in;  // top-level residual
@@ -99,13 +112,13 @@ LevelOps ops_of(const Level& L, int prec) {
 double vt_bytes(ValType vt) { return vt == VT_F64 ? 8.0 : vt == VT_F32 ? 4.0 : 2.0; }
 
 template <class X>
-void horner(const Level& L, const OpView& Aff, const X* sv, X* ef, X* y0, X* y1, hipStream_t s,
-            LaunchTally* tally = nullptr) {
+void horner(const Level& L, const OpView& Aff, int K, const X* sv, X* ef, X* y0, X* y1,
+            hipStream_t s, LaunchTally* tally = nullptr) {
   const std::vector<double>& a = L.alpha;
   const int d = (int)a.size() - 1;
-  const int64_t n = L.nF;
+  const int64_t n = L.nF * K;
   const double xb = (double)sizeof(X);
-  const double mb = csr_bytes(n, Aff.nnz, vt_bytes(Aff.vt)), mf = 2.0 * (double)Aff.nnz;
+  const double mb = csr_bytes(L.nF, Aff.nnz, vt_bytes(Aff.vt)), mf = 2.0 * (double)Aff.nnz * K;
   // per step: y gathered, s read, out written (and read when accumulating)
   auto count = [&](bool acc) {
     if (tally) tally->add(mb + xb * n * (acc ? 4 : 3), mf + 3.0 * n);
@@ -116,45 +129,46 @@ void horner(const Level& L, const OpView& Aff, const X* sv, X* ef, X* y0, X* y1,
     return;
   }
   if (d == 1) {
-    spmv_horner_t<X>(Aff, L.tpr_ff, sv, sv, ef, a[1], a[0], true, s);
+    spmv_horner_t<X>(Aff, L.tpr_ff, K, sv, sv, ef, a[1], a[0], true, s);
     count(true);
     return;
   }
   X* y[2] = {y0, y1};
   int c = 0;
-  spmv_horner_t<X>(Aff, L.tpr_ff, sv, sv, y[0], a[d], a[d - 1], false, s);
+  spmv_horner_t<X>(Aff, L.tpr_ff, K, sv, sv, y[0], a[d], a[d - 1], false, s);
   count(false);
   for (int k = d - 2; k >= 1; --k) {
-    spmv_horner_t<X>(Aff, L.tpr_ff, y[c], sv, y[c ^ 1], 1.0, a[k], false, s);
+    spmv_horner_t<X>(Aff, L.tpr_ff, K, y[c], sv, y[c ^ 1], 1.0, a[k], false, s);
     count(false);
     c ^= 1;
   }
-  spmv_horner_t<X>(Aff, L.tpr_ff, y[c], sv, ef, 1.0, a[0], true, s);
+  spmv_horner_t<X>(Aff, L.tpr_ff, K, y[c], sv, ef, 1.0, a[0], true, s);
   count(true);
 }
 
 template <class X>
-void vcycle_t(const Hierarchy& H, const VecSet<X>& v) {
+void vcycle_t(const Hierarchy& H, const VecSet<X>& v, int K) {
   hipStream_t s = H.s;
   const int prec = H.p.precision;
   const int L = (int)H.levels.size() - 1;
   for (int l = 0; l < L; ++l) {
     const Level& lv = H.levels[l];
-    const X* src = (l == 0 ? v.in : v.rr) + lv.off;
-    X* dst = v.rr + H.levels[l + 1].off;
-    spmv_restrict_t<X>(ops_of(lv, prec).z, lv.tpr_z, src, src + lv.nF, dst, s);
+    const X* src = (l == 0 ? v.in : v.rr) + lv.off * K;
+    X* dst = v.rr + H.levels[l + 1].off * K;
+    spmv_restrict_t<X>(ops_of(lv, prec).z, lv.tpr_z, K, src, src + lv.nF * K, dst, s);
   }
   const Level& lc = H.levels[L];
-  const X* rc = (L == 0 ? v.in : v.rr) + lc.off;
-  newton_apply_t<X>(ops_of(lc, prec).a, lc.tpr_a, lc.roots, rc, v.e + lc.off, v.cw0, v.cw1, v.ct, s);
+  const X* rc = (L == 0 ? v.in : v.rr) + lc.off * K;
+  newton_apply_t<X>(ops_of(lc, prec).a, lc.tpr_a, K, lc.roots, rc, v.e + lc.off * K, v.cw0, v.cw1,
+                    v.ct, s);
   for (int l = L - 1; l >= 0; --l) {
     const Level& lv = H.levels[l];
     const LevelOps o = ops_of(lv, prec);
-    const X* rf = (l == 0 ? v.in : v.rr) + lv.off;
-    X* ef = v.e + lv.off;
-    const X* ec = v.e + H.levels[l + 1].off;
-    residual_fpoint_t<X>(o.ff, o.fc, lv.cmap.get(), lv.tpr_fc, rf, ec, ef, v.sv, s);
-    horner<X>(lv, o.ff, v.sv, ef, v.y0, v.y1, s);
+    const X* rf = (l == 0 ? v.in : v.rr) + lv.off * K;
+    X* ef = v.e + lv.off * K;
+    const X* ec = v.e + H.levels[l + 1].off * K;
+    residual_fpoint_t<X>(o.ff, o.fc, lv.cmap.get(), lv.tpr_fc, K, rf, ec, ef, v.sv, s);
+    horner<X>(lv, o.ff, K, v.sv, ef, v.y0, v.y1, s);
   }
 }
 
@@ -166,28 +180,52 @@ void dots(const double* V, int64_t ld, int nv, const double* w, int64_t n, doubl
   }
 }
 
-double norm_host(const double* x, int64_t n, Workspace& W, hipStream_t s) {
-  double* out = W.hbuf.get() + 2 * (W.restart + 1) + 1;
-  launch_tree_dots(x, 0, 1, x, n, out, W.dot_work.get(), s);
-  return std::sqrt(fetch(out, s));
+// Norms of the convergence groups of a stacked vector in nested numbering:
+// its K columns, or (K = 1, a batch of problems) each problem's rows.
+std::vector<double> group_norms(const Hierarchy& H, Workspace& W, const double* v) {
+  hipStream_t s = H.s;
+  const int K = W.K;
+  double* g = W.gbuf.get();
+  size_t ng;
+  if (K > 1) {
+    ng = (size_t)K;
+    launch_col_sumsq(v, H.n0, K, g, W.col_work.get(), s);
+  } else if (!H.seg.empty()) {
+    ng = H.seg.size() - 1;
+    launch_gather(W.nat.get(), v, H.levels[0].pos.get(), H.n0, s);
+    for (size_t p = 0; p < ng; ++p) {
+      const double* a = W.nat.get() + H.seg[p];
+      launch_tree_dots(a, 0, 1, a, H.seg[p + 1] - H.seg[p], g + p, W.dot_work.get(), s);
+    }
+  } else {
+    ng = 1;
+    launch_tree_dots(v, 0, 1, v, H.n0, g, W.dot_work.get(), s);
+  }
+  std::vector<double> out(ng);
+  W.gbuf.to_host(out.data(), ng);
+  AIRG_HIP(hipStreamSynchronize(s));
+  for (double& x : out) x = std::sqrt(x);
+  return out;
 }
 
 }  // namespace
 
 void vcycle(const Hierarchy& H, Workspace& W, const double* in, double* e) {
+  const int64_t n = H.n0 * W.K;
   if (H.p.precision == AIRG_FP64) {
-    vcycle_t<double>(H, vecs64(W, in, e));
+    vcycle_t<double>(H, vecs64(W, in, e), W.K);
     return;
   }
-  convert_d2f(W.in32.get(), in, H.n0, H.s);
-  vcycle_t<float>(H, vecs32(W));
-  convert_f2d(e, W.e32.get(), H.n0, H.s);
+  convert_d2f(W.in32.get(), in, n, H.s);
+  vcycle_t<float>(H, vecs32(W), W.K);
+  convert_f2d(e, W.e32.get(), n, H.s);
 }
 
-int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, double* x, bool guess,
-                 airg_solve_info* info) {
+int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb, double* x,
+                 int64_t ldx, int kvalid, bool guess, airg_solve_info* info) {
   hipStream_t s = H.s;
-  const int64_t n = H.n0;
+  const int K = W.K;
+  const int64_t n = H.n0 * K;  // stacked length
   const int R = W.restart;
   const int64_t ld = W.ld;
   const int32_t* pos = H.levels[0].pos.get();
@@ -195,35 +233,57 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, double* x, b
   const int max_it = H.p.max_it;
   AIRG_HIP(hipEventRecord(W.ev0, s));
 
-  launch_scatter(W.bperm.get(), b, pos, n, s);
-  if (guess) launch_scatter(W.xperm.get(), x, pos, n, s);
-  else launch_fill(W.xperm.get(), n, 0.0, s);
-  const double bnorm = norm_host(W.bperm.get(), n, W, s);
-
-  airg_solve_info out{};
-  int status = AIRG_OK;
-  if (bnorm == 0.0) {
-    launch_fill(x, n, 0.0, s);
-    out.converged = 1;
-  } else if (!std::isfinite(bnorm)) {
-    fail(AIRG_ERR_NONFINITE, "right-hand side is not finite");
+  if (K == 1) {
+    launch_scatter(W.bperm.get(), b, pos, H.n0, s);
+    if (guess) launch_scatter(W.xperm.get(), x, pos, H.n0, s);
+    else launch_fill(W.xperm.get(), n, 0.0, s);
   } else {
-    int its = 0;
+    launch_scatter_cols(W.bperm.get(), b, ldb, pos, H.n0, K, kvalid, s);
+    if (guess) launch_scatter_cols(W.xperm.get(), x, ldx, pos, H.n0, K, kvalid, s);
+    else launch_fill(W.xperm.get(), n, 0.0, s);
+  }
+  const std::vector<double> bn = group_norms(H, W, W.bperm.get());
+  const size_t ng = bn.size();
+  double bmin = 0.0, btot2 = 0.0;
+  for (double v : bn) {
+    if (!std::isfinite(v)) fail(AIRG_ERR_NONFINITE, "right-hand side is not finite");
+    btot2 += v * v;
+    if (v > 0.0 && (bmin == 0.0 || v < bmin)) bmin = v;
+  }
+  const double bnorm = std::sqrt(btot2);
+  // stopping test of the stacked Krylov process: |r| <= rtol min_g |b_g| makes
+  // every group's residual small enough (it equals rtol |b| for one group)
+  const double thr = rtol * bmin;
+
+  std::vector<airg_solve_info> out(ng);
+  for (auto& o : out) std::memset(&o, 0, sizeof(o));
+  int status = AIRG_OK;
+  int its = 0, restarts = 0;
+  double est_rel = 0.0;
+  std::vector<double> rn(ng, 0.0);
+  bool converged = false;
+  if (bnorm == 0.0) {
+    launch_fill(W.xperm.get(), n, 0.0, s);  // the solution of A x = 0
+    converged = true;
+  } else {
     std::vector<double> Hm((size_t)(R + 1) * R), g(R + 1), cs(R), sn(R), hh(2 * (R + 1) + 2), y(R);
     double* V = W.V.get();
     double* Zb = W.Zb.get();
     double* hd = W.hbuf.get();
     for (;;) {
-      spmv(H.Aperm, H.tpr_top, W.xperm.get(), W.w.get(), s);
+      spmv_t<double>(opview(H.Aperm), H.tpr_top, K, W.xperm.get(), W.w.get(), s);
       launch_sub(V, W.bperm.get(), W.w.get(), n, s);
-      const double beta = norm_host(V, n, W, s);
-      out.rel_residual = beta / bnorm;
-      if (beta <= rtol * bnorm) {
-        out.converged = 1;
-        break;
+      rn = group_norms(H, W, V);
+      converged = true;
+      double beta2 = 0.0;
+      for (size_t q = 0; q < ng; ++q) {
+        beta2 += rn[q] * rn[q];
+        if (!(rn[q] <= rtol * bn[q])) converged = false;
       }
-      if (its >= max_it) break;
-      if (its > 0) out.restarts++;
+      const double beta = std::sqrt(beta2);
+      if (converged || its >= max_it) break;
+      if (!std::isfinite(beta)) fail(AIRG_ERR_BREAKDOWN, "FGMRES breakdown (non-finite residual)");
+      if (its > 0) ++restarts;
       launch_divide(V, V, beta, n, s);
       std::fill(Hm.begin(), Hm.end(), 0.0);
       std::fill(g.begin(), g.end(), 0.0);
@@ -233,7 +293,7 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, double* x, b
         double* vj = V + (int64_t)j * ld;
         double* zj = Zb + (int64_t)j * ld;
         vcycle(H, W, vj, zj);
-        spmv(H.Aperm, H.tpr_top, zj, W.w.get(), s);
+        spmv_t<double>(opview(H.Aperm), H.tpr_top, K, zj, W.w.get(), s);
         ++its;
         dots(V, ld, j + 1, W.w.get(), n, hd, W, s);
         launch_cgs_update(W.w.get(), V, ld, hd, j + 1, n, s);
@@ -265,9 +325,9 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, double* x, b
         g[j] = cs[j] * g[j];
         k = j + 1;
         const double est = std::fabs(g[j + 1]);
-        out.rel_residual_estimate = est / bnorm;
+        est_rel = est / bnorm;
         if (!std::isfinite(est)) fail(AIRG_ERR_BREAKDOWN, "FGMRES breakdown (non-finite residual)");
-        if (est <= rtol * bnorm || its >= max_it) break;
+        if (est <= thr || its >= max_it) break;
         if (hn == 0.0) break;
         launch_divide(V + (int64_t)(j + 1) * ld, W.w.get(), hn, n, s);
       }
@@ -279,16 +339,26 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, double* x, b
       W.ybuf.from_host(y.data(), k);
       launch_basis_combine(W.xperm.get(), Zb, ld, W.ybuf.get(), k, n, s);
     }
-    out.iterations = its;
-    launch_gather(x, W.xperm.get(), pos, n, s);
-    if (!out.converged) status = AIRG_NOT_CONVERGED;
   }
+  if (K == 1) launch_gather(x, W.xperm.get(), pos, H.n0, s);
+  else launch_gather_cols(x, ldx, W.xperm.get(), pos, H.n0, K, kvalid, s);
+  if (!converged) status = AIRG_NOT_CONVERGED;
   AIRG_HIP(hipEventRecord(W.ev1, s));
   AIRG_HIP(hipEventSynchronize(W.ev1));
   float ms = 0.f;
   AIRG_HIP(hipEventElapsedTime(&ms, W.ev0, W.ev1));
-  out.solve_ms = ms;
-  if (info) *info = out;
+  for (size_t q = 0; q < ng; ++q) {
+    out[q].iterations = its;
+    out[q].restarts = restarts;
+    out[q].converged = rn[q] <= rtol * bn[q] ? 1 : 0;
+    out[q].rel_residual = bn[q] > 0.0 ? rn[q] / bn[q] : 0.0;
+    out[q].rel_residual_estimate = est_rel;
+    out[q].solve_ms = ms;
+  }
+  if (info) {
+    const size_t nout = K > 1 ? (size_t)kvalid : ng;
+    for (size_t q = 0; q < nout; ++q) info[q] = out[q];
+  }
   return status;
 }
 
@@ -305,18 +375,18 @@ void time_pass(const Hierarchy& H, const VecSet<X>& v, int cls, LaunchTally* t) 
   if (poly || cls == AIRG_K_HORNER)
     for (int l = 0; l < L; ++l) {
       const Level& lv = H.levels[l];
-      horner<X>(lv, ops_of(lv, prec).ff, v.sv, v.e + lv.off, v.y0, v.y1, s, t);
+      horner<X>(lv, ops_of(lv, prec).ff, 1, v.sv, v.e + lv.off, v.y0, v.y1, s, t);
     }
   if (poly || cls == AIRG_K_NEWTON) {
     const Level& lc = H.levels[L];
-    newton_apply_t<X>(ops_of(lc, prec).a, lc.tpr_a, lc.roots, v.rr + lc.off, v.e + lc.off, v.cw0,
-                      v.cw1, v.ct, s, t);
+    newton_apply_t<X>(ops_of(lc, prec).a, lc.tpr_a, 1, lc.roots, v.rr + lc.off, v.e + lc.off,
+                      v.cw0, v.cw1, v.ct, s, t);
   }
   if (cls == AIRG_K_RESIDUAL)
     for (int l = 0; l < L; ++l) {
       const Level& lv = H.levels[l];
       const LevelOps o = ops_of(lv, prec);
-      residual_fpoint_t<X>(o.ff, o.fc, lv.cmap.get(), lv.tpr_fc, v.rr + lv.off,
+      residual_fpoint_t<X>(o.ff, o.fc, lv.cmap.get(), lv.tpr_fc, 1, v.rr + lv.off,
                            v.e + H.levels[l + 1].off, v.e + lv.off, v.sv, s);
       if (t)
         t->add(csr_bytes(lv.nF, lv.Aff.nnz, vb) + csr_bytes(lv.nF, lv.Afc.nnz, vb) + 4.0 * lv.nF +
@@ -326,7 +396,7 @@ void time_pass(const Hierarchy& H, const VecSet<X>& v, int cls, LaunchTally* t) 
   if (cls == AIRG_K_RESTRICT)
     for (int l = 0; l < L; ++l) {
       const Level& lv = H.levels[l];
-      spmv_restrict_t<X>(ops_of(lv, prec).z, lv.tpr_z, v.rr + lv.off, v.rr + lv.off + lv.nF,
+      spmv_restrict_t<X>(ops_of(lv, prec).z, lv.tpr_z, 1, v.rr + lv.off, v.rr + lv.off + lv.nF,
                          v.rr + H.levels[l + 1].off, s);
       if (t) t->add(csr_bytes(lv.nC, lv.Z.nnz, vb) + xb * (lv.nF + 2 * lv.nC), 2.0 * lv.Z.nnz + lv.nC);
     }
@@ -338,6 +408,7 @@ int time_kernels(const Hierarchy& H, Workspace& W, int cls, int reps, airg_kerne
   hipStream_t s = H.s;
   if (reps < 1) fail(AIRG_ERR_INVALID, "reps must be >= 1");
   if (cls < AIRG_K_POLY || cls > AIRG_K_TOP_SPMV) fail(AIRG_ERR_INVALID, "unknown kernel class");
+  if (W.K != 1) fail(AIRG_ERR_INTERNAL, "kernel timing uses the single-column workspace");
   const bool f64 = H.p.precision == AIRG_FP64;
   double* in = W.V.get();
   launch_fill(in, H.n0, 1.0, s);

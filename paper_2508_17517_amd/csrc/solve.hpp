@@ -1,5 +1,5 @@
 // Solve phase: FGMRES preconditioned by AIRG V-cycles (device vectors in the
-// nested numbering of the hierarchy).
+// nested numbering of the hierarchy, K interleaved columns).
 #pragma once
 
 #include "hierarchy.hpp"
@@ -7,27 +7,33 @@
 namespace airg {
 
 struct Workspace {
-  int64_t ld = 0;      // leading dimension of the Krylov bases
+  int K = 1;           // interleaved columns (right-hand sides solved together)
+  int64_t ld = 0;      // leading dimension of the Krylov bases (>= n K)
   int restart = 0;
   DBuf<double> V, Zb;  // (restart + 1) and restart basis vectors
   DBuf<double> w, rr, sv, y0, y1;
   DBuf<double> cw0, cw1, ct;
   // FP32 vectors of the mixed-precision V-cycle
   DBuf<float> in32, e32, rr32, sv32, y032, y132, cw032, cw132, ct32;
-  DBuf<double> bperm, xperm;
-  DBuf<double> hbuf, ybuf, dot_work;
+  DBuf<double> bperm, xperm, nat;
+  DBuf<double> hbuf, ybuf, gbuf, dot_work, col_work;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   ~Workspace();
 };
 
-void workspace_init(const Hierarchy& H, Workspace& W);
+void workspace_init(const Hierarchy& H, Workspace& W, int K = 1);
 
-// One V-cycle: e = M r for a top-level vector `in` (nested numbering).
+// One V-cycle: e = M r for a top-level vector `in` (nested numbering, W.K columns).
 void vcycle(const Hierarchy& H, Workspace& W, const double* in, double* e);
 
-// FGMRES on A x = b for one right-hand side (b, x in setup numbering, device).
-int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, double* x, bool guess,
-                 airg_solve_info* info);
+// FGMRES on A x = b for W.K right-hand sides solved together: column c of b
+// starts at b + c ldb and of x at x + c ldx (setup numbering, device); only
+// the first kvalid columns are read and written.  With K = 1 and a batch of
+// problems (H.seg), each problem is a convergence group.  One Krylov process
+// runs over the stacked columns; every group must reach |r_g| <= rtol |b_g|.
+// info receives one entry per group.
+int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb, double* x,
+                 int64_t ldx, int kvalid, bool guess, airg_solve_info* info);
 
 // Replays one V-cycle's launches of a kernel class `reps` times between HIP
 // events (airg_time_kernels).

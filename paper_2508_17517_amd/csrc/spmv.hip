@@ -1,14 +1,17 @@
-// CSR SpMV kernels of the solve and setup.  One group of TPR lanes (a power of
-// two up to 64) handles one row: the lanes stride over the row's entries and
-// then combine with a shuffle tree inside the group.  The row result goes to a
-// fused epilogue (Horner step, restriction, Newton step, ...), so every
-// smoother and coarse-solver step is one pass over its matrix.  With TPR = 1 a
-// row is summed left to right from 0, the order the setup relies on.
+// CSR SpMV / SpMM kernels of the solve and setup.
+//
+// Vectors hold K interleaved columns: element (row, c) at row * K + c.  With
+// K = 1 a group of TPR lanes (a power of two up to 64) handles one row: the
+// lanes stride over the row's entries and combine with a shuffle tree inside
+// the group.  With K > 1 a group of K lanes handles one row, lane c owning
+// column c: every matrix entry is loaded once for all K columns and the x
+// gathers are K-wide and contiguous.  The row result goes to a fused epilogue
+// (Horner step, restriction, Newton step, ...) indexed by row * K + c, so each
+// smoother and coarse-solver step is one pass over its matrix.  With K = 1 and
+// TPR = 1 a row is summed left to right from 0, the order the setup relies on.
 //
 // The kernels are generic over the matrix value storage (FP64, FP32 or BF16)
-// and the vector type (FP64 or FP32); a row is accumulated in the vector type,
-// so the mixed-precision V-cycle stores matrices in FP32 or BF16 and
-// accumulates in FP32.
+// and the vector type (FP64 or FP32); rows accumulate in the vector type.
 #include "kernels.hpp"
 
 namespace airg {
@@ -30,8 +33,11 @@ static CSRT<MV> csr_t(const OpView& A) {
   return {A.rowptr, A.col, (const MV*)A.val, A.rows};
 }
 
-template <int TPR, class MV, class X>
-__device__ __forceinline__ X row_dot(const CSRT<MV>& A, int64_t row, int lane, const X* __restrict__ x) {
+// lanes-per-row kernel (K = 1)
+template <int TPR, class MV, class X, class Epi>
+__global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV> A, const X* __restrict__ x, Epi epi) {
+  const int lane = threadIdx.x & (TPR - 1);
+  const int64_t row = (int64_t)blockIdx.x * (256 / TPR) + threadIdx.x / TPR;
   X sum = 0;
   if (row < A.rows) {
     const int s = A.rowptr[row], e = A.rowptr[row + 1];
@@ -41,42 +47,59 @@ __device__ __forceinline__ X row_dot(const CSRT<MV>& A, int64_t row, int lane, c
 #pragma unroll
     for (int o = TPR / 2; o > 0; o >>= 1) sum = sum + __shfl_down(sum, o, TPR);
   }
-  return sum;
-}
-
-template <int TPR, class MV, class X, class Epi>
-__global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV> A, const X* __restrict__ x, Epi epi) {
-  const int lane = threadIdx.x & (TPR - 1);
-  const int64_t row = (int64_t)blockIdx.x * (256 / TPR) + threadIdx.x / TPR;
-  X sum = row_dot<TPR>(A, row, lane, x);
   if (lane == 0 && row < A.rows) epi(row, sum);
 }
 
+// column-per-lane kernel (K > 1 interleaved columns)
+template <int K, class MV, class X, class Epi>
+__global__ __launch_bounds__(256) void spmm_kernel(CSRT<MV> A, const X* __restrict__ x, Epi epi) {
+  const int c = threadIdx.x & (K - 1);
+  const int64_t row = (int64_t)blockIdx.x * (256 / K) + threadIdx.x / K;
+  if (row >= A.rows) return;
+  X sum = 0;
+  const int s = A.rowptr[row], e = A.rowptr[row + 1];
+  for (int p = s; p < e; ++p) sum = sum + (X)ldv(A.val[p]) * x[(int64_t)A.col[p] * K + c];
+  epi(row * K + c, sum);
+}
+
 template <class MV, class X, class Epi>
-static void launch_spmv_t(const OpView& Av, int tpr, const X* x, Epi epi, hipStream_t s) {
+static void launch_spmv_t(const OpView& Av, int tpr, int K, const X* x, Epi epi, hipStream_t s) {
   if (Av.rows <= 0) return;
   CSRT<MV> A = csr_t<MV>(Av);
-  unsigned nb = blocks_for(Av.rows, 256 / tpr);
-  switch (tpr) {
-    case 1: spmv_kernel<1, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-    case 2: spmv_kernel<2, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-    case 4: spmv_kernel<4, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-    case 8: spmv_kernel<8, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-    case 16: spmv_kernel<16, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-    case 32: spmv_kernel<32, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-    case 64: spmv_kernel<64, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-    default: fail(AIRG_ERR_INTERNAL, "bad lanes-per-row");
+  if (K == 1) {
+    unsigned nb = blocks_for(Av.rows, 256 / tpr);
+    switch (tpr) {
+      case 1: spmv_kernel<1, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 2: spmv_kernel<2, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 4: spmv_kernel<4, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 8: spmv_kernel<8, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 16: spmv_kernel<16, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 32: spmv_kernel<32, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 64: spmv_kernel<64, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      default: fail(AIRG_ERR_INTERNAL, "bad lanes-per-row");
+    }
+  } else {
+    unsigned nb = blocks_for(Av.rows, 256 / K);
+    switch (K) {
+      case 2: spmm_kernel<2, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 4: spmm_kernel<4, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 8: spmm_kernel<8, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 16: spmm_kernel<16, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 32: spmm_kernel<32, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 64: spmm_kernel<64, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      default: fail(AIRG_ERR_INTERNAL, "column count must be a power of two <= 64");
+    }
   }
   AIRG_CHECK_LAUNCH();
 }
 
 // dispatch on the matrix storage type
 template <class X, class Epi>
-static void launch_spmv(const OpView& A, int tpr, const X* x, Epi epi, hipStream_t s) {
+static void launch_spmv(const OpView& A, int tpr, int K, const X* x, Epi epi, hipStream_t s) {
   switch (A.vt) {
-    case VT_F64: launch_spmv_t<double>(A, tpr, x, epi, s); break;
-    case VT_F32: launch_spmv_t<float>(A, tpr, x, epi, s); break;
-    case VT_BF16: launch_spmv_t<bf16>(A, tpr, x, epi, s); break;
+    case VT_F64: launch_spmv_t<double>(A, tpr, K, x, epi, s); break;
+    case VT_F32: launch_spmv_t<float>(A, tpr, K, x, epi, s); break;
+    case VT_BF16: launch_spmv_t<bf16>(A, tpr, K, x, epi, s); break;
     default: fail(AIRG_ERR_INTERNAL, "bad value type");
   }
 }
@@ -92,6 +115,7 @@ int pick_tpr(int64_t rows, int64_t nnz) {
 }
 
 // ------------------------------------------------------------------ epilogues
+// i is the linear index row * K + c of the element.
 template <class X>
 struct EpiStore {
   X* y;
@@ -157,32 +181,33 @@ struct EpiNewtonPair2 {
 };
 
 template <class X>
-void spmv_t(const OpView& A, int tpr, const X* x, X* y, hipStream_t s) {
-  launch_spmv(A, tpr, x, EpiStore<X>{y}, s);
+void spmv_t(const OpView& A, int tpr, int K, const X* x, X* y, hipStream_t s) {
+  launch_spmv(A, tpr, K, x, EpiStore<X>{y}, s);
 }
 template <class X>
-void spmv_horner_t(const OpView& A, int tpr, const X* y, const X* sv, X* out, double a, double b,
-                   bool acc, hipStream_t st) {
-  launch_spmv(A, tpr, y, EpiHorner<X>{out, sv, (X)a, (X)b, acc ? 1 : 0}, st);
+void spmv_horner_t(const OpView& A, int tpr, int K, const X* y, const X* sv, X* out, double a,
+                   double b, bool acc, hipStream_t st) {
+  launch_spmv(A, tpr, K, y, EpiHorner<X>{out, sv, (X)a, (X)b, acc ? 1 : 0}, st);
 }
 template <class X>
-void spmv_restrict_t(const OpView& Z, int tpr, const X* rf, const X* src, X* dst, hipStream_t s) {
-  launch_spmv(Z, tpr, rf, EpiRestrict<X>{src, dst}, s);
+void spmv_restrict_t(const OpView& Z, int tpr, int K, const X* rf, const X* src, X* dst,
+                     hipStream_t s) {
+  launch_spmv(Z, tpr, K, rf, EpiRestrict<X>{src, dst}, s);
 }
 template <class X>
-void newton_real_t(const OpView& A, int tpr, const X* w, X* wn, X* x, double inv, bool first,
-                   double inv_last, hipStream_t s) {
-  launch_spmv(A, tpr, w, EpiNewtonReal<X>{w, wn, x, (X)inv, (X)inv_last, first ? 1 : 0}, s);
+void newton_real_t(const OpView& A, int tpr, int K, const X* w, X* wn, X* x, double inv,
+                   bool first, double inv_last, hipStream_t s) {
+  launch_spmv(A, tpr, K, w, EpiNewtonReal<X>{w, wn, x, (X)inv, (X)inv_last, first ? 1 : 0}, s);
 }
 template <class X>
-void newton_pair1_t(const OpView& A, int tpr, const X* w, X* t, X* x, double c1, double c2,
+void newton_pair1_t(const OpView& A, int tpr, int K, const X* w, X* t, X* x, double c1, double c2,
                     bool first, hipStream_t s) {
-  launch_spmv(A, tpr, w, EpiNewtonPair1<X>{w, t, x, (X)c1, (X)c2, first ? 1 : 0}, s);
+  launch_spmv(A, tpr, K, w, EpiNewtonPair1<X>{w, t, x, (X)c1, (X)c2, first ? 1 : 0}, s);
 }
 template <class X>
-void newton_pair2_t(const OpView& A, int tpr, const X* w, const X* t, X* wn, X* x, double c1,
-                    double c2, double inv_last, hipStream_t s) {
-  launch_spmv(A, tpr, t, EpiNewtonPair2<X>{w, t, wn, x, (X)c1, (X)c2, (X)inv_last}, s);
+void newton_pair2_t(const OpView& A, int tpr, int K, const X* w, const X* t, X* wn, X* x,
+                    double c1, double c2, double inv_last, hipStream_t s) {
+  launch_spmv(A, tpr, K, t, EpiNewtonPair2<X>{w, t, wn, x, (X)c1, (X)c2, (X)inv_last}, s);
 }
 
 template <class X>
@@ -229,59 +254,97 @@ __global__ __launch_bounds__(256) void residual_kernel(CSRT<MV> Aff, CSRT<MV> Af
   }
 }
 
+template <int K, class MV, class X>
+__global__ __launch_bounds__(256) void residual_cols_kernel(CSRT<MV> Aff, CSRT<MV> Afc,
+                                                            const int32_t* __restrict__ cmap,
+                                                            const X* __restrict__ rf,
+                                                            const X* __restrict__ ec,
+                                                            X* __restrict__ ef,
+                                                            X* __restrict__ sv) {
+  const int c = threadIdx.x & (K - 1);
+  const int64_t row = (int64_t)blockIdx.x * (256 / K) + threadIdx.x / K;
+  if (row >= Aff.rows) return;
+  X sum = 0;
+  for (int p = Afc.rowptr[row]; p < Afc.rowptr[row + 1]; ++p)
+    sum = sum + (X)ldv(Afc.val[p]) * ec[(int64_t)Afc.col[p] * K + c];
+  for (int p = Aff.rowptr[row]; p < Aff.rowptr[row + 1]; ++p) {
+    int m = cmap[Aff.col[p]];
+    if (m >= 0) sum = sum + (X)ldv(Aff.val[p]) * ec[(int64_t)m * K + c];
+  }
+  const int m = cmap[row];
+  const int64_t i = row * K + c;
+  ef[i] = m >= 0 ? ec[(int64_t)m * K + c] : X(0);
+  sv[i] = rf[i] - sum;
+}
+
 template <class MV, class X>
-static void residual_t(const OpView& Affv, const OpView& Afcv, const int32_t* cmap, int tpr,
+static void residual_t(const OpView& Affv, const OpView& Afcv, const int32_t* cmap, int tpr, int K,
                        const X* rf, const X* ec, X* ef, X* sv, hipStream_t s) {
   CSRT<MV> a = csr_t<MV>(Affv), b = csr_t<MV>(Afcv);
-  unsigned nb = blocks_for(Affv.rows, 256 / tpr);
-  switch (tpr) {
-    case 1: residual_kernel<1, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-    case 2: residual_kernel<2, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-    case 4: residual_kernel<4, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-    case 8: residual_kernel<8, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-    case 16: residual_kernel<16, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-    case 32: residual_kernel<32, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-    case 64: residual_kernel<64, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-    default: fail(AIRG_ERR_INTERNAL, "bad lanes-per-row");
+  if (K == 1) {
+    unsigned nb = blocks_for(Affv.rows, 256 / tpr);
+    switch (tpr) {
+      case 1: residual_kernel<1, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+      case 2: residual_kernel<2, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+      case 4: residual_kernel<4, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+      case 8: residual_kernel<8, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+      case 16: residual_kernel<16, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+      case 32: residual_kernel<32, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+      case 64: residual_kernel<64, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+      default: fail(AIRG_ERR_INTERNAL, "bad lanes-per-row");
+    }
+  } else {
+    unsigned nb = blocks_for(Affv.rows, 256 / K);
+    switch (K) {
+      case 2: residual_cols_kernel<2, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+      case 4: residual_cols_kernel<4, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+      case 8: residual_cols_kernel<8, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+      case 16: residual_cols_kernel<16, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+      case 32: residual_cols_kernel<32, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+      case 64: residual_cols_kernel<64, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
+      default: fail(AIRG_ERR_INTERNAL, "column count must be a power of two <= 64");
+    }
   }
   AIRG_CHECK_LAUNCH();
 }
 
 template <class X>
-void residual_fpoint_t(const OpView& Aff, const OpView& Afc, const int32_t* cmap, int tpr,
+void residual_fpoint_t(const OpView& Aff, const OpView& Afc, const int32_t* cmap, int tpr, int K,
                        const X* rf, const X* ec, X* ef, X* sv, hipStream_t s) {
   if (Aff.rows <= 0) return;
   if (Aff.vt != Afc.vt) fail(AIRG_ERR_INTERNAL, "mixed value types in the residual");
   switch (Aff.vt) {
-    case VT_F64: residual_t<double>(Aff, Afc, cmap, tpr, rf, ec, ef, sv, s); break;
-    case VT_F32: residual_t<float>(Aff, Afc, cmap, tpr, rf, ec, ef, sv, s); break;
-    case VT_BF16: residual_t<bf16>(Aff, Afc, cmap, tpr, rf, ec, ef, sv, s); break;
+    case VT_F64: residual_t<double>(Aff, Afc, cmap, tpr, K, rf, ec, ef, sv, s); break;
+    case VT_F32: residual_t<float>(Aff, Afc, cmap, tpr, K, rf, ec, ef, sv, s); break;
+    case VT_BF16: residual_t<bf16>(Aff, Afc, cmap, tpr, K, rf, ec, ef, sv, s); break;
     default: fail(AIRG_ERR_INTERNAL, "bad value type");
   }
 }
 
-#define AIRG_INSTANTIATE(X)                                                                      \
-  template void spmv_t<X>(const OpView&, int, const X*, X*, hipStream_t);                        \
-  template void spmv_horner_t<X>(const OpView&, int, const X*, const X*, X*, double, double, bool, \
-                                 hipStream_t);                                                   \
-  template void spmv_restrict_t<X>(const OpView&, int, const X*, const X*, X*, hipStream_t);     \
-  template void newton_real_t<X>(const OpView&, int, const X*, X*, X*, double, bool, double,     \
-                                 hipStream_t);                                                   \
-  template void newton_pair1_t<X>(const OpView&, int, const X*, X*, X*, double, double, bool,    \
-                                  hipStream_t);                                                  \
-  template void newton_pair2_t<X>(const OpView&, int, const X*, const X*, X*, X*, double, double, \
-                                  double, hipStream_t);                                          \
-  template void axpy_first_t<X>(X*, const X*, double, bool, int64_t, hipStream_t);               \
-  template void residual_fpoint_t<X>(const OpView&, const OpView&, const int32_t*, int, const X*,  \
-                                     const X*, X*, X*, hipStream_t);
+#define AIRG_INSTANTIATE(X)                                                                        \
+  template void spmv_t<X>(const OpView&, int, int, const X*, X*, hipStream_t);                     \
+  template void spmv_horner_t<X>(const OpView&, int, int, const X*, const X*, X*, double, double,  \
+                                 bool, hipStream_t);                                               \
+  template void spmv_restrict_t<X>(const OpView&, int, int, const X*, const X*, X*, hipStream_t);  \
+  template void newton_real_t<X>(const OpView&, int, int, const X*, X*, X*, double, bool, double,  \
+                                 hipStream_t);                                                     \
+  template void newton_pair1_t<X>(const OpView&, int, int, const X*, X*, X*, double, double, bool, \
+                                  hipStream_t);                                                    \
+  template void newton_pair2_t<X>(const OpView&, int, int, const X*, const X*, X*, X*, double,     \
+                                  double, double, hipStream_t);                                    \
+  template void axpy_first_t<X>(X*, const X*, double, bool, int64_t, hipStream_t);                 \
+  template void residual_fpoint_t<X>(const OpView&, const OpView&, const int32_t*, int, int,       \
+                                     const X*, const X*, X*, X*, hipStream_t);
 AIRG_INSTANTIATE(double)
 AIRG_INSTANTIATE(float)
 #undef AIRG_INSTANTIATE
 
 // ------------------------------------------------------------------ FP64 wrappers
-void spmv_seq(const CSR& A, const double* x, double* y, hipStream_t s) { spmv_t(opview(A), 1, x, y, s); }
+void spmv_seq(const CSR& A, const double* x, double* y, hipStream_t s) {
+  spmv_t(opview(A), 1, 1, x, y, s);
+}
 void spmv(const CSR& A, int tpr, const double* x, double* y, hipStream_t s) {
-  spmv_t(opview(A), tpr, x, y, s);
+  spmv_t(opview(A), tpr, 1, x, y, s);
 }
 
 // ------------------------------------------------------------------ conversions

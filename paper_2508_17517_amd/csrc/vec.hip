@@ -255,6 +255,94 @@ void launch_gather(double* y, const double* x, const int32_t* perm, int64_t n, h
   AIRG_CHECK_LAUNCH();
 }
 
+// K columns: ys[pos[i] * K + c] = b[c * ldb + i] and back; columns c >= kv
+// are padding (zero in ys, not written back).
+__global__ void scatter_cols_kernel(double* ys, const double* b, int64_t ldb, const int32_t* pos,
+                                    int64_t n, int K, int kv) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * K) return;
+  const int64_t i = t / K;
+  const int c = (int)(t % K);
+  ys[(int64_t)pos[i] * K + c] = c < kv ? b[(int64_t)c * ldb + i] : 0.0;
+}
+__global__ void gather_cols_kernel(double* x, int64_t ldx, const double* xs, const int32_t* pos,
+                                   int64_t n, int K, int kv) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * K) return;
+  const int64_t i = t / K;
+  const int c = (int)(t % K);
+  if (c < kv) x[(int64_t)c * ldx + i] = xs[(int64_t)pos[i] * K + c];
+}
+void launch_scatter_cols(double* ys, const double* b, int64_t ldb, const int32_t* pos, int64_t n,
+                         int K, int kv, hipStream_t s) {
+  if (n <= 0) return;
+  scatter_cols_kernel<<<blocks_for(n * K, kBlock), kBlock, 0, s>>>(ys, b, ldb, pos, n, K, kv);
+  AIRG_CHECK_LAUNCH();
+}
+void launch_gather_cols(double* x, int64_t ldx, const double* xs, const int32_t* pos, int64_t n,
+                        int K, int kv, hipStream_t s) {
+  if (n <= 0) return;
+  gather_cols_kernel<<<blocks_for(n * K, kBlock), kBlock, 0, s>>>(x, ldx, xs, pos, n, K, kv);
+  AIRG_CHECK_LAUNCH();
+}
+
+// Per-column sums of squares of an [n][K] array: block b sums rows
+// b*R .. b*R+R-1 of every column sequentially per thread, the threads of a
+// column combine in a fixed order, then one thread per column adds the block
+// partials in order.
+constexpr int kColRows = 4096;
+__global__ __launch_bounds__(256) void col_sumsq_stage1(const double* x, int64_t n, int K,
+                                                        double* part) {
+  __shared__ double sh[256];
+  const int t = threadIdx.x;
+  const int c = t % K;
+  const int lanes = 256 / K;  // threads per column
+  const int q = t / K;
+  const int64_t r0 = (int64_t)blockIdx.x * kColRows;
+  double acc = 0.0;
+  for (int64_t r = r0 + q; r < r0 + kColRows && r < n; r += lanes) {
+    double v = x[r * K + c];
+    acc = acc + v * v;
+  }
+  sh[t] = acc;
+  __syncthreads();
+  if (t < K) {
+    double s = 0.0;
+    for (int j = 0; j < lanes; ++j) s = s + sh[j * K + t];
+    part[(int64_t)t * gridDim.x + blockIdx.x] = s;
+  }
+}
+__global__ void col_sumsq_stage2(const double* part, int64_t nb, int K, double* out) {
+  int c = threadIdx.x;
+  if (c >= K) return;
+  double s = 0.0;
+  for (int64_t b = 0; b < nb; ++b) s = s + part[(int64_t)c * nb + b];
+  out[c] = s;
+}
+size_t col_sumsq_work_size(int64_t n, int K) {
+  return (size_t)K * (size_t)((n + kColRows - 1) / kColRows + 1);
+}
+void launch_col_sumsq(const double* x, int64_t n, int K, double* out, double* work, hipStream_t s) {
+  if (K < 1 || K > 256 || (256 % K) != 0) fail(AIRG_ERR_INTERNAL, "bad column count");
+  int64_t nb = (n + kColRows - 1) / kColRows;
+  if (nb < 1) nb = 1;
+  col_sumsq_stage1<<<(unsigned)nb, 256, 0, s>>>(x, n, K, work);
+  AIRG_CHECK_LAUNCH();
+  col_sumsq_stage2<<<1, 256, 0, s>>>(work, nb, K, out);
+  AIRG_CHECK_LAUNCH();
+}
+
+__global__ void offset_copy_i32_kernel(int32_t* dst, const int32_t* src, int64_t n, int64_t add) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (int32_t)(src[i] + add);
+}
+void launch_offset_copy_i32(int32_t* dst, const int32_t* src, int64_t n, int64_t add,
+                            hipStream_t s) {
+  if (n <= 0) return;
+  offset_copy_i32_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(dst, src, n, add);
+  AIRG_CHECK_LAUNCH();
+}
+
 // ------------------------------------------------------------------ scans
 // Three phases over chunks of 1024: chunk totals, a single-block exclusive scan
 // of the totals, then per-chunk exclusive scans offset by the chunk prefix.

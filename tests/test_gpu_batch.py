@@ -1,0 +1,177 @@
+"""Batched solves through the C ABI (needs an MI355X).
+
+Two kinds of batching: several right-hand sides of one matrix (K interleaved
+columns, one stacked Krylov process) and several independent problems in one
+block-diagonal hierarchy.  Every column or problem must reach the FP64
+tolerance in its own residual, checked here on the CPU, and agree with the
+exact discrete solution from the oracle's sweep.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from airg_inputs import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+RTOL = 1e-10
+
+
+def _needs_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _rel_residual(A, x, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(b - A @ x) / nb if nb > 0 else np.linalg.norm(x)
+
+
+def _check_columns(p, B, X, infos, single=None):
+    A = p.scipy()
+    for k in range(B.shape[0]):
+        x = X[k]
+        rr = _rel_residual(A, x, B[k])
+        assert infos[k]["converged"] == 1, k
+        assert rr <= RTOL * (1 + 1e-6), (k, rr)
+        u = oracle.sweep_solve(A, B[k], p.level)
+        assert np.linalg.norm(x - u) <= 1e-8 * np.linalg.norm(u), k
+        if single is not None:
+            assert np.linalg.norm(x - single[k]) <= 1e-8 * np.linalg.norm(single[k]), k
+
+
+def test_column_batch_matches_single_solves():
+    _needs_gpu()
+    from paper_2508_17517_amd import Solver
+    p = workloads.fv_random(96, 0.4, True)
+    B = workloads.rhs_batch(p, 11)  # padded to 16 interleaved columns
+    print(f"fv96 perm, 11 columns", flush=True)
+    s = Solver(p.indptr, p.indices, p.data)
+    X, infos = s.solve(torch.from_numpy(B).cuda())
+    single = [s.solve(torch.from_numpy(B[k]).cuda())[0].cpu().numpy() for k in range(11)]
+    _check_columns(p, B, X.cpu().numpy(), infos, single)
+    s.close()
+
+
+def test_column_batch_above_64_is_chunked():
+    _needs_gpu()
+    from paper_2508_17517_amd import Solver
+    p = workloads.fv_random(32, 1.1, True)
+    B = workloads.rhs_batch(p, 70)  # 64 columns, then 6 padded to 8
+    print("fv32 perm, 70 columns", flush=True)
+    s = Solver(p.indptr, p.indices, p.data)
+    X, infos = s.solve(torch.from_numpy(B).cuda())
+    assert len(infos) == 70
+    _check_columns(p, B, X.cpu().numpy(), infos)
+    s.close()
+
+
+def test_column_batch_with_a_zero_column_and_guesses():
+    _needs_gpu()
+    from paper_2508_17517_amd import Solver
+    p = workloads.fv_random(64, 0.9, True)
+    B = workloads.rhs_batch(p, 5)
+    B[2] = 0.0
+    s = Solver(p.indptr, p.indices, p.data)
+    X, infos = s.solve(torch.from_numpy(B).cuda())
+    Xh = X.cpu().numpy()
+    assert float(np.abs(Xh[2]).max()) == 0.0 and infos[2]["converged"] == 1
+    keep = [0, 1, 3, 4]
+    _check_columns(p, B[keep], Xh[keep], [infos[k] for k in keep])
+    # restarting every column from its converged solution needs no iteration
+    X2, infos2 = s.solve(torch.from_numpy(B).cuda(), x=X.clone(), guess=True)
+    assert all(i["iterations"] == 0 and i["converged"] == 1 for i in infos2)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_column_batch_mixed_precision(prec):
+    _needs_gpu()
+    from paper_2508_17517_amd import Solver
+    p = workloads.fv_random(128, 0.3, True)
+    B = workloads.rhs_batch(p, 8)
+    s = Solver(p.indptr, p.indices, p.data, precision=prec)
+    X, infos = s.solve(torch.from_numpy(B).cuda())
+    _check_columns(p, B, X.cpu().numpy(), infos)
+    s.close()
+
+
+def _problems():
+    return [workloads.fv_random(24, 0.2, True, seed=101),
+            workloads.fv_random(40, 1.3, True, seed=102),
+            workloads.fv_random(64, 0.7, True, seed=103),
+            workloads.fv_random(33, 0.4, True, seed=104, ny=17),
+            workloads.fv_random(50, 0.0, False, seed=105),
+            workloads.fv_random(8, 1.0, True, seed=106)]
+
+
+def test_problem_batch_solves_every_problem():
+    _needs_gpu()
+    from paper_2508_17517_amd import BatchSolver
+    probs = _problems()
+    print("batch of", [q.n for q in probs], flush=True)
+    s = BatchSolver([(q.indptr, q.indices, q.data) for q in probs])
+    assert s.n == sum(q.n for q in probs)
+    bs = [torch.from_numpy(q.b).cuda() for q in probs]
+    xs, infos = s.solve(bs)
+    assert len(infos) == len(probs)
+    for q, x, info in zip(probs, xs, infos):
+        A = q.scipy()
+        xh = x.cpu().numpy()
+        assert info["converged"] == 1
+        assert _rel_residual(A, xh, q.b) <= RTOL * (1 + 1e-6)
+        u = oracle.sweep_solve(A, q.b, q.level)
+        assert np.linalg.norm(xh - u) <= 1e-8 * np.linalg.norm(u)
+    # from the converged solutions no iteration is needed
+    xs2, infos2 = s.solve(bs, xs=[x.clone() for x in xs], guess=True)
+    assert all(i["iterations"] == 0 for i in infos2)
+    s.close()
+
+
+def test_problem_batch_of_one_matches_the_single_solver():
+    # one problem: the same matrix, the same hierarchy, the same iterates
+    _needs_gpu()
+    from paper_2508_17517_amd import BatchSolver, Solver
+    p = workloads.fv_random(80, 0.6, True)
+    s1 = Solver(p.indptr, p.indices, p.data)
+    sb = BatchSolver([(p.indptr, p.indices, p.data)])
+    b = torch.from_numpy(p.b).cuda()
+    x1, i1 = s1.solve(b)
+    xb, ib = sb.solve([b])
+    assert ib[0]["iterations"] == i1["iterations"]
+    assert float(torch.linalg.norm(xb[0] - x1) / torch.linalg.norm(x1)) <= 1e-12
+    s1.close()
+    sb.close()
+
+
+def test_batch_argument_errors():
+    _needs_gpu()
+    from paper_2508_17517_amd import AirgError, BatchSolver, Solver, binding
+    probs = _problems()[:2]
+    s = BatchSolver([(q.indptr, q.indices, q.data) for q in probs])
+    lib = binding.load()
+    B = torch.zeros(2, s.n, dtype=torch.float64, device="cuda")
+    X = torch.zeros_like(B)
+    infos = (binding.SolveInfo * 2)()
+    code = lib.airg_solve(s.h, 2, ctypes.c_void_p(B.data_ptr()), s.n,
+                          ctypes.c_void_p(X.data_ptr()), s.n, 0, infos)
+    assert code == -1
+    q = probs[0]
+    single = Solver(q.indptr, q.indices, q.data)
+    vp = ctypes.c_void_p * 1
+    b = torch.from_numpy(q.b).cuda()
+    x = torch.zeros_like(b)
+    code = lib.airg_solve_batch(single.h, vp(b.data_ptr()), vp(x.data_ptr()), 0, infos)
+    assert code == -1
+    with pytest.raises(ValueError):
+        s.solve([b])
+    bad = q.data.copy()
+    bad[0] = np.nan
+    with pytest.raises(AirgError):
+        BatchSolver([(q.indptr, q.indices, q.data), (q.indptr, q.indices, bad)])
+    s.close()
+    single.close()
