@@ -117,15 +117,26 @@ def fv_advection(nx, theta, g_west, g_south, perm_seed=None, ny=None):
         order = np.argsort(keys, kind="stable").astype(np.int64)
         inv = np.empty(n, dtype=np.int64)
         inv[order] = np.arange(n, dtype=np.int64)
-        # row p of the permuted system is grid row order[p]; relabel its columns
-        # and sort each row's (at most three) slots, absent slots last
-        cols, vals, dvals, mask = cols[order], vals[order], dvals[order], mask[order]
-        cols = np.where(mask, inv[np.where(mask, cols, 0)], np.iinfo(np.int64).max)
-        srt = np.argsort(cols, axis=1, kind="stable")
-        cols = np.take_along_axis(cols, srt, axis=1)
-        vals = np.take_along_axis(vals, srt, axis=1)
-        dvals = np.take_along_axis(dvals, srt, axis=1)
-        mask = np.take_along_axis(mask, srt, axis=1)
+        # row p of the permuted system is grid cell order[p]: its (at most three)
+        # columns are relabelled, then put in ascending order by a three-element
+        # sorting network that carries each entry's slot (absent slots last)
+        big = np.iinfo(np.int64).max
+        msk = mask[order]
+        c = [np.full(n, big, dtype=np.int64) for _ in range(3)]
+        for t, off in ((0, nx), (1, 1)):
+            sel = msk[:, t]
+            c[t][sel] = inv[order[sel] - off]
+        c[2] = np.arange(n, dtype=np.int64)
+        slot = [np.full(n, t, dtype=np.int8) for t in range(3)]
+        for a_, b_ in ((0, 1), (1, 2), (0, 1)):
+            sw = c[a_] > c[b_]
+            c[a_], c[b_] = np.where(sw, c[b_], c[a_]), np.where(sw, c[a_], c[b_])
+            slot[a_], slot[b_] = np.where(sw, slot[b_], slot[a_]), np.where(sw, slot[a_], slot[b_])
+        cols = np.stack(c, axis=1)
+        slot = np.stack(slot, axis=1)
+        mask = cols != big
+        vals = vals[0][slot]
+        dvals = dvals[0][slot]
         b = b[order]
         db = db[order]
         level = level[order]

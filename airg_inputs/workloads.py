@@ -71,3 +71,13 @@ def batch_shapes(count, seed=SEED):
     sides = np.array(BATCH_SIDES)[np.minimum((u * 4).astype(np.int64), 3)]
     theta = rng.uniform(seed, rng.BATCH_THETA, 0, count) * (0.5 * math.pi)
     return sides, theta
+
+
+def batch_problems(count, seed=SEED, sides=None):
+    """``count`` independent FV problems with the shapes of ``batch_shapes``; problem q
+    draws its inflow values and permutation from seed + 1 + q.  ``sides`` (optional)
+    overrides the drawn grid sides, e.g. to shrink a batch for tests."""
+    s, theta = batch_shapes(count, seed)
+    if sides is not None:
+        s = np.asarray(sides)
+    return [fv_random(int(s[q]), float(theta[q]), True, seed=seed + 1 + q) for q in range(count)]

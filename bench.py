@@ -18,6 +18,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E, published peak
+METRIC = "AIRG solve DOF/s to rel-res 1e-10 + poly-SpMV HBM GB/s, FP64 vs mixed"
 
 WORKLOADS = {
     # name: (grid side, theta, permuted)
@@ -47,6 +48,91 @@ def cpu_baseline(sample_side=512):
                       f"{os.cpu_count()} cores, the oracle's sparse kernels run on one thread"}
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Read + write bandwidth of a plain device copy of nbytes (the calibration
+    kernel for the HBM byte counters)."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def _timed(fn, warmup, steps):
+    import torch
+    for _ in range(warmup):
+        r = fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, r
+
+
+def batched_legs(a, p, s64, value64, ip, ix, dv):
+    """Batching with FP32 storage in the V-cycle (FP64 FGMRES): many right-hand
+    sides of the big matrix as interleaved columns, and many independent
+    problems of uneven sizes in one block-diagonal hierarchy.  Every column and
+    problem must reach the FP64 1e-10 true relative residual."""
+    import torch
+    from airg_inputs import workloads
+    from paper_2508_17517_amd import BatchSolver, Solver, binding
+    res = {}
+    k = a.batch_cols
+    print(f"bench: batch: {k} right-hand sides, FP32 V-cycle", file=sys.stderr, flush=True)
+    B = torch.from_numpy(workloads.rhs_batch(p, k)).cuda()
+    sm = Solver(ip, ix, dv, precision=binding.FP32)
+    X = torch.zeros_like(B)
+    dt, (X, infos) = _timed(lambda: sm.solve(B, X), 1, max(1, min(a.steps, 3)))
+    assert all(i["converged"] == 1 and i["rel_residual"] <= 1e-10 for i in infos), infos
+    # the same columns one at a time in FP64, for the error of each column
+    xs = torch.zeros_like(B[0])
+    err = 0.0
+    for c in (0, k - 1):
+        xs, _ = s64.solve(B[c], xs)
+        err = max(err, float(torch.linalg.norm(X[c] - xs) / torch.linalg.norm(xs)))
+    v = p.n * k / dt
+    res["columns"] = {"rhs": k, "value": v, "unit": "DOF/s", "ms_per_step": 1e3 * dt,
+                      "iterations": max(i["iterations"] for i in infos),
+                      "max_rel_residual": max(i["rel_residual"] for i in infos),
+                      "rel_diff_vs_fp64_single": err, "speedup_vs_fp64": v / value64}
+    print(f"bench: columns {res['columns']}", file=sys.stderr, flush=True)
+    sm.close()
+    del B, X
+    q = a.batch_problems
+    print(f"bench: batch: {q} problems, FP32 V-cycle (generating)", file=sys.stderr, flush=True)
+    probs = workloads.batch_problems(q)
+    ntot = sum(pr.n for pr in probs)
+    mats = [(torch.from_numpy(pr.indptr).cuda(), torch.from_numpy(pr.indices).cuda(),
+             torch.from_numpy(pr.data).cuda()) for pr in probs]
+    bs = [torch.from_numpy(pr.b).cuda() for pr in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sb = BatchSolver(mats, precision=binding.FP32)
+    torch.cuda.synchronize()
+    setup_b = time.perf_counter() - t0
+    xs = [torch.zeros_like(b_) for b_ in bs]
+    dt, (xs, infos) = _timed(lambda: sb.solve(bs, xs), 1, max(1, min(a.steps, 3)))
+    assert all(i["converged"] == 1 and i["rel_residual"] <= 1e-10 for i in infos), infos
+    st = sb.stats()
+    v = ntot / dt
+    res["problems"] = {"problems": q, "dofs": ntot, "value": v, "unit": "DOF/s",
+                       "ms_per_step": 1e3 * dt, "iterations": infos[0]["iterations"],
+                       "max_rel_residual": max(i["rel_residual"] for i in infos),
+                       "levels": st["levels"], "setup_s": round(setup_b, 3),
+                       "speedup_vs_fp64": v / value64}
+    print(f"bench: problems {res['problems']}", file=sys.stderr, flush=True)
+    sb.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +143,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-cols", type=int, default=64)
+    ap.add_argument("--batch-problems", type=int, default=48)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the solver has no multi-GPU "
@@ -107,7 +196,7 @@ def main():
     its = infos[-1]["iterations"]
     value = p.n * a.steps / dt
     out = {
-        "metric": "AIRG solve DOF/s to rel-res 1e-10",
+        "metric": METRIC,
         "value": value,
         "unit": "DOF/s",
         "n_gpus": 1,
@@ -176,6 +265,10 @@ def main():
                                   "poly_gbps": ktm["bytes_per_launch"] / (ktm["avg_launch_ms"] * 1e-3) / 1e9}
             print(f"bench: {name}: {out['mixed'][name]}", file=sys.stderr, flush=True)
             sm.close()
+    if not a.no_batch:
+        out["batched"] = batched_legs(a, p, s, value, ip, ix, dv)
+    out["hbm_copy_gbps"] = copy_bandwidth()
+    print(f"bench: copy kernel {out['hbm_copy_gbps']:.1f} GB/s", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.cpu_sample)
