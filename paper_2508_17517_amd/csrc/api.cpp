@@ -338,7 +338,18 @@ int airg_export_level(airg_handle h, int level, airg_level_arrays* o) {
     const Level& L = c->H.levels[level];
     hipStream_t s = c->H.s;
     copy_out(o->state, L.state, L.coarsest ? 0 : L.n, s, "state");
-    copy_csr_out(o->a_rowptr, o->a_col, o->a_val, level_matrix(c, level), s, "level matrix");
+    if (L.coarsest && level > 0 && L.a_permuted) {
+      // the coarsest matrix is kept in its solve order: undo the permutation
+      DBuf<int32_t> inv(L.n, s);
+      invert_perm(L.pos.get(), L.n, inv.get(), s);
+      CSR A;
+      permute_rows(L.A, inv.get(), inv.get(), L.n, A, s);
+      sort_rows(A, s);
+      copy_csr_out(o->a_rowptr, o->a_col, o->a_val, &A, s, "level matrix");
+      AIRG_HIP(hipStreamSynchronize(s));
+    } else {
+      copy_csr_out(o->a_rowptr, o->a_col, o->a_val, level_matrix(c, level), s, "level matrix");
+    }
     if (!L.coarsest) {
       // A_ff in setup numbering: the solve copy unless the solve order differs
       const CSR* ff = L.Aff_nat.rowptr.get() ? &L.Aff_nat

@@ -437,16 +437,12 @@ void finalize_hierarchy(Hierarchy& H) {
   hipStream_t s = H.s;
   const int nl = (int)H.levels.size();
   const bool order = H.p.locality_order != 0;
-  // locality keys, top down: breadth-first distance on A_0 + A_0^T from a far
-  // node, inherited by the coarse points
+  // locality keys, top down: two breadth-first distances on A_0 + A_0^T,
+  // inherited by the coarse points
   std::vector<DBuf<int32_t>> key(nl);
-  if (order && nl > 1) {
+  if (order) {
     key[0].alloc(H.n0, s);
-    CSR At;
-    transpose(H.A0, At, s);
-    bfs_levels(H.A0, At, 0, key[0].get(), s);
-    const int64_t src = far_node(key[0].get(), H.n0, s);
-    bfs_levels(H.A0, At, src, key[0].get(), s);
+    locality_keys(H.A0, key[0].get(), s);
     for (int l = 0; l + 1 < nl; ++l) {
       Level& L = H.levels[l];
       DBuf<int64_t> clist(L.nC, s);
@@ -455,9 +451,19 @@ void finalize_hierarchy(Hierarchy& H) {
       inherit_keys(key[l].get(), clist.get(), L.nC, key[l + 1].get(), s);
     }
   }
+  // the coarsest level: ordered by key too, its matrix permuted to match
   Level& Lc = H.levels.back();
   Lc.pos.alloc(Lc.n, s);
-  launch_iota(Lc.pos.get(), Lc.n, s);
+  if (order) {
+    rank_points(key[nl - 1].get(), Lc.n, Lc.pos.get(), s);
+    CSR Ap;
+    permute_rows(Lc.A, Lc.pos.get(), Lc.pos.get(), Lc.n, Ap, s);
+    sort_rows(Ap, s);
+    Lc.A = std::move(Ap);
+    Lc.a_permuted = true;
+  } else {
+    launch_iota(Lc.pos.get(), Lc.n, s);
+  }
   for (int l = nl - 2; l >= 0; --l) {
     Level& L = H.levels[l];
     Level& N = H.levels[l + 1];
@@ -474,6 +480,11 @@ void finalize_hierarchy(Hierarchy& H) {
       L.Aff = std::move(Aff);
       permute_rows(L.Afc_nat, frank.get(), N.pos.get(), L.nC, L.Afc, s);
       permute_rows(L.Z_nat, N.pos.get(), frank.get(), L.nF, L.Z, s);
+      // ascending columns in the solve numbering: neighbouring lanes gather
+      // neighbouring elements
+      sort_rows(L.Aff, s);
+      sort_rows(L.Afc, s);
+      sort_rows(L.Z, s);
       launch_remap_ranked(L.cmap_nat.get(), N.pos.get(), frank.get(), L.nF, L.cmap.get(), s);
     } else {
       launch_nested_pos(L.state.get(), L.fidx.get(), L.cidx.get(), L.nF, N.pos.get(), L.n,
@@ -492,6 +503,7 @@ void finalize_hierarchy(Hierarchy& H) {
     off += L.nF;
   }
   permute_rows(H.A0, H.levels[0].pos.get(), H.levels[0].pos.get(), H.n0, H.Aperm, s);
+  if (order) sort_rows(H.Aperm, s);
   H.tpr_top = pick_tpr(H.Aperm.rows, H.Aperm.nnz);
   // value copies in the storage precision of the mixed-precision V-cycle
   if (H.p.precision != AIRG_FP64) {

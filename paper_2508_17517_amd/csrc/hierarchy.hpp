@@ -41,6 +41,8 @@ struct Level {
   std::vector<double> alpha;
   std::vector<cplx> roots;
   int tpr_ff = 1, tpr_fc = 1, tpr_z = 1, tpr_a = 1;
+  // the coarsest level's A is stored in its solve order (pos) when true
+  bool a_permuted = false;
 
   // low-precision copies of the solve operators' values (FP32 or BF16 storage)
   DBuf<float> ff32, fc32, z32, a32;

@@ -171,6 +171,15 @@ int64_t far_node(const int32_t* level, int64_t n, hipStream_t s);
 // rank[f] = position of F point f ordered by (key, F index).
 void rank_f_points(const int8_t* state, const int64_t* fidx, const int32_t* key, int64_t n,
                    int64_t nf, int32_t* rank, hipStream_t s);
+// Locality key of every node of A: with d1 the BFS distance from a far node
+// and d2 the distance from an end of d1's middle band, key = d1 * (max d2 + 1)
+// + d2 (d1 alone if that overflows 31 bits).  On a structured grid this
+// orders by anti-diagonal, then by position along it.
+void locality_keys(const CSR& A, int32_t* key, hipStream_t s);
+// rank[i] = position of node i ordered by (key, i).
+void rank_points(const int32_t* key, int64_t n, int32_t* rank, hipStream_t s);
+// inv[pos[i]] = i
+void invert_perm(const int32_t* pos, int64_t n, int32_t* inv, hipStream_t s);
 // out[c] = key[clist[c]]
 void inherit_keys(const int32_t* key, const int64_t* clist, int64_t nc, int32_t* out, hipStream_t s);
 // pos[i] = frank[fidx[i]] for F points, nF + pos_next[cidx[i]] for C points.
@@ -214,6 +223,8 @@ void build_p(const int8_t* state, const int64_t* fidx, const int64_t* cidx, cons
 // is preserved.
 void permute_rows(const CSR& A, const int32_t* newrow, const int32_t* colmap, int64_t out_cols,
                   CSR& out, hipStream_t s);
+// Sort the entries of every row by column (insertion sort per row).
+void sort_rows(CSR& A, hipStream_t s);
 // Explicit transpose with ascending columns.
 void transpose(const CSR& A, CSR& At, hipStream_t s);
 // Deep copy of a device CSR.

@@ -2,11 +2,12 @@
 //
 // The hierarchy is built in the input's numbering (which may be a random
 // permutation).  For the solve only the block structure [F_l | C_l] of the
-// nested numbering matters, so the F points of every level may be placed in
-// any order; placing them by breadth-first distance on the graph of A + A^T
-// (ties by index) turns the gathers of every SpMV into accesses within a few
-// BFS bands, which stay in cache.  Coarse points inherit the distance of the
-// fine point they are.
+// nested numbering matters, so the F points of every level, and the points of
+// the coarsest level, may be placed in any order.  They are placed by a key
+// made of two breadth-first distances on the graph of A + A^T (ties by
+// index), which keeps the gathers of every SpMV within a few neighbouring
+// stretches of the vector that stay in cache.  Coarse points inherit the key
+// of the fine point they are.
 #include "kernels.hpp"
 
 namespace airg {
@@ -99,6 +100,62 @@ int64_t far_node(const int32_t* level, int64_t n, hipStream_t s) {
   return (int64_t)(0xffffffffull - (k & 0xffffffffull));
 }
 
+// Smallest index on a given level.
+__global__ void band_first_kernel(const int32_t* level, int64_t n, int32_t target,
+                                  unsigned long long* first) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && level[i] == target) atomicMin(first, (unsigned long long)i);
+}
+// Node of largest dist among the nodes with band[i] == target (ties: smallest index).
+__global__ void far_in_band_kernel(const int32_t* dist, const int32_t* band, int64_t n,
+                                   int32_t target, unsigned long long* best) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || band[i] != target) return;
+  unsigned long long k =
+      ((unsigned long long)(uint32_t)dist[i] << 32) | (0xffffffffull - (uint64_t)i);
+  atomicMax(best, k);
+}
+__global__ void combine_keys_kernel(int32_t* d1, const int32_t* d2, int64_t n, int64_t mult) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d1[i] = (int32_t)((int64_t)d1[i] * mult + d2[i]);
+}
+
+void locality_keys(const CSR& A, int32_t* key, hipStream_t s) {
+  const int64_t n = A.rows;
+  if (n <= 0) return;
+  const unsigned nb = blocks_for(n, kBlock);
+  CSR At;
+  transpose(A, At, s);
+  DBuf<int32_t> d2(n, s);
+  DBuf<unsigned long long> red(1, s);
+  // d1: distance from a far node (the node farthest from node 0)
+  bfs_levels(A, At, 0, key, s);
+  bfs_levels(A, At, far_node(key, n, s), key, s);
+  const int64_t f1 = far_node(key, n, s);
+  const int32_t d1max = fetch(key + f1, s);
+  if (d1max < 2) return;
+  // an end of the middle band: the band node farthest from some band node
+  const int32_t mid = d1max / 2;
+  unsigned long long first = ~0ull;
+  red.from_host(&first, 1);
+  band_first_kernel<<<nb, kBlock, 0, s>>>(key, n, mid, red.get());
+  AIRG_CHECK_LAUNCH();
+  first = fetch(red.get(), s);
+  if (first == ~0ull) return;
+  bfs_levels(A, At, (int64_t)first, d2.get(), s);
+  unsigned long long zero = 0;
+  red.from_host(&zero, 1);
+  far_in_band_kernel<<<nb, kBlock, 0, s>>>(d2.get(), key, n, mid, red.get());
+  AIRG_CHECK_LAUNCH();
+  const int64_t f2 = (int64_t)(0xffffffffull - (fetch(red.get(), s) & 0xffffffffull));
+  bfs_levels(A, At, f2, d2.get(), s);
+  const int32_t d2max = fetch(d2.get() + far_node(d2.get(), n, s), s);
+  const int64_t mult = (int64_t)d2max + 1;
+  if (((int64_t)d1max + 1) * mult >= (int64_t)1 << 31) return;
+  combine_keys_kernel<<<nb, kBlock, 0, s>>>(key, d2.get(), n, mult);
+  AIRG_CHECK_LAUNCH();
+}
+
 // ------------------------------------------------------------------ ranking
 __global__ void make_keys_kernel(const int8_t* state, const int64_t* fidx, const int32_t* key,
                                  int64_t n, uint64_t* out) {
@@ -122,6 +179,14 @@ __global__ void bitonic_step_kernel(uint64_t* keys, int64_t P, int64_t j, int64_
     keys[l] = a;
   }
 }
+static void bitonic_sort(uint64_t* keys, int64_t P, hipStream_t s) {
+  const unsigned nb = blocks_for(P, kBlock);
+  for (int64_t k = 2; k <= P; k <<= 1)
+    for (int64_t j = k >> 1; j > 0; j >>= 1) {
+      bitonic_step_kernel<<<nb, kBlock, 0, s>>>(keys, P, j, k);
+      AIRG_CHECK_LAUNCH();
+    }
+}
 __global__ void rank_kernel(const uint64_t* sorted, int64_t nf, int32_t* rank) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r < nf) rank[sorted[r] & 0xffffffffull] = (int32_t)r;
@@ -141,13 +206,37 @@ void rank_f_points(const int8_t* state, const int64_t* fidx, const int32_t* key,
     pad_keys_kernel<<<blocks_for(P - nf, kBlock), kBlock, 0, s>>>(keys.get(), nf, P);
     AIRG_CHECK_LAUNCH();
   }
-  const unsigned nb = blocks_for(P, kBlock);
-  for (int64_t k = 2; k <= P; k <<= 1)
-    for (int64_t j = k >> 1; j > 0; j >>= 1) {
-      bitonic_step_kernel<<<nb, kBlock, 0, s>>>(keys.get(), P, j, k);
-      AIRG_CHECK_LAUNCH();
-    }
+  bitonic_sort(keys.get(), P, s);
   rank_kernel<<<blocks_for(nf, kBlock), kBlock, 0, s>>>(keys.get(), nf, rank);
+  AIRG_CHECK_LAUNCH();
+}
+
+__global__ void point_keys_kernel(const int32_t* key, int64_t n, uint64_t* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = ((uint64_t)(uint32_t)key[i] << 32) | (uint64_t)i;
+}
+void rank_points(const int32_t* key, int64_t n, int32_t* rank, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t P = 1;
+  while (P < n) P <<= 1;
+  DBuf<uint64_t> keys(P, s);
+  point_keys_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(key, n, keys.get());
+  AIRG_CHECK_LAUNCH();
+  if (P > n) {
+    pad_keys_kernel<<<blocks_for(P - n, kBlock), kBlock, 0, s>>>(keys.get(), n, P);
+    AIRG_CHECK_LAUNCH();
+  }
+  bitonic_sort(keys.get(), P, s);
+  rank_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(keys.get(), n, rank);
+  AIRG_CHECK_LAUNCH();
+}
+__global__ void invert_perm_kernel(const int32_t* pos, int64_t n, int32_t* inv) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) inv[pos[i]] = (int32_t)i;
+}
+void invert_perm(const int32_t* pos, int64_t n, int32_t* inv, hipStream_t s) {
+  if (n <= 0) return;
+  invert_perm_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(pos, n, inv);
   AIRG_CHECK_LAUNCH();
 }
 

@@ -527,6 +527,13 @@ __global__ void row_sort_kernel(int64_t rows, const int32_t* rowptr, int32_t* co
   }
 }
 
+void sort_rows(CSR& A, hipStream_t s) {
+  if (A.rows <= 0 || A.nnz <= 0) return;
+  row_sort_kernel<<<blocks_for(A.rows, kBlock), kBlock, 0, s>>>(A.rows, A.rowptr.get(), A.col.get(),
+                                                                A.val.get());
+  AIRG_CHECK_LAUNCH();
+}
+
 void transpose(const CSR& A, CSR& At, hipStream_t s) {
   const int64_t m = A.cols;
   DBuf<int64_t> cnt(m, s), off;

@@ -33,33 +33,74 @@ static CSRT<MV> csr_t(const OpView& A) {
   return {A.rowptr, A.col, (const MV*)A.val, A.rows};
 }
 
+// Entries in flight per lane: every lane first loads the column indices and
+// values of its next U entries, then their x values, and only then adds them,
+// so a row costs two dependent memory round trips per U entries instead of
+// two per entry.  The additions keep the lane's ascending entry order.
+template <int TPR>
+constexpr int unroll_for() { return TPR >= 16 ? 8 : 4; }
+
+// Column index transforms for row_dot: the CSR column itself, or the column
+// looked up in a map (entries whose mapped index is negative are skipped).
+struct IdxPlain {
+  __device__ __forceinline__ int operator()(int c) const { return c; }
+};
+struct IdxMap {
+  const int32_t* __restrict__ m;
+  __device__ __forceinline__ int operator()(int c) const { return m[c]; }
+};
+
+// sum over entries p = s + lane, s + lane + TPR, ... < e of val[p] * x[idx(col[p]) * K + c]
+template <int TPR, int U, int K, class MV, class X, class Idx>
+__device__ __forceinline__ X row_dot(const CSRT<MV>& A, int s, int e, int lane, const X* __restrict__ x,
+                                     int c, Idx idx, X sum) {
+  for (int p0 = s + lane; p0 < e; p0 += TPR * U) {
+    int col[U];
+    X v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = p0 + u * TPR;
+      col[u] = p < e ? idx(A.col[p]) : -1;
+      v[u] = p < e ? (X)ldv(A.val[p]) : X(0);
+    }
+    X xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = col[u] >= 0 ? x[(int64_t)col[u] * K + c] : X(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (col[u] >= 0) sum = sum + v[u] * xv[u];
+  }
+  return sum;
+}
+
 // lanes-per-row kernel (K = 1)
 template <int TPR, class MV, class X, class Epi>
 __global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV> A, const X* __restrict__ x, Epi epi) {
   const int lane = threadIdx.x & (TPR - 1);
   const int64_t row = (int64_t)blockIdx.x * (256 / TPR) + threadIdx.x / TPR;
+  const bool live = row < A.rows;
+  typename Epi::Pre pre{};
+  if (live && lane == 0) pre = epi.pre(row);
   X sum = 0;
-  if (row < A.rows) {
-    const int s = A.rowptr[row], e = A.rowptr[row + 1];
-    for (int p = s + lane; p < e; p += TPR) sum = sum + (X)ldv(A.val[p]) * x[A.col[p]];
-  }
+  if (live) sum = row_dot<TPR, unroll_for<TPR>(), 1>(A, A.rowptr[row], A.rowptr[row + 1], lane, x, 0,
+                                                      IdxPlain{}, sum);
   if constexpr (TPR > 1) {
 #pragma unroll
     for (int o = TPR / 2; o > 0; o >>= 1) sum = sum + __shfl_down(sum, o, TPR);
   }
-  if (lane == 0 && row < A.rows) epi(row, sum);
+  if (lane == 0 && live) epi(row, sum, pre);
 }
 
-// column-per-lane kernel (K > 1 interleaved columns)
+// column-per-lane kernel (K > 1 interleaved columns): each column's row sum
+// runs left to right from 0, as the TPR = 1 kernel does
 template <int K, class MV, class X, class Epi>
 __global__ __launch_bounds__(256) void spmm_kernel(CSRT<MV> A, const X* __restrict__ x, Epi epi) {
   const int c = threadIdx.x & (K - 1);
   const int64_t row = (int64_t)blockIdx.x * (256 / K) + threadIdx.x / K;
   if (row >= A.rows) return;
-  X sum = 0;
-  const int s = A.rowptr[row], e = A.rowptr[row + 1];
-  for (int p = s; p < e; ++p) sum = sum + (X)ldv(A.val[p]) * x[(int64_t)A.col[p] * K + c];
-  epi(row * K + c, sum);
+  const typename Epi::Pre pre = epi.pre(row * K + c);
+  const X sum = row_dot<1, 4, K>(A, A.rowptr[row], A.rowptr[row + 1], 0, x, c, IdxPlain{}, X(0));
+  epi(row * K + c, sum, pre);
 }
 
 template <class MV, class X, class Epi>
@@ -106,20 +147,25 @@ static void launch_spmv(const OpView& A, int tpr, int K, const X* x, Epi epi, hi
 
 int pick_tpr(int64_t rows, int64_t nnz) {
   double avg = rows > 0 ? (double)nnz / (double)rows : 0.0;
-  if (avg < 4.0) return 1;
-  if (avg < 8.0) return 2;
-  if (avg < 16.0) return 4;
-  if (avg < 32.0) return 8;
-  if (avg < 64.0) return 16;
+  if (avg <= 4.0) return 1;
+  if (avg <= 8.0) return 2;
+  if (avg <= 16.0) return 4;
+  if (avg <= 32.0) return 8;
+  if (avg <= 96.0) return 16;
   return 32;
 }
 
 // ------------------------------------------------------------------ epilogues
-// i is the linear index row * K + c of the element.
+// i is the linear index row * K + c of the element.  pre(i) loads what the
+// epilogue reads of the element before the row sum starts, so those loads
+// overlap the row's gathers.
+struct NoPre {};
 template <class X>
 struct EpiStore {
   X* y;
-  __device__ void operator()(int64_t i, X t) const { y[i] = t; }
+  using Pre = NoPre;
+  __device__ Pre pre(int64_t) const { return {}; }
+  __device__ void operator()(int64_t i, X t, const Pre&) const { y[i] = t; }
 };
 template <class X>
 struct EpiHorner {
@@ -127,16 +173,24 @@ struct EpiHorner {
   const X* sv;
   X a, b;
   int acc;
-  __device__ void operator()(int64_t i, X t) const {
-    X v = a * t + b * sv[i];
-    out[i] = acc ? out[i] + v : v;
+  struct Pre {
+    X s, o;
+  };
+  __device__ Pre pre(int64_t i) const { return {sv[i], acc ? out[i] : X(0)}; }
+  __device__ void operator()(int64_t i, X t, const Pre& p) const {
+    X v = a * t + b * p.s;
+    out[i] = acc ? p.o + v : v;
   }
 };
 template <class X>
 struct EpiRestrict {
   const X* src;
   X* dst;
-  __device__ void operator()(int64_t i, X t) const { dst[i] = src[i] + t; }
+  struct Pre {
+    X s;
+  };
+  __device__ Pre pre(int64_t i) const { return {src[i]}; }
+  __device__ void operator()(int64_t i, X t, const Pre& p) const { dst[i] = p.s + t; }
 };
 template <class X>
 struct EpiNewtonReal {
@@ -145,10 +199,13 @@ struct EpiNewtonReal {
   X* x;
   X inv, inv_last;
   int first;
-  __device__ void operator()(int64_t i, X t) const {
-    X wi = w[i];
-    X xi = (first ? X(0) : x[i]) + wi * inv;
-    X wni = wi - t * inv;
+  struct Pre {
+    X w, x;
+  };
+  __device__ Pre pre(int64_t i) const { return {w[i], first ? X(0) : x[i]}; }
+  __device__ void operator()(int64_t i, X t, const Pre& p) const {
+    X xi = p.x + p.w * inv;
+    X wni = p.w - t * inv;
     wn[i] = wni;
     if (inv_last != X(0)) xi = xi + wni * inv_last;
     x[i] = xi;
@@ -161,9 +218,13 @@ struct EpiNewtonPair1 {
   X* x;
   X c1, c2;
   int first;
-  __device__ void operator()(int64_t i, X t) const {
+  struct Pre {
+    X w, x;
+  };
+  __device__ Pre pre(int64_t i) const { return {w[i], first ? X(0) : x[i]}; }
+  __device__ void operator()(int64_t i, X t, const Pre& p) const {
     tv[i] = t;
-    x[i] = (first ? X(0) : x[i]) + (c1 * w[i] - c2 * t);
+    x[i] = p.x + (c1 * p.w - c2 * t);
   }
 };
 template <class X>
@@ -173,10 +234,14 @@ struct EpiNewtonPair2 {
   X* wn;
   X* x;
   X c1, c2, inv_last;
-  __device__ void operator()(int64_t i, X u) const {
-    X wni = w[i] - c1 * tv[i] + c2 * u;
+  struct Pre {
+    X w, t, x;
+  };
+  __device__ Pre pre(int64_t i) const { return {w[i], tv[i], inv_last != X(0) ? x[i] : X(0)}; }
+  __device__ void operator()(int64_t i, X u, const Pre& p) const {
+    X wni = p.w - c1 * p.t + c2 * u;
     wn[i] = wni;
-    if (inv_last != X(0)) x[i] = x[i] + wni * inv_last;
+    if (inv_last != X(0)) x[i] = p.x + wni * inv_last;
   }
 };
 
@@ -230,27 +295,28 @@ __global__ __launch_bounds__(256) void residual_kernel(CSRT<MV> Aff, CSRT<MV> Af
                                                        const X* __restrict__ rf,
                                                        const X* __restrict__ ec,
                                                        X* __restrict__ ef, X* __restrict__ sv) {
+  constexpr int U = unroll_for<TPR>();
   const int lane = threadIdx.x & (TPR - 1);
   const int64_t row = (int64_t)blockIdx.x * (256 / TPR) + threadIdx.x / TPR;
+  const bool live = row < Aff.rows;
+  X r = 0, e = 0;
+  if (live && lane == 0) {
+    r = rf[row];
+    const int m = cmap[row];
+    e = m >= 0 ? ec[m] : X(0);
+  }
   X sum = 0;
-  if (row < Aff.rows) {
-    int s = Afc.rowptr[row], e = Afc.rowptr[row + 1];
-    for (int p = s + lane; p < e; p += TPR) sum = sum + (X)ldv(Afc.val[p]) * ec[Afc.col[p]];
-    s = Aff.rowptr[row];
-    e = Aff.rowptr[row + 1];
-    for (int p = s + lane; p < e; p += TPR) {
-      int c = cmap[Aff.col[p]];
-      if (c >= 0) sum = sum + (X)ldv(Aff.val[p]) * ec[c];
-    }
+  if (live) {
+    sum = row_dot<TPR, U, 1>(Afc, Afc.rowptr[row], Afc.rowptr[row + 1], lane, ec, 0, IdxPlain{}, sum);
+    sum = row_dot<TPR, U, 1>(Aff, Aff.rowptr[row], Aff.rowptr[row + 1], lane, ec, 0, IdxMap{cmap}, sum);
   }
   if constexpr (TPR > 1) {
 #pragma unroll
     for (int o = TPR / 2; o > 0; o >>= 1) sum = sum + __shfl_down(sum, o, TPR);
   }
-  if (lane == 0 && row < Aff.rows) {
-    int c = cmap[row];
-    ef[row] = c >= 0 ? ec[c] : X(0);
-    sv[row] = rf[row] - sum;
+  if (lane == 0 && live) {
+    ef[row] = e;
+    sv[row] = r - sum;
   }
 }
 
@@ -264,17 +330,14 @@ __global__ __launch_bounds__(256) void residual_cols_kernel(CSRT<MV> Aff, CSRT<M
   const int c = threadIdx.x & (K - 1);
   const int64_t row = (int64_t)blockIdx.x * (256 / K) + threadIdx.x / K;
   if (row >= Aff.rows) return;
-  X sum = 0;
-  for (int p = Afc.rowptr[row]; p < Afc.rowptr[row + 1]; ++p)
-    sum = sum + (X)ldv(Afc.val[p]) * ec[(int64_t)Afc.col[p] * K + c];
-  for (int p = Aff.rowptr[row]; p < Aff.rowptr[row + 1]; ++p) {
-    int m = cmap[Aff.col[p]];
-    if (m >= 0) sum = sum + (X)ldv(Aff.val[p]) * ec[(int64_t)m * K + c];
-  }
-  const int m = cmap[row];
   const int64_t i = row * K + c;
-  ef[i] = m >= 0 ? ec[(int64_t)m * K + c] : X(0);
-  sv[i] = rf[i] - sum;
+  const X r = rf[i];
+  const int m = cmap[row];
+  const X e = m >= 0 ? ec[(int64_t)m * K + c] : X(0);
+  X sum = row_dot<1, 4, K>(Afc, Afc.rowptr[row], Afc.rowptr[row + 1], 0, ec, c, IdxPlain{}, X(0));
+  sum = row_dot<1, 4, K>(Aff, Aff.rowptr[row], Aff.rowptr[row + 1], 0, ec, c, IdxMap{cmap}, sum);
+  ef[i] = e;
+  sv[i] = r - sum;
 }
 
 template <class MV, class X>
