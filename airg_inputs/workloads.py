@@ -7,7 +7,11 @@
                with N(0,1) loss weights on the outflow cells.
 * ``fv8192``:  FV 8192 x 8192 with fv2048's settings (a working set far above the
                on-die caches, for HBM roofline measurements).
-* ``fv_small(N, theta, permute)``: the same recipe at any size (parity cases).
+* ``dg1024``:  upwind DG-Q1 on 1024 x 1024 cells (4 unknowns per cell), theta = pi / 5,
+               g ~ U(0,1) per inflow face, element-block scaled, unknowns permuted
+               (the mixed-precision workload).
+* ``fv_random(N, theta, permute)`` / ``dg_random(N, theta, permute)``: the same
+  recipes at any size (parity cases).
 """
 import math
 
@@ -15,6 +19,7 @@ import numpy as np
 
 from . import rng
 from .fv import fv_advection, inflow_values
+from .dg import dg_advection
 
 SEED = rng.DEFAULT_SEED
 
@@ -26,6 +31,15 @@ def fv64():
 def fv_random(n, theta=0.3, permute=True, seed=SEED, ny=None):
     gw, gs = inflow_values(seed, n, ny)
     return fv_advection(n, theta, gw, gs, perm_seed=seed if permute else None, ny=ny)
+
+
+def dg_random(n, theta=math.pi / 5.0, permute=True, seed=SEED, ny=None):
+    gw, gs = inflow_values(seed, n, ny)
+    return dg_advection(n, theta, gw, gs, perm_seed=seed if permute else None, ny=ny)
+
+
+def dg1024():
+    return dg_random(1024, math.pi / 5.0, True)
 
 
 def fv2048():

@@ -30,7 +30,7 @@ WORKLOADS = {
 }
 
 
-def cpu_baseline(sample_side=512):
+def cpu_baseline(sample_side=1024):
     """The oracle (NumPy/SciPy FP64) timed on the host on a bounded sample: the
     same recipe (theta 0.3, permuted, U(0,1) inflow) on a smaller grid."""
     import oracle
@@ -64,6 +64,20 @@ def copy_bandwidth(nbytes=1 << 30, reps=10):
     return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
+TUNE = {"on": True}
+
+
+def _tune(solver):
+    """Pick the lanes per row of every solve operator by timing (airg_autotune)
+    unless --no-autotune; returns a summary."""
+    if not TUNE["on"]:
+        return None
+    t = solver.autotune(reps=10)
+    return {"operators": len(t), "changed": sum(e["lanes"] != e["default_lanes"] for e in t),
+            "default_us_sum": round(sum(e["default_us"] for e in t), 1),
+            "tuned_us_sum": round(sum(e["best_us"] for e in t), 1)}
+
+
 def _timed(fn, warmup, steps):
     import torch
     for _ in range(warmup):
@@ -89,6 +103,7 @@ def batched_legs(a, p, s64, value64, ip, ix, dv):
     print(f"bench: batch: {k} right-hand sides, FP32 V-cycle", file=sys.stderr, flush=True)
     B = torch.from_numpy(workloads.rhs_batch(p, k)).cuda()
     sm = Solver(ip, ix, dv, precision=binding.FP32)
+    _tune(sm)
     X = torch.zeros_like(B)
     dt, (X, infos) = _timed(lambda: sm.solve(B, X), 1, max(1, min(a.steps, 3)))
     assert all(i["converged"] == 1 and i["rel_residual"] <= 1e-10 for i in infos), infos
@@ -118,6 +133,7 @@ def batched_legs(a, p, s64, value64, ip, ix, dv):
     sb = BatchSolver(mats, precision=binding.FP32)
     torch.cuda.synchronize()
     setup_b = time.perf_counter() - t0
+    _tune(sb)
     xs = [torch.zeros_like(b_) for b_ in bs]
     dt, (xs, infos) = _timed(lambda: sb.solve(bs, xs), 1, max(1, min(a.steps, 3)))
     assert all(i["converged"] == 1 and i["rel_residual"] <= 1e-10 for i in infos), infos
@@ -133,6 +149,52 @@ def batched_legs(a, p, s64, value64, ip, ix, dv):
     return res
 
 
+def dg_legs(a, side=1024):
+    """The upwind DG-Q1 system (theta = pi/5, element-block scaled, permuted):
+    FP64, then FP32 and BF16 storage in the V-cycle inside FP64 FGMRES, each to
+    the FP64 1e-10 true relative residual, with the error against the FP64
+    solution."""
+    import torch
+    from airg_inputs import workloads
+    from paper_2508_17517_amd import Solver, binding
+    print(f"bench: dg: generating DG-Q1 {side}x{side}", file=sys.stderr, flush=True)
+    p = workloads.dg_random(side, math.pi / 5.0, True)
+    ip = torch.from_numpy(p.indptr).cuda()
+    ix = torch.from_numpy(p.indices).cuda()
+    dv = torch.from_numpy(p.data).cuda()
+    b = torch.from_numpy(p.b).cuda()
+    res = {"workload": f"upwind DG-Q1 {side}x{side} cells, theta pi/5, block-scaled, permuted, "
+                       "g~U(0,1)", "n": p.n, "nnz": p.nnz}
+    xref = None
+    for name, prec in (("fp64", binding.FP64), ("fp32", binding.FP32), ("bf16", binding.BF16)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sm = Solver(ip, ix, dv, precision=prec)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        _tune(sm)
+        xm = torch.zeros_like(b)
+        dt, (xm, im) = _timed(lambda: sm.solve(b, xm), a.warmup, a.steps)
+        assert im["converged"] == 1 and im["rel_residual"] <= 1e-10, im
+        kt = sm.time_kernels("poly", reps=a.kernel_reps)
+        leg = {"value": p.n / dt, "unit": "DOF/s", "ms_per_step": 1e3 * dt,
+               "iterations": im["iterations"], "rel_residual": im["rel_residual"],
+               "setup_s": round(setup_s, 3),
+               "poly_gbps": kt["bytes_per_launch"] / (kt["avg_launch_ms"] * 1e-3) / 1e9}
+        if xref is None:
+            xref = xm.clone()
+            st = sm.stats()
+            leg.update(levels=st["levels"], cycle_complexity=round(st["cycle_complexity"], 2))
+        else:
+            leg["rel_diff_vs_fp64_solution"] = float(torch.linalg.norm(xm - xref) /
+                                                     torch.linalg.norm(xref))
+            leg["speedup_vs_fp64"] = leg["value"] / res["fp64"]["value"]
+        res[name] = leg
+        print(f"bench: dg {name}: {leg}", file=sys.stderr, flush=True)
+        sm.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,10 +202,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="fv2048", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=512)
+    ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-dg", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--batch-cols", type=int, default=64)
     ap.add_argument("--batch-problems", type=int, default=48)
     a = ap.parse_args()
@@ -172,6 +236,9 @@ def main():
     s = Solver(ip, ix, dv)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    TUNE["on"] = not a.no_autotune
+    tune = _tune(s)
+    print(f"bench: autotune {tune}", file=sys.stderr, flush=True)
     st = s.stats()
     for l in range(st["levels"]):
         print(f"bench: level {l}: n {st['n'][l]} nnz {st['nnz'][l]} nF {st['n_f'][l]} "
@@ -215,7 +282,7 @@ def main():
                    "levels": st["levels"], "cycle_complexity": round(st["cycle_complexity"], 2),
                    "storage_complexity": round(st["storage_complexity"], 2),
                    "grid_complexity": round(st["grid_complexity"], 3),
-                   "setup_s": round(setup_s, 3),
+                   "setup_s": round(setup_s, 3), "autotune": tune,
                    "dof_per_s_per_vcycle": p.n * its * a.steps / dt},
         "roofline": None,
         "cpu_baseline": None,
@@ -237,6 +304,9 @@ def main():
                        "frac": dom["gbps"] / HBM_PEAK_GBPS, "traffic": None,
                        "avg_launch_us": 1e3 * dom["avg_launch_ms"],
                        "bytes_per_launch": dom["bytes_per_launch"],
+                       "stored_bytes_per_launch": dom["stored_bytes_per_launch"],
+                       "stored_gbps": dom["stored_bytes_per_launch"] /
+                                      (dom["avg_launch_ms"] * 1e-3) / 1e9,
                        "launches_per_vcycle": dom["launches"]}
     out["kernel_classes_gbps"] = {k: round(v["gbps"], 1) for k, v in classes.items()}
     # mixed precision: FP32 / BF16 storage in the V-cycle inside FP64 FGMRES,
@@ -246,6 +316,7 @@ def main():
         xref = x.clone()
         for name, prec in (("fp32", binding.FP32), ("bf16", binding.BF16)):
             sm = Solver(ip, ix, dv, precision=prec)
+            _tune(sm)
             xm = torch.zeros_like(b)
             for w in range(a.warmup):
                 xm, _ = sm.solve(b, xm)
@@ -267,6 +338,8 @@ def main():
             sm.close()
     if not a.no_batch:
         out["batched"] = batched_legs(a, p, s, value, ip, ix, dv)
+    if not a.no_dg:
+        out["dg_q1"] = dg_legs(a)
     out["hbm_copy_gbps"] = copy_bandwidth()
     print(f"bench: copy kernel {out['hbm_copy_gbps']:.1f} GB/s", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:

@@ -153,11 +153,12 @@ int airg_setup(airg_handle* out, int64_t n, int64_t nnz, const int32_t* rowptr,
  * use_x_as_guess, else the guess is 0.  info (nrhs entries, may be NULL)
  * receives per right-hand-side results.  Returns AIRG_NOT_CONVERGED if any
  * column missed rtol within max_it.
- * Several columns are solved together, up to 64 at a time: every V-cycle
- * kernel then reads each matrix entry once for all columns (SpMM on
- * interleaved columns) and one FGMRES process runs over the stacked columns,
- * stopped only when every column has |b_k - A x_k| <= rtol |b_k|.  The
- * Krylov bases then hold (2 restart + 1) vectors of n * 64 doubles. */
+ * Several columns are solved together, K at a time (K a power of two, at
+ * most 64 and with n K < 2^31): every V-cycle kernel then reads each matrix
+ * entry once for all K columns (SpMM on interleaved columns) and one FGMRES
+ * process runs over the stacked columns, stopped only when every column has
+ * |b_k - A x_k| <= rtol |b_k|.  The Krylov bases then hold (2 restart + 1)
+ * vectors of n K doubles (136 GB for n = 2048^2, K = 64, restart 30). */
 int airg_solve(airg_handle h, int nrhs, const double* b, int64_t ldb, double* x,
                int64_t ldx, int use_x_as_guess, airg_solve_info* info);
 
@@ -204,7 +205,7 @@ enum airg_kernel_class {
                            all levels and the Newton steps of the coarse solve */
   AIRG_K_HORNER = 1,    /* smoother steps only (Sec. 2.2) */
   AIRG_K_NEWTON = 2,    /* coarse Newton steps only (Sec. 2.3) */
-  AIRG_K_RESIDUAL = 3,  /* F-point residual with fused one-point prolongation (Eq. f_point) */
+  AIRG_K_RESIDUAL = 3,  /* F-point residual s = r_f - (A_fc + A_ff W) e_c (Eq. f_point) */
   AIRG_K_RESTRICT = 4,  /* restriction r_c + Z r_f */
   AIRG_K_TOP_SPMV = 5   /* top-level y = A x of the outer loop */
 };
@@ -216,6 +217,8 @@ typedef struct {
   double bytes_per_launch;   /* algorithmic HBM bytes per launch: each matrix entry and
                                 each vector element read or written once */
   double flops_per_launch;   /* 2 per matrix entry plus the vector updates */
+  double stored_bytes_per_launch; /* the same with the bytes the operators' stored form
+                                     actually has (16-bit compressed columns) */
 } airg_kernel_timing;
 
 /* Diagnostics for benchmarks: enqueue `reps` passes of exactly the launches
@@ -224,6 +227,39 @@ typedef struct {
  * handle's stream, and report the average launch time and the algorithmic
  * bytes and flops per launch.  Does not change the solver's state. */
 int airg_time_kernels(airg_handle h, int cls, int reps, airg_kernel_timing* out);
+
+/* Solve operators, for the launch-shape tuner. */
+enum airg_operator {
+  AIRG_OP_FF = 0,   /* A_ff of a level (smoother steps) */
+  AIRG_OP_B = 1,    /* A_fc + A_ff W of a level (F-point residual) */
+  AIRG_OP_Z = 2,    /* Z of a level (restriction) */
+  AIRG_OP_A = 3,    /* the coarsest matrix (Newton steps) */
+  AIRG_OP_TOP = 4   /* the top matrix of the outer loop (level 0) */
+};
+
+typedef struct {
+  int32_t level;
+  int32_t op;          /* airg_operator */
+  int32_t lanes;       /* lanes per row of single-column products (1..64, power of two) */
+  int32_t default_lanes;
+  double best_us;      /* device time of one product with `lanes` */
+  double default_us;   /* ... with the default lanes (a rule on the mean row length) */
+} airg_tune_entry;
+
+/* Launch-shape tuner: time every solve operator's single-column product with
+ * 1, 2, ..., 64 lanes per row (`reps` launches each, HIP events on the
+ * handle's stream) and keep the fastest per operator.  A row split over more
+ * lanes sums in a different order, so solves after tuning agree with untuned
+ * ones to rounding, not bit for bit; timings vary run to run, so a caller
+ * that needs reproducible results pins the shapes with airg_set_lanes.
+ * Writes at most max_out entries to out (may be NULL) and the number of
+ * operators to *n_out (may be NULL). */
+int airg_autotune(airg_handle h, int reps, airg_tune_entry* out, int max_out, int* n_out);
+
+/* Set the lanes per row of one solve operator (level is ignored for
+ * AIRG_OP_TOP and AIRG_OP_A).  AIRG_ERR_INVALID for an unknown operator or
+ * lanes not a power of two in 1..64. */
+int airg_set_lanes(airg_handle h, int level, int op, int lanes);
 
 /* ---- differentiable advection solve -------------------------------------
  * The upwind finite-volume system of v.grad(u) = 0 with inflow values g

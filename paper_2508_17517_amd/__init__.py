@@ -118,6 +118,19 @@ class Solver:
         binding.check(code, self.lib)
         return kt.as_dict()
 
+    def autotune(self, reps=10):
+        """Time every solve operator's product with 1..64 lanes per row and keep
+        the fastest (see airg_autotune); returns one dict per operator."""
+        n = ctypes.c_int()
+        cap = 3 * 64 + 2  # three operators per level plus the coarsest and the top matrix
+        buf = (binding.TuneEntry * cap)()
+        binding.check(self.lib.airg_autotune(self.h, reps, buf, cap, ctypes.byref(n)), self.lib)
+        return [buf[i].as_dict() for i in range(min(n.value, cap))]
+
+    def set_lanes(self, level, op, lanes):
+        """Pin the lanes per row of one solve operator ("ff", "b", "z", "a", "top")."""
+        binding.check(self.lib.airg_set_lanes(self.h, level, binding.OPERATORS[op], lanes), self.lib)
+
     def level_info(self, level):
         li = binding.LevelInfo()
         binding.check(self.lib.airg_level_info_get(self.h, level, ctypes.byref(li)), self.lib)

@@ -78,11 +78,25 @@ class LevelArrays(ctypes.Structure):
 
 class KernelTiming(ctypes.Structure):
     _fields_ = [("launches", c_i32), ("reserved", c_i32), ("avg_launch_ms", c_dbl),
-                ("bytes_per_launch", c_dbl), ("flops_per_launch", c_dbl)]
+                ("bytes_per_launch", c_dbl), ("flops_per_launch", c_dbl),
+                ("stored_bytes_per_launch", c_dbl)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("level", c_i32), ("op", c_i32), ("lanes", c_i32), ("default_lanes", c_i32),
+                ("best_us", c_dbl), ("default_us", c_dbl)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["op"] = OPERATORS_BY_CODE[d["op"]]
+        return d
+
+
+OPERATORS = {"ff": 0, "b": 1, "z": 2, "a": 3, "top": 4}
+OPERATORS_BY_CODE = {v: k for k, v in OPERATORS.items()}
 
 KERNEL_CLASSES = {"poly": 0, "horner": 1, "newton": 2, "residual": 3, "restrict": 4, "top_spmv": 5}
 
@@ -105,6 +119,8 @@ SYMBOLS = {
     "airg_import_hierarchy": (c_i32, [P(ctypes.c_void_p), ctypes.c_int, P(LevelInfo),
                                       P(LevelArrays), P(Params), ctypes.c_void_p]),
     "airg_time_kernels": (c_i32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, P(KernelTiming)]),
+    "airg_autotune": (c_i32, [ctypes.c_void_p, ctypes.c_int, P(TuneEntry), ctypes.c_int, P(ctypes.c_int)]),
+    "airg_set_lanes": (c_i32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "airg_fv_nnz": (c_i32, [c_i64, c_i64, c_dbl, P(c_i64)]),
     "airg_fv_assemble": (c_i32, [c_i64, c_i64, c_dbl] + [ctypes.c_void_p] * 9),
     "airg_fv_gradients": (c_i32, [c_i64, c_i64, c_dbl] + [ctypes.c_void_p] * 10),

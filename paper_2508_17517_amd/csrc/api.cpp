@@ -85,7 +85,7 @@ void load_csr(CSR& A, int64_t n, int64_t nnz, const int32_t* rowptr, const int32
 }
 
 // Up to 64 columns are solved together as K interleaved columns, K the next
-// power of two (padding columns are zero).
+// power of two (padding columns are zero), fewer when n K would pass 2^31.
 int solve_columns(Hierarchy& H, Workspace& W, std::map<int, std::unique_ptr<Workspace>>& Wk,
                   int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, int guess,
                   airg_solve_info* info) {
@@ -95,7 +95,10 @@ int solve_columns(Hierarchy& H, Workspace& W, std::map<int, std::unique_ptr<Work
   if (nrhs > 1 && !H.seg.empty()) fail(AIRG_ERR_INVALID, "a batch handle solves one column per problem");
   int status = AIRG_OK;
   for (int k0 = 0; k0 < nrhs;) {
-    const int cnt = std::min(64, nrhs - k0);
+    // K interleaved columns, with n K elements addressable by one launch
+    int kmax = 64;
+    while (kmax > 1 && H.n0 * (int64_t)kmax > (int64_t)INT32_MAX) kmax >>= 1;
+    const int cnt = std::min(kmax, nrhs - k0);
     int K = 1;
     while (K < cnt) K <<= 1;
     Workspace* ws = &W;
@@ -322,7 +325,7 @@ int airg_level_info_get(airg_handle h, int level, airg_level_info* out) {
     out->n_c = L.nC;
     out->nnz_a = L.nnz_a;
     out->nnz_ff = L.Aff.nnz;
-    out->nnz_fc = L.coarsest ? 0 : (L.Afc_nat.rowptr.get() ? L.Afc_nat.nnz : L.Afc.nnz);
+    out->nnz_fc = L.coarsest ? 0 : L.nnz_fc;
     out->nnz_z = L.coarsest ? 0 : (L.Z_nat.rowptr.get() ? L.Z_nat.nnz : L.Z.nnz);
     out->is_coarsest = L.coarsest ? 1 : 0;
     out->poly_len = (int32_t)L.alpha.size();
@@ -396,6 +399,25 @@ int airg_time_kernels(airg_handle h, int cls, int reps, airg_kernel_timing* out)
     airg_ctx* c = handle_of(h);
     if (!out) fail(AIRG_ERR_INVALID, "null output");
     return time_kernels(c->H, c->W, cls, reps, out);
+  });
+}
+
+int airg_autotune(airg_handle h, int reps, airg_tune_entry* out, int max_out, int* n_out) {
+  return guard([&]() {
+    airg_ctx* c = handle_of(h);
+    std::vector<airg_tune_entry> e;
+    autotune(c->H, c->W, reps, e);
+    if (out)
+      for (int i = 0; i < (int)e.size() && i < max_out; ++i) out[i] = e[i];
+    if (n_out) *n_out = (int)e.size();
+    return (int)AIRG_OK;
+  });
+}
+
+int airg_set_lanes(airg_handle h, int level, int op, int lanes) {
+  return guard([&]() {
+    set_lanes(handle_of(h)->H, level, op, lanes);
+    return (int)AIRG_OK;
   });
 }
 

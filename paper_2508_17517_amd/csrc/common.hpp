@@ -83,15 +83,25 @@ class DBuf {
 };
 
 // Device CSR matrix, int32 row pointers and columns.
+// Rows per base of the compressed column form (see compress_columns).
+constexpr int kColBlockShift = 6;
+
 struct CSR {
   int64_t rows = 0, cols = 0, nnz = 0;
   DBuf<int32_t> rowptr, col;
   DBuf<double> val;
+  // optional compressed columns for the solve kernels: the column of entry p
+  // in row i is cbase[i >> kColBlockShift] + col16[p], or col[p] where that
+  // base is negative
+  DBuf<uint16_t> col16;
+  DBuf<int32_t> cbase;
   void alloc(int64_t r, int64_t c, int64_t nz, hipStream_t s) {
     rows = r; cols = c; nnz = nz;
     rowptr.alloc(r + 1, s);
     col.alloc(nz, s);
     val.alloc(nz, s);
+    col16.release();
+    cbase.release();
   }
 };
 
@@ -109,9 +119,12 @@ struct OpView {
   ValType vt;
   int64_t rows;
   int64_t nnz;
+  const uint16_t* col16;  // compressed columns, or null
+  const int32_t* cbase;
 };
 inline OpView opview(const CSR& A) {
-  return {A.rowptr.get(), A.col.get(), A.val.get(), VT_F64, A.rows, A.nnz};
+  return {A.rowptr.get(), A.col.get(), A.val.get(), VT_F64, A.rows, A.nnz, A.col16.get(),
+          A.cbase.get()};
 }
 
 // Read-only view passed to kernels.

@@ -315,7 +315,7 @@ void newton_apply_t(const OpView& A, int tpr, int K, const std::vector<cplx>& ro
   const double vb = A.vt == VT_F64 ? 8.0 : A.vt == VT_F32 ? 4.0 : 2.0;
   const double mb = csr_bytes(A.rows, A.nnz, vb), mf = 2.0 * (double)A.nnz * K;
   auto count = [&](double vecs, double vec_flops) {
-    if (tally) tally->add(mb + xb * n * vecs, mf + vec_flops);
+    if (tally) tally->add(mb + xb * n * vecs, mf + vec_flops, col_saving(A));
   };
   const int m = (int)roots.size();
   if (m == 0) fail(AIRG_ERR_INTERNAL, "no coarse roots");
@@ -483,7 +483,6 @@ void finalize_hierarchy(Hierarchy& H) {
       // ascending columns in the solve numbering: neighbouring lanes gather
       // neighbouring elements
       sort_rows(L.Aff, s);
-      sort_rows(L.Afc, s);
       sort_rows(L.Z, s);
       launch_remap_ranked(L.cmap_nat.get(), N.pos.get(), frank.get(), L.nF, L.cmap.get(), s);
     } else {
@@ -493,8 +492,12 @@ void finalize_hierarchy(Hierarchy& H) {
       permute_rows(L.Z_nat, N.pos.get(), nullptr, L.nF, L.Z, s);
       launch_remap(L.cmap_nat.get(), N.pos.get(), L.nF, L.cmap.get(), s);
     }
+    // the residual operator on e_c; A_fc itself is not needed by the solve
+    merge_fc_ffw(L.Afc, L.Aff, L.cmap.get(), L.B, s);
+    L.nnz_fc = L.Afc.nnz;
+    L.Afc = CSR();
     L.tpr_ff = pick_tpr(L.Aff.rows, L.Aff.nnz);
-    L.tpr_fc = pick_tpr(L.Afc.rows, L.Afc.nnz + L.Aff.nnz);
+    L.tpr_b = pick_tpr(L.B.rows, L.B.nnz);
     L.tpr_z = pick_tpr(L.Z.rows, L.Z.nnz);
   }
   int64_t off = 0;
@@ -523,9 +526,20 @@ void finalize_hierarchy(Hierarchy& H) {
         continue;
       }
       lower(L.Aff, L.ff32, L.ff16);
-      lower(L.Afc, L.fc32, L.fc16);
+      lower(L.B, L.b32, L.b16);
       lower(L.Z, L.z32, L.z16);
     }
+  }
+  // compressed columns for every solve operator whose row blocks allow them
+  compress_columns(H.Aperm, s);
+  for (Level& L : H.levels) {
+    if (L.coarsest) {
+      compress_columns(L.A, s);
+      continue;
+    }
+    compress_columns(L.Aff, s);
+    compress_columns(L.B, s);
+    compress_columns(L.Z, s);
   }
   // every solve-phase operator is checked once, so an inconsistent hierarchy
   // (for example a bad import) fails here instead of in a kernel
@@ -540,11 +554,11 @@ void finalize_hierarchy(Hierarchy& H) {
         continue;
       }
       launch_check_csr(L.Aff, flags.get(), s);
-      launch_check_csr(L.Afc, flags.get(), s);
+      launch_check_csr(L.B, flags.get(), s);
       launch_check_csr(L.Z, flags.get(), s);
       launch_check_map(L.cmap.get(), L.nF, -1, L.nC, flags.get(), s);
       launch_check_map(L.pos.get(), L.n, 0, L.n, flags.get(), s);
-      if (L.Aff.rows != L.nF || L.Aff.cols != L.nF || L.Afc.rows != L.nF || L.Afc.cols != L.nC ||
+      if (L.Aff.rows != L.nF || L.Aff.cols != L.nF || L.B.rows != L.nF || L.B.cols != L.nC ||
           L.Z.rows != L.nC || L.Z.cols != L.nF || H.levels[l + 1].n != L.nC)
         fail(AIRG_ERR_INVALID, "inconsistent operator shapes on level " + std::to_string(l));
     }
@@ -654,7 +668,7 @@ void hierarchy_stats(const Hierarchy& H, airg_stats* st) {
     st->nnz[l] = L.nnz_a;
     st->n_f[l] = L.nF;
     st->nnz_ff[l] = L.Aff.nnz;
-    st->nnz_fc[l] = L.Afc.nnz;
+    st->nnz_fc[l] = L.nnz_fc;
     st->nnz_z[l] = L.Z.nnz;
     st->poly_degree[l] = L.coarsest ? 0 : (int)L.alpha.size() - 1;
     st->pmisr_rounds[l] = L.pmisr_rounds;
@@ -669,15 +683,16 @@ void hierarchy_stats(const Hierarchy& H, airg_stats* st) {
       st->coarse_roots = (int)L.roots.size();
     } else {
       const int d = (int)L.alpha.size() - 1;
-      cyc += (double)L.Z.nnz + (double)L.Afc.nnz + (double)L.Aff.nnz * (1 + d);
-      sto += (double)L.Z.nnz + (double)L.Afc.nnz + (double)L.Aff.nnz;
+      // complexities in the paper's terms: Z, A_fc and A_ff (d + 1 times)
+      cyc += (double)L.Z.nnz + (double)L.nnz_fc + (double)L.Aff.nnz * (1 + d);
+      sto += (double)L.Z.nnz + (double)L.nnz_fc + (double)L.Aff.nnz;
       // restriction: Z, r_f gathered, r_c read, r_c' written
       bytes += csr_bytes((double)L.nC, (double)L.Z.nnz) + 8.0 * (L.nF + 2 * L.nC);
-      // residual: A_ff, A_fc, cmap, e_c gathered, r_f read, e_f and s written
-      bytes += csr_bytes((double)L.nF, (double)L.Aff.nnz) + csr_bytes((double)L.nF, (double)L.Afc.nnz) +
-               4.0 * L.nF + 8.0 * (L.nC + 3 * L.nF);
-      // d Horner steps: A_ff, y gathered, s read, out written (+ e_f read on the last)
-      bytes += d * (csr_bytes((double)L.nF, (double)L.Aff.nnz) + 8.0 * 3 * L.nF) + 8.0 * L.nF;
+      // residual: B, e_c gathered, r_f read, s written
+      bytes += csr_bytes((double)L.nF, (double)L.B.nnz) + 8.0 * (L.nC + 2 * L.nF);
+      // d Horner steps: A_ff, y gathered, s read, out written; the last one
+      // also reads cmap and gathers W e_c
+      bytes += d * (csr_bytes((double)L.nF, (double)L.Aff.nnz) + 8.0 * 3 * L.nF) + 12.0 * L.nF;
     }
   }
   st->grid_complexity = grid / (double)H.n0;

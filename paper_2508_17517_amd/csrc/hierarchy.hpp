@@ -35,21 +35,23 @@ struct Level {
   DBuf<int32_t> cmap_nat;
 
   // solve numbering
-  CSR Aff, Afc, Z;          // Afc columns and Z rows in level l+1's nested order
+  CSR Aff, Z;               // Z rows in level l+1's nested order
+  CSR Afc;                  // A_fc in solve numbering (only until B is built)
+  CSR B;                    // A_fc + A_ff W: the F-point residual operator on e_c
   DBuf<int32_t> cmap;       // nested position on level l+1, or -1
   DBuf<int32_t> pos;        // setup index -> nested position on this level
   std::vector<double> alpha;
   std::vector<cplx> roots;
-  int tpr_ff = 1, tpr_fc = 1, tpr_z = 1, tpr_a = 1;
+  int tpr_ff = 1, tpr_b = 1, tpr_z = 1, tpr_a = 1;
   // the coarsest level's A is stored in its solve order (pos) when true
   bool a_permuted = false;
 
   // low-precision copies of the solve operators' values (FP32 or BF16 storage)
-  DBuf<float> ff32, fc32, z32, a32;
-  DBuf<bf16> ff16, fc16, z16, a16;
+  DBuf<float> ff32, b32, z32, a32;
+  DBuf<bf16> ff16, b16, z16, a16;
 
   // statistics
-  int64_t nnz_a = 0;
+  int64_t nnz_a = 0, nnz_fc = 0;
   int pmisr_rounds = 0;
   double trunc_rel = std::numeric_limits<double>::quiet_NaN();
 };
@@ -85,17 +87,25 @@ void hierarchy_stats(const Hierarchy& H, airg_stats* st);
 // Launch count and algorithmic traffic of a sequence of kernel launches: each
 // matrix entry (12 bytes with its column), row pointer and vector element read
 // or written once; flops count 2 per matrix entry plus the vector updates.
+// `stored` counts what the kernels actually move: `saving` is subtracted for
+// operators kept with compressed columns.
 struct LaunchTally {
   int launches = 0;
-  double bytes = 0.0, flops = 0.0;
-  void add(double b, double f) {
+  double bytes = 0.0, flops = 0.0, stored = 0.0;
+  void add(double b, double f, double saving = 0.0) {
     ++launches;
     bytes += b;
     flops += f;
+    stored += b - saving;
   }
 };
 inline double csr_bytes(int64_t rows, int64_t nnz, double vbytes = 8.0) {
   return (4.0 + vbytes) * nnz + 4.0 * (rows + 1);
+}
+// Bytes the compressed column form saves on one pass over A (at most 1 in 16
+// row blocks keeps int32 columns; counted as if none did).
+inline double col_saving(const OpView& A) {
+  return A.col16 ? 2.0 * (double)A.nnz - 4.0 * (double)((A.rows + 63) / 64) : 0.0;
 }
 
 // Operator view of A in the storage precision prec (airg_precision): FP64

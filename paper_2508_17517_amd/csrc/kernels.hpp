@@ -84,11 +84,19 @@ void spmv_horner_t(const OpView& A, int tpr, int K, const X* y, const X* sv, X* 
 template <class X>
 void spmv_restrict_t(const OpView& Z, int tpr, int K, const X* rf, const X* src, X* dst,
                      hipStream_t s);
-// F-point residual with fused one-point prolongation:
-//   ef[i] = W e_c, s[i] = r_f[i] - (A_fc e_c)[i] - (A_ff W e_c)[i]
+// F-point residual s = r_f - B e_c with B = A_fc + A_ff W (see merge_fc_ffw).
 template <class X>
-void residual_fpoint_t(const OpView& Aff, const OpView& Afc, const int32_t* cmap, int tpr, int K,
-                       const X* rf, const X* ec, X* ef, X* sv, hipStream_t s);
+void spmv_residual_t(const OpView& B, int tpr, int K, const X* ec, const X* rf, X* sv,
+                     hipStream_t s);
+// Last Horner step fused with the one-point prolongation:
+//   ef = W e_c + a (A y) + b s,  (W e_c)[i] = ec[cmap[i]] (0 where cmap[i] < 0)
+template <class X>
+void spmv_horner_prolong_t(const OpView& A, int tpr, int K, const X* y, const X* sv, X* ef,
+                           double a, double b, const int32_t* cmap, const X* ec, hipStream_t st);
+// ef = W e_c + a s (a degree-0 smoother)
+template <class X>
+void prolong_axpy_t(X* ef, const X* sv, const int32_t* cmap, const X* ec, double a, int64_t rows,
+                    int K, hipStream_t s);
 // Newton steps of the coarse solver (see newton_apply_t).
 template <class X>
 void newton_real_t(const OpView& A, int tpr, int K, const X* w, X* wn, X* x, double inv,
@@ -223,6 +231,12 @@ void build_p(const int8_t* state, const int64_t* fidx, const int64_t* cidx, cons
 // is preserved.
 void permute_rows(const CSR& A, const int32_t* newrow, const int32_t* colmap, int64_t out_cols,
                   CSR& out, hipStream_t s);
+// B = A_fc + A_ff W for the one-point W given by cmap (rows ascending by
+// column; entries with equal columns summed A_fc first, then A_ff in order).
+void merge_fc_ffw(const CSR& Afc, const CSR& Aff, const int32_t* cmap, CSR& B, hipStream_t s);
+// Build A's compressed column form (see CSR::col16) if every block of rows
+// spans fewer than 65536 columns; returns whether it did.
+bool compress_columns(CSR& A, hipStream_t s);
 // Sort the entries of every row by column (insertion sort per row).
 void sort_rows(CSR& A, hipStream_t s);
 // Explicit transpose with ascending columns.

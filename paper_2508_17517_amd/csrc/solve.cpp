@@ -102,34 +102,38 @@ VecSet<float> vecs32(Workspace& W) {
 }
 
 struct LevelOps {
-  OpView ff, fc, z, a;
+  OpView ff, b, z, a;
 };
 LevelOps ops_of(const Level& L, int prec) {
-  return {op_view(L.Aff, L.ff32, L.ff16, prec), op_view(L.Afc, L.fc32, L.fc16, prec),
+  return {op_view(L.Aff, L.ff32, L.ff16, prec), op_view(L.B, L.b32, L.b16, prec),
           op_view(L.Z, L.z32, L.z16, prec), op_view(L.A, L.a32, L.a16, prec)};
 }
 
 double vt_bytes(ValType vt) { return vt == VT_F64 ? 8.0 : vt == VT_F32 ? 4.0 : 2.0; }
 
 template <class X>
-void horner(const Level& L, const OpView& Aff, int K, const X* sv, X* ef, X* y0, X* y1,
-            hipStream_t s, LaunchTally* tally = nullptr) {
+void horner(const Level& L, const OpView& Aff, int K, const X* sv, const X* ec, X* ef, X* y0,
+            X* y1, hipStream_t s, LaunchTally* tally = nullptr) {
   const std::vector<double>& a = L.alpha;
   const int d = (int)a.size() - 1;
   const int64_t n = L.nF * K;
   const double xb = (double)sizeof(X);
   const double mb = csr_bytes(L.nF, Aff.nnz, vt_bytes(Aff.vt)), mf = 2.0 * (double)Aff.nnz * K;
-  // per step: y gathered, s read, out written (and read when accumulating)
-  auto count = [&](bool acc) {
-    if (tally) tally->add(mb + xb * n * (acc ? 4 : 3), mf + 3.0 * n);
+  // per step: y gathered, s read, out written; the last step also reads cmap
+  // and gathers W e_c
+  auto count = [&](bool last) {
+    if (tally)
+      tally->add(mb + xb * n * (last ? 4 : 3) + (last ? 4.0 * L.nF : 0.0), mf + 3.0 * n,
+                 col_saving(Aff));
   };
+  const int32_t* cmap = L.cmap.get();
   if (d == 0) {
-    axpy_first_t<X>(ef, sv, a[0], false, n, s);
-    if (tally) tally->add(3.0 * xb * n, 2.0 * n);
+    prolong_axpy_t<X>(ef, sv, cmap, ec, a[0], L.nF, K, s);
+    if (tally) tally->add(4.0 * xb * n + 4.0 * L.nF, 2.0 * n);
     return;
   }
   if (d == 1) {
-    spmv_horner_t<X>(Aff, L.tpr_ff, K, sv, sv, ef, a[1], a[0], true, s);
+    spmv_horner_prolong_t<X>(Aff, L.tpr_ff, K, sv, sv, ef, a[1], a[0], cmap, ec, s);
     count(true);
     return;
   }
@@ -142,7 +146,7 @@ void horner(const Level& L, const OpView& Aff, int K, const X* sv, X* ef, X* y0,
     count(false);
     c ^= 1;
   }
-  spmv_horner_t<X>(Aff, L.tpr_ff, K, y[c], sv, ef, 1.0, a[0], true, s);
+  spmv_horner_prolong_t<X>(Aff, L.tpr_ff, K, y[c], sv, ef, 1.0, a[0], cmap, ec, s);
   count(true);
 }
 
@@ -167,8 +171,8 @@ void vcycle_t(const Hierarchy& H, const VecSet<X>& v, int K) {
     const X* rf = (l == 0 ? v.in : v.rr) + lv.off * K;
     X* ef = v.e + lv.off * K;
     const X* ec = v.e + H.levels[l + 1].off * K;
-    residual_fpoint_t<X>(o.ff, o.fc, lv.cmap.get(), lv.tpr_fc, K, rf, ec, ef, v.sv, s);
-    horner<X>(lv, o.ff, K, v.sv, ef, v.y0, v.y1, s);
+    spmv_residual_t<X>(o.b, lv.tpr_b, K, ec, rf, v.sv, s);
+    horner<X>(lv, o.ff, K, v.sv, ec, ef, v.y0, v.y1, s);
   }
 }
 
@@ -375,7 +379,8 @@ void time_pass(const Hierarchy& H, const VecSet<X>& v, int cls, LaunchTally* t) 
   if (poly || cls == AIRG_K_HORNER)
     for (int l = 0; l < L; ++l) {
       const Level& lv = H.levels[l];
-      horner<X>(lv, ops_of(lv, prec).ff, 1, v.sv, v.e + lv.off, v.y0, v.y1, s, t);
+      horner<X>(lv, ops_of(lv, prec).ff, 1, v.sv, v.e + H.levels[l + 1].off, v.e + lv.off, v.y0,
+                v.y1, s, t);
     }
   if (poly || cls == AIRG_K_NEWTON) {
     const Level& lc = H.levels[L];
@@ -386,19 +391,19 @@ void time_pass(const Hierarchy& H, const VecSet<X>& v, int cls, LaunchTally* t) 
     for (int l = 0; l < L; ++l) {
       const Level& lv = H.levels[l];
       const LevelOps o = ops_of(lv, prec);
-      residual_fpoint_t<X>(o.ff, o.fc, lv.cmap.get(), lv.tpr_fc, 1, v.rr + lv.off,
-                           v.e + H.levels[l + 1].off, v.e + lv.off, v.sv, s);
+      spmv_residual_t<X>(o.b, lv.tpr_b, 1, v.e + H.levels[l + 1].off, v.rr + lv.off, v.sv, s);
       if (t)
-        t->add(csr_bytes(lv.nF, lv.Aff.nnz, vb) + csr_bytes(lv.nF, lv.Afc.nnz, vb) + 4.0 * lv.nF +
-                   xb * (lv.nC + 3 * lv.nF),
-               2.0 * (lv.Aff.nnz + lv.Afc.nnz) + lv.nF);
+        t->add(csr_bytes(lv.nF, lv.B.nnz, vb) + xb * (lv.nC + 2 * lv.nF), 2.0 * lv.B.nnz + lv.nF,
+               col_saving(o.b));
     }
   if (cls == AIRG_K_RESTRICT)
     for (int l = 0; l < L; ++l) {
       const Level& lv = H.levels[l];
       spmv_restrict_t<X>(ops_of(lv, prec).z, lv.tpr_z, 1, v.rr + lv.off, v.rr + lv.off + lv.nF,
                          v.rr + H.levels[l + 1].off, s);
-      if (t) t->add(csr_bytes(lv.nC, lv.Z.nnz, vb) + xb * (lv.nF + 2 * lv.nC), 2.0 * lv.Z.nnz + lv.nC);
+      if (t)
+        t->add(csr_bytes(lv.nC, lv.Z.nnz, vb) + xb * (lv.nF + 2 * lv.nC), 2.0 * lv.Z.nnz + lv.nC,
+               col_saving(ops_of(lv, prec).z));
     }
 }
 
@@ -424,7 +429,9 @@ int time_kernels(const Hierarchy& H, Workspace& W, int cls, int reps, airg_kerne
   auto pass = [&](LaunchTally* t) {
     if (cls == AIRG_K_TOP_SPMV) {
       spmv(H.Aperm, H.tpr_top, in, W.w.get(), s);
-      if (t) t->add(csr_bytes(H.n0, H.Aperm.nnz) + 16.0 * H.n0, 2.0 * H.Aperm.nnz);
+      if (t)
+        t->add(csr_bytes(H.n0, H.Aperm.nnz) + 16.0 * H.n0, 2.0 * H.Aperm.nnz,
+               col_saving(opview(H.Aperm)));
       return;
     }
     if (f64) time_pass<double>(H, vecs64(W, in, W.Zb.get()), cls, t);
@@ -443,9 +450,103 @@ int time_kernels(const Hierarchy& H, Workspace& W, int cls, int reps, airg_kerne
   if (tally.launches > 0) {
     out->avg_launch_ms = (double)ms / ((double)reps * tally.launches);
     out->bytes_per_launch = tally.bytes / tally.launches;
+    out->stored_bytes_per_launch = tally.stored / tally.launches;
     out->flops_per_launch = tally.flops / tally.launches;
   }
   return AIRG_OK;
+}
+
+}  // namespace airg
+
+namespace airg {
+
+namespace {
+
+template <class X>
+double time_product(const OpView& A, int tpr, const X* x, X* y, int reps, Workspace& W,
+                    hipStream_t s) {
+  spmv_t<X>(A, tpr, 1, x, y, s);  // warm-up
+  AIRG_HIP(hipEventRecord(W.ev0, s));
+  for (int r = 0; r < reps; ++r) spmv_t<X>(A, tpr, 1, x, y, s);
+  AIRG_HIP(hipEventRecord(W.ev1, s));
+  AIRG_HIP(hipEventSynchronize(W.ev1));
+  float ms = 0.f;
+  AIRG_HIP(hipEventElapsedTime(&ms, W.ev0, W.ev1));
+  return 1e3 * (double)ms / reps;
+}
+
+struct TuneTarget {
+  int level, op;
+  OpView A;
+  int* tpr;
+  bool f64;  // product in FP64 vectors
+};
+
+}  // namespace
+
+int autotune(Hierarchy& H, Workspace& W, int reps, std::vector<airg_tune_entry>& out) {
+  if (reps < 1) fail(AIRG_ERR_INVALID, "reps must be >= 1");
+  if (W.K != 1) fail(AIRG_ERR_INTERNAL, "tuning uses the single-column workspace");
+  hipStream_t s = H.s;
+  const int prec = H.p.precision;
+  const bool low = prec != AIRG_FP64;
+  const int L = (int)H.levels.size() - 1;
+  std::vector<TuneTarget> t;
+  for (int l = 0; l < L; ++l) {
+    Level& lv = H.levels[l];
+    const LevelOps o = ops_of(lv, prec);
+    t.push_back({l, AIRG_OP_FF, o.ff, &lv.tpr_ff, !low});
+    t.push_back({l, AIRG_OP_B, o.b, &lv.tpr_b, !low});
+    t.push_back({l, AIRG_OP_Z, o.z, &lv.tpr_z, !low});
+  }
+  Level& lc = H.levels[L];
+  t.push_back({L, AIRG_OP_A, ops_of(lc, prec).a, &lc.tpr_a, !low});
+  t.push_back({0, AIRG_OP_TOP, opview(H.Aperm), &H.tpr_top, true});
+  double* x64 = W.V.get();
+  launch_fill(x64, H.n0, 1.0, s);
+  float* x32 = low ? W.in32.get() : nullptr;
+  if (low) convert_d2f(x32, x64, H.n0, s);
+  out.clear();
+  for (const TuneTarget& g : t) {
+    if (g.A.rows <= 0) continue;
+    airg_tune_entry e{};
+    e.level = g.level;
+    e.op = g.op;
+    e.default_lanes = *g.tpr;
+    e.best_us = 1e300;
+    for (int tpr = 1; tpr <= 64; tpr <<= 1) {
+      if (g.A.rows * (int64_t)tpr > (int64_t)INT32_MAX) break;
+      const double us = g.f64 ? time_product<double>(g.A, tpr, x64, W.w.get(), reps, W, s)
+                              : time_product<float>(g.A, tpr, x32, W.e32.get(), reps, W, s);
+      if (tpr == e.default_lanes) e.default_us = us;
+      if (us < e.best_us) {
+        e.best_us = us;
+        e.lanes = tpr;
+      }
+    }
+    *g.tpr = e.lanes;
+    out.push_back(e);
+  }
+  return AIRG_OK;
+}
+
+void set_lanes(Hierarchy& H, int level, int op, int lanes) {
+  if (lanes < 1 || lanes > 64 || (lanes & (lanes - 1)))
+    fail(AIRG_ERR_INVALID, "lanes must be a power of two in 1..64");
+  const int L = (int)H.levels.size() - 1;
+  switch (op) {
+    case AIRG_OP_TOP: H.tpr_top = lanes; return;
+    case AIRG_OP_A: H.levels[L].tpr_a = lanes; return;
+    default: break;
+  }
+  if (level < 0 || level >= L) fail(AIRG_ERR_INVALID, "level has no such operator");
+  Level& lv = H.levels[level];
+  switch (op) {
+    case AIRG_OP_FF: lv.tpr_ff = lanes; break;
+    case AIRG_OP_B: lv.tpr_b = lanes; break;
+    case AIRG_OP_Z: lv.tpr_z = lanes; break;
+    default: fail(AIRG_ERR_INVALID, "unknown operator");
+  }
 }
 
 }  // namespace airg

@@ -38,5 +38,8 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
 // Replays one V-cycle's launches of a kernel class `reps` times between HIP
 // events (airg_time_kernels).
 int time_kernels(const Hierarchy& H, Workspace& W, int cls, int reps, airg_kernel_timing* out);
+// Launch-shape tuner (see airg_autotune) and its manual setter.
+int autotune(Hierarchy& H, Workspace& W, int reps, std::vector<airg_tune_entry>& out);
+void set_lanes(Hierarchy& H, int level, int op, int lanes);
 
 }  // namespace airg

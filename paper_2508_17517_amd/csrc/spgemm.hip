@@ -576,3 +576,159 @@ void copy_csr(const CSR& A, CSR& out, hipStream_t s) {
 }
 
 }  // namespace airg
+
+namespace airg {
+
+// ------------------------------------------------------------------ merged F-point residual operator
+// B = A_fc + A_ff W with W the one-point prolongation (column j of A_ff moves
+// to column cmap[j] of e_c; columns with cmap[j] < 0 drop out).  Each row's
+// entries are collected (A_fc first, then A_ff in stored order), sorted by
+// column with a stable insertion sort and equal columns summed left to right.
+__global__ void fcw_count_kernel(CSRView Afc, CSRView Aff, const int32_t* cmap, int64_t* cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Afc.rows) return;
+  int64_t c = Afc.rowptr[i + 1] - Afc.rowptr[i];
+  for (int p = Aff.rowptr[i]; p < Aff.rowptr[i + 1]; ++p) c += cmap[Aff.col[p]] >= 0 ? 1 : 0;
+  cnt[i] = c;
+}
+__global__ void fcw_fill_kernel(CSRView Afc, CSRView Aff, const int32_t* cmap, const int32_t* off,
+                                int32_t* col, double* val, int64_t* distinct) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Afc.rows) return;
+  const int s = off[i];
+  int e = s;
+  for (int p = Afc.rowptr[i]; p < Afc.rowptr[i + 1]; ++p, ++e) {
+    col[e] = Afc.col[p];
+    val[e] = Afc.val[p];
+  }
+  for (int p = Aff.rowptr[i]; p < Aff.rowptr[i + 1]; ++p) {
+    const int m = cmap[Aff.col[p]];
+    if (m < 0) continue;
+    col[e] = m;
+    val[e] = Aff.val[p];
+    ++e;
+  }
+  for (int p = s + 1; p < e; ++p) {  // stable: strictly greater moves right
+    const int c = col[p];
+    const double v = val[p];
+    int q = p - 1;
+    while (q >= s && col[q] > c) {
+      col[q + 1] = col[q];
+      val[q + 1] = val[q];
+      --q;
+    }
+    col[q + 1] = c;
+    val[q + 1] = v;
+  }
+  int w = s;
+  for (int p = s; p < e; ++p) {
+    if (p > s && col[p] == col[w - 1]) {
+      val[w - 1] = val[w - 1] + val[p];
+    } else {
+      col[w] = col[p];
+      val[w] = val[p];
+      ++w;
+    }
+  }
+  distinct[i] = w - s;
+}
+__global__ void fcw_compact_kernel(int64_t rows, const int32_t* off, const int32_t* rowptr,
+                                   const int32_t* tcol, const double* tval, int32_t* col,
+                                   double* val) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  const int s = off[i];
+  for (int p = rowptr[i], q = s; p < rowptr[i + 1]; ++p, ++q) {
+    col[p] = tcol[q];
+    val[p] = tval[q];
+  }
+}
+
+void merge_fc_ffw(const CSR& Afc, const CSR& Aff, const int32_t* cmap, CSR& B, hipStream_t s) {
+  const int64_t n = Afc.rows;
+  B.rows = n;
+  B.cols = Afc.cols;
+  if (n <= 0) {
+    B.nnz = 0;
+    B.rowptr.alloc(1, s);
+    launch_fill_i32(B.rowptr.get(), 1, 0, s);
+    return;
+  }
+  const unsigned nb = blocks_for(n, kBlock);
+  DBuf<int64_t> cnt(n, s), off;
+  fcw_count_kernel<<<nb, kBlock, 0, s>>>(view(Afc), view(Aff), cmap, cnt.get());
+  AIRG_CHECK_LAUNCH();
+  scan_counts(cnt, n, off, s);
+  DBuf<int32_t> toff;
+  const int64_t tot = offsets_to_rowptr(off, n, toff, s);
+  DBuf<int32_t> tcol(std::max<int64_t>(tot, 1), s);
+  DBuf<double> tval(std::max<int64_t>(tot, 1), s);
+  fcw_fill_kernel<<<nb, kBlock, 0, s>>>(view(Afc), view(Aff), cmap, toff.get(), tcol.get(),
+                                        tval.get(), cnt.get());
+  AIRG_CHECK_LAUNCH();
+  DBuf<int64_t> boff;
+  scan_counts(cnt, n, boff, s);
+  B.nnz = offsets_to_rowptr(boff, n, B.rowptr, s);
+  B.col.alloc(B.nnz, s);
+  B.val.alloc(B.nnz, s);
+  fcw_compact_kernel<<<nb, kBlock, 0, s>>>(n, toff.get(), B.rowptr.get(), tcol.get(), tval.get(),
+                                           B.col.get(), B.val.get());
+  AIRG_CHECK_LAUNCH();
+}
+
+// ------------------------------------------------------------------ compressed columns
+// Every block of 2^kColBlockShift consecutive rows whose columns span less
+// than 65536 stores them as 16-bit offsets from the block's smallest column
+// (true for almost every block of a locality-ordered operator, whose rows see
+// nearby columns); a block that spans more keeps its int32 columns, marked by
+// a negative base.  Saves 2 of the 12 bytes of an FP64 entry.
+__global__ void col_span_kernel(CSRView A, int64_t nblk, int32_t* cbase, unsigned long long* nwide) {
+  int64_t blk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blk >= nblk) return;
+  const int64_t r0 = blk << kColBlockShift;
+  const int64_t r1 = min(r0 + ((int64_t)1 << kColBlockShift), A.rows);
+  int mn = 0x7fffffff, mx = -1;
+  for (int p = A.rowptr[r0]; p < A.rowptr[r1]; ++p) {
+    const int c = A.col[p];
+    mn = min(mn, c);
+    mx = max(mx, c);
+  }
+  if (mx < 0) mn = mx = 0;
+  if (mx - mn > 65535) {
+    cbase[blk] = -1;
+    atomicAdd(nwide, 1ull);
+  } else {
+    cbase[blk] = mn;
+  }
+}
+__global__ void col16_kernel(CSRView A, const int32_t* cbase, uint16_t* col16) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.rows) return;
+  const int b = cbase[i >> kColBlockShift];
+  for (int p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p)
+    col16[p] = b >= 0 ? (uint16_t)(A.col[p] - b) : (uint16_t)0;
+}
+
+bool compress_columns(CSR& A, hipStream_t s) {
+  A.col16.release();
+  A.cbase.release();
+  if (A.rows <= 0 || A.nnz <= 0) return false;
+  const int64_t nblk = (A.rows + (1 << kColBlockShift) - 1) >> kColBlockShift;
+  DBuf<unsigned long long> nwide(1, s);
+  launch_zero_bytes(nwide.get(), sizeof(unsigned long long), s);
+  A.cbase.alloc(nblk, s);
+  col_span_kernel<<<blocks_for(nblk, kBlock), kBlock, 0, s>>>(view(A), nblk, A.cbase.get(),
+                                                             nwide.get());
+  AIRG_CHECK_LAUNCH();
+  // worth it only if nearly every block compresses
+  if (fetch(nwide.get(), s) * 16 > (unsigned long long)nblk) {
+    A.cbase.release();
+    return false;
+  }
+  A.col16.alloc(A.nnz, s);
+  col16_kernel<<<blocks_for(A.rows, kBlock), kBlock, 0, s>>>(view(A), A.cbase.get(), A.col16.get());
+  AIRG_CHECK_LAUNCH();
+  return true;
+}
+
+}  // namespace airg

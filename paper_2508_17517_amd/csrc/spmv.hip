@@ -20,17 +20,31 @@ __device__ __forceinline__ double ldv(double v) { return v; }
 __device__ __forceinline__ float ldv(float v) { return v; }
 __device__ __forceinline__ float ldv(bf16 v) { return __uint_as_float((uint32_t)v.bits << 16); }
 
-template <class MV>
+// Kernel view of a CSR operator with values of type MV; with C16 the columns
+// are read in the compressed form (16-bit offsets from a base per 64 rows,
+// int32 columns in the blocks whose base is negative).
+template <class MV, bool C16>
 struct CSRT {
   const int32_t* __restrict__ rowptr;
   const int32_t* __restrict__ col;
+  const uint16_t* __restrict__ col16;
+  const int32_t* __restrict__ cbase;
   const MV* __restrict__ val;
   int64_t rows;
+  __device__ __forceinline__ int base(int64_t row) const {
+    if constexpr (C16) return cbase[row >> kColBlockShift];
+    return 0;
+  }
+  // the column of entry p in a row of base b (callers pass b >= 0 only with C16)
+  __device__ __forceinline__ int column(int p, int b) const {
+    if constexpr (C16) return b + (int)col16[p];
+    return col[p];
+  }
 };
 
-template <class MV>
-static CSRT<MV> csr_t(const OpView& A) {
-  return {A.rowptr, A.col, (const MV*)A.val, A.rows};
+template <class MV, bool C16>
+static CSRT<MV, C16> csr_t(const OpView& A) {
+  return {A.rowptr, A.col, A.col16, A.cbase, (const MV*)A.val, A.rows};
 }
 
 // Entries in flight per lane: every lane first loads the column indices and
@@ -51,16 +65,16 @@ struct IdxMap {
 };
 
 // sum over entries p = s + lane, s + lane + TPR, ... < e of val[p] * x[idx(col[p]) * K + c]
-template <int TPR, int U, int K, class MV, class X, class Idx>
-__device__ __forceinline__ X row_dot(const CSRT<MV>& A, int s, int e, int lane, const X* __restrict__ x,
-                                     int c, Idx idx, X sum) {
+template <int TPR, int U, int K, class MV, bool C16, class X, class Idx>
+__device__ __forceinline__ X row_dot_cols(const CSRT<MV, C16>& A, int s, int e, int b, int lane,
+                                          const X* __restrict__ x, int c, Idx idx, X sum) {
   for (int p0 = s + lane; p0 < e; p0 += TPR * U) {
     int col[U];
     X v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int p = p0 + u * TPR;
-      col[u] = p < e ? idx(A.col[p]) : -1;
+      col[u] = p < e ? idx(A.column(p, b)) : -1;
       v[u] = p < e ? (X)ldv(A.val[p]) : X(0);
     }
     X xv[U];
@@ -72,18 +86,34 @@ __device__ __forceinline__ X row_dot(const CSRT<MV>& A, int s, int e, int lane, 
   }
   return sum;
 }
+// b: the row's column base in the compressed form; a negative base (a block
+// that kept int32 columns) takes the int32 path.  Rows of one wavefront lie
+// in one 64-row block, so the branch is uniform.
+template <int TPR, int U, int K, class MV, bool C16, class X, class Idx>
+__device__ __forceinline__ X row_dot(const CSRT<MV, C16>& A, int s, int e, int b, int lane,
+                                     const X* __restrict__ x, int c, Idx idx, X sum) {
+  if constexpr (C16) {
+    if (b < 0) {
+      const CSRT<MV, false> W{A.rowptr, A.col, nullptr, nullptr, A.val, A.rows};
+      return row_dot_cols<TPR, U, K>(W, s, e, 0, lane, x, c, idx, sum);
+    }
+  }
+  return row_dot_cols<TPR, U, K>(A, s, e, b, lane, x, c, idx, sum);
+}
 
 // lanes-per-row kernel (K = 1)
-template <int TPR, class MV, class X, class Epi>
-__global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV> A, const X* __restrict__ x, Epi epi) {
+template <int TPR, class MV, bool C16, class X, class Epi>
+__global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV, C16> A, const X* __restrict__ x,
+                                                   Epi epi) {
   const int lane = threadIdx.x & (TPR - 1);
   const int64_t row = (int64_t)blockIdx.x * (256 / TPR) + threadIdx.x / TPR;
   const bool live = row < A.rows;
   typename Epi::Pre pre{};
   if (live && lane == 0) pre = epi.pre(row);
   X sum = 0;
-  if (live) sum = row_dot<TPR, unroll_for<TPR>(), 1>(A, A.rowptr[row], A.rowptr[row + 1], lane, x, 0,
-                                                      IdxPlain{}, sum);
+  if (live)
+    sum = row_dot<TPR, unroll_for<TPR>(), 1>(A, A.rowptr[row], A.rowptr[row + 1], A.base(row), lane,
+                                             x, 0, IdxPlain{}, sum);
   if constexpr (TPR > 1) {
 #pragma unroll
     for (int o = TPR / 2; o > 0; o >>= 1) sum = sum + __shfl_down(sum, o, TPR);
@@ -93,55 +123,69 @@ __global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV> A, const X* __restri
 
 // column-per-lane kernel (K > 1 interleaved columns): each column's row sum
 // runs left to right from 0, as the TPR = 1 kernel does
-template <int K, class MV, class X, class Epi>
-__global__ __launch_bounds__(256) void spmm_kernel(CSRT<MV> A, const X* __restrict__ x, Epi epi) {
+template <int K, class MV, bool C16, class X, class Epi>
+__global__ __launch_bounds__(256) void spmm_kernel(CSRT<MV, C16> A, const X* __restrict__ x,
+                                                   Epi epi) {
   const int c = threadIdx.x & (K - 1);
   const int64_t row = (int64_t)blockIdx.x * (256 / K) + threadIdx.x / K;
   if (row >= A.rows) return;
   const typename Epi::Pre pre = epi.pre(row * K + c);
-  const X sum = row_dot<1, 4, K>(A, A.rowptr[row], A.rowptr[row + 1], 0, x, c, IdxPlain{}, X(0));
+  const X sum = row_dot<1, 4, K>(A, A.rowptr[row], A.rowptr[row + 1], A.base(row), 0, x, c,
+                                 IdxPlain{}, X(0));
   epi(row * K + c, sum, pre);
 }
 
-template <class MV, class X, class Epi>
+template <class MV, bool C16, class X, class Epi>
 static void launch_spmv_t(const OpView& Av, int tpr, int K, const X* x, Epi epi, hipStream_t s) {
   if (Av.rows <= 0) return;
-  CSRT<MV> A = csr_t<MV>(Av);
+  if (Av.rows * (int64_t)(K == 1 ? tpr : K) > (int64_t)INT32_MAX)
+    fail(AIRG_ERR_INVALID, "product launch exceeds 2^31 threads (fewer lanes or columns needed)");
+  CSRT<MV, C16> A = csr_t<MV, C16>(Av);
   if (K == 1) {
     unsigned nb = blocks_for(Av.rows, 256 / tpr);
     switch (tpr) {
-      case 1: spmv_kernel<1, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 2: spmv_kernel<2, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 4: spmv_kernel<4, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 8: spmv_kernel<8, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 16: spmv_kernel<16, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 32: spmv_kernel<32, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 64: spmv_kernel<64, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 1: spmv_kernel<1, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 2: spmv_kernel<2, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 4: spmv_kernel<4, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 8: spmv_kernel<8, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 16: spmv_kernel<16, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 32: spmv_kernel<32, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 64: spmv_kernel<64, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
       default: fail(AIRG_ERR_INTERNAL, "bad lanes-per-row");
     }
   } else {
     unsigned nb = blocks_for(Av.rows, 256 / K);
     switch (K) {
-      case 2: spmm_kernel<2, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 4: spmm_kernel<4, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 8: spmm_kernel<8, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 16: spmm_kernel<16, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 32: spmm_kernel<32, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 64: spmm_kernel<64, MV, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 2: spmm_kernel<2, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 4: spmm_kernel<4, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 8: spmm_kernel<8, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 16: spmm_kernel<16, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 32: spmm_kernel<32, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 64: spmm_kernel<64, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
       default: fail(AIRG_ERR_INTERNAL, "column count must be a power of two <= 64");
     }
   }
   AIRG_CHECK_LAUNCH();
 }
 
-// dispatch on the matrix storage type
-template <class X, class Epi>
-static void launch_spmv(const OpView& A, int tpr, int K, const X* x, Epi epi, hipStream_t s) {
+// dispatch on the matrix storage and column form: FP64 values go with FP64
+// vectors, FP32 and BF16 values with FP32 vectors
+template <class MV, class X, class Epi>
+static void launch_cols(const OpView& A, int tpr, int K, const X* x, Epi epi, hipStream_t s) {
+  if (A.col16) launch_spmv_t<MV, true>(A, tpr, K, x, epi, s);
+  else launch_spmv_t<MV, false>(A, tpr, K, x, epi, s);
+}
+template <class Epi>
+static void launch_spmv(const OpView& A, int tpr, int K, const double* x, Epi epi, hipStream_t s) {
+  if (A.vt != VT_F64) fail(AIRG_ERR_INTERNAL, "FP64 vectors need FP64 values");
+  launch_cols<double>(A, tpr, K, x, epi, s);
+}
+template <class Epi>
+static void launch_spmv(const OpView& A, int tpr, int K, const float* x, Epi epi, hipStream_t s) {
   switch (A.vt) {
-    case VT_F64: launch_spmv_t<double>(A, tpr, K, x, epi, s); break;
-    case VT_F32: launch_spmv_t<float>(A, tpr, K, x, epi, s); break;
-    case VT_BF16: launch_spmv_t<bf16>(A, tpr, K, x, epi, s); break;
-    default: fail(AIRG_ERR_INTERNAL, "bad value type");
+    case VT_F32: launch_cols<float>(A, tpr, K, x, epi, s); break;
+    case VT_BF16: launch_cols<bf16>(A, tpr, K, x, epi, s); break;
+    default: fail(AIRG_ERR_INTERNAL, "FP32 vectors need FP32 or BF16 values");
   }
 }
 
@@ -245,6 +289,43 @@ struct EpiNewtonPair2 {
   }
 };
 
+// F-point residual s = r_f - B e_c
+template <class X>
+struct EpiResidual {
+  const X* rf;
+  X* sv;
+  struct Pre {
+    X r;
+  };
+  __device__ Pre pre(int64_t i) const { return {rf[i]}; }
+  __device__ void operator()(int64_t i, X t, const Pre& p) const { sv[i] = p.r - t; }
+};
+// last Horner step fused with the prolongation: e_f = W e_c + (a t + b s)
+template <class X>
+struct EpiHornerProlong {
+  X* out;
+  const X* sv;
+  const int32_t* cmap;
+  const X* ec;
+  X a, b;
+  int kshift;
+  struct Pre {
+    X s, e;
+  };
+  __device__ Pre pre(int64_t i) const {
+    const int64_t row = i >> kshift;
+    const int m = cmap[row];
+    return {sv[i], m >= 0 ? ec[((int64_t)m << kshift) + (i - (row << kshift))] : X(0)};
+  }
+  __device__ void operator()(int64_t i, X t, const Pre& p) const { out[i] = p.e + (a * t + b * p.s); }
+};
+
+static int log2_of(int K) {
+  int k = 0;
+  while ((1 << k) < K) ++k;
+  return k;
+}
+
 template <class X>
 void spmv_t(const OpView& A, int tpr, int K, const X* x, X* y, hipStream_t s) {
   launch_spmv(A, tpr, K, x, EpiStore<X>{y}, s);
@@ -276,6 +357,37 @@ void newton_pair2_t(const OpView& A, int tpr, int K, const X* w, const X* t, X* 
 }
 
 template <class X>
+void spmv_residual_t(const OpView& B, int tpr, int K, const X* ec, const X* rf, X* sv,
+                     hipStream_t s) {
+  launch_spmv(B, tpr, K, ec, EpiResidual<X>{rf, sv}, s);
+}
+template <class X>
+void spmv_horner_prolong_t(const OpView& A, int tpr, int K, const X* y, const X* sv, X* ef,
+                           double a, double b, const int32_t* cmap, const X* ec, hipStream_t st) {
+  launch_spmv(A, tpr, K, y, EpiHornerProlong<X>{ef, sv, cmap, ec, (X)a, (X)b, log2_of(K)}, st);
+}
+
+template <class X>
+__global__ void prolong_axpy_kernel(X* ef, const X* sv, const int32_t* cmap, const X* ec, X a,
+                                    int kshift, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t row = i >> kshift;
+  const int m = cmap[row];
+  const X e = m >= 0 ? ec[((int64_t)m << kshift) + (i - (row << kshift))] : X(0);
+  ef[i] = e + a * sv[i];
+}
+template <class X>
+void prolong_axpy_t(X* ef, const X* sv, const int32_t* cmap, const X* ec, double a, int64_t rows,
+                    int K, hipStream_t s) {
+  const int64_t n = rows * K;
+  if (n <= 0) return;
+  prolong_axpy_kernel<X><<<blocks_for(n, kBlock), kBlock, 0, s>>>(ef, sv, cmap, ec, (X)a,
+                                                                   log2_of(K), n);
+  AIRG_CHECK_LAUNCH();
+}
+
+template <class X>
 __global__ void axpy_first_kernel(X* x, const X* w, X a, int first, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = (first ? X(0) : x[i]) + a * w[i];
@@ -285,103 +397,6 @@ void axpy_first_t(X* x, const X* w, double a, bool first, int64_t n, hipStream_t
   if (n <= 0) return;
   axpy_first_kernel<X><<<blocks_for(n, kBlock), kBlock, 0, s>>>(x, w, (X)a, first ? 1 : 0, n);
   AIRG_CHECK_LAUNCH();
-}
-
-// ------------------------------------------------------------------ F-point residual
-// s_i = r_i - sum_j Afc_ij e_c[j] - sum_j Aff_ij e_c[cmap[j]], ef_i = e_c[cmap[i]]
-template <int TPR, class MV, class X>
-__global__ __launch_bounds__(256) void residual_kernel(CSRT<MV> Aff, CSRT<MV> Afc,
-                                                       const int32_t* __restrict__ cmap,
-                                                       const X* __restrict__ rf,
-                                                       const X* __restrict__ ec,
-                                                       X* __restrict__ ef, X* __restrict__ sv) {
-  constexpr int U = unroll_for<TPR>();
-  const int lane = threadIdx.x & (TPR - 1);
-  const int64_t row = (int64_t)blockIdx.x * (256 / TPR) + threadIdx.x / TPR;
-  const bool live = row < Aff.rows;
-  X r = 0, e = 0;
-  if (live && lane == 0) {
-    r = rf[row];
-    const int m = cmap[row];
-    e = m >= 0 ? ec[m] : X(0);
-  }
-  X sum = 0;
-  if (live) {
-    sum = row_dot<TPR, U, 1>(Afc, Afc.rowptr[row], Afc.rowptr[row + 1], lane, ec, 0, IdxPlain{}, sum);
-    sum = row_dot<TPR, U, 1>(Aff, Aff.rowptr[row], Aff.rowptr[row + 1], lane, ec, 0, IdxMap{cmap}, sum);
-  }
-  if constexpr (TPR > 1) {
-#pragma unroll
-    for (int o = TPR / 2; o > 0; o >>= 1) sum = sum + __shfl_down(sum, o, TPR);
-  }
-  if (lane == 0 && live) {
-    ef[row] = e;
-    sv[row] = r - sum;
-  }
-}
-
-template <int K, class MV, class X>
-__global__ __launch_bounds__(256) void residual_cols_kernel(CSRT<MV> Aff, CSRT<MV> Afc,
-                                                            const int32_t* __restrict__ cmap,
-                                                            const X* __restrict__ rf,
-                                                            const X* __restrict__ ec,
-                                                            X* __restrict__ ef,
-                                                            X* __restrict__ sv) {
-  const int c = threadIdx.x & (K - 1);
-  const int64_t row = (int64_t)blockIdx.x * (256 / K) + threadIdx.x / K;
-  if (row >= Aff.rows) return;
-  const int64_t i = row * K + c;
-  const X r = rf[i];
-  const int m = cmap[row];
-  const X e = m >= 0 ? ec[(int64_t)m * K + c] : X(0);
-  X sum = row_dot<1, 4, K>(Afc, Afc.rowptr[row], Afc.rowptr[row + 1], 0, ec, c, IdxPlain{}, X(0));
-  sum = row_dot<1, 4, K>(Aff, Aff.rowptr[row], Aff.rowptr[row + 1], 0, ec, c, IdxMap{cmap}, sum);
-  ef[i] = e;
-  sv[i] = r - sum;
-}
-
-template <class MV, class X>
-static void residual_t(const OpView& Affv, const OpView& Afcv, const int32_t* cmap, int tpr, int K,
-                       const X* rf, const X* ec, X* ef, X* sv, hipStream_t s) {
-  CSRT<MV> a = csr_t<MV>(Affv), b = csr_t<MV>(Afcv);
-  if (K == 1) {
-    unsigned nb = blocks_for(Affv.rows, 256 / tpr);
-    switch (tpr) {
-      case 1: residual_kernel<1, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-      case 2: residual_kernel<2, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-      case 4: residual_kernel<4, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-      case 8: residual_kernel<8, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-      case 16: residual_kernel<16, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-      case 32: residual_kernel<32, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-      case 64: residual_kernel<64, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-      default: fail(AIRG_ERR_INTERNAL, "bad lanes-per-row");
-    }
-  } else {
-    unsigned nb = blocks_for(Affv.rows, 256 / K);
-    switch (K) {
-      case 2: residual_cols_kernel<2, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-      case 4: residual_cols_kernel<4, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-      case 8: residual_cols_kernel<8, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-      case 16: residual_cols_kernel<16, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-      case 32: residual_cols_kernel<32, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-      case 64: residual_cols_kernel<64, MV, X><<<nb, 256, 0, s>>>(a, b, cmap, rf, ec, ef, sv); break;
-      default: fail(AIRG_ERR_INTERNAL, "column count must be a power of two <= 64");
-    }
-  }
-  AIRG_CHECK_LAUNCH();
-}
-
-template <class X>
-void residual_fpoint_t(const OpView& Aff, const OpView& Afc, const int32_t* cmap, int tpr, int K,
-                       const X* rf, const X* ec, X* ef, X* sv, hipStream_t s) {
-  if (Aff.rows <= 0) return;
-  if (Aff.vt != Afc.vt) fail(AIRG_ERR_INTERNAL, "mixed value types in the residual");
-  switch (Aff.vt) {
-    case VT_F64: residual_t<double>(Aff, Afc, cmap, tpr, K, rf, ec, ef, sv, s); break;
-    case VT_F32: residual_t<float>(Aff, Afc, cmap, tpr, K, rf, ec, ef, sv, s); break;
-    case VT_BF16: residual_t<bf16>(Aff, Afc, cmap, tpr, K, rf, ec, ef, sv, s); break;
-    default: fail(AIRG_ERR_INTERNAL, "bad value type");
-  }
 }
 
 #define AIRG_INSTANTIATE(X)                                                                        \
@@ -396,8 +411,11 @@ void residual_fpoint_t(const OpView& Aff, const OpView& Afc, const int32_t* cmap
   template void newton_pair2_t<X>(const OpView&, int, int, const X*, const X*, X*, X*, double,     \
                                   double, double, hipStream_t);                                    \
   template void axpy_first_t<X>(X*, const X*, double, bool, int64_t, hipStream_t);                 \
-  template void residual_fpoint_t<X>(const OpView&, const OpView&, const int32_t*, int, int,       \
-                                     const X*, const X*, X*, X*, hipStream_t);
+  template void spmv_residual_t<X>(const OpView&, int, int, const X*, const X*, X*, hipStream_t);  \
+  template void spmv_horner_prolong_t<X>(const OpView&, int, int, const X*, const X*, X*, double,  \
+                                         double, const int32_t*, const X*, hipStream_t);           \
+  template void prolong_axpy_t<X>(X*, const X*, const int32_t*, const X*, double, int64_t, int,    \
+                                  hipStream_t);
 AIRG_INSTANTIATE(double)
 AIRG_INSTANTIATE(float)
 #undef AIRG_INSTANTIATE

@@ -175,3 +175,29 @@ def test_batch_argument_errors():
         BatchSolver([(q.indptr, q.indices, q.data), (q.indptr, q.indices, bad)])
     s.close()
     single.close()
+
+
+def test_autotuned_shapes_keep_the_solution_and_can_be_pinned():
+    _needs_gpu()
+    from paper_2508_17517_amd import AirgError, Solver
+    p = workloads.fv_random(128, 0.5, True)
+    s = Solver(p.indptr, p.indices, p.data)
+    b = torch.from_numpy(p.b).cuda()
+    x0, i0 = s.solve(b)
+    tuned = s.autotune(reps=3)
+    st = s.stats()
+    assert len(tuned) == 3 * (st["levels"] - 1) + 2
+    assert all(t["lanes"] in (1, 2, 4, 8, 16, 32, 64) for t in tuned)
+    assert all(t["best_us"] <= t["default_us"] for t in tuned)
+    x1, i1 = s.solve(b)
+    assert i1["converged"] == 1 and abs(i1["iterations"] - i0["iterations"]) <= 1
+    assert float(torch.linalg.norm(x1 - x0) / torch.linalg.norm(x0)) <= 1e-8
+    # pinned shapes give bit-identical solves
+    for t in tuned:
+        s.set_lanes(t["level"], t["op"], 64 if t["op"] == "a" else 1)
+    x2, _ = s.solve(b)
+    x3, _ = s.solve(b)
+    assert torch.equal(x2, x3)
+    with pytest.raises(AirgError):
+        s.set_lanes(0, "ff", 3)
+    s.close()

@@ -36,6 +36,8 @@ CASES = {
     "fv128_perm": lambda: workloads.fv_random(128, 0.3, True),
     "fv100_theta1": lambda: workloads.fv_random(100, 1.0, True),
     "fv80x40_rect": lambda: workloads.fv_random(80, 0.7, True, ny=40),
+    "dg24_perm": lambda: workloads.dg_random(24, math.pi / 5, True),
+    "dg20x12_rect": lambda: workloads.dg_random(20, 1.2, True, ny=12),
 }
 
 

@@ -4,6 +4,7 @@ import math
 import os
 
 import numpy as np
+import pytest
 import scipy.sparse as sp
 
 from airg_inputs import rng, fv_advection, workloads
@@ -92,3 +93,53 @@ def test_batch_shapes_are_seeded_and_in_range():
     assert np.array_equal(s, s2) and np.array_equal(t, t2)
     assert set(np.unique(s)) <= set(workloads.BATCH_SIDES)
     assert np.all((t > 0) & (t < math.pi / 2))
+
+
+# --------------------------------------------------------------------- DG-Q1 (reading of the paper's DG remark)
+
+def test_dg_element_blocks_by_hand():
+    # own-block diagonal (vx + vy)/6 on every node; west/south couple only the
+    # inflow-face nodes to the neighbour's facing nodes with -v M entries
+    from airg_inputs.dg import element_blocks
+    t = math.pi / 5
+    vx, vy = math.cos(t), math.sin(t)
+    own, west, south = element_blocks(t)
+    assert np.allclose(np.diag(own), (vx + vy) / 6.0, rtol=0, atol=1e-15)
+    # test node (0,0) = row 0: west trial nodes (1,0), (1,1) = columns 1, 3
+    assert west[0, 1] == -vx / 3.0 and west[0, 3] == -vx / 6.0
+    assert np.count_nonzero(west) == 4 and np.count_nonzero(south) == 4
+    # test node (0,0): south trial nodes (0,1), (1,1) = columns 2, 3
+    assert south[0, 2] == -vy / 3.0 and south[0, 3] == -vy / 6.0
+    # v.grad(1) = 0: the three blocks together annihilate constants
+    assert np.allclose((own + west + south).sum(axis=1), 0.0, atol=1e-15)
+
+
+@pytest.mark.parametrize("scaled", [True, False])
+def test_dg_constant_inflow_gives_constant_solution(scaled):
+    from airg_inputs import dg_advection
+    p = dg_advection(6, math.pi / 5, 0.7, 0.7, scaled=scaled, ny=5)
+    u = sp.linalg.spsolve(p.scipy().tocsc(), p.b)
+    assert np.abs(u - 0.7).max() < 1e-14
+    if scaled:
+        # own blocks are the identity and rows keep at most 1 + 2 + 2 entries
+        assert np.array_equal(p.scipy().diagonal(), np.ones(p.n))
+        assert np.diff(p.indptr).max() == 5
+
+
+def test_dg_scaled_system_is_triangular_in_cell_order_and_sweeps_exactly():
+    p = workloads.dg_random(12, 0.9, True)
+    A = p.scipy()
+    u = oracle.sweep_solve(A, p.b, p.level)
+    assert np.allclose(u, sp.linalg.spsolve(A.tocsc(), p.b), rtol=0, atol=1e-13)
+
+
+def test_dg_permutation_is_a_relabelling():
+    from airg_inputs import dg_advection
+    gw, gs = np.linspace(0.1, 0.9, 5), np.linspace(0.2, 0.8, 7)
+    p0 = dg_advection(7, 0.6, gw, gs, ny=5)
+    p1 = dg_advection(7, 0.6, gw, gs, perm_seed=3, ny=5)
+    A0, A1 = p0.scipy(), p1.scipy()
+    o = p1.order
+    assert np.array_equal(A1.toarray(), A0.toarray()[np.ix_(o, o)])
+    assert np.array_equal(p1.b, p0.b[o])
+    assert all(np.all(np.diff(p1.indices[p1.indptr[i]:p1.indptr[i + 1]]) > 0) for i in range(p1.n))

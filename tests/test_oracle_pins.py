@@ -370,6 +370,17 @@ def test_airg_solution_matches_sweep(n, theta):
     assert its < 30
 
 
+def test_airg_solution_matches_sweep_on_dg():
+    # the block-scaled upwind DG-Q1 system of the mixed-precision workload
+    p = workloads.dg_random(32, math.pi / 5, True)
+    A = p.scipy()
+    x, its, rel, levels, _ = oracle.solve(A, p.b)
+    u = oracle.sweep_solve(A, p.b, p.level)
+    assert rel <= 1e-10
+    assert np.linalg.norm(x - u) <= 1e-8 * np.linalg.norm(u)
+    assert its < 30 and len(levels) >= 2
+
+
 def test_fgmres_matches_brute_force_gmres_residuals():
     A = _rand_diag_dominant(80, 12, dom=1.1)
     b = np.random.default_rng(1).uniform(size=80)
