@@ -10,6 +10,8 @@
 * ``dg1024``:  upwind DG-Q1 on 1024 x 1024 cells (4 unknowns per cell), theta = pi / 5,
                g ~ U(0,1) per inflow face, element-block scaled, unknowns permuted
                (the mixed-precision workload).
+* ``fd_paper(N)``: the paper's own FD system (boundary nodes kept, theta = pi/4,
+               g = 0, natural order); N = 3606 is its 13M-unknown single-GPU case.
 * ``fv_random(N, theta, permute)`` / ``dg_random(N, theta, permute)``: the same
   recipes at any size (parity cases).
 """
@@ -20,6 +22,7 @@ import numpy as np
 from . import rng
 from .fv import fv_advection, inflow_values
 from .dg import dg_advection
+from .fd import fd_advection
 
 SEED = rng.DEFAULT_SEED
 
@@ -40,6 +43,12 @@ def dg_random(n, theta=math.pi / 5.0, permute=True, seed=SEED, ny=None):
 
 def dg1024():
     return dg_random(1024, math.pi / 5.0, True)
+
+
+def fd_paper(n=3606):
+    """The paper's single-GPU setting (Sec. 3.1): FD with the inflow boundary
+    nodes kept, theta = pi/4, g = 0; n = 3606 gives 13.0M unknowns."""
+    return fd_advection(n, math.pi / 4.0, 0.0)
 
 
 def fv2048():

@@ -64,6 +64,38 @@ def copy_bandwidth(nbytes=1 << 30, reps=10):
     return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fv2048_poly_hbm_traffic.md")
+# sources that decide the poly-SpMV launches and their operators
+TRAFFIC_SOURCES = ["spmv.hip", "hierarchy.cpp", "solve.cpp", "order.hip", "spgemm.hip",
+                   "common.hpp"]
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2508_17517_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per poly-SpMV launch from the committed counter summary, if it
+    was taken on this workload with the current kernel sources (else None)."""
+    if workload != "fv2048" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and line.split(":")[0].strip() in ("kernel_source_sha256",
+                                                              "traffic_bytes_per_launch"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 TUNE = {"on": True}
 
 
@@ -73,6 +105,10 @@ def _tune(solver):
     if not TUNE["on"]:
         return None
     t = solver.autotune(reps=10)
+    for e in t:
+        print(f"bench: tune level {e['level']:2d} {e['op']:3s} lanes {e['lanes']:2d} xcd {e['xcd_map']} "
+              f"{e['best_us']:8.2f} us (default {e['default_lanes']:2d}/{e['default_xcd_map']} "
+              f"{e['default_us']:8.2f} us)", file=sys.stderr)
     return {"operators": len(t), "changed": sum(e["lanes"] != e["default_lanes"] for e in t),
             "default_us_sum": round(sum(e["default_us"] for e in t), 1),
             "tuned_us_sum": round(sum(e["best_us"] for e in t), 1)}
@@ -301,7 +337,8 @@ def main():
     out["roofline"] = {"bound": "hbm", "kernel": "poly-SpMV (Horner smoother steps + Newton "
                                                  "coarse steps, one V-cycle's launches)",
                        "achieved": dom["gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                       "frac": dom["gbps"] / HBM_PEAK_GBPS, "traffic": None,
+                       "frac": dom["gbps"] / HBM_PEAK_GBPS,
+                       "traffic": measured_traffic(a.workload),
                        "avg_launch_us": 1e3 * dom["avg_launch_ms"],
                        "bytes_per_launch": dom["bytes_per_launch"],
                        "stored_bytes_per_launch": dom["stored_bytes_per_launch"],

@@ -62,7 +62,7 @@ typedef struct {
   double a_drop;             /* relative drop on A_coarse, 1e-6 (Sec. 2) */
   double r_drop;             /* relative drop on R, 0.01 (value not in the paper) */
   double trunc_tol;          /* automatic truncation tolerance, 1e-2; <= 0 disables (Sec. 2.4) */
-  double rtol;               /* FGMRES relative tolerance on |b - A x|, 1e-10 */
+  double rtol;               /* relative tolerance of the outer loop on |b - A x|, 1e-10 */
   uint64_t seed;             /* every random draw of the setup, 17517 */
   int64_t min_coarse_rows;   /* a level this small is always the coarsest, 64 */
   int32_t ddc_its;           /* DDC passes, 2 */
@@ -76,17 +76,26 @@ typedef struct {
   int32_t max_it;            /* FGMRES iteration cap (V-cycles), 500 */
   int32_t restart;           /* FGMRES restart length, 30 */
   int32_t keep_setup_data;   /* keep level data in setup numbering for export, 0 */
-  int32_t locality_order;    /* order each level's F points in the solve numbering by
-                                breadth-first distance on A + A^T (cache locality of the
+  int32_t locality_order;    /* order each level's F points and the coarsest level's
+                                points in the solve numbering by a locality key of two
+                                breadth-first distances on A + A^T (cache locality of the
                                 SpMV gathers; the hierarchy itself is unchanged), 1 */
+  int32_t outer;             /* airg_outer: the outer iteration, AIRG_OUTER_FGMRES */
 } airg_params;
+
+/* Outer iterations.  AIRG_OUTER_RICHARDSON is the paper's undamped Richardson
+ * x <- x + M (b - A x) with M one V-cycle (Sec. 3), stopped when the true
+ * residual |b - A x| <= rtol |b|, or rtol |b - A x0| when b = 0; its
+ * iteration count is the number of V-cycles. */
+typedef enum { AIRG_OUTER_FGMRES = 0, AIRG_OUTER_RICHARDSON = 1 } airg_outer;
 
 typedef struct {
   int32_t iterations;        /* V-cycles applied */
   int32_t converged;         /* 1 when the true relative residual <= rtol */
   int32_t restarts;
   int32_t reserved;
-  double rel_residual;       /* true |b - A x| / |b| at exit */
+  double rel_residual;       /* true |b - A x| / |b| at exit (Richardson with b = 0:
+                                relative to |b - A x0|) */
   double rel_residual_estimate; /* Arnoldi estimate at exit */
   double solve_ms;           /* device time of the solve */
 } airg_solve_info;
@@ -240,15 +249,23 @@ enum airg_operator {
 typedef struct {
   int32_t level;
   int32_t op;          /* airg_operator */
-  int32_t lanes;       /* lanes per row of single-column products (1..64, power of two) */
+  int32_t lanes;       /* lanes per row of single-column products (1..64, power of two),
+                          or 0: the row-block kernel (a workgroup loads a block of rows
+                          with at most 2048 entries at once and each row's thread sums
+                          its products in order; operators with 8 or more entries per
+                          row on average) */
+  int32_t xcd_map;     /* 1: workgroups of one XCD take one contiguous eighth of the rows
+                          (each XCD has its own L2); 0: workgroup i takes row block i */
   int32_t default_lanes;
-  double best_us;      /* device time of one product with `lanes` */
-  double default_us;   /* ... with the default lanes (a rule on the mean row length) */
+  int32_t default_xcd_map;
+  double best_us;      /* device time of one product with the chosen shape */
+  double default_us;   /* ... with the default shape (a rule on the mean row length) */
 } airg_tune_entry;
 
 /* Launch-shape tuner: time every solve operator's single-column product with
- * 1, 2, ..., 64 lanes per row (`reps` launches each, HIP events on the
- * handle's stream) and keep the fastest per operator.  A row split over more
+ * 1, 2, ..., 64 lanes per row and the row-block kernel where it exists, each
+ * with and without the XCD mapping (`reps` launches each, HIP events on the
+ * handle's stream), and keep the fastest per operator.  A row split over more
  * lanes sums in a different order, so solves after tuning agree with untuned
  * ones to rounding, not bit for bit; timings vary run to run, so a caller
  * that needs reproducible results pins the shapes with airg_set_lanes.
@@ -256,10 +273,11 @@ typedef struct {
  * operators to *n_out (may be NULL). */
 int airg_autotune(airg_handle h, int reps, airg_tune_entry* out, int max_out, int* n_out);
 
-/* Set the lanes per row of one solve operator (level is ignored for
- * AIRG_OP_TOP and AIRG_OP_A).  AIRG_ERR_INVALID for an unknown operator or
- * lanes not a power of two in 1..64. */
-int airg_set_lanes(airg_handle h, int level, int op, int lanes);
+/* Set the launch shape (lanes per row and XCD mapping, as in airg_tune_entry)
+ * of one solve operator (level is ignored for AIRG_OP_TOP and AIRG_OP_A).
+ * AIRG_ERR_INVALID for an unknown operator, lanes not 0 or a power of two in
+ * 1..64, 0 for an operator without row blocks, or xcd_map not 0 or 1. */
+int airg_set_lanes(airg_handle h, int level, int op, int lanes, int xcd_map);
 
 /* ---- differentiable advection solve -------------------------------------
  * The upwind finite-volume system of v.grad(u) = 0 with inflow values g

@@ -21,6 +21,6 @@ properties live in tests/test_oracle_*.py.
 """
 from .params import Params  # noqa: F401
 from .hierarchy import setup, ZeroDiagonal  # noqa: F401
-from .solve import solve, adjoint_solve, vcycle, fgmres, loss_gradients  # noqa: F401
+from .solve import solve, adjoint_solve, vcycle, fgmres, richardson, loss_gradients  # noqa: F401
 from .sweep import sweep_solve  # noqa: F401
 from . import linalg, rng  # noqa: F401

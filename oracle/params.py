@@ -26,5 +26,6 @@ class Params:
     rtol: float = 1e-10
     max_it: int = 500
     restart: int = 30
+    outer: str = "fgmres"            # or "richardson": the paper's undamped Richardson (Sec. 3)
     # oracle-only knob for the exactness pins: solve the coarsest level by LU
     exact_coarse: bool = False

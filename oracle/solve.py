@@ -7,9 +7,10 @@ e_f += q(A_ff) (r_f - A_fc e_c - A_ff e_f).  The coarsest level applies its
 Newton polynomial.
 
 Outer loop: the paper uses undamped Richardson from an initial guess of one
-(Sec. 3); this workload uses right-preconditioned FGMRES(restart) from x0 = 0
-with classical Gram-Schmidt applied twice, stopping when the Arnoldi residual
-estimate reaches rtol |b| and the true residual |b - A x| confirms it.
+(Sec. 3), available as `richardson`; the default workloads use
+right-preconditioned FGMRES(restart) from x0 = 0 with classical Gram-Schmidt
+applied twice, stopping when the Arnoldi residual estimate reaches rtol |b|
+and the true residual |b - A x| confirms it.
 """
 import math
 
@@ -99,15 +100,45 @@ def fgmres(A, precond, b, rtol=1e-10, max_it=500, restart=30, x0=None):
             x = x + y[i] * Zs[i]
 
 
-def solve(A, b, p=None, levels=None):
-    """Set up (unless `levels` is given) and solve A x = b.
-    Returns (x, iterations, true relative residual, levels, history)."""
+def richardson(A, precond, b, rtol=1e-10, max_it=500, x0=None):
+    """Undamped Richardson, x <- x + M (b - A x), the paper's outer loop (Sec. 3),
+    stopped on the unpreconditioned residual: |b - A x| <= rtol |b|, or
+    rtol |b - A x0| when b = 0 (the paper's runs have g = 0 and x0 = 1).
+    Returns (x, iterations, relative residual, residual-norm history)."""
+    n = len(b)
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - linalg.spmv(A, x)
+    rn = linalg.norm(r)
+    bnorm = linalg.norm(b)
+    ref = bnorm if bnorm > 0.0 else rn
+    hist = [rn]
+    if ref == 0.0:
+        return x, 0, 0.0, hist
+    its = 0
+    while rn > rtol * ref and its < max_it:
+        x = x + precond(r)
+        r = b - linalg.spmv(A, x)
+        rn = linalg.norm(r)
+        hist.append(rn)
+        its += 1
+    return x, its, rn / ref, hist
+
+
+def solve(A, b, p=None, levels=None, x0=None):
+    """Set up (unless `levels` is given) and solve A x = b with the outer loop
+    p.outer (FGMRES, or the paper's Richardson).  x0: the initial guess (zero
+    if None).  Returns (x, iterations, relative residual, levels, history)."""
     p = p or Params()
     A = sp.csr_matrix(A)
     if levels is None:
         levels = setup(A, p)
-    x, its, rel, hist = fgmres(A, lambda v: vcycle(levels, v, 0, p.exact_coarse), b,
-                               p.rtol, p.max_it, p.restart)
+    M = lambda v: vcycle(levels, v, 0, p.exact_coarse)  # noqa: E731
+    if p.outer == "richardson":
+        x, its, rel, hist = richardson(A, M, b, p.rtol, p.max_it, x0)
+    elif p.outer == "fgmres":
+        x, its, rel, hist = fgmres(A, M, b, p.rtol, p.max_it, p.restart, x0)
+    else:
+        raise ValueError(f"unknown outer loop {p.outer!r}")
     return x, its, rel, levels, hist
 
 

@@ -63,6 +63,7 @@ void check_params(const airg_params& p) {
   if (!(p.rtol > 0.0 && p.rtol < 1.0)) bad("rtol");
   if (p.max_it < 0) bad("max_it");
   if (p.restart < 1 || p.restart > 512) bad("restart");
+  if (p.outer != AIRG_OUTER_FGMRES && p.outer != AIRG_OUTER_RICHARDSON) bad("outer");
 }
 
 // Copy the caller's CSR (host or device) into library memory.
@@ -174,6 +175,7 @@ int airg_params_default(airg_params* p) {
   p->restart = 30;
   p->keep_setup_data = 0;
   p->locality_order = 1;
+  p->outer = AIRG_OUTER_FGMRES;
   return AIRG_OK;
 }
 
@@ -414,9 +416,9 @@ int airg_autotune(airg_handle h, int reps, airg_tune_entry* out, int max_out, in
   });
 }
 
-int airg_set_lanes(airg_handle h, int level, int op, int lanes) {
+int airg_set_lanes(airg_handle h, int level, int op, int lanes, int xcd_map) {
   return guard([&]() {
-    set_lanes(handle_of(h)->H, level, op, lanes);
+    set_lanes(handle_of(h)->H, level, op, lanes, xcd_map);
     return (int)AIRG_OK;
   });
 }

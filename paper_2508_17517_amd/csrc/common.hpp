@@ -95,6 +95,10 @@ struct CSR {
   // base is negative
   DBuf<uint16_t> col16;
   DBuf<int32_t> cbase;
+  // optional row blocks for the row-block product: block b holds rows
+  // rblk[b] .. rblk[b+1]-1 (see build_row_blocks)
+  DBuf<int32_t> rblk;
+  int64_t nrblk = 0;
   void alloc(int64_t r, int64_t c, int64_t nz, hipStream_t s) {
     rows = r; cols = c; nnz = nz;
     rowptr.alloc(r + 1, s);
@@ -102,6 +106,8 @@ struct CSR {
     val.alloc(nz, s);
     col16.release();
     cbase.release();
+    rblk.release();
+    nrblk = 0;
   }
 };
 
@@ -121,10 +127,12 @@ struct OpView {
   int64_t nnz;
   const uint16_t* col16;  // compressed columns, or null
   const int32_t* cbase;
+  const int32_t* rblk;    // row blocks, or null
+  int64_t nrblk;
 };
 inline OpView opview(const CSR& A) {
   return {A.rowptr.get(), A.col.get(), A.val.get(), VT_F64, A.rows, A.nnz, A.col16.get(),
-          A.cbase.get()};
+          A.cbase.get(), A.rblk.get(), A.nrblk};
 }
 
 // Read-only view passed to kernels.

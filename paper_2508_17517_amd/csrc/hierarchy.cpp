@@ -530,16 +530,21 @@ void finalize_hierarchy(Hierarchy& H) {
       lower(L.Z, L.z32, L.z16);
     }
   }
-  // compressed columns for every solve operator whose row blocks allow them
-  compress_columns(H.Aperm, s);
+  // compressed columns for every solve operator whose row blocks allow them,
+  // and row blocks for the operators with long rows
+  auto prepare = [&](CSR& A) {
+    compress_columns(A, s);
+    if (A.rows > 0 && A.nnz >= 8 * A.rows) build_row_blocks(A, s);
+  };
+  prepare(H.Aperm);
   for (Level& L : H.levels) {
     if (L.coarsest) {
-      compress_columns(L.A, s);
+      prepare(L.A);
       continue;
     }
-    compress_columns(L.Aff, s);
-    compress_columns(L.B, s);
-    compress_columns(L.Z, s);
+    prepare(L.Aff);
+    prepare(L.B);
+    prepare(L.Z);
   }
   // every solve-phase operator is checked once, so an inconsistent hierarchy
   // (for example a bad import) fails here instead of in a kernel

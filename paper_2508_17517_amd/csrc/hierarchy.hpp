@@ -42,6 +42,8 @@ struct Level {
   DBuf<int32_t> pos;        // setup index -> nested position on this level
   std::vector<double> alpha;
   std::vector<cplx> roots;
+  // launch shapes of the products: lanes per row (bits 0-7, 0 = row-block
+  // kernel) and the XCD mapping (bit 8)
   int tpr_ff = 1, tpr_b = 1, tpr_z = 1, tpr_a = 1;
   // the coarsest level's A is stored in its solve order (pos) when true
   bool a_permuted = false;

@@ -237,6 +237,9 @@ void merge_fc_ffw(const CSR& Afc, const CSR& Aff, const int32_t* cmap, CSR& B, h
 // Build A's compressed column form (see CSR::col16) if every block of rows
 // spans fewer than 65536 columns; returns whether it did.
 bool compress_columns(CSR& A, hipStream_t s);
+// Row blocks of A for the row-block product (lanes per row 0): at most 64
+// consecutive rows of one 64-row group with at most 2048 entries, or one row.
+void build_row_blocks(CSR& A, hipStream_t s);
 // Sort the entries of every row by column (insertion sort per row).
 void sort_rows(CSR& A, hipStream_t s);
 // Explicit transpose with ascending columns.

@@ -265,8 +265,41 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
   int its = 0, restarts = 0;
   double est_rel = 0.0;
   std::vector<double> rn(ng, 0.0);
+  std::vector<double> ref = bn;  // the norms the relative residuals refer to
   bool converged = false;
-  if (bnorm == 0.0) {
+  if (H.p.outer == AIRG_OUTER_RICHARDSON) {
+    // undamped Richardson x <- x + M (b - A x) (Sec. 3); a group with b = 0
+    // is measured against its initial residual
+    double* r = W.V.get();
+    double* e = W.Zb.get();
+    const double one = 1.0;
+    W.ybuf.from_host(&one, 1);
+    auto residual = [&]() {
+      spmv_t<double>(opview(H.Aperm), H.tpr_top, K, W.xperm.get(), W.w.get(), s);
+      launch_sub(r, W.bperm.get(), W.w.get(), n, s);
+      rn = group_norms(H, W, r);
+      for (size_t q = 0; q < ng; ++q)
+        if (!std::isfinite(rn[q])) fail(AIRG_ERR_BREAKDOWN, "Richardson diverged (non-finite residual)");
+    };
+    auto done = [&]() {
+      for (size_t q = 0; q < ng; ++q)
+        if (!(rn[q] <= rtol * ref[q])) return false;
+      return true;
+    };
+    residual();
+    for (size_t q = 0; q < ng; ++q)
+      if (ref[q] == 0.0) ref[q] = rn[q];
+    converged = done();
+    while (!converged && its < max_it) {
+      vcycle(H, W, r, e);
+      launch_basis_combine(W.xperm.get(), e, W.ld, W.ybuf.get(), 1, n, s);
+      ++its;
+      residual();
+      converged = done();
+    }
+    est_rel = 0.0;
+    for (size_t q = 0; q < ng; ++q) est_rel = std::max(est_rel, ref[q] > 0 ? rn[q] / ref[q] : 0.0);
+  } else if (bnorm == 0.0) {
     launch_fill(W.xperm.get(), n, 0.0, s);  // the solution of A x = 0
     converged = true;
   } else {
@@ -354,8 +387,8 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
   for (size_t q = 0; q < ng; ++q) {
     out[q].iterations = its;
     out[q].restarts = restarts;
-    out[q].converged = rn[q] <= rtol * bn[q] ? 1 : 0;
-    out[q].rel_residual = bn[q] > 0.0 ? rn[q] / bn[q] : 0.0;
+    out[q].converged = rn[q] <= rtol * ref[q] ? 1 : 0;
+    out[q].rel_residual = ref[q] > 0.0 ? rn[q] / ref[q] : 0.0;
     out[q].rel_residual_estimate = est_rel;
     out[q].solve_ms = ms;
   }
@@ -512,41 +545,58 @@ int autotune(Hierarchy& H, Workspace& W, int reps, std::vector<airg_tune_entry>&
     airg_tune_entry e{};
     e.level = g.level;
     e.op = g.op;
-    e.default_lanes = *g.tpr;
+    e.default_lanes = *g.tpr & 0xff;
+    e.default_xcd_map = (*g.tpr >> 8) & 1;
     e.best_us = 1e300;
-    for (int tpr = 1; tpr <= 64; tpr <<= 1) {
+    e.default_us = 1e300;
+    int best = *g.tpr;
+    for (int tpr = g.A.rblk ? 0 : 1; tpr <= 64; tpr = tpr ? tpr << 1 : 1) {
       if (g.A.rows * (int64_t)tpr > (int64_t)INT32_MAX) break;
-      const double us = g.f64 ? time_product<double>(g.A, tpr, x64, W.w.get(), reps, W, s)
-                              : time_product<float>(g.A, tpr, x32, W.e32.get(), reps, W, s);
-      if (tpr == e.default_lanes) e.default_us = us;
-      if (us < e.best_us) {
-        e.best_us = us;
-        e.lanes = tpr;
+      for (int xcd = 0; xcd < 2; ++xcd) {
+        const int shape = tpr | (xcd << 8);
+        const double us = g.f64 ? time_product<double>(g.A, shape, x64, W.w.get(), reps, W, s)
+                                : time_product<float>(g.A, shape, x32, W.e32.get(), reps, W, s);
+        if (shape == *g.tpr) e.default_us = us;
+        if (us < e.best_us) {
+          e.best_us = us;
+          best = shape;
+        }
       }
     }
-    *g.tpr = e.lanes;
+    e.lanes = best & 0xff;
+    e.xcd_map = (best >> 8) & 1;
+    *g.tpr = best;
     out.push_back(e);
   }
   return AIRG_OK;
 }
 
-void set_lanes(Hierarchy& H, int level, int op, int lanes) {
-  if (lanes < 1 || lanes > 64 || (lanes & (lanes - 1)))
-    fail(AIRG_ERR_INVALID, "lanes must be a power of two in 1..64");
+void set_lanes(Hierarchy& H, int level, int op, int lanes, int xcd_map) {
+  if (lanes < 0 || lanes > 64 || (lanes & (lanes - 1)))
+    fail(AIRG_ERR_INVALID, "lanes must be 0 or a power of two in 1..64");
+  if (xcd_map != 0 && xcd_map != 1) fail(AIRG_ERR_INVALID, "xcd_map must be 0 or 1");
   const int L = (int)H.levels.size() - 1;
-  switch (op) {
-    case AIRG_OP_TOP: H.tpr_top = lanes; return;
-    case AIRG_OP_A: H.levels[L].tpr_a = lanes; return;
-    default: break;
+  const CSR* A = nullptr;
+  int* tpr = nullptr;
+  if (op == AIRG_OP_TOP) {
+    A = &H.Aperm;
+    tpr = &H.tpr_top;
+  } else if (op == AIRG_OP_A) {
+    A = &H.levels[L].A;
+    tpr = &H.levels[L].tpr_a;
+  } else {
+    if (level < 0 || level >= L) fail(AIRG_ERR_INVALID, "level has no such operator");
+    Level& lv = H.levels[level];
+    switch (op) {
+      case AIRG_OP_FF: A = &lv.Aff; tpr = &lv.tpr_ff; break;
+      case AIRG_OP_B: A = &lv.B; tpr = &lv.tpr_b; break;
+      case AIRG_OP_Z: A = &lv.Z; tpr = &lv.tpr_z; break;
+      default: fail(AIRG_ERR_INVALID, "unknown operator");
+    }
   }
-  if (level < 0 || level >= L) fail(AIRG_ERR_INVALID, "level has no such operator");
-  Level& lv = H.levels[level];
-  switch (op) {
-    case AIRG_OP_FF: lv.tpr_ff = lanes; break;
-    case AIRG_OP_B: lv.tpr_b = lanes; break;
-    case AIRG_OP_Z: lv.tpr_z = lanes; break;
-    default: fail(AIRG_ERR_INVALID, "unknown operator");
-  }
+  if (lanes == 0 && !A->rblk.get())
+    fail(AIRG_ERR_INVALID, "this operator has no row blocks (rows shorter than 8 on average)");
+  *tpr = lanes | (xcd_map << 8);
 }
 
 }  // namespace airg

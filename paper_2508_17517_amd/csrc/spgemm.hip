@@ -2,10 +2,12 @@
 // fixed_sparsity, prolong and the coarse product R A P).
 //
 // C = A B is formed row by row with a k-way merge of the sorted rows of B
-// selected by row i of A: one thread walks the merge, so every c_ij is
-// accumulated over k in ascending order starting from 0.0 and the result does
+// selected by row i of A (one thread per row for short rows of A, one
+// wavefront per row for longer ones), so every c_ij is accumulated over A's
+// entries in stored (ascending k) order starting from 0.0 and the result does
 // not depend on scheduling.  Exact zeros are dropped afterwards.
 #include <cmath>
+#include <vector>
 
 #include "kernels.hpp"
 
@@ -126,17 +128,133 @@ static void drop_zeros(const CSR& in, CSR& out, hipStream_t s) {
   }
 }
 
+// The same merge with one wavefront per row of A: lane l holds the cursors of
+// A's entries s + l + 64 t (t < T), the smallest pending column is found with
+// a wave-wide min, and the products of the entries that hit it are added in
+// ascending entry order (t, then lane) -- the order of the one-thread merge,
+// so the results agree bit for bit.  Rows are visited in a wave-stride loop.
+__device__ __forceinline__ int wave_min_i32(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int T, bool NUMERIC>
+__global__ __launch_bounds__(256) void wave_merge_kernel(CSRView A, CSRView B,
+                                                         const int32_t* rowptrC, int32_t* colC,
+                                                         double* valC, int64_t* count,
+                                                         int64_t nwaves) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (w0 >= nwaves) return;  // the grid's last block may hold spare waves
+  for (int64_t i = w0; i < A.rows; i += nwaves) {
+    const int s = A.rowptr[i], e = A.rowptr[i + 1];
+    int q[T], qe[T], head[T];
+    double a[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int p = s + lane + 64 * t;
+      q[t] = qe[t] = 0;
+      a[t] = 0.0;
+      head[t] = 0x7fffffff;
+      if (p < e) {
+        const int k = A.col[p];
+        q[t] = B.rowptr[k];
+        qe[t] = B.rowptr[k + 1];
+        a[t] = A.val[p];
+        if (q[t] < qe[t]) head[t] = B.col[q[t]];
+      }
+    }
+    int64_t o = NUMERIC ? (int64_t)rowptrC[i] : 0;
+    int64_t c = 0;
+    for (;;) {
+      int m = 0x7fffffff;
+#pragma unroll
+      for (int t = 0; t < T; ++t) m = min(m, head[t]);
+      m = wave_min_i32(m);
+      if (m == 0x7fffffff) break;
+      if constexpr (NUMERIC) {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          const bool hit = head[t] == m;
+          double prod = 0.0;
+          if (hit) prod = a[t] * B.val[q[t]];
+          unsigned long long mask = __ballot(hit);
+          while (mask) {
+            const int l = __ffsll(mask) - 1;
+            mask &= mask - 1;
+            acc = acc + __shfl(prod, l, 64);
+          }
+        }
+        if (lane == 0) {
+          colC[o] = m;
+          valC[o] = acc;
+        }
+        ++o;
+      } else {
+        ++c;
+      }
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+        if (head[t] == m) {
+          ++q[t];
+          head[t] = q[t] < qe[t] ? B.col[q[t]] : 0x7fffffff;
+        }
+    }
+    if (!NUMERIC && lane == 0) count[i] = c;
+  }
+}
+
+__global__ void max_row_len_kernel(CSRView A, unsigned long long* mx) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < A.rows) atomicMax(mx, (unsigned long long)(A.rowptr[i + 1] - A.rowptr[i]));
+}
+
+template <bool NUMERIC>
+static void launch_wave_merge(int T, const CSR& A, const CSR& B, const int32_t* rowptrC,
+                              int32_t* colC, double* valC, int64_t* count, hipStream_t s) {
+  const int64_t nwaves = std::min<int64_t>(A.rows, (int64_t)1 << 22);
+  const unsigned nb = blocks_for(nwaves * 64, 256);
+  switch (T) {
+    case 1: wave_merge_kernel<1, NUMERIC><<<nb, 256, 0, s>>>(view(A), view(B), rowptrC, colC, valC, count, nwaves); break;
+    case 2: wave_merge_kernel<2, NUMERIC><<<nb, 256, 0, s>>>(view(A), view(B), rowptrC, colC, valC, count, nwaves); break;
+    case 4: wave_merge_kernel<4, NUMERIC><<<nb, 256, 0, s>>>(view(A), view(B), rowptrC, colC, valC, count, nwaves); break;
+    case 8: wave_merge_kernel<8, NUMERIC><<<nb, 256, 0, s>>>(view(A), view(B), rowptrC, colC, valC, count, nwaves); break;
+    default: fail(AIRG_ERR_INTERNAL, "bad cursor count");
+  }
+  AIRG_CHECK_LAUNCH();
+}
+
 void spgemm(const CSR& A, const CSR& B, CSR& C, hipStream_t s) {
   if (A.cols != B.rows) fail(AIRG_ERR_INTERNAL, "spgemm shape mismatch");
   const int64_t n = A.rows;
   unsigned nb = blocks_for(n, kBlock);
-  DBuf<int32_t> cur(A.nnz, s);
+  // rows of A with more than 8 entries: one wavefront per row; else one thread
+  int T = 0;
+  if (n > 0) {
+    DBuf<unsigned long long> mx(1, s);
+    launch_zero_bytes(mx.get(), sizeof(unsigned long long), s);
+    max_row_len_kernel<<<nb, kBlock, 0, s>>>(view(A), mx.get());
+    AIRG_CHECK_LAUNCH();
+    const unsigned long long la = fetch(mx.get(), s);
+    if (la > 8 && la <= 512) {
+      T = 1;
+      while (64 * (unsigned long long)T < la) T <<= 1;
+    }
+  }
+  DBuf<int32_t> cur;
+  if (T == 0) cur.alloc(A.nnz, s);
   DBuf<int64_t> cnt(n, s), off;
   if (n > 0) {
-    merge_init_kernel<<<nb, kBlock, 0, s>>>(view(A), view(B), cur.get());
-    AIRG_CHECK_LAUNCH();
-    merge_count_kernel<<<nb, kBlock, 0, s>>>(view(A), view(B), cur.get(), cnt.get());
-    AIRG_CHECK_LAUNCH();
+    if (T) {
+      launch_wave_merge<false>(T, A, B, nullptr, nullptr, nullptr, cnt.get(), s);
+    } else {
+      merge_init_kernel<<<nb, kBlock, 0, s>>>(view(A), view(B), cur.get());
+      AIRG_CHECK_LAUNCH();
+      merge_count_kernel<<<nb, kBlock, 0, s>>>(view(A), view(B), cur.get(), cnt.get());
+      AIRG_CHECK_LAUNCH();
+    }
   }
   scan_counts(cnt, n, off, s);
   CSR full;
@@ -146,11 +264,16 @@ void spgemm(const CSR& A, const CSR& B, CSR& C, hipStream_t s) {
   full.col.alloc(full.nnz, s);
   full.val.alloc(full.nnz, s);
   if (n > 0) {
-    merge_init_kernel<<<nb, kBlock, 0, s>>>(view(A), view(B), cur.get());
-    AIRG_CHECK_LAUNCH();
-    merge_numeric_kernel<<<nb, kBlock, 0, s>>>(view(A), view(B), cur.get(), full.rowptr.get(),
-                                               full.col.get(), full.val.get());
-    AIRG_CHECK_LAUNCH();
+    if (T) {
+      launch_wave_merge<true>(T, A, B, full.rowptr.get(), full.col.get(), full.val.get(), nullptr,
+                              s);
+    } else {
+      merge_init_kernel<<<nb, kBlock, 0, s>>>(view(A), view(B), cur.get());
+      AIRG_CHECK_LAUNCH();
+      merge_numeric_kernel<<<nb, kBlock, 0, s>>>(view(A), view(B), cur.get(), full.rowptr.get(),
+                                                 full.col.get(), full.val.get());
+      AIRG_CHECK_LAUNCH();
+    }
   }
   drop_zeros(full, C, s);
 }
@@ -729,6 +852,40 @@ bool compress_columns(CSR& A, hipStream_t s) {
   col16_kernel<<<blocks_for(A.rows, kBlock), kBlock, 0, s>>>(view(A), A.cbase.get(), A.col16.get());
   AIRG_CHECK_LAUNCH();
   return true;
+}
+
+// ------------------------------------------------------------------ row blocks
+// Row blocks for the row-block product: greedy over the rows, a block takes
+// consecutive rows of one 64-row group while its entries fit in
+// kRowBlockEntries; a longer row is a block by itself.
+void build_row_blocks(CSR& A, hipStream_t s) {
+  constexpr int64_t kRowBlockEntries = 2048;
+  A.rblk.release();
+  A.nrblk = 0;
+  if (A.rows <= 0) return;
+  std::vector<int32_t> rp(A.rows + 1);
+  A.rowptr.to_host(rp.data(), A.rows + 1);
+  AIRG_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> rb;
+  rb.reserve(A.rows / 4 + 2);
+  int64_t r = 0;
+  rb.push_back(0);
+  while (r < A.rows) {
+    const int64_t start = r;
+    const int64_t gend = std::min<int64_t>(((r >> kColBlockShift) + 1) << kColBlockShift, A.rows);
+    int64_t nz = 0;
+    while (r < gend) {
+      const int64_t len = rp[r + 1] - rp[r];
+      if (r > start && nz + len > kRowBlockEntries) break;
+      nz += len;
+      ++r;
+    }
+    rb.push_back((int32_t)r);
+  }
+  A.nrblk = (int64_t)rb.size() - 1;
+  A.rblk.alloc(rb.size(), s);
+  A.rblk.from_host(rb.data(), rb.size());
+  AIRG_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace airg

@@ -101,12 +101,29 @@ __device__ __forceinline__ X row_dot(const CSRT<MV, C16>& A, int s, int e, int b
   return row_dot_cols<TPR, U, K>(A, s, e, b, lane, x, c, idx, sum);
 }
 
+// Workgroups go to the 8 XCDs round robin (workgroup i to XCD i mod 8), and
+// each XCD has its own L2.  With the XCD mapping (launch shape bit 8) the grid
+// is padded to a multiple of 8 and workgroup i takes row block
+// (i mod 8) * (grid / 8) + i / 8, so every XCD sweeps one contiguous eighth of
+// the rows and the x elements that neighbouring rows share are fetched into
+// one L2, not up to eight; without it workgroup i takes block i, which spreads
+// uneven rows evenly over the XCDs.  The tuner picks per operator.
+__device__ __forceinline__ int64_t row_block_index(int xcd) {
+  if (!xcd) return blockIdx.x;
+  const int64_t per = gridDim.x >> 3;
+  return (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+static unsigned grid_for(int64_t rows, int rows_per_block, int xcd) {
+  const int64_t nb = (rows + rows_per_block - 1) / rows_per_block;
+  return (unsigned)(xcd ? (nb + 7) & ~(int64_t)7 : (nb < 1 ? 1 : nb));
+}
+
 // lanes-per-row kernel (K = 1)
 template <int TPR, class MV, bool C16, class X, class Epi>
 __global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV, C16> A, const X* __restrict__ x,
-                                                   Epi epi) {
+                                                   Epi epi, int xcd) {
   const int lane = threadIdx.x & (TPR - 1);
-  const int64_t row = (int64_t)blockIdx.x * (256 / TPR) + threadIdx.x / TPR;
+  const int64_t row = row_block_index(xcd) * (256 / TPR) + threadIdx.x / TPR;
   const bool live = row < A.rows;
   typename Epi::Pre pre{};
   if (live && lane == 0) pre = epi.pre(row);
@@ -125,9 +142,9 @@ __global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV, C16> A, const X* __r
 // runs left to right from 0, as the TPR = 1 kernel does
 template <int K, class MV, bool C16, class X, class Epi>
 __global__ __launch_bounds__(256) void spmm_kernel(CSRT<MV, C16> A, const X* __restrict__ x,
-                                                   Epi epi) {
+                                                   Epi epi, int xcd) {
   const int c = threadIdx.x & (K - 1);
-  const int64_t row = (int64_t)blockIdx.x * (256 / K) + threadIdx.x / K;
+  const int64_t row = row_block_index(xcd) * (256 / K) + threadIdx.x / K;
   if (row >= A.rows) return;
   const typename Epi::Pre pre = epi.pre(row * K + c);
   const X sum = row_dot<1, 4, K>(A, A.rowptr[row], A.rowptr[row + 1], A.base(row), 0, x, c,
@@ -135,33 +152,102 @@ __global__ __launch_bounds__(256) void spmm_kernel(CSRT<MV, C16> A, const X* __r
   epi(row * K + c, sum, pre);
 }
 
+// Row-block kernel (K = 1, selected with tpr = 0): a workgroup takes one row
+// block -- up to 64 consecutive rows inside one 64-row group, holding at most
+// kRowBlockNnz entries, or a single longer row -- and loads all its entries
+// at once, 8 per thread, coalesced across the workgroup; their products go to
+// LDS and each row's owner thread then adds its products left to right from
+// 0.  The sum order is that of the TPR = 1 kernel, so the results are the
+// same bit for bit; what changes is that a workgroup needs two dependent
+// memory round trips for all of its rows, which suits long rows.
+constexpr int kRowBlockNnz = 2048;
+
 template <class MV, bool C16, class X, class Epi>
-static void launch_spmv_t(const OpView& Av, int tpr, int K, const X* x, Epi epi, hipStream_t s) {
+__global__ __launch_bounds__(256) void spmv_rowblock_kernel(CSRT<MV, C16> A,
+                                                            const int32_t* __restrict__ rblk,
+                                                            int64_t nblk, const X* __restrict__ x,
+                                                            Epi epi, int xcd) {
+  __shared__ X prod[kRowBlockNnz];
+  const int64_t b = row_block_index(xcd);
+  if (b >= nblk) return;
+  const int t = threadIdx.x;
+  const int r0 = rblk[b], r1 = rblk[b + 1];
+  const int64_t row = (int64_t)r0 + t;
+  const bool mine = row < r1;
+  typename Epi::Pre pre{};
+  int rs = 0, re = 0;
+  if (mine) {
+    pre = epi.pre(row);
+    rs = A.rowptr[row];
+    re = A.rowptr[row + 1];
+  }
+  const int p0 = A.rowptr[r0], p1 = A.rowptr[r1];
+  const int base = A.base(r0);  // one 64-row group per block
+  X sum = 0;
+  for (int c0 = p0; c0 < p1; c0 += kRowBlockNnz) {  // one pass unless a single long row
+    const int c1 = min(c0 + kRowBlockNnz, p1);
+    int col[8];
+    X v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int p = c0 + t + 256 * u;
+      bool in = p < c1;
+      if constexpr (C16) col[u] = in ? (base >= 0 ? A.column(p, base) : A.col[p]) : 0;
+      else col[u] = in ? A.col[p] : 0;
+      v[u] = in ? (X)ldv(A.val[p]) : X(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int p = c0 + t + 256 * u;
+      if (p < c1) prod[p - c0] = v[u] * x[col[u]];
+    }
+    __syncthreads();
+    if (mine) {
+      const int e = min(re, c1);
+      for (int p = max(rs, c0); p < e; ++p) sum = sum + prod[p - c0];
+    }
+    __syncthreads();
+  }
+  if (mine) epi(row, sum, pre);
+}
+
+// shape: lanes per row in bits 0-7 (0: the row-block kernel), the XCD
+// mapping in bit 8
+template <class MV, bool C16, class X, class Epi>
+static void launch_spmv_t(const OpView& Av, int shape, int K, const X* x, Epi epi, hipStream_t s) {
   if (Av.rows <= 0) return;
+  const int tpr = shape & 0xff, xcd = (shape >> 8) & 1;
+  CSRT<MV, C16> A = csr_t<MV, C16>(Av);
+  if (K == 1 && tpr == 0) {
+    if (!Av.rblk) fail(AIRG_ERR_INTERNAL, "row-block product without row blocks");
+    spmv_rowblock_kernel<MV, C16, X, Epi><<<grid_for(Av.nrblk, 1, xcd), 256, 0, s>>>(
+        A, Av.rblk, Av.nrblk, x, epi, xcd);
+    AIRG_CHECK_LAUNCH();
+    return;
+  }
   if (Av.rows * (int64_t)(K == 1 ? tpr : K) > (int64_t)INT32_MAX)
     fail(AIRG_ERR_INVALID, "product launch exceeds 2^31 threads (fewer lanes or columns needed)");
-  CSRT<MV, C16> A = csr_t<MV, C16>(Av);
   if (K == 1) {
-    unsigned nb = blocks_for(Av.rows, 256 / tpr);
+    unsigned nb = grid_for(Av.rows, 256 / tpr, xcd);
     switch (tpr) {
-      case 1: spmv_kernel<1, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 2: spmv_kernel<2, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 4: spmv_kernel<4, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 8: spmv_kernel<8, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 16: spmv_kernel<16, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 32: spmv_kernel<32, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 64: spmv_kernel<64, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 1: spmv_kernel<1, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 2: spmv_kernel<2, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 4: spmv_kernel<4, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 8: spmv_kernel<8, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 16: spmv_kernel<16, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 32: spmv_kernel<32, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 64: spmv_kernel<64, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
       default: fail(AIRG_ERR_INTERNAL, "bad lanes-per-row");
     }
   } else {
-    unsigned nb = blocks_for(Av.rows, 256 / K);
+    unsigned nb = grid_for(Av.rows, 256 / K, xcd);
     switch (K) {
-      case 2: spmm_kernel<2, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 4: spmm_kernel<4, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 8: spmm_kernel<8, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 16: spmm_kernel<16, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 32: spmm_kernel<32, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
-      case 64: spmm_kernel<64, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi); break;
+      case 2: spmm_kernel<2, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 4: spmm_kernel<4, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 8: spmm_kernel<8, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 16: spmm_kernel<16, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 32: spmm_kernel<32, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 64: spmm_kernel<64, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
       default: fail(AIRG_ERR_INTERNAL, "column count must be a power of two <= 64");
     }
   }

@@ -187,17 +187,46 @@ def test_autotuned_shapes_keep_the_solution_and_can_be_pinned():
     tuned = s.autotune(reps=3)
     st = s.stats()
     assert len(tuned) == 3 * (st["levels"] - 1) + 2
-    assert all(t["lanes"] in (1, 2, 4, 8, 16, 32, 64) for t in tuned)
+    assert all(t["lanes"] in (0, 1, 2, 4, 8, 16, 32, 64) for t in tuned)
+    assert all(t["xcd_map"] in (0, 1) for t in tuned)
     assert all(t["best_us"] <= t["default_us"] for t in tuned)
     x1, i1 = s.solve(b)
     assert i1["converged"] == 1 and abs(i1["iterations"] - i0["iterations"]) <= 1
     assert float(torch.linalg.norm(x1 - x0) / torch.linalg.norm(x0)) <= 1e-8
     # pinned shapes give bit-identical solves
     for t in tuned:
-        s.set_lanes(t["level"], t["op"], 64 if t["op"] == "a" else 1)
+        s.set_lanes(t["level"], t["op"], 64 if t["op"] == "a" else 1, t["xcd_map"])
     x2, _ = s.solve(b)
     x3, _ = s.solve(b)
     assert torch.equal(x2, x3)
     with pytest.raises(AirgError):
         s.set_lanes(0, "ff", 3)
+    s.close()
+
+
+def test_row_block_kernel_sums_like_one_lane_per_row():
+    # the row-block product adds each row's products in the one-lane order,
+    # so pinning it instead of one lane per row changes no bit of the solve
+    _needs_gpu()
+    from paper_2508_17517_amd import AirgError, Solver
+    p = workloads.dg_random(48, 0.4, True)
+    s = Solver(p.indptr, p.indices, p.data)
+    st = s.stats()
+    ops = [(l, op) for l in range(st["levels"] - 1) for op in ("ff", "b", "z")]
+    ops += [(st["levels"] - 1, "a"), (0, "top")]
+    for l, op in ops:
+        s.set_lanes(l, op, 1)
+    b = torch.from_numpy(p.b).cuda()
+    x1, i1 = s.solve(b)
+    switched = 0
+    for l, op in ops:
+        try:
+            s.set_lanes(l, op, 0, 1)
+            switched += 1
+        except AirgError:
+            pass
+    assert switched >= 1
+    x0, i0 = s.solve(b)
+    assert i0["iterations"] == i1["iterations"]
+    assert torch.equal(x0, x1)
     s.close()

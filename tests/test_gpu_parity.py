@@ -13,7 +13,7 @@ import pytest
 import scipy.sparse as sp
 
 import oracle
-from airg_inputs import workloads, fv_advection
+from airg_inputs import workloads, fv_advection, fd_advection
 
 pytestmark = pytest.mark.gpu
 
@@ -37,6 +37,7 @@ CASES = {
     "fv100_theta1": lambda: workloads.fv_random(100, 1.0, True),
     "fv80x40_rect": lambda: workloads.fv_random(80, 0.7, True, ny=40),
     "dg24_perm": lambda: workloads.dg_random(24, math.pi / 5, True),
+    "fd48_paper_g05": lambda: fd_advection(48, math.pi / 4, 0.5),
     "dg20x12_rect": lambda: workloads.dg_random(20, 1.2, True, ny=12),
 }
 
@@ -322,3 +323,30 @@ def test_locality_order_changes_only_the_summation_order():
     assert float(torch.linalg.norm(x0 - x1) / torch.linalg.norm(x0)) <= 1e-11
     s0.close()
     s1.close()
+
+
+PAPER_OPTS = dict(poly_order=6, coarse_poly_order=10, trunc_tol=0.1)
+
+
+@pytest.mark.parametrize("case", ["fd64_paper", "fv64_perm"])
+def test_richardson_matches_oracle(case):
+    # the paper's outer loop: undamped Richardson from x0 = 1 (Sec. 3)
+    _needs_gpu()
+    if case == "fd64_paper":
+        p = fd_advection(64, math.pi / 4, 0.0)
+    else:
+        p = workloads.fv_random(64, 0.8, True)
+    print(f"case {case} n={p.n}", flush=True)
+    prm = oracle.Params(outer="richardson", **PAPER_OPTS)
+    x0 = np.ones(p.n)
+    xo, its, rel, levels, hist = oracle.solve(p.scipy(), p.b, prm, x0=x0)
+    s = _solver(p, outer=1, **PAPER_OPTS)
+    x = torch.ones(p.n, dtype=torch.float64, device="cuda")
+    x, info = s.solve(torch.from_numpy(p.b).cuda(), x=x, guess=True)
+    xg = x.cpu().numpy()
+    assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
+    assert info["iterations"] == its
+    assert abs(info["rel_residual"] - rel) <= 1e-3 * rel + 1e-16
+    scale = max(np.linalg.norm(xo), np.linalg.norm(x0))
+    assert np.linalg.norm(xg - xo) <= 1e-10 * scale
+    s.close()

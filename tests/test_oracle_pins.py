@@ -435,3 +435,42 @@ def test_gradients_match_finite_differences():
         assert dgw[j] == pytest.approx(fdj, rel=1e-7, abs=1e-9)
         fdj = (loss(theta, gw, gs + h * e) - loss(theta, gw, gs - h * e)) / (2 * h)
         assert dgs[j] == pytest.approx(fdj, rel=1e-7, abs=1e-9)
+
+
+# --------------------------------------------------------------------- Richardson (Sec. 3)
+
+def test_richardson_residuals_follow_the_error_propagator():
+    # r_k = (I - A M)^k r_0 for the V-cycle M, with M formed column by column
+    p = workloads.fv_random(10, 0.6, True)
+    A = p.scipy()
+    levels = oracle.setup(A)
+    M = lambda v: oracle.vcycle(levels, v)  # noqa: E731
+    n = p.n
+    Mm = np.column_stack([M(e) for e in np.eye(n)])
+    E = np.eye(n) - A.toarray() @ Mm
+    x0 = np.ones(n)
+    x, its, rel, hist = oracle.richardson(A, M, p.b, rtol=1e-12, x0=x0)
+    r = p.b - A @ x0
+    for k in range(1, min(its, 6) + 1):
+        r = E @ r
+        assert abs(np.linalg.norm(r) - hist[k]) <= 1e-10 * hist[0]
+
+
+def test_richardson_with_an_exact_inverse_takes_one_step():
+    p = workloads.fv_random(12, 1.0, True)
+    A = p.scipy()
+    lu = sp.linalg.splu(A.tocsc())
+    x, its, rel, _ = oracle.richardson(A, lu.solve, p.b, rtol=1e-10)
+    assert its == 1 and rel <= 1e-13
+
+
+def test_richardson_on_the_paper_fd_system_goes_to_zero():
+    # g = 0 and x0 = 1 (Sec. 3): the solution is 0 and the test is relative to r_0
+    from airg_inputs import fd_advection
+    p = fd_advection(40, math.pi / 4, 0.0)
+    A = p.scipy()
+    prm = oracle.Params(outer="richardson", poly_order=6, coarse_poly_order=10, trunc_tol=0.1)
+    x, its, rel, levels, hist = oracle.solve(A, p.b, prm, x0=np.ones(p.n))
+    assert rel <= 1e-10 and its < 20
+    assert np.abs(x).max() <= 1e-9
+    assert hist[-1] <= 1e-10 * hist[0]
