@@ -231,6 +231,94 @@ def dg_legs(a, side=1024):
     return res
 
 
+PAPER_SINGLE_GCD = {  # Sec. 3.1, one MI250X GCD, 13M unknowns, pi/4, d = 6
+    "truncated_mc10": {"iterations": 7, "levels": 13, "cycle_complexity": 28.0,
+                       "storage_complexity": 10.22},
+    "untruncated": {"iterations": 7, "levels": 22, "cycle_complexity": 27.2,
+                    "storage_complexity": 10.21},
+}
+
+
+def paper_legs(a, side=3606):
+    """The paper's own setting (Sec. 3): FD with the inflow boundary nodes kept,
+    theta = pi/4, g = 0, x0 = 1, undamped Richardson to 1e-10 of the initial
+    residual, smoother degree 6, truncation 1e-1 with coarse degree 10 (and
+    100), and without truncation; the paper's single-GCD figures alongside."""
+    import torch
+    from airg_inputs import workloads
+    from paper_2508_17517_amd import Solver, binding
+    print(f"bench: paper: generating FD {side}x{side}", file=sys.stderr, flush=True)
+    p = workloads.fd_paper(side)
+    ip = torch.from_numpy(p.indptr).cuda()
+    ix = torch.from_numpy(p.indices).cuda()
+    dv = torch.from_numpy(p.data).cuda()
+    b = torch.from_numpy(p.b).cuda()
+    res = {"workload": f"FD {side}x{side} (inflow boundary nodes kept), theta pi/4, g = 0, x0 = 1, "
+                       "Richardson rtol 1e-10, d = 6", "n": p.n, "nnz": p.nnz, "paper": PAPER_SINGLE_GCD}
+    legs = (("truncated_mc10", dict(coarse_poly_order=10, trunc_tol=0.1)),
+            ("truncated_mc100", dict(coarse_poly_order=100, trunc_tol=0.1)),
+            ("untruncated", dict(coarse_poly_order=10, trunc_tol=0.0)))
+    for name, over in legs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sm = Solver(ip, ix, dv, poly_order=6, outer=binding.OUTER_RICHARDSON, **over)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        _tune(sm)
+        x = torch.ones_like(b)
+
+        def run():
+            x.fill_(1.0)
+            return sm.solve(b, x=x, guess=True)
+        dt, (x, info) = _timed(run, 1, max(1, min(a.steps, 3)))
+        assert info["converged"] == 1, info
+        st = sm.stats()
+        leg = {"iterations": info["iterations"], "rel_residual": info["rel_residual"],
+               "levels": st["levels"], "cycle_complexity": round(st["cycle_complexity"], 2),
+               "storage_complexity": round(st["storage_complexity"], 2),
+               "grid_complexity": round(st["grid_complexity"], 3), "setup_s": round(setup_s, 3),
+               "solve_ms": round(1e3 * dt, 3), "value": p.n / dt, "unit": "DOF/s",
+               "dof_per_s_per_vcycle": p.n * info["iterations"] / dt}
+        res[name] = leg
+        print(f"bench: paper {name}: {leg}", file=sys.stderr, flush=True)
+        sm.close()
+    return res
+
+
+def mixed_legs(a, p, x64, value64, ip, ix, dv, b):
+    """FP32 and BF16 storage in the V-cycle inside FP64 FGMRES on the bench
+    workload, to the same 1e-10 true FP64 residual."""
+    import torch
+    from paper_2508_17517_amd import Solver, binding
+    res = {}
+    xref = x64.clone()
+    for name, prec in (("fp32", binding.FP32), ("bf16", binding.BF16)):
+        sm = Solver(ip, ix, dv, precision=prec)
+        _tune(sm)
+        xm = torch.zeros_like(b)
+        dtm, (xm, im) = _timed(lambda: sm.solve(b, xm), a.warmup, a.steps)
+        assert im["converged"] == 1 and im["rel_residual"] <= 1e-10, im
+        err = float(torch.linalg.norm(xm - xref) / torch.linalg.norm(xref))
+        ktm = sm.time_kernels("poly", reps=a.kernel_reps)
+        res[name] = {"value": p.n / dtm, "ms_per_step": 1000.0 * dtm,
+                     "iterations": im["iterations"], "rel_residual": im["rel_residual"],
+                     "rel_diff_vs_fp64_solution": err, "speedup_vs_fp64": (p.n / dtm) / value64,
+                     "poly_gbps": ktm["bytes_per_launch"] / (ktm["avg_launch_ms"] * 1e-3) / 1e9}
+        print(f"bench: {name}: {res[name]}", file=sys.stderr, flush=True)
+        sm.close()
+    return res
+
+
+def optional(name, fn, *args):
+    """Run one extra bench leg; a failure is reported and does not lose the
+    main result."""
+    try:
+        return fn(*args)
+    except Exception as e:  # noqa: BLE001
+        print(f"bench: {name} leg failed: {type(e).__name__}: {e}", file=sys.stderr, flush=True)
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +331,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-dg", action="store_true")
+    ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--batch-cols", type=int, default=64)
     ap.add_argument("--batch-problems", type=int, default=48)
@@ -349,34 +438,13 @@ def main():
     # mixed precision: FP32 / BF16 storage in the V-cycle inside FP64 FGMRES,
     # the same 1e-10 true FP64 residual
     if not a.no_mixed:
-        out["mixed"] = {}
-        xref = x.clone()
-        for name, prec in (("fp32", binding.FP32), ("bf16", binding.BF16)):
-            sm = Solver(ip, ix, dv, precision=prec)
-            _tune(sm)
-            xm = torch.zeros_like(b)
-            for w in range(a.warmup):
-                xm, _ = sm.solve(b, xm)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for k in range(a.steps):
-                xm, im = sm.solve(b, xm)
-                assert im["converged"] == 1 and im["rel_residual"] <= 1e-10, im
-            torch.cuda.synchronize()
-            dtm = time.perf_counter() - t0
-            err = float(torch.linalg.norm(xm - xref) / torch.linalg.norm(xref))
-            ktm = sm.time_kernels("poly", reps=a.kernel_reps)
-            out["mixed"][name] = {"value": p.n * a.steps / dtm, "ms_per_step": 1000.0 * dtm / a.steps,
-                                  "iterations": im["iterations"], "rel_residual": im["rel_residual"],
-                                  "rel_diff_vs_fp64_solution": err,
-                                  "speedup_vs_fp64": (p.n * a.steps / dtm) / value,
-                                  "poly_gbps": ktm["bytes_per_launch"] / (ktm["avg_launch_ms"] * 1e-3) / 1e9}
-            print(f"bench: {name}: {out['mixed'][name]}", file=sys.stderr, flush=True)
-            sm.close()
+        out["mixed"] = optional("mixed", mixed_legs, a, p, x, value, ip, ix, dv, b)
     if not a.no_batch:
-        out["batched"] = batched_legs(a, p, s, value, ip, ix, dv)
+        out["batched"] = optional("batched", batched_legs, a, p, s, value, ip, ix, dv)
     if not a.no_dg:
-        out["dg_q1"] = dg_legs(a)
+        out["dg_q1"] = optional("dg", dg_legs, a)
+    if not a.no_paper:
+        out["paper_fd"] = optional("paper", paper_legs, a)
     out["hbm_copy_gbps"] = copy_bandwidth()
     print(f"bench: copy kernel {out['hbm_copy_gbps']:.1f} GB/s", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
