@@ -107,8 +107,8 @@ def _tune(solver):
     t = solver.autotune(reps=10)
     for e in t:
         print(f"bench: tune level {e['level']:2d} {e['op']:3s} lanes {e['lanes']:2d} xcd {e['xcd_map']} "
-              f"{e['best_us']:8.2f} us (default {e['default_lanes']:2d}/{e['default_xcd_map']} "
-              f"{e['default_us']:8.2f} us)", file=sys.stderr)
+              f"lds {e['lds']} {e['best_us']:8.2f} us (default {e['default_lanes']:2d}/"
+              f"{e['default_xcd_map']}/{e['default_lds']} {e['default_us']:8.2f} us)", file=sys.stderr)
     return {"operators": len(t), "changed": sum(e["lanes"] != e["default_lanes"] for e in t),
             "default_us_sum": round(sum(e["default_us"] for e in t), 1),
             "tuned_us_sum": round(sum(e["best_us"] for e in t), 1)}
@@ -236,6 +236,9 @@ PAPER_SINGLE_GCD = {  # Sec. 3.1, one MI250X GCD, 13M unknowns, pi/4, d = 6
                        "storage_complexity": 10.22},
     "untruncated": {"iterations": 7, "levels": 22, "cycle_complexity": 27.2,
                     "storage_complexity": 10.21},
+    # Sec. 3.4: 500 x N rectangles weak-scaled in y, m_c = 10 (constant over the runs)
+    "rectangular_mc10": {"iterations": 6, "levels": 10, "cycle_complexity": 28.2,
+                         "storage_complexity": 9.5},
 }
 
 
@@ -257,8 +260,19 @@ def paper_legs(a, side=3606):
                        "Richardson rtol 1e-10, d = 6", "n": p.n, "nnz": p.nnz, "paper": PAPER_SINGLE_GCD}
     legs = (("truncated_mc10", dict(coarse_poly_order=10, trunc_tol=0.1)),
             ("truncated_mc100", dict(coarse_poly_order=100, trunc_tol=0.1)),
-            ("untruncated", dict(coarse_poly_order=10, trunc_tol=0.0)))
+            ("untruncated", dict(coarse_poly_order=10, trunc_tol=0.0)),
+            ("rectangular_mc10", dict(coarse_poly_order=10, trunc_tol=0.1)))
     for name, over in legs:
+        if name == "rectangular_mc10":
+            # one GPU's share of the rectangular study: 500 x 26000 nodes (13.0M)
+            from airg_inputs import fd_advection
+            del ip, ix, dv, b
+            q = fd_advection(500, math.pi / 4.0, 0.0, ny=26000)
+            ip = torch.from_numpy(q.indptr).cuda()
+            ix = torch.from_numpy(q.indices).cuda()
+            dv = torch.from_numpy(q.data).cuda()
+            b = torch.from_numpy(q.b).cuda()
+            p = q
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sm = Solver(ip, ix, dv, poly_order=6, outer=binding.OUTER_RICHARDSON, **over)
@@ -279,6 +293,8 @@ def paper_legs(a, side=3606):
                "grid_complexity": round(st["grid_complexity"], 3), "setup_s": round(setup_s, 3),
                "solve_ms": round(1e3 * dt, 3), "value": p.n / dt, "unit": "DOF/s",
                "dof_per_s_per_vcycle": p.n * info["iterations"] / dt}
+        if name == "rectangular_mc10":
+            leg["grid"] = "500 x 26000"
         res[name] = leg
         print(f"bench: paper {name}: {leg}", file=sys.stderr, flush=True)
         sm.close()
@@ -306,6 +322,28 @@ def mixed_legs(a, p, x64, value64, ip, ix, dv, b):
                      "poly_gbps": ktm["bytes_per_launch"] / (ktm["avg_launch_ms"] * 1e-3) / 1e9}
         print(f"bench: {name}: {res[name]}", file=sys.stderr, flush=True)
         sm.close()
+    return res
+
+
+def assembled_leg(a, p, value64, ip, ix, dv, b):
+    """F-point smoothing with the assembled fixed-sparsity Ahat^{-1} (one
+    product per level instead of d matrix-free ones), FP64, same tolerance."""
+    import torch
+    from paper_2508_17517_amd import Solver, binding
+    sm = Solver(ip, ix, dv, smoother=binding.SMOOTH_ASSEMBLED)
+    _tune(sm)
+    xm = torch.zeros_like(b)
+    dt, (xm, im) = _timed(lambda: sm.solve(b, xm), a.warmup, a.steps)
+    assert im["converged"] == 1 and im["rel_residual"] <= 1e-10, im
+    st = sm.stats()
+    res = {"value": p.n / dt, "unit": "DOF/s", "ms_per_step": 1e3 * dt,
+           "iterations": im["iterations"], "rel_residual": im["rel_residual"],
+           "cycle_complexity": round(st["cycle_complexity"], 2),
+           "storage_complexity": round(st["storage_complexity"], 2),
+           "ms_per_vcycle": 1e3 * dt / max(im["iterations"], 1),
+           "speedup_vs_fp64_poly": (p.n / dt) / value64}
+    print(f"bench: assembled smoother: {res}", file=sys.stderr, flush=True)
+    sm.close()
     return res
 
 
@@ -439,6 +477,8 @@ def main():
     # the same 1e-10 true FP64 residual
     if not a.no_mixed:
         out["mixed"] = optional("mixed", mixed_legs, a, p, x, value, ip, ix, dv, b)
+    if not a.no_mixed:
+        out["assembled_smoother"] = optional("assembled", assembled_leg, a, p, value, ip, ix, dv, b)
     if not a.no_batch:
         out["batched"] = optional("batched", batched_legs, a, p, s, value, ip, ix, dv)
     if not a.no_dg:

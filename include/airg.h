@@ -81,7 +81,14 @@ typedef struct {
                                 breadth-first distances on A + A^T (cache locality of the
                                 SpMV gathers; the hierarchy itself is unchanged), 1 */
   int32_t outer;             /* airg_outer: the outer iteration, AIRG_OUTER_FGMRES */
+  int32_t smoother;          /* airg_smoother: the F-point smoother, AIRG_SMOOTH_POLY */
 } airg_params;
+
+/* F-point smoothers.  AIRG_SMOOTH_POLY applies the GMRES polynomial
+ * matrix-free (d products with A_ff, Sec. 2.2); AIRG_SMOOTH_ASSEMBLED applies
+ * the assembled fixed-sparsity Ahat^{-1} of Eq. fixed_sparsity (one product
+ * with an operator of A_ff's pattern, kept per level). */
+typedef enum { AIRG_SMOOTH_POLY = 0, AIRG_SMOOTH_ASSEMBLED = 1 } airg_smoother;
 
 /* Outer iterations.  AIRG_OUTER_RICHARDSON is the paper's undamped Richardson
  * x <- x + M (b - A x) with M one V-cycle (Sec. 3), stopped when the true
@@ -243,7 +250,8 @@ enum airg_operator {
   AIRG_OP_B = 1,    /* A_fc + A_ff W of a level (F-point residual) */
   AIRG_OP_Z = 2,    /* Z of a level (restriction) */
   AIRG_OP_A = 3,    /* the coarsest matrix (Newton steps) */
-  AIRG_OP_TOP = 4   /* the top matrix of the outer loop (level 0) */
+  AIRG_OP_TOP = 4,  /* the top matrix of the outer loop (level 0) */
+  AIRG_OP_HAT = 5   /* the assembled Ahat^{-1} of a level (AIRG_SMOOTH_ASSEMBLED) */
 };
 
 typedef struct {
@@ -256,15 +264,19 @@ typedef struct {
                           row on average) */
   int32_t xcd_map;     /* 1: workgroups of one XCD take one contiguous eighth of the rows
                           (each XCD has its own L2); 0: workgroup i takes row block i */
+  int32_t lds;         /* 1: the LDS-staged kernel (a workgroup per 64-row group copies the
+                          group's window of x to LDS and gathers there; operators with
+                          compressed columns; lanes 2..16) */
   int32_t default_lanes;
   int32_t default_xcd_map;
+  int32_t default_lds;
   double best_us;      /* device time of one product with the chosen shape */
   double default_us;   /* ... with the default shape (a rule on the mean row length) */
 } airg_tune_entry;
 
 /* Launch-shape tuner: time every solve operator's single-column product with
- * 1, 2, ..., 64 lanes per row and the row-block kernel where it exists, each
- * with and without the XCD mapping (`reps` launches each, HIP events on the
+ * 1, 2, ..., 64 lanes per row, the row-block kernel and the LDS-staged kernel
+ * where they exist, each with and without the XCD mapping (`reps` launches each, HIP events on the
  * handle's stream), and keep the fastest per operator.  A row split over more
  * lanes sums in a different order, so solves after tuning agree with untuned
  * ones to rounding, not bit for bit; timings vary run to run, so a caller
@@ -273,11 +285,13 @@ typedef struct {
  * operators to *n_out (may be NULL). */
 int airg_autotune(airg_handle h, int reps, airg_tune_entry* out, int max_out, int* n_out);
 
-/* Set the launch shape (lanes per row and XCD mapping, as in airg_tune_entry)
- * of one solve operator (level is ignored for AIRG_OP_TOP and AIRG_OP_A).
- * AIRG_ERR_INVALID for an unknown operator, lanes not 0 or a power of two in
- * 1..64, 0 for an operator without row blocks, or xcd_map not 0 or 1. */
-int airg_set_lanes(airg_handle h, int level, int op, int lanes, int xcd_map);
+/* Set the launch shape (lanes per row, XCD mapping and LDS staging, as in
+ * airg_tune_entry) of one solve operator (level is ignored for AIRG_OP_TOP
+ * and AIRG_OP_A).  AIRG_ERR_INVALID for an unknown operator, lanes not 0 or a
+ * power of two in 1..64, 0 for an operator without row blocks, xcd_map or lds
+ * not 0 or 1, or lds = 1 with lanes outside 2..16 or for an operator without
+ * compressed columns. */
+int airg_set_lanes(airg_handle h, int level, int op, int lanes, int xcd_map, int lds);
 
 /* ---- differentiable advection solve -------------------------------------
  * The upwind finite-volume system of v.grad(u) = 0 with inflow values g

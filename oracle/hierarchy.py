@@ -291,6 +291,7 @@ class Level:
     Z: sp.csr_matrix = None          # n_C x n_F after the relative drop
     cmap: np.ndarray = None          # W: F point -> coarse index (or -1)
     alpha: np.ndarray = None         # smoother coefficients alpha_0..alpha_d
+    Ahat: sp.csr_matrix = None       # the assembled fixed-sparsity Ahat^{-1} (Eq. fixed_sparsity)
     roots: list = None               # Newton roots (coarsest level)
     trunc_rel: float = None          # truncation test result on this level
     info: dict = field(default_factory=dict)
@@ -344,6 +345,7 @@ def coarsen(A, level, p):
     Ac = _csr(relative_drop(Ac, p.a_drop, p.lump))
     diagonal_of(Ac)
     L.Aff, L.Afc, L.Acf, L.Z, L.cmap, L.alpha = Aff, Afc, Acf, Z, cmap, alpha
+    L.Ahat = Ahat
     return L, Ac
 
 

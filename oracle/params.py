@@ -27,5 +27,6 @@ class Params:
     max_it: int = 500
     restart: int = 30
     outer: str = "fgmres"            # or "richardson": the paper's undamped Richardson (Sec. 3)
+    smoother: str = "poly"           # or "assembled": F-smoothing with the assembled Ahat^{-1} (Sec. 2.2)
     # oracle-only knob for the exactness pins: solve the coarsest level by LU
     exact_coarse: bool = False

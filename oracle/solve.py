@@ -23,7 +23,10 @@ from .params import Params
 from .hierarchy import setup
 
 
-def vcycle(levels, r, lvl=0, exact_coarse=False):
+def vcycle(levels, r, lvl=0, exact_coarse=False, assembled=False):
+    """One V-cycle applied to r.  assembled: the F-point smoother applies the
+    assembled fixed-sparsity Ahat^{-1} (one product, Sec. 2.2) instead of the
+    polynomial matrix-free."""
     L = levels[lvl]
     if L.coarsest:
         if exact_coarse:
@@ -32,10 +35,13 @@ def vcycle(levels, r, lvl=0, exact_coarse=False):
     rf = r[L.F]
     rc = r[L.C]
     rc2 = linalg.spmv(L.Z, rf) + rc
-    ec = vcycle(levels, rc2, lvl + 1, exact_coarse)
+    ec = vcycle(levels, rc2, lvl + 1, exact_coarse, assembled)
     ef = np.where(L.cmap >= 0, ec[np.maximum(L.cmap, 0)], 0.0)
     s = rf - linalg.spmv(L.Afc, ec) - linalg.spmv(L.Aff, ef)
-    ef = ef + linalg.horner_apply(L.Aff, L.alpha, s)
+    if assembled:
+        ef = ef + linalg.spmv(L.Ahat, s)
+    else:
+        ef = ef + linalg.horner_apply(L.Aff, L.alpha, s)
     e = np.zeros(len(r))
     e[L.F] = ef
     e[L.C] = ec
@@ -132,7 +138,9 @@ def solve(A, b, p=None, levels=None, x0=None):
     A = sp.csr_matrix(A)
     if levels is None:
         levels = setup(A, p)
-    M = lambda v: vcycle(levels, v, 0, p.exact_coarse)  # noqa: E731
+    if p.smoother not in ("poly", "assembled"):
+        raise ValueError(f"unknown smoother {p.smoother!r}")
+    M = lambda v: vcycle(levels, v, 0, p.exact_coarse, p.smoother == "assembled")  # noqa: E731
     if p.outer == "richardson":
         x, its, rel, hist = richardson(A, M, b, p.rtol, p.max_it, x0)
     elif p.outer == "fgmres":

@@ -127,11 +127,11 @@ class Solver:
         binding.check(self.lib.airg_autotune(self.h, reps, buf, cap, ctypes.byref(n)), self.lib)
         return [buf[i].as_dict() for i in range(min(n.value, cap))]
 
-    def set_lanes(self, level, op, lanes, xcd_map=0):
+    def set_lanes(self, level, op, lanes, xcd_map=0, lds=0):
         """Pin the launch shape of one solve operator ("ff", "b", "z", "a", "top"):
-        lanes per row (0 = row-block kernel) and the XCD mapping."""
-        binding.check(self.lib.airg_set_lanes(self.h, level, binding.OPERATORS[op], lanes, xcd_map),
-                      self.lib)
+        lanes per row (0 = row-block kernel), the XCD mapping and LDS staging."""
+        binding.check(self.lib.airg_set_lanes(self.h, level, binding.OPERATORS[op], lanes, xcd_map,
+                                              lds), self.lib)
 
     def level_info(self, level):
         li = binding.LevelInfo()

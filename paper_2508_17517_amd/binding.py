@@ -15,6 +15,7 @@ STATUS = {0: "AIRG_OK", 1: "AIRG_NOT_CONVERGED", -1: "AIRG_ERR_INVALID", -2: "AI
           -6: "AIRG_ERR_BREAKDOWN", -7: "AIRG_ERR_INTERNAL"}
 FP64, FP32, BF16 = 0, 1, 2
 OUTER_FGMRES, OUTER_RICHARDSON = 0, 1
+SMOOTH_POLY, SMOOTH_ASSEMBLED = 0, 1
 
 
 class Params(ctypes.Structure):
@@ -24,7 +25,7 @@ class Params(ctypes.Structure):
                 ("poly_order", c_i32), ("coarse_poly_order", c_i32), ("trunc_start_level", c_i32),
                 ("max_levels", c_i32), ("added_roots", c_i32), ("precision", c_i32),
                 ("max_it", c_i32), ("restart", c_i32), ("keep_setup_data", c_i32),
-                ("locality_order", c_i32), ("outer", c_i32)]
+                ("locality_order", c_i32), ("outer", c_i32), ("smoother", c_i32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -88,8 +89,8 @@ class KernelTiming(ctypes.Structure):
 
 class TuneEntry(ctypes.Structure):
     _fields_ = [("level", c_i32), ("op", c_i32), ("lanes", c_i32), ("xcd_map", c_i32),
-                ("default_lanes", c_i32), ("default_xcd_map", c_i32),
-                ("best_us", c_dbl), ("default_us", c_dbl)]
+                ("lds", c_i32), ("default_lanes", c_i32), ("default_xcd_map", c_i32),
+                ("default_lds", c_i32), ("best_us", c_dbl), ("default_us", c_dbl)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -97,7 +98,7 @@ class TuneEntry(ctypes.Structure):
         return d
 
 
-OPERATORS = {"ff": 0, "b": 1, "z": 2, "a": 3, "top": 4}
+OPERATORS = {"ff": 0, "b": 1, "z": 2, "a": 3, "top": 4, "hat": 5}
 OPERATORS_BY_CODE = {v: k for k, v in OPERATORS.items()}
 
 KERNEL_CLASSES = {"poly": 0, "horner": 1, "newton": 2, "residual": 3, "restrict": 4, "top_spmv": 5}
@@ -123,7 +124,7 @@ SYMBOLS = {
     "airg_time_kernels": (c_i32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, P(KernelTiming)]),
     "airg_autotune": (c_i32, [ctypes.c_void_p, ctypes.c_int, P(TuneEntry), ctypes.c_int, P(ctypes.c_int)]),
     "airg_set_lanes": (c_i32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                               ctypes.c_int]),
+                               ctypes.c_int, ctypes.c_int]),
     "airg_fv_nnz": (c_i32, [c_i64, c_i64, c_dbl, P(c_i64)]),
     "airg_fv_assemble": (c_i32, [c_i64, c_i64, c_dbl] + [ctypes.c_void_p] * 9),
     "airg_fv_gradients": (c_i32, [c_i64, c_i64, c_dbl] + [ctypes.c_void_p] * 10),

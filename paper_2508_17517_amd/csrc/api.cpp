@@ -64,6 +64,7 @@ void check_params(const airg_params& p) {
   if (p.max_it < 0) bad("max_it");
   if (p.restart < 1 || p.restart > 512) bad("restart");
   if (p.outer != AIRG_OUTER_FGMRES && p.outer != AIRG_OUTER_RICHARDSON) bad("outer");
+  if (p.smoother != AIRG_SMOOTH_POLY && p.smoother != AIRG_SMOOTH_ASSEMBLED) bad("smoother");
 }
 
 // Copy the caller's CSR (host or device) into library memory.
@@ -176,6 +177,7 @@ int airg_params_default(airg_params* p) {
   p->keep_setup_data = 0;
   p->locality_order = 1;
   p->outer = AIRG_OUTER_FGMRES;
+  p->smoother = AIRG_SMOOTH_POLY;
   return AIRG_OK;
 }
 
@@ -416,9 +418,9 @@ int airg_autotune(airg_handle h, int reps, airg_tune_entry* out, int max_out, in
   });
 }
 
-int airg_set_lanes(airg_handle h, int level, int op, int lanes, int xcd_map) {
+int airg_set_lanes(airg_handle h, int level, int op, int lanes, int xcd_map, int lds) {
   return guard([&]() {
-    set_lanes(handle_of(h)->H, level, op, lanes, xcd_map);
+    set_lanes(handle_of(h)->H, level, op, lanes, xcd_map, lds);
     return (int)AIRG_OK;
   });
 }

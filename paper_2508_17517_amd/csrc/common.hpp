@@ -95,6 +95,10 @@ struct CSR {
   // base is negative
   DBuf<uint16_t> col16;
   DBuf<int32_t> cbase;
+  // with col16: number of columns each 64-row group spans (max - min + 1),
+  // and the largest span over the groups
+  DBuf<int32_t> cspan;
+  int64_t max_span = 0;
   // optional row blocks for the row-block product: block b holds rows
   // rblk[b] .. rblk[b+1]-1 (see build_row_blocks)
   DBuf<int32_t> rblk;
@@ -106,6 +110,8 @@ struct CSR {
     val.alloc(nz, s);
     col16.release();
     cbase.release();
+    cspan.release();
+    max_span = 0;
     rblk.release();
     nrblk = 0;
   }
@@ -129,10 +135,12 @@ struct OpView {
   const int32_t* cbase;
   const int32_t* rblk;    // row blocks, or null
   int64_t nrblk;
+  const int32_t* cspan;   // column span per 64-row group (with col16)
+  int64_t max_span;
 };
 inline OpView opview(const CSR& A) {
   return {A.rowptr.get(), A.col.get(), A.val.get(), VT_F64, A.rows, A.nnz, A.col16.get(),
-          A.cbase.get(), A.rblk.get(), A.nrblk};
+          A.cbase.get(), A.rblk.get(), A.nrblk, A.cspan.get(), A.max_span};
 }
 
 // Read-only view passed to kernels.

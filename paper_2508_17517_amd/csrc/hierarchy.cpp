@@ -469,9 +469,16 @@ void finalize_hierarchy(Hierarchy& H) {
     Level& N = H.levels[l + 1];
     L.pos.alloc(L.n, s);
     L.cmap.alloc(L.nF, s);
+    const bool asm_smoother = H.p.smoother == AIRG_SMOOTH_ASSEMBLED;
+    CSR Ahat_setup;  // the assembled smoother in setup numbering, from A_ff and alpha
+    if (asm_smoother) fixed_sparsity_inverse(L.Aff, L.alpha, Ahat_setup, s);
     if (order) {
       DBuf<int32_t> frank(L.nF, s);
       rank_f_points(L.state.get(), L.fidx.get(), key[l].get(), L.n, L.nF, frank.get(), s);
+      if (asm_smoother) {
+        permute_rows(Ahat_setup, frank.get(), frank.get(), L.nF, L.Ahat, s);
+        sort_rows(L.Ahat, s);
+      }
       launch_nested_pos_ranked(L.state.get(), L.fidx.get(), L.cidx.get(), frank.get(), L.nF,
                                N.pos.get(), L.n, L.pos.get(), s);
       CSR Aff;
@@ -486,6 +493,7 @@ void finalize_hierarchy(Hierarchy& H) {
       sort_rows(L.Z, s);
       launch_remap_ranked(L.cmap_nat.get(), N.pos.get(), frank.get(), L.nF, L.cmap.get(), s);
     } else {
+      if (asm_smoother) L.Ahat = std::move(Ahat_setup);
       launch_nested_pos(L.state.get(), L.fidx.get(), L.cidx.get(), L.nF, N.pos.get(), L.n,
                         L.pos.get(), s);
       permute_rows(L.Afc_nat, nullptr, N.pos.get(), L.nC, L.Afc, s);
@@ -499,6 +507,7 @@ void finalize_hierarchy(Hierarchy& H) {
     L.tpr_ff = pick_tpr(L.Aff.rows, L.Aff.nnz);
     L.tpr_b = pick_tpr(L.B.rows, L.B.nnz);
     L.tpr_z = pick_tpr(L.Z.rows, L.Z.nnz);
+    if (asm_smoother) L.tpr_hat = pick_tpr(L.Ahat.rows, L.Ahat.nnz);
   }
   int64_t off = 0;
   for (Level& L : H.levels) {
@@ -528,6 +537,7 @@ void finalize_hierarchy(Hierarchy& H) {
       lower(L.Aff, L.ff32, L.ff16);
       lower(L.B, L.b32, L.b16);
       lower(L.Z, L.z32, L.z16);
+      if (L.Ahat.rows > 0) lower(L.Ahat, L.hat32, L.hat16);
     }
   }
   // compressed columns for every solve operator whose row blocks allow them,
@@ -545,6 +555,7 @@ void finalize_hierarchy(Hierarchy& H) {
     prepare(L.Aff);
     prepare(L.B);
     prepare(L.Z);
+    if (L.Ahat.rows > 0) prepare(L.Ahat);
   }
   // every solve-phase operator is checked once, so an inconsistent hierarchy
   // (for example a bad import) fails here instead of in a kernel
@@ -561,6 +572,11 @@ void finalize_hierarchy(Hierarchy& H) {
       launch_check_csr(L.Aff, flags.get(), s);
       launch_check_csr(L.B, flags.get(), s);
       launch_check_csr(L.Z, flags.get(), s);
+      if (H.p.smoother == AIRG_SMOOTH_ASSEMBLED) {
+        if (L.Ahat.rows != L.nF || L.Ahat.cols != L.nF)
+          fail(AIRG_ERR_INVALID, "assembled smoother missing on level " + std::to_string(l));
+        launch_check_csr(L.Ahat, flags.get(), s);
+      }
       launch_check_map(L.cmap.get(), L.nF, -1, L.nC, flags.get(), s);
       launch_check_map(L.pos.get(), L.n, 0, L.n, flags.get(), s);
       if (L.Aff.rows != L.nF || L.Aff.cols != L.nF || L.B.rows != L.nF || L.B.cols != L.nC ||
@@ -688,16 +704,25 @@ void hierarchy_stats(const Hierarchy& H, airg_stats* st) {
       st->coarse_roots = (int)L.roots.size();
     } else {
       const int d = (int)L.alpha.size() - 1;
-      // complexities in the paper's terms: Z, A_fc and A_ff (d + 1 times)
-      cyc += (double)L.Z.nnz + (double)L.nnz_fc + (double)L.Aff.nnz * (1 + d);
-      sto += (double)L.Z.nnz + (double)L.nnz_fc + (double)L.Aff.nnz;
+      // complexities in the paper's terms: Z, A_fc and A_ff (d + 1 times), or
+      // Z, A_fc, A_ff and Ahat^{-1} once each with the assembled smoother
+      const bool asm_smoother = L.Ahat.rows > 0;
+      const double smooth = asm_smoother ? (double)L.Aff.nnz + (double)L.Ahat.nnz
+                                         : (double)L.Aff.nnz * (1 + d);
+      cyc += (double)L.Z.nnz + (double)L.nnz_fc + smooth;
+      sto += (double)L.Z.nnz + (double)L.nnz_fc + (double)L.Aff.nnz +
+             (asm_smoother ? (double)L.Ahat.nnz : 0.0);
       // restriction: Z, r_f gathered, r_c read, r_c' written
       bytes += csr_bytes((double)L.nC, (double)L.Z.nnz) + 8.0 * (L.nF + 2 * L.nC);
       // residual: B, e_c gathered, r_f read, s written
       bytes += csr_bytes((double)L.nF, (double)L.B.nnz) + 8.0 * (L.nC + 2 * L.nF);
-      // d Horner steps: A_ff, y gathered, s read, out written; the last one
-      // also reads cmap and gathers W e_c
-      bytes += d * (csr_bytes((double)L.nF, (double)L.Aff.nnz) + 8.0 * 3 * L.nF) + 12.0 * L.nF;
+      // d Horner steps (or one product with Ahat^{-1}): the operator, y
+      // gathered, s read, out written; the last one also reads cmap and
+      // gathers W e_c
+      if (asm_smoother)
+        bytes += csr_bytes((double)L.nF, (double)L.Ahat.nnz) + 8.0 * 3 * L.nF + 12.0 * L.nF;
+      else
+        bytes += d * (csr_bytes((double)L.nF, (double)L.Aff.nnz) + 8.0 * 3 * L.nF) + 12.0 * L.nF;
     }
   }
   st->grid_complexity = grid / (double)H.n0;

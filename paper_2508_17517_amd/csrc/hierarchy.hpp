@@ -38,19 +38,20 @@ struct Level {
   CSR Aff, Z;               // Z rows in level l+1's nested order
   CSR Afc;                  // A_fc in solve numbering (only until B is built)
   CSR B;                    // A_fc + A_ff W: the F-point residual operator on e_c
+  CSR Ahat;                 // assembled Ahat^{-1} (AIRG_SMOOTH_ASSEMBLED), A_ff's pattern
   DBuf<int32_t> cmap;       // nested position on level l+1, or -1
   DBuf<int32_t> pos;        // setup index -> nested position on this level
   std::vector<double> alpha;
   std::vector<cplx> roots;
   // launch shapes of the products: lanes per row (bits 0-7, 0 = row-block
   // kernel) and the XCD mapping (bit 8)
-  int tpr_ff = 1, tpr_b = 1, tpr_z = 1, tpr_a = 1;
+  int tpr_ff = 1, tpr_b = 1, tpr_z = 1, tpr_a = 1, tpr_hat = 1;
   // the coarsest level's A is stored in its solve order (pos) when true
   bool a_permuted = false;
 
   // low-precision copies of the solve operators' values (FP32 or BF16 storage)
-  DBuf<float> ff32, b32, z32, a32;
-  DBuf<bf16> ff16, b16, z16, a16;
+  DBuf<float> ff32, b32, z32, a32, hat32;
+  DBuf<bf16> ff16, b16, z16, a16, hat16;
 
   // statistics
   int64_t nnz_a = 0, nnz_fc = 0;

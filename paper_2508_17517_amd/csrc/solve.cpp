@@ -102,11 +102,12 @@ VecSet<float> vecs32(Workspace& W) {
 }
 
 struct LevelOps {
-  OpView ff, b, z, a;
+  OpView ff, b, z, a, hat;
 };
 LevelOps ops_of(const Level& L, int prec) {
   return {op_view(L.Aff, L.ff32, L.ff16, prec), op_view(L.B, L.b32, L.b16, prec),
-          op_view(L.Z, L.z32, L.z16, prec), op_view(L.A, L.a32, L.a16, prec)};
+          op_view(L.Z, L.z32, L.z16, prec), op_view(L.A, L.a32, L.a16, prec),
+          op_view(L.Ahat, L.hat32, L.hat16, prec)};
 }
 
 double vt_bytes(ValType vt) { return vt == VT_F64 ? 8.0 : vt == VT_F32 ? 4.0 : 2.0; }
@@ -150,6 +151,24 @@ void horner(const Level& L, const OpView& Aff, int K, const X* sv, const X* ec, 
   count(true);
 }
 
+// The F-point smoother: the polynomial matrix-free (Horner), or one product
+// with the assembled Ahat^{-1} fused with the prolongation.
+template <class X>
+void smooth(const Level& L, const LevelOps& o, int K, const X* sv, const X* ec, X* ef, X* y0,
+            X* y1, hipStream_t s, LaunchTally* tally = nullptr) {
+  if (L.Ahat.rows == 0) {
+    horner<X>(L, o.ff, K, sv, ec, ef, y0, y1, s, tally);
+    return;
+  }
+  spmv_horner_prolong_t<X>(o.hat, L.tpr_hat, K, sv, sv, ef, 1.0, 0.0, L.cmap.get(), ec, s);
+  if (tally) {
+    const double xb = (double)sizeof(X);
+    const int64_t n = L.nF * K;
+    tally->add(csr_bytes(L.nF, o.hat.nnz, vt_bytes(o.hat.vt)) + xb * n * 4 + 4.0 * L.nF,
+               2.0 * (double)o.hat.nnz * K + 3.0 * n, col_saving(o.hat));
+  }
+}
+
 template <class X>
 void vcycle_t(const Hierarchy& H, const VecSet<X>& v, int K) {
   hipStream_t s = H.s;
@@ -172,7 +191,7 @@ void vcycle_t(const Hierarchy& H, const VecSet<X>& v, int K) {
     X* ef = v.e + lv.off * K;
     const X* ec = v.e + H.levels[l + 1].off * K;
     spmv_residual_t<X>(o.b, lv.tpr_b, K, ec, rf, v.sv, s);
-    horner<X>(lv, o.ff, K, v.sv, ec, ef, v.y0, v.y1, s);
+    smooth<X>(lv, o, K, v.sv, ec, ef, v.y0, v.y1, s);
   }
 }
 
@@ -412,7 +431,7 @@ void time_pass(const Hierarchy& H, const VecSet<X>& v, int cls, LaunchTally* t) 
   if (poly || cls == AIRG_K_HORNER)
     for (int l = 0; l < L; ++l) {
       const Level& lv = H.levels[l];
-      horner<X>(lv, ops_of(lv, prec).ff, 1, v.sv, v.e + H.levels[l + 1].off, v.e + lv.off, v.y0,
+      smooth<X>(lv, ops_of(lv, prec), 1, v.sv, v.e + H.levels[l + 1].off, v.e + lv.off, v.y0,
                 v.y1, s, t);
     }
   if (poly || cls == AIRG_K_NEWTON) {
@@ -531,6 +550,7 @@ int autotune(Hierarchy& H, Workspace& W, int reps, std::vector<airg_tune_entry>&
     t.push_back({l, AIRG_OP_FF, o.ff, &lv.tpr_ff, !low});
     t.push_back({l, AIRG_OP_B, o.b, &lv.tpr_b, !low});
     t.push_back({l, AIRG_OP_Z, o.z, &lv.tpr_z, !low});
+    if (lv.Ahat.rows > 0) t.push_back({l, AIRG_OP_HAT, o.hat, &lv.tpr_hat, !low});
   }
   Level& lc = H.levels[L];
   t.push_back({L, AIRG_OP_A, ops_of(lc, prec).a, &lc.tpr_a, !low});
@@ -547,13 +567,20 @@ int autotune(Hierarchy& H, Workspace& W, int reps, std::vector<airg_tune_entry>&
     e.op = g.op;
     e.default_lanes = *g.tpr & 0xff;
     e.default_xcd_map = (*g.tpr >> 8) & 1;
+    e.default_lds = (*g.tpr >> 9) & 1;
     e.best_us = 1e300;
     e.default_us = 1e300;
     int best = *g.tpr;
+    std::vector<int> shapes;
     for (int tpr = g.A.rblk ? 0 : 1; tpr <= 64; tpr = tpr ? tpr << 1 : 1) {
       if (g.A.rows * (int64_t)tpr > (int64_t)INT32_MAX) break;
+      shapes.push_back(tpr);
+    }
+    if (g.A.col16)  // LDS-staged kernel: 64-row groups, 2..16 lanes per row
+      for (int tpr = 2; tpr <= 16; tpr <<= 1) shapes.push_back(tpr | kShapeLds);
+    for (int base : shapes)
       for (int xcd = 0; xcd < 2; ++xcd) {
-        const int shape = tpr | (xcd << 8);
+        const int shape = base | (xcd << 8);
         const double us = g.f64 ? time_product<double>(g.A, shape, x64, W.w.get(), reps, W, s)
                                 : time_product<float>(g.A, shape, x32, W.e32.get(), reps, W, s);
         if (shape == *g.tpr) e.default_us = us;
@@ -562,19 +589,22 @@ int autotune(Hierarchy& H, Workspace& W, int reps, std::vector<airg_tune_entry>&
           best = shape;
         }
       }
-    }
     e.lanes = best & 0xff;
     e.xcd_map = (best >> 8) & 1;
+    e.lds = (best >> 9) & 1;
     *g.tpr = best;
     out.push_back(e);
   }
   return AIRG_OK;
 }
 
-void set_lanes(Hierarchy& H, int level, int op, int lanes, int xcd_map) {
+void set_lanes(Hierarchy& H, int level, int op, int lanes, int xcd_map, int lds) {
   if (lanes < 0 || lanes > 64 || (lanes & (lanes - 1)))
     fail(AIRG_ERR_INVALID, "lanes must be 0 or a power of two in 1..64");
   if (xcd_map != 0 && xcd_map != 1) fail(AIRG_ERR_INVALID, "xcd_map must be 0 or 1");
+  if (lds != 0 && lds != 1) fail(AIRG_ERR_INVALID, "lds must be 0 or 1");
+  if (lds && (lanes < 2 || lanes > 16))
+    fail(AIRG_ERR_INVALID, "the LDS-staged product takes 2, 4, 8 or 16 lanes per row");
   const int L = (int)H.levels.size() - 1;
   const CSR* A = nullptr;
   int* tpr = nullptr;
@@ -591,12 +621,19 @@ void set_lanes(Hierarchy& H, int level, int op, int lanes, int xcd_map) {
       case AIRG_OP_FF: A = &lv.Aff; tpr = &lv.tpr_ff; break;
       case AIRG_OP_B: A = &lv.B; tpr = &lv.tpr_b; break;
       case AIRG_OP_Z: A = &lv.Z; tpr = &lv.tpr_z; break;
+      case AIRG_OP_HAT:
+        if (lv.Ahat.rows == 0) fail(AIRG_ERR_INVALID, "no assembled smoother (smoother = poly)");
+        A = &lv.Ahat;
+        tpr = &lv.tpr_hat;
+        break;
       default: fail(AIRG_ERR_INVALID, "unknown operator");
     }
   }
   if (lanes == 0 && !A->rblk.get())
     fail(AIRG_ERR_INVALID, "this operator has no row blocks (rows shorter than 8 on average)");
-  *tpr = lanes | (xcd_map << 8);
+  if (lds && !A->col16.get())
+    fail(AIRG_ERR_INVALID, "this operator has no compressed columns for the LDS-staged product");
+  *tpr = lanes | (xcd_map << 8) | (lds ? kShapeLds : 0);
 }
 
 }  // namespace airg

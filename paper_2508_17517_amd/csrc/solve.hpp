@@ -40,6 +40,6 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
 int time_kernels(const Hierarchy& H, Workspace& W, int cls, int reps, airg_kernel_timing* out);
 // Launch-shape tuner (see airg_autotune) and its manual setter.
 int autotune(Hierarchy& H, Workspace& W, int reps, std::vector<airg_tune_entry>& out);
-void set_lanes(Hierarchy& H, int level, int op, int lanes, int xcd_map);
+void set_lanes(Hierarchy& H, int level, int op, int lanes, int xcd_map, int lds);
 
 }  // namespace airg

@@ -805,7 +805,8 @@ void merge_fc_ffw(const CSR& Afc, const CSR& Aff, const int32_t* cmap, CSR& B, h
 // (true for almost every block of a locality-ordered operator, whose rows see
 // nearby columns); a block that spans more keeps its int32 columns, marked by
 // a negative base.  Saves 2 of the 12 bytes of an FP64 entry.
-__global__ void col_span_kernel(CSRView A, int64_t nblk, int32_t* cbase, unsigned long long* nwide) {
+__global__ void col_span_kernel(CSRView A, int64_t nblk, int32_t* cbase, int32_t* cspan,
+                                unsigned long long* nwide, unsigned long long* maxspan) {
   int64_t blk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (blk >= nblk) return;
   const int64_t r0 = blk << kColBlockShift;
@@ -819,9 +820,12 @@ __global__ void col_span_kernel(CSRView A, int64_t nblk, int32_t* cbase, unsigne
   if (mx < 0) mn = mx = 0;
   if (mx - mn > 65535) {
     cbase[blk] = -1;
+    cspan[blk] = 0;
     atomicAdd(nwide, 1ull);
   } else {
     cbase[blk] = mn;
+    cspan[blk] = mx - mn + 1;
+    atomicMax(maxspan, (unsigned long long)(mx - mn + 1));
   }
 }
 __global__ void col16_kernel(CSRView A, const int32_t* cbase, uint16_t* col16) {
@@ -835,19 +839,28 @@ __global__ void col16_kernel(CSRView A, const int32_t* cbase, uint16_t* col16) {
 bool compress_columns(CSR& A, hipStream_t s) {
   A.col16.release();
   A.cbase.release();
+  A.cspan.release();
+  A.max_span = 0;
   if (A.rows <= 0 || A.nnz <= 0) return false;
   const int64_t nblk = (A.rows + (1 << kColBlockShift) - 1) >> kColBlockShift;
-  DBuf<unsigned long long> nwide(1, s);
-  launch_zero_bytes(nwide.get(), sizeof(unsigned long long), s);
+  DBuf<unsigned long long> stat(2, s);
+  launch_zero_bytes(stat.get(), 2 * sizeof(unsigned long long), s);
   A.cbase.alloc(nblk, s);
+  A.cspan.alloc(nblk, s);
   col_span_kernel<<<blocks_for(nblk, kBlock), kBlock, 0, s>>>(view(A), nblk, A.cbase.get(),
-                                                             nwide.get());
+                                                             A.cspan.get(), stat.get(),
+                                                             stat.get() + 1);
   AIRG_CHECK_LAUNCH();
+  unsigned long long st[2];
+  stat.to_host(st, 2);
+  AIRG_HIP(hipStreamSynchronize(s));
   // worth it only if nearly every block compresses
-  if (fetch(nwide.get(), s) * 16 > (unsigned long long)nblk) {
+  if (st[0] * 16 > (unsigned long long)nblk) {
     A.cbase.release();
+    A.cspan.release();
     return false;
   }
+  A.max_span = (int64_t)st[1];
   A.col16.alloc(A.nnz, s);
   col16_kernel<<<blocks_for(A.rows, kBlock), kBlock, 0, s>>>(view(A), A.cbase.get(), A.col16.get());
   AIRG_CHECK_LAUNCH();

@@ -211,13 +211,107 @@ __global__ __launch_bounds__(256) void spmv_rowblock_kernel(CSRT<MV, C16> A,
   if (mine) epi(row, sum, pre);
 }
 
+// LDS-staged kernel (K = 1, shape bit 9, operators with compressed columns):
+// a workgroup of 64 TPR threads takes one 64-row group, copies the group's
+// window of x (columns cbase .. cbase + span - 1) into LDS with coalesced
+// loads and gathers from LDS through the 16-bit column offsets.  Rows sum in
+// the order of the TPR-lane row kernel, so the results are the same bit for
+// bit.  A group that spans more than the LDS budget, or that kept int32
+// columns, gathers from global memory instead.
+constexpr int kLdsBytes = 64 * 1024;
+
+template <int TPR, int U, class MV, class X>
+__device__ __forceinline__ X row_dot_lds(const CSRT<MV, true>& A, int s, int e, int lane,
+                                         const X* xs, X sum) {
+  for (int p0 = s + lane; p0 < e; p0 += TPR * U) {
+    int c[U];
+    X v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = p0 + u * TPR;
+      c[u] = p < e ? (int)A.col16[p] : -1;
+      v[u] = p < e ? (X)ldv(A.val[p]) : X(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (c[u] >= 0) sum = sum + v[u] * xs[c[u]];
+  }
+  return sum;
+}
+
+template <int TPR, class MV, class X, class Epi>
+__global__ __launch_bounds__(64 * TPR) void spmv_lds_kernel(CSRT<MV, true> A,
+                                                            const int32_t* __restrict__ cspan,
+                                                            int64_t ngroups, int lds_cap,
+                                                            const X* __restrict__ x, Epi epi,
+                                                            int xcd) {
+  extern __shared__ unsigned char smem_raw[];
+  X* xs = reinterpret_cast<X*>(smem_raw);
+  const int64_t g = row_block_index(xcd);
+  if (g >= ngroups) return;
+  const int t = threadIdx.x;
+  const int lane = t & (TPR - 1);
+  const int64_t row = (g << kColBlockShift) + t / TPR;
+  const bool live = row < A.rows;
+  const int base = A.cbase[g];
+  const int span = cspan[g];
+  const bool staged = base >= 0 && span <= lds_cap;  // the same for the whole workgroup
+  typename Epi::Pre pre{};
+  if (live && lane == 0) pre = epi.pre(row);
+  int s = 0, e = 0;
+  if (live) {
+    s = A.rowptr[row];
+    e = A.rowptr[row + 1];
+  }
+  if (staged) {
+    for (int i = t; i < span; i += 64 * TPR) xs[i] = x[base + i];
+    __syncthreads();
+  }
+  X sum = 0;
+  constexpr int U = unroll_for<TPR>();
+  if (live) {
+    if (staged) {
+      sum = row_dot_lds<TPR, U>(A, s, e, lane, xs, sum);
+    } else if (base >= 0) {
+      sum = row_dot_cols<TPR, U, 1>(A, s, e, base, lane, x, 0, IdxPlain{}, sum);
+    } else {
+      const CSRT<MV, false> W{A.rowptr, A.col, nullptr, nullptr, A.val, A.rows};
+      sum = row_dot_cols<TPR, U, 1>(W, s, e, 0, lane, x, 0, IdxPlain{}, sum);
+    }
+  }
+  if constexpr (TPR > 1) {
+#pragma unroll
+    for (int o = TPR / 2; o > 0; o >>= 1) sum = sum + __shfl_down(sum, o, TPR);
+  }
+  if (lane == 0 && live) epi(row, sum, pre);
+}
+
 // shape: lanes per row in bits 0-7 (0: the row-block kernel), the XCD
-// mapping in bit 8
+// mapping in bit 8, the LDS-staged kernel in bit 9
 template <class MV, bool C16, class X, class Epi>
 static void launch_spmv_t(const OpView& Av, int shape, int K, const X* x, Epi epi, hipStream_t s) {
   if (Av.rows <= 0) return;
-  const int tpr = shape & 0xff, xcd = (shape >> 8) & 1;
+  const int tpr = shape & 0xff, xcd = (shape >> 8) & 1, lds = (shape >> 9) & 1;
   CSRT<MV, C16> A = csr_t<MV, C16>(Av);
+  if (K == 1 && lds) {
+    if constexpr (C16) {
+      const int64_t ngroups = (Av.rows + 63) >> kColBlockShift;
+      const int cap = (int)std::min<int64_t>(Av.max_span, kLdsBytes / (int)sizeof(X));
+      const size_t smem = (size_t)std::max(cap, 1) * sizeof(X);
+      const unsigned nb = grid_for(ngroups, 1, xcd);
+      switch (tpr) {
+        case 2: spmv_lds_kernel<2, MV, X, Epi><<<nb, 128, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
+        case 4: spmv_lds_kernel<4, MV, X, Epi><<<nb, 256, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
+        case 8: spmv_lds_kernel<8, MV, X, Epi><<<nb, 512, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
+        case 16: spmv_lds_kernel<16, MV, X, Epi><<<nb, 1024, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
+        default: fail(AIRG_ERR_INTERNAL, "LDS-staged product takes 2, 4, 8 or 16 lanes per row");
+      }
+      AIRG_CHECK_LAUNCH();
+      return;
+    } else {
+      fail(AIRG_ERR_INTERNAL, "LDS-staged product needs compressed columns");
+    }
+  }
   if (K == 1 && tpr == 0) {
     if (!Av.rblk) fail(AIRG_ERR_INTERNAL, "row-block product without row blocks");
     spmv_rowblock_kernel<MV, C16, X, Epi><<<grid_for(Av.nrblk, 1, xcd), 256, 0, s>>>(

@@ -199,6 +199,20 @@ def test_autotuned_shapes_keep_the_solution_and_can_be_pinned():
     x2, _ = s.solve(b)
     x3, _ = s.solve(b)
     assert torch.equal(x2, x3)
+    # the LDS-staged product sums like the row kernel with the same lanes
+    staged = 0
+    for t in tuned:
+        s.set_lanes(t["level"], t["op"], 4)
+    x4, _ = s.solve(b)
+    for t in tuned:
+        try:
+            s.set_lanes(t["level"], t["op"], 4, 1, 1)
+            staged += 1
+        except AirgError:
+            pass
+    assert staged >= 1
+    x5, _ = s.solve(b)
+    assert torch.equal(x4, x5)
     with pytest.raises(AirgError):
         s.set_lanes(0, "ff", 3)
     s.close()

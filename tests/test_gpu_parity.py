@@ -350,3 +350,19 @@ def test_richardson_matches_oracle(case):
     scale = max(np.linalg.norm(xo), np.linalg.norm(x0))
     assert np.linalg.norm(xg - xo) <= 1e-10 * scale
     s.close()
+
+
+@pytest.mark.parametrize("case", ["fv96_perm", "dg20_perm"])
+def test_assembled_smoother_matches_oracle(case):
+    # F-point smoothing with the assembled fixed-sparsity Ahat^{-1} (Sec. 2.2)
+    _needs_gpu()
+    p = workloads.fv_random(96, 0.3, True) if case == "fv96_perm" else \
+        workloads.dg_random(20, math.pi / 5, True)
+    print(f"case {case} n={p.n}", flush=True)
+    xo, its, rel, levels, _ = oracle.solve(p.scipy(), p.b, oracle.Params(smoother="assembled"))
+    s = _solver(p, smoother=1)
+    x, info = s.solve(torch.from_numpy(p.b).cuda())
+    assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
+    assert info["iterations"] == its
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    s.close()

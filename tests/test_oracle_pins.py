@@ -474,3 +474,31 @@ def test_richardson_on_the_paper_fd_system_goes_to_zero():
     assert rel <= 1e-10 and its < 20
     assert np.abs(x).max() <= 1e-9
     assert hist[-1] <= 1e-10 * hist[0]
+
+
+# --------------------------------------------------------------------- assembled smoother (Sec. 2.2)
+
+def test_assembled_smoother_equals_the_polynomial_when_the_pattern_is_closed():
+    # with theta_s = 0 every upwind neighbour is strong, A_ff is diagonal (P9),
+    # its pattern is closed under products, so Ahat^{-1} = q(A_ff) exactly and
+    # both smoothers give the same V-cycle
+    p = workloads.fv_random(24, 0.6, True)
+    A = p.scipy()
+    prm = oracle.Params(strong_threshold=0.0, trunc_tol=0.0, min_coarse_rows=64)
+    levels = oracle.setup(A, prm)
+    L0 = levels[0]
+    assert L0.Aff.nnz == L0.Aff.shape[0]
+    r = np.random.default_rng(5).standard_normal(p.n)
+    e_poly = oracle.vcycle(levels, r)
+    e_asm = oracle.vcycle(levels, r, assembled=True)
+    assert np.allclose(e_asm, e_poly, rtol=1e-12, atol=1e-12 * np.abs(e_poly).max())
+
+
+def test_assembled_smoother_solves_to_tolerance():
+    p = workloads.fv_random(48, 0.3, True)
+    A = p.scipy()
+    x, its, rel, levels, _ = oracle.solve(A, p.b, oracle.Params(smoother="assembled"))
+    u = oracle.sweep_solve(A, p.b, p.level)
+    assert rel <= 1e-10 and np.linalg.norm(x - u) <= 1e-8 * np.linalg.norm(u)
+    x2, its2, _, _, _ = oracle.solve(A, p.b, oracle.Params(), levels=levels)
+    assert its >= its2 - 1  # the paper: assembled needs as many or more iterations
