@@ -366,3 +366,31 @@ def test_assembled_smoother_matches_oracle(case):
     assert info["iterations"] == its
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
     s.close()
+
+
+DEGENERATE = {
+    "1x1": lambda: (sp.csr_matrix(np.array([[2.0]])), np.array([4.0])),
+    "2x2_lower": lambda: (sp.csr_matrix(np.array([[2.0, 0.0], [-1.0, 3.0]])), np.array([1.0, 2.0])),
+    "diagonal_100": lambda: (sp.diags(np.arange(1.0, 101.0)).tocsr(), np.ones(100)),
+    "bidiagonal_300": lambda: (sp.csr_matrix(sp.diags([np.full(300, 2.0), np.full(299, -1.0)],
+                                                       [0, -1])), np.ones(300)),
+}
+
+
+@pytest.mark.parametrize("case", list(DEGENERATE))
+def test_degenerate_systems_match_oracle(case):
+    # single-level hierarchies, no off-diagonal entries, a 1D chain (cyclic
+    # reduction, Sec. 2): the same iteration count and solution as the oracle
+    _needs_gpu()
+    from paper_2508_17517_amd import Solver
+    A, b = DEGENERATE[case]()
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    print(f"case {case} n={A.shape[0]}", flush=True)
+    xo, its, rel, levels, _ = oracle.solve(A, b)
+    s = Solver(A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data)
+    assert s.stats()["levels"] == len(levels)
+    x, info = s.solve(torch.from_numpy(b).cuda())
+    assert info["converged"] == 1 and info["iterations"] == its
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * max(np.linalg.norm(xo), 1.0)
+    s.close()
