@@ -12,26 +12,28 @@
 
 namespace airg {
 
-__global__ void bfs_step_kernel(CSRView A, CSRView At, int32_t* level, int32_t d,
-                                int32_t* changed) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.rows || level[i] != d) return;
-  bool ch = false;
-  for (int p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) {
-    int j = A.col[p];
-    if (level[j] < 0) {
-      level[j] = d + 1;  // every writer stores the same value
-      ch = true;
+// One breadth-first step over the frontier q_in (count cnt[d % 3]): every
+// unreached neighbour (in A or A^T) of a frontier node gets level d + 1 and
+// joins q_out (count cnt[(d + 1) % 3]).  Which thread claims a node does not
+// matter: the levels are the breadth-first distances either way.  The
+// counter for step d + 2 is cleared here.
+__global__ void bfs_frontier_kernel(CSRView A, CSRView At, int32_t* level, int32_t d,
+                                    const int32_t* q_in, int32_t* q_out, int32_t* cnt) {
+  const int32_t n_in = cnt[d % 3];
+  int32_t* n_out = cnt + (d + 1) % 3;
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt[(d + 2) % 3] = 0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_in;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int u = q_in[t];
+    for (int p = A.rowptr[u]; p < A.rowptr[u + 1]; ++p) {
+      const int v = A.col[p];
+      if (level[v] < 0 && atomicCAS(&level[v], -1, d + 1) == -1) q_out[atomicAdd(n_out, 1)] = v;
+    }
+    for (int p = At.rowptr[u]; p < At.rowptr[u + 1]; ++p) {
+      const int v = At.col[p];
+      if (level[v] < 0 && atomicCAS(&level[v], -1, d + 1) == -1) q_out[atomicAdd(n_out, 1)] = v;
     }
   }
-  for (int p = At.rowptr[i]; p < At.rowptr[i + 1]; ++p) {
-    int j = At.col[p];
-    if (level[j] < 0) {
-      level[j] = d + 1;
-      ch = true;
-    }
-  }
-  if (ch) *changed = 1;
 }
 
 // Largest level, ties to the smallest index, packed as level << 32 | ~index.
@@ -50,42 +52,50 @@ __global__ void first_unvisited_kernel(const int32_t* level, int64_t n, unsigned
   if (i < n && level[i] < 0) atomicMin(first, (unsigned long long)i);
 }
 
-__global__ void set_level_kernel(int32_t* level, int64_t i, int32_t v) { level[i] = v; }
+// Start a frontier: level[i] = v, q[0] = i, cnt[slot] = 1.
+__global__ void seed_frontier_kernel(int32_t* level, int64_t i, int32_t v, int32_t* q, int32_t* cnt,
+                                     int slot) {
+  level[i] = v;
+  q[0] = (int32_t)i;
+  cnt[0] = cnt[1] = cnt[2] = 0;
+  cnt[slot] = 1;
+}
 
 // Breadth-first levels of the graph of A + A^T from src; unreached
 // components restart from their smallest index at the next level.
 void bfs_levels(const CSR& A, const CSR& At, int64_t src, int32_t* level, hipStream_t s) {
   const int64_t n = A.rows;
   launch_fill_i32(level, n, -1, s);
-  DBuf<int32_t> changed(1, s);
+  DBuf<int32_t> qa(n, s), qb(n, s), cnt(3, s);
   DBuf<unsigned long long> red(1, s);
-  const unsigned nb = blocks_for(n, kBlock);
+  const unsigned nb = blocks_for(std::min<int64_t>(n, 256 * 1024), kBlock);
   int32_t d = 0;
-  set_level_kernel<<<1, 1, 0, s>>>(level, src, 0);
+  seed_frontier_kernel<<<1, 1, 0, s>>>(level, src, 0, qa.get(), cnt.get(), 0);
   AIRG_CHECK_LAUNCH();
+  int32_t* q[2] = {qa.get(), qb.get()};
   for (;;) {
     // a batch of steps between host checks; steps past the end do nothing
-    launch_fill_i32(changed.get(), 1, 0, s);
     const int batch = 32;
     for (int k = 0; k < batch; ++k, ++d) {
-      bfs_step_kernel<<<nb, kBlock, 0, s>>>(view(A), view(At), level, d, changed.get());
+      bfs_frontier_kernel<<<nb, kBlock, 0, s>>>(view(A), view(At), level, d, q[d & 1],
+                                                q[(d + 1) & 1], cnt.get());
       AIRG_CHECK_LAUNCH();
     }
-    if (fetch(changed.get(), s)) continue;
-    // no growth in the whole batch: every component reached so far is done
+    if (fetch(cnt.get() + d % 3, s) > 0) continue;
+    // the frontier is empty: every component reached so far is done
     unsigned long long first = ~0ull;
     red.from_host(&first, 1);
-    first_unvisited_kernel<<<nb, kBlock, 0, s>>>(level, n, red.get());
+    first_unvisited_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(level, n, red.get());
     AIRG_CHECK_LAUNCH();
     first = fetch(red.get(), s);
     if (first == ~0ull) break;
     unsigned long long zero = 0;
     red.from_host(&zero, 1);
-    far_node_kernel<<<nb, kBlock, 0, s>>>(level, n, red.get());
+    far_node_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(level, n, red.get());
     AIRG_CHECK_LAUNCH();
-    int32_t dmax = (int32_t)(fetch(red.get(), s) >> 32);
+    const int32_t dmax = (int32_t)(fetch(red.get(), s) >> 32);
     d = dmax + 1;
-    set_level_kernel<<<1, 1, 0, s>>>(level, (int64_t)first, d);
+    seed_frontier_kernel<<<1, 1, 0, s>>>(level, (int64_t)first, d, q[d & 1], cnt.get(), d % 3);
     AIRG_CHECK_LAUNCH();
   }
 }

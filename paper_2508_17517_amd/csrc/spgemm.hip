@@ -292,20 +292,27 @@ __device__ __forceinline__ int find_col(const int32_t* col, int lo, int hi, int 
   return -1;
 }
 
-__global__ void masked_power_kernel(CSRView Aff, const double* tin, double* tout) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Aff.rows) return;
+// One thread per output entry p (its row i from the entry's row index): the
+// entry sums over the row's entries q in ascending order.
+__global__ void masked_power_entry_kernel(CSRView Aff, const int32_t* __restrict__ row_of,
+                                          int64_t nnz, const double* tin, double* tout) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const int i = row_of[p];
   const int s = Aff.rowptr[i], e = Aff.rowptr[i + 1];
-  for (int p = s; p < e; ++p) {
-    const int j = Aff.col[p];
-    double acc = 0.0;
-    for (int q = s; q < e; ++q) {
-      const int k = Aff.col[q];
-      int r = find_col(Aff.col, Aff.rowptr[k], Aff.rowptr[k + 1], j);
-      if (r >= 0) acc = acc + tin[q] * Aff.val[r];
-    }
-    tout[p] = acc;
+  const int j = Aff.col[p];
+  double acc = 0.0;
+  for (int q = s; q < e; ++q) {
+    const int k = Aff.col[q];
+    int r = find_col(Aff.col, Aff.rowptr[k], Aff.rowptr[k + 1], j);
+    if (r >= 0) acc = acc + tin[q] * Aff.val[r];
   }
+  tout[p] = acc;
+}
+__global__ void row_of_entry_kernel(CSRView A, int32_t* row_of) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.rows) return;
+  for (int p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) row_of[p] = (int32_t)i;
 }
 
 // v = alpha_0 [i == j]; v = v + alpha_k T_k  (k = 1..d, left to right)
@@ -346,10 +353,14 @@ void fixed_sparsity_inverse(const CSR& Aff, const std::vector<double>& alpha, CS
   }
   if (alpha.size() > 2) {
     DBuf<double> ta(Aff.nnz, s), tb(Aff.nnz, s);
+    DBuf<int32_t> row_of(Aff.nnz, s);
+    row_of_entry_kernel<<<nb, kBlock, 0, s>>>(view(Aff), row_of.get());
+    AIRG_CHECK_LAUNCH();
     AIRG_HIP(hipMemcpyAsync(ta.get(), Aff.val.get(), Aff.nnz * sizeof(double),
                             hipMemcpyDeviceToDevice, s));
     for (size_t k = 2; k < alpha.size(); ++k) {
-      masked_power_kernel<<<nb, kBlock, 0, s>>>(view(Aff), ta.get(), tb.get());
+      masked_power_entry_kernel<<<blocks_for(Aff.nnz, kBlock), kBlock, 0, s>>>(
+          view(Aff), row_of.get(), Aff.nnz, ta.get(), tb.get());
       AIRG_CHECK_LAUNCH();
       poly_add_kernel<<<blocks_for(Aff.nnz, kBlock), kBlock, 0, s>>>(Aff.nnz, alpha[k], tb.get(),
                                                                      full.val.get());
