@@ -236,6 +236,8 @@ PAPER_SINGLE_GCD = {  # Sec. 3.1, one MI250X GCD, 13M unknowns, pi/4, d = 6
                        "storage_complexity": 10.22},
     "untruncated": {"iterations": 7, "levels": 22, "cycle_complexity": 27.2,
                     "storage_complexity": 10.21},
+    # Sec. 3.3: nAIR with the same options, 7 iterations on 2 nodes (15 on 2048)
+    "nair_truncated_mc10": {"iterations": 7},
     # Sec. 3.4: 500 x N rectangles weak-scaled in y, m_c = 10 (constant over the runs)
     "rectangular_mc10": {"iterations": 6, "levels": 10, "cycle_complexity": 28.2,
                          "storage_complexity": 9.5},
@@ -261,6 +263,8 @@ def paper_legs(a, side=3606):
     legs = (("truncated_mc10", dict(coarse_poly_order=10, trunc_tol=0.1)),
             ("truncated_mc100", dict(coarse_poly_order=100, trunc_tol=0.1)),
             ("untruncated", dict(coarse_poly_order=10, trunc_tol=0.0)),
+            ("nair_truncated_mc10", dict(coarse_poly_order=10, trunc_tol=0.1,
+                                         inverse_type=binding.INVERSE_NEUMANN)),
             ("rectangular_mc10", dict(coarse_poly_order=10, trunc_tol=0.1)))
     for name, over in legs:
         if name == "rectangular_mc10":

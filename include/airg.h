@@ -82,7 +82,18 @@ typedef struct {
                                 SpMV gathers; the hierarchy itself is unchanged), 1 */
   int32_t outer;             /* airg_outer: the outer iteration, AIRG_OUTER_FGMRES */
   int32_t smoother;          /* airg_smoother: the F-point smoother, AIRG_SMOOTH_POLY */
+  int32_t inverse_type;      /* airg_inverse: the polynomial approximating A_ff^{-1},
+                                AIRG_INVERSE_ARNOLDI */
 } airg_params;
+
+/* The polynomial approximation of A_ff^{-1} in the smoother and in Ahat^{-1}.
+ * AIRG_INVERSE_ARNOLDI: the GMRES polynomial of AIRG (Sec. 2.2).
+ * AIRG_INVERSE_NEUMANN: nAIR's Neumann polynomial of the same degree d (the
+ * paper's comparison, Sec. 3.3), read as the Jacobi-scaled series
+ * sum_{k=0}^{d} N^k D^{-1} with D = diag(A_ff), N = I - D^{-1} A_ff; matrix-free
+ * it is d + 1 Jacobi sweeps from zero, assembled it keeps the powers of N on
+ * A_ff's pattern as Eq. fixed_sparsity does. */
+typedef enum { AIRG_INVERSE_ARNOLDI = 0, AIRG_INVERSE_NEUMANN = 1 } airg_inverse;
 
 /* F-point smoothers.  AIRG_SMOOTH_POLY applies the GMRES polynomial
  * matrix-free (d products with A_ff, Sec. 2.2); AIRG_SMOOTH_ASSEMBLED applies

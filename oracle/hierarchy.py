@@ -200,6 +200,32 @@ def cf_split(A, level, p):
 # operators
 # ---------------------------------------------------------------------------
 
+def neumann_fixed_sparsity(Aff, d):
+    """The assembled Neumann approximation of nAIR with fixed sparsity:
+    Ahat^{-1} = (I + N~ + N~^2 + ... + N~^d) D^{-1}, N = I - D^{-1} A_ff kept on
+    A_ff's pattern (a zero diagonal), N~^1 = N and N~^k = (N~^{k-1} N)
+    restricted to A_ff's pattern, as for the GMRES polynomial (Eq.
+    fixed_sparsity); the sum runs left to right, then column j is scaled by
+    1 / a_jj."""
+    n = Aff.shape[0]
+    pattern = Aff.copy()
+    pattern.data = np.ones_like(pattern.data)
+    diag = Aff.diagonal()
+    rows = np.repeat(np.arange(n), np.diff(Aff.indptr))
+    N = Aff.copy()
+    N.data = np.where(Aff.indices == rows, 0.0, -Aff.data / diag[rows])
+    S = _csr(sp.identity(n, format="csr"))
+    if d >= 1:
+        S = _csr(S + N)
+    Pk = N
+    for _ in range(2, d + 1):
+        Pk = _csr((Pk @ N).multiply(pattern))
+        S = _csr(S + Pk)
+    S = S.copy()
+    S.data = S.data * (1.0 / diag)[S.indices]
+    return S
+
+
 def fixed_sparsity_inverse(Aff, alpha):
     """Ahat^{-1} = alpha_0 I + alpha_1 A_ff + alpha_2 A~^2 + ... (Eq. fixed_sparsity)
     with A~^1 = A_ff and A~^k = (A~^{k-1} A_ff) restricted to the sparsity of A_ff
@@ -322,9 +348,13 @@ def coarsen(A, level, p):
     Aff = _csr(Ar[:, F])
     Afc = _csr(Ar[:, C])
     Acf = _csr(A[C][:, F])
-    bpoly = rng.uniform(p.seed, rng.POLY_RHS, level, len(F))
-    alpha = linalg.gmres_poly_coeffs(Aff, bpoly, p.poly_order)
-    Ahat = fixed_sparsity_inverse(Aff, alpha)
+    if p.inverse_type == "neumann":
+        alpha = np.zeros(p.poly_order + 1)   # unused: the Neumann polynomial has no coefficients
+        Ahat = neumann_fixed_sparsity(Aff, p.poly_order)
+    else:
+        bpoly = rng.uniform(p.seed, rng.POLY_RHS, level, len(F))
+        alpha = linalg.gmres_poly_coeffs(Aff, bpoly, p.poly_order)
+        Ahat = fixed_sparsity_inverse(Aff, alpha)
     Z = _csr(-(Acf @ Ahat))
     Z = _csr(restrictor_drop(Z, p.r_drop))
     cidx = np.full(n, -1, dtype=np.int64)

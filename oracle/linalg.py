@@ -183,6 +183,18 @@ def horner_apply(A, alpha, s):
     return y
 
 
+def neumann_apply(A, d, s):
+    """The Jacobi-scaled Neumann polynomial of nAIR (Sec. 3.3's comparison),
+    q(A) s = sum_{k=0}^{d} N^k D^{-1} s with D = diag(A), N = I - D^{-1} A,
+    applied as y = D^{-1} s, then d times y = y + D^{-1} (s - A y)
+    (d products with A)."""
+    dinv = 1.0 / A.diagonal()
+    y = dinv * s
+    for _ in range(d):
+        y = y + dinv * (s - spmv(A, y))
+    return y
+
+
 # ---------------------------------------------------------------------------
 # Coarse solver: harmonic Ritz roots in Newton form (Sec. 2.3)
 # ---------------------------------------------------------------------------

@@ -23,10 +23,11 @@ from .params import Params
 from .hierarchy import setup
 
 
-def vcycle(levels, r, lvl=0, exact_coarse=False, assembled=False):
+def vcycle(levels, r, lvl=0, exact_coarse=False, assembled=False, neumann=False):
     """One V-cycle applied to r.  assembled: the F-point smoother applies the
     assembled fixed-sparsity Ahat^{-1} (one product, Sec. 2.2) instead of the
-    polynomial matrix-free."""
+    polynomial matrix-free.  neumann: the matrix-free polynomial is nAIR's
+    Jacobi-scaled Neumann polynomial of the same degree."""
     L = levels[lvl]
     if L.coarsest:
         if exact_coarse:
@@ -35,11 +36,13 @@ def vcycle(levels, r, lvl=0, exact_coarse=False, assembled=False):
     rf = r[L.F]
     rc = r[L.C]
     rc2 = linalg.spmv(L.Z, rf) + rc
-    ec = vcycle(levels, rc2, lvl + 1, exact_coarse, assembled)
+    ec = vcycle(levels, rc2, lvl + 1, exact_coarse, assembled, neumann)
     ef = np.where(L.cmap >= 0, ec[np.maximum(L.cmap, 0)], 0.0)
     s = rf - linalg.spmv(L.Afc, ec) - linalg.spmv(L.Aff, ef)
     if assembled:
         ef = ef + linalg.spmv(L.Ahat, s)
+    elif neumann:
+        ef = ef + linalg.neumann_apply(L.Aff, len(L.alpha) - 1, s)
     else:
         ef = ef + linalg.horner_apply(L.Aff, L.alpha, s)
     e = np.zeros(len(r))
@@ -140,7 +143,10 @@ def solve(A, b, p=None, levels=None, x0=None):
         levels = setup(A, p)
     if p.smoother not in ("poly", "assembled"):
         raise ValueError(f"unknown smoother {p.smoother!r}")
-    M = lambda v: vcycle(levels, v, 0, p.exact_coarse, p.smoother == "assembled")  # noqa: E731
+    if p.inverse_type not in ("arnoldi", "neumann"):
+        raise ValueError(f"unknown inverse type {p.inverse_type!r}")
+    M = lambda v: vcycle(levels, v, 0, p.exact_coarse, p.smoother == "assembled",  # noqa: E731
+                         p.inverse_type == "neumann")
     if p.outer == "richardson":
         x, its, rel, hist = richardson(A, M, b, p.rtol, p.max_it, x0)
     elif p.outer == "fgmres":

@@ -16,6 +16,7 @@ STATUS = {0: "AIRG_OK", 1: "AIRG_NOT_CONVERGED", -1: "AIRG_ERR_INVALID", -2: "AI
 FP64, FP32, BF16 = 0, 1, 2
 OUTER_FGMRES, OUTER_RICHARDSON = 0, 1
 SMOOTH_POLY, SMOOTH_ASSEMBLED = 0, 1
+INVERSE_ARNOLDI, INVERSE_NEUMANN = 0, 1
 
 
 class Params(ctypes.Structure):
@@ -25,7 +26,8 @@ class Params(ctypes.Structure):
                 ("poly_order", c_i32), ("coarse_poly_order", c_i32), ("trunc_start_level", c_i32),
                 ("max_levels", c_i32), ("added_roots", c_i32), ("precision", c_i32),
                 ("max_it", c_i32), ("restart", c_i32), ("keep_setup_data", c_i32),
-                ("locality_order", c_i32), ("outer", c_i32), ("smoother", c_i32)]
+                ("locality_order", c_i32), ("outer", c_i32), ("smoother", c_i32),
+                ("inverse_type", c_i32)]
 
 
 class SolveInfo(ctypes.Structure):

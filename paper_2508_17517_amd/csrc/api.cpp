@@ -65,6 +65,8 @@ void check_params(const airg_params& p) {
   if (p.restart < 1 || p.restart > 512) bad("restart");
   if (p.outer != AIRG_OUTER_FGMRES && p.outer != AIRG_OUTER_RICHARDSON) bad("outer");
   if (p.smoother != AIRG_SMOOTH_POLY && p.smoother != AIRG_SMOOTH_ASSEMBLED) bad("smoother");
+  if (p.inverse_type != AIRG_INVERSE_ARNOLDI && p.inverse_type != AIRG_INVERSE_NEUMANN)
+    bad("inverse_type");
 }
 
 // Copy the caller's CSR (host or device) into library memory.
@@ -178,6 +180,7 @@ int airg_params_default(airg_params* p) {
   p->locality_order = 1;
   p->outer = AIRG_OUTER_FGMRES;
   p->smoother = AIRG_SMOOTH_POLY;
+  p->inverse_type = AIRG_INVERSE_ARNOLDI;
   return AIRG_OK;
 }
 

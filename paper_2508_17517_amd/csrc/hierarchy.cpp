@@ -242,14 +242,18 @@ bool coarsen(Hierarchy& H, int lvl, const CSR& A, Level& L, CSR& Anext) {
     extract(A, L.state, 1, 2, L.fidx, L.cidx, L.nF, L.nC, L.Afc_nat, s);
     extract(A, L.state, 2, 1, L.fidx, L.cidx, L.nC, L.nF, Acf, s);
   }
+  const bool neumann = p.inverse_type == AIRG_INVERSE_NEUMANN;
   {
     Section t(H.comp_ms[C_POLY], s);
-    L.alpha = smoother_coeffs(L.Aff, lvl, p, s);
+    // nAIR's Neumann polynomial has no fitted coefficients: only its degree
+    if (neumann) L.alpha.assign((size_t)p.poly_order + 1, 0.0);
+    else L.alpha = smoother_coeffs(L.Aff, lvl, p, s);
   }
   {
     Section t(H.comp_ms[C_RSPGEMM], s);
     CSR Ahat, Zfull;
-    fixed_sparsity_inverse(L.Aff, L.alpha, Ahat, s);
+    if (neumann) neumann_fixed_sparsity(L.Aff, (int)L.alpha.size() - 1, Ahat, s);
+    else fixed_sparsity_inverse(L.Aff, L.alpha, Ahat, s);
     spgemm(Acf, Ahat, Zfull, s);
     restrictor_drop(Zfull, p.r_drop, true, L.Z_nat, s);
   }
@@ -470,14 +474,24 @@ void finalize_hierarchy(Hierarchy& H) {
     L.pos.alloc(L.n, s);
     L.cmap.alloc(L.nF, s);
     const bool asm_smoother = H.p.smoother == AIRG_SMOOTH_ASSEMBLED;
+    const bool neumann = H.p.inverse_type == AIRG_INVERSE_NEUMANN;
     CSR Ahat_setup;  // the assembled smoother in setup numbering, from A_ff and alpha
-    if (asm_smoother) fixed_sparsity_inverse(L.Aff, L.alpha, Ahat_setup, s);
+    if (asm_smoother) {
+      if (neumann) neumann_fixed_sparsity(L.Aff, (int)L.alpha.size() - 1, Ahat_setup, s);
+      else fixed_sparsity_inverse(L.Aff, L.alpha, Ahat_setup, s);
+    }
+    DBuf<double> dinv_setup;  // D^{-1} of A_ff for the matrix-free Neumann smoother
+    if (neumann && !asm_smoother) diag_inverse(L.Aff, dinv_setup, s);
     if (order) {
       DBuf<int32_t> frank(L.nF, s);
       rank_f_points(L.state.get(), L.fidx.get(), key[l].get(), L.n, L.nF, frank.get(), s);
       if (asm_smoother) {
         permute_rows(Ahat_setup, frank.get(), frank.get(), L.nF, L.Ahat, s);
         sort_rows(L.Ahat, s);
+      }
+      if (dinv_setup.get()) {
+        L.dinv.alloc(L.nF, s);
+        launch_scatter(L.dinv.get(), dinv_setup.get(), frank.get(), L.nF, s);
       }
       launch_nested_pos_ranked(L.state.get(), L.fidx.get(), L.cidx.get(), frank.get(), L.nF,
                                N.pos.get(), L.n, L.pos.get(), s);
@@ -494,6 +508,7 @@ void finalize_hierarchy(Hierarchy& H) {
       launch_remap_ranked(L.cmap_nat.get(), N.pos.get(), frank.get(), L.nF, L.cmap.get(), s);
     } else {
       if (asm_smoother) L.Ahat = std::move(Ahat_setup);
+      if (dinv_setup.get()) L.dinv = std::move(dinv_setup);
       launch_nested_pos(L.state.get(), L.fidx.get(), L.cidx.get(), L.nF, N.pos.get(), L.n,
                         L.pos.get(), s);
       permute_rows(L.Afc_nat, nullptr, N.pos.get(), L.nC, L.Afc, s);
@@ -538,6 +553,10 @@ void finalize_hierarchy(Hierarchy& H) {
       lower(L.B, L.b32, L.b16);
       lower(L.Z, L.z32, L.z16);
       if (L.Ahat.rows > 0) lower(L.Ahat, L.hat32, L.hat16);
+      if (L.dinv.get()) {
+        L.dinv32.alloc(L.nF, s);
+        convert_d2f(L.dinv32.get(), L.dinv.get(), L.nF, s);
+      }
     }
   }
   // compressed columns for every solve operator whose row blocks allow them,

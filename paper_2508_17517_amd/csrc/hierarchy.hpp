@@ -39,6 +39,8 @@ struct Level {
   CSR Afc;                  // A_fc in solve numbering (only until B is built)
   CSR B;                    // A_fc + A_ff W: the F-point residual operator on e_c
   CSR Ahat;                 // assembled Ahat^{-1} (AIRG_SMOOTH_ASSEMBLED), A_ff's pattern
+  DBuf<double> dinv;        // 1 / diag(A_ff) for the matrix-free Neumann smoother
+  DBuf<float> dinv32;
   DBuf<int32_t> cmap;       // nested position on level l+1, or -1
   DBuf<int32_t> pos;        // setup index -> nested position on this level
   std::vector<double> alpha;

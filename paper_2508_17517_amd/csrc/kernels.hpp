@@ -97,6 +97,18 @@ void spmv_residual_t(const OpView& B, int tpr, int K, const X* ec, const X* rf, 
 template <class X>
 void spmv_horner_prolong_t(const OpView& A, int tpr, int K, const X* y, const X* sv, X* ef,
                            double a, double b, const int32_t* cmap, const X* ec, hipStream_t st);
+// nAIR's Neumann step out = y + D^{-1} (s - A y), the last step fused with the
+// prolongation (ef = W e_c + ...), and y = D^{-1} s (ef = W e_c + D^{-1} s when
+// cmap is given); D^{-1} holds one value per row.
+template <class X>
+void spmv_neumann_t(const OpView& A, int tpr, int K, const X* y, const X* sv, const X* dinv, X* out,
+                    hipStream_t st);
+template <class X>
+void spmv_neumann_prolong_t(const OpView& A, int tpr, int K, const X* y, const X* sv,
+                            const X* dinv, X* ef, const int32_t* cmap, const X* ec, hipStream_t st);
+template <class X>
+void dinv_apply_t(X* out, const X* sv, const X* dinv, const int32_t* cmap, const X* ec,
+                  int64_t rows, int K, hipStream_t s);
 // ef = W e_c + a s (a degree-0 smoother)
 template <class X>
 void prolong_axpy_t(X* ef, const X* sv, const int32_t* cmap, const X* ec, double a, int64_t rows,
@@ -218,6 +230,10 @@ void spgemm(const CSR& A, const CSR& B, CSR& C, hipStream_t s);
 //   out = alpha_0 I + alpha_1 A + alpha_2 A~^2 + ..., zeros dropped.
 void fixed_sparsity_inverse(const CSR& Aff, const std::vector<double>& alpha, CSR& out,
                             hipStream_t s);
+// nAIR's assembled Neumann approximation (I + N~ + ... + N~^d) D^{-1} with
+// N = I - D^{-1} A_ff kept on A_ff's pattern, and the diagonal inverse D^{-1}.
+void neumann_fixed_sparsity(const CSR& Aff, int degree, CSR& out, hipStream_t s);
+void diag_inverse(const CSR& A, DBuf<double>& dinv, hipStream_t s);
 // Drop |z| < tol * max_j |z_ij| per row (no lumping), optionally negating.
 void restrictor_drop(const CSR& Zin, double tol, bool negate, CSR& Z, hipStream_t s);
 // Relative off-diagonal drop with lumping to the diagonal; sets *bad_diag if a

@@ -154,10 +154,47 @@ void horner(const Level& L, const OpView& Aff, int K, const X* sv, const X* ec, 
 // The F-point smoother: the polynomial matrix-free (Horner), or one product
 // with the assembled Ahat^{-1} fused with the prolongation.
 template <class X>
+const X* dinv_of(const Level& L);
+template <>
+const double* dinv_of<double>(const Level& L) { return L.dinv.get(); }
+template <>
+const float* dinv_of<float>(const Level& L) { return L.dinv32.get(); }
+
+// nAIR's Neumann smoother: y = D^{-1} s, then d steps y += D^{-1} (s - A_ff y),
+// the last one fused with the prolongation
+template <class X>
+void neumann(const Level& L, const OpView& Aff, int K, const X* sv, const X* ec, X* ef, X* y0,
+             X* y1, hipStream_t s, LaunchTally* tally) {
+  const int d = (int)L.alpha.size() - 1;
+  const int64_t n = L.nF * K;
+  const double xb = (double)sizeof(X);
+  const X* dinv = dinv_of<X>(L);
+  const int32_t* cmap = L.cmap.get();
+  const double mb = csr_bytes(L.nF, Aff.nnz, vt_bytes(Aff.vt)), mf = 2.0 * (double)Aff.nnz * K;
+  if (d == 0) {
+    dinv_apply_t<X>(ef, sv, dinv, cmap, ec, L.nF, K, s);
+    if (tally) tally->add(3.0 * xb * n + xb * L.nF + 4.0 * L.nF, 2.0 * n);
+    return;
+  }
+  X* y[2] = {y0, y1};
+  dinv_apply_t<X>(y[0], sv, dinv, nullptr, nullptr, L.nF, K, s);
+  if (tally) tally->add(2.0 * xb * n + xb * L.nF, (double)n);
+  int c = 0;
+  for (int k = 1; k < d; ++k) {
+    spmv_neumann_t<X>(Aff, L.tpr_ff, K, y[c], sv, dinv, y[c ^ 1], s);
+    if (tally) tally->add(mb + xb * n * 3 + xb * L.nF, mf + 3.0 * n, col_saving(Aff));
+    c ^= 1;
+  }
+  spmv_neumann_prolong_t<X>(Aff, L.tpr_ff, K, y[c], sv, dinv, ef, cmap, ec, s);
+  if (tally) tally->add(mb + xb * n * 4 + xb * L.nF + 4.0 * L.nF, mf + 4.0 * n, col_saving(Aff));
+}
+
+template <class X>
 void smooth(const Level& L, const LevelOps& o, int K, const X* sv, const X* ec, X* ef, X* y0,
             X* y1, hipStream_t s, LaunchTally* tally = nullptr) {
   if (L.Ahat.rows == 0) {
-    horner<X>(L, o.ff, K, sv, ec, ef, y0, y1, s, tally);
+    if (L.dinv.get()) neumann<X>(L, o.ff, K, sv, ec, ef, y0, y1, s, tally);
+    else horner<X>(L, o.ff, K, sv, ec, ef, y0, y1, s, tally);
     return;
   }
   spmv_horner_prolong_t<X>(o.hat, L.tpr_hat, K, sv, sv, ef, 1.0, 0.0, L.cmap.get(), ec, s);

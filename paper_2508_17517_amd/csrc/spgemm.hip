@@ -371,6 +371,69 @@ void fixed_sparsity_inverse(const CSR& Aff, const std::vector<double>& alpha, CS
   drop_zeros(full, out, s);
 }
 
+// ------------------------------------------------------------------ Neumann (nAIR)
+__global__ void row_diag_kernel(CSRView A, double* d) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.rows) return;
+  double v = 0.0;
+  for (int p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p)
+    if (A.col[p] == i) v = A.val[p];
+  d[i] = v;
+}
+// N = I - D^{-1} A on A's pattern: -a_ij / a_ii off the diagonal, 0 on it
+__global__ void jacobi_iteration_matrix_kernel(CSRView A, const double* d, double* nval) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.rows) return;
+  for (int p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p)
+    nval[p] = A.col[p] == i ? 0.0 : -A.val[p] / d[i];
+}
+__global__ void col_scale_kernel(int64_t nnz, const int32_t* col, const double* dinv, double* val) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nnz) val[p] = val[p] * dinv[col[p]];
+}
+__global__ void reciprocal_kernel(int64_t n, const double* d, double* r) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) r[i] = 1.0 / d[i];
+}
+
+void diag_inverse(const CSR& A, DBuf<double>& dinv, hipStream_t s) {
+  const int64_t n = A.rows;
+  DBuf<double> d(n, s);
+  dinv.alloc(n, s);
+  if (n <= 0) return;
+  row_diag_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(view(A), d.get());
+  AIRG_CHECK_LAUNCH();
+  reciprocal_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(n, d.get(), dinv.get());
+  AIRG_CHECK_LAUNCH();
+}
+
+void neumann_fixed_sparsity(const CSR& Aff, int degree, CSR& out, hipStream_t s) {
+  const int64_t n = Aff.rows;
+  DBuf<double> d(n, s), dinv;
+  CSR N;
+  copy_csr(Aff, N, s);
+  if (n > 0) {
+    row_diag_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(view(Aff), d.get());
+    AIRG_CHECK_LAUNCH();
+    jacobi_iteration_matrix_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(view(Aff), d.get(),
+                                                                           N.val.get());
+    AIRG_CHECK_LAUNCH();
+  }
+  // I + N + N~^2 + ... + N~^d through the fixed-sparsity sum with unit coefficients
+  std::vector<double> ones((size_t)std::max(degree, 0) + 1, 1.0);
+  CSR S;
+  fixed_sparsity_inverse(N, ones, S, s);
+  diag_inverse(Aff, dinv, s);
+  if (S.nnz > 0) {
+    col_scale_kernel<<<blocks_for(S.nnz, kBlock), kBlock, 0, s>>>(S.nnz, S.col.get(), dinv.get(),
+                                                                 S.val.get());
+    AIRG_CHECK_LAUNCH();
+  }
+  drop_zeros(S, out, s);
+}
+
+
+
 // ------------------------------------------------------------------ drops
 __global__ void rdrop_count_kernel(CSRView Z, double tol, int64_t* count) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

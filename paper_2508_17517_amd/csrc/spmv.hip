@@ -500,6 +500,45 @@ struct EpiHornerProlong {
   __device__ void operator()(int64_t i, X t, const Pre& p) const { out[i] = p.e + (a * t + b * p.s); }
 };
 
+// nAIR's Jacobi-scaled Neumann step y' = y + D^{-1} (s - A y), and the last
+// step fused with the prolongation: e_f = W e_c + (y + D^{-1} (s - A y)).
+// y is the gathered vector; D^{-1} is per row.
+template <class X>
+struct EpiNeumann {
+  X* out;
+  const X* y;
+  const X* sv;
+  const X* dinv;
+  int kshift;
+  struct Pre {
+    X y, s, d;
+  };
+  __device__ Pre pre(int64_t i) const { return {y[i], sv[i], dinv[i >> kshift]}; }
+  __device__ void operator()(int64_t i, X t, const Pre& p) const { out[i] = p.y + p.d * (p.s - t); }
+};
+template <class X>
+struct EpiNeumannProlong {
+  X* out;
+  const X* y;
+  const X* sv;
+  const X* dinv;
+  const int32_t* cmap;
+  const X* ec;
+  int kshift;
+  struct Pre {
+    X y, s, d, e;
+  };
+  __device__ Pre pre(int64_t i) const {
+    const int64_t row = i >> kshift;
+    const int m = cmap[row];
+    return {y[i], sv[i], dinv[row],
+            m >= 0 ? ec[((int64_t)m << kshift) + (i - (row << kshift))] : X(0)};
+  }
+  __device__ void operator()(int64_t i, X t, const Pre& p) const {
+    out[i] = p.e + (p.y + p.d * (p.s - t));
+  }
+};
+
 static int log2_of(int K) {
   int k = 0;
   while ((1 << k) < K) ++k;
@@ -545,6 +584,45 @@ template <class X>
 void spmv_horner_prolong_t(const OpView& A, int tpr, int K, const X* y, const X* sv, X* ef,
                            double a, double b, const int32_t* cmap, const X* ec, hipStream_t st) {
   launch_spmv(A, tpr, K, y, EpiHornerProlong<X>{ef, sv, cmap, ec, (X)a, (X)b, log2_of(K)}, st);
+}
+
+template <class X>
+void spmv_neumann_t(const OpView& A, int tpr, int K, const X* y, const X* sv, const X* dinv, X* out,
+                    hipStream_t st) {
+  launch_spmv(A, tpr, K, y, EpiNeumann<X>{out, y, sv, dinv, log2_of(K)}, st);
+}
+template <class X>
+void spmv_neumann_prolong_t(const OpView& A, int tpr, int K, const X* y, const X* sv,
+                            const X* dinv, X* ef, const int32_t* cmap, const X* ec,
+                            hipStream_t st) {
+  launch_spmv(A, tpr, K, y,
+              EpiNeumannProlong<X>{ef, y, sv, dinv, cmap, ec, log2_of(K)}, st);
+}
+
+// y = D^{-1} s, or (prolong) e_f = W e_c + D^{-1} s
+template <class X>
+__global__ void dinv_apply_kernel(X* out, const X* sv, const X* dinv, const int32_t* cmap,
+                                  const X* ec, int kshift, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t row = i >> kshift;
+  const X v = dinv[row] * sv[i];
+  if (cmap) {
+    const int m = cmap[row];
+    const X e = m >= 0 ? ec[((int64_t)m << kshift) + (i - (row << kshift))] : X(0);
+    out[i] = e + v;
+  } else {
+    out[i] = v;
+  }
+}
+template <class X>
+void dinv_apply_t(X* out, const X* sv, const X* dinv, const int32_t* cmap, const X* ec,
+                  int64_t rows, int K, hipStream_t s) {
+  const int64_t n = rows * K;
+  if (n <= 0) return;
+  dinv_apply_kernel<X><<<blocks_for(n, kBlock), kBlock, 0, s>>>(out, sv, dinv, cmap, ec,
+                                                                 log2_of(K), n);
+  AIRG_CHECK_LAUNCH();
 }
 
 template <class X>
@@ -595,7 +673,13 @@ void axpy_first_t(X* x, const X* w, double a, bool first, int64_t n, hipStream_t
   template void spmv_horner_prolong_t<X>(const OpView&, int, int, const X*, const X*, X*, double,  \
                                          double, const int32_t*, const X*, hipStream_t);           \
   template void prolong_axpy_t<X>(X*, const X*, const int32_t*, const X*, double, int64_t, int,    \
-                                  hipStream_t);
+                                  hipStream_t);                                                    \
+  template void spmv_neumann_t<X>(const OpView&, int, int, const X*, const X*, const X*, X*,       \
+                                  hipStream_t);                                                    \
+  template void spmv_neumann_prolong_t<X>(const OpView&, int, int, const X*, const X*, const X*,   \
+                                          X*, const int32_t*, const X*, hipStream_t);              \
+  template void dinv_apply_t<X>(X*, const X*, const X*, const int32_t*, const X*, int64_t, int,    \
+                                hipStream_t);
 AIRG_INSTANTIATE(double)
 AIRG_INSTANTIATE(float)
 #undef AIRG_INSTANTIATE

@@ -394,3 +394,19 @@ def test_degenerate_systems_match_oracle(case):
     assert info["converged"] == 1 and info["iterations"] == its
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * max(np.linalg.norm(xo), 1.0)
     s.close()
+
+
+@pytest.mark.parametrize("smoother", [0, 1])
+def test_nair_matches_oracle(smoother):
+    # nAIR: Neumann polynomials in the smoother and in Ahat^{-1} (Sec. 3.3)
+    _needs_gpu()
+    p = workloads.fv_random(96, 0.3, True)
+    prm = oracle.Params(inverse_type="neumann", smoother="assembled" if smoother else "poly")
+    xo, its, rel, levels, _ = oracle.solve(p.scipy(), p.b, prm)
+    s = _solver(p, inverse_type=1, smoother=smoother, keep_setup_data=1)
+    compare_hierarchy(s, levels)
+    x, info = s.solve(torch.from_numpy(p.b).cuda())
+    assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
+    assert info["iterations"] == its
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    s.close()

@@ -502,3 +502,46 @@ def test_assembled_smoother_solves_to_tolerance():
     assert rel <= 1e-10 and np.linalg.norm(x - u) <= 1e-8 * np.linalg.norm(u)
     x2, its2, _, _, _ = oracle.solve(A, p.b, oracle.Params(), levels=levels)
     assert its >= its2 - 1  # the paper: assembled needs as many or more iterations
+
+
+# --------------------------------------------------------------------- nAIR: Neumann polynomials (Sec. 3.3)
+
+def test_neumann_apply_is_the_jacobi_scaled_series():
+    rng_ = np.random.default_rng(11)
+    n = 12
+    M = np.diag(rng_.uniform(2.0, 3.0, n)) + np.tril(rng_.uniform(-0.4, 0.4, (n, n)), -1)
+    A = sp.csr_matrix(M)
+    s = rng_.standard_normal(n)
+    D = np.diag(M)
+    N = np.eye(n) - M / D[:, None]
+    for d in (0, 1, 3):
+        want = sum(np.linalg.matrix_power(N, k) @ (s / D) for k in range(d + 1))
+        assert np.allclose(oracle.linalg.neumann_apply(A, d, s), want, rtol=1e-13, atol=1e-14)
+    # N is strictly lower triangular, so N^n = 0: degree n - 1 inverts exactly
+    x = oracle.linalg.neumann_apply(A, n - 1, s)
+    assert np.allclose(M @ x, s, rtol=0, atol=1e-12)
+
+
+def test_neumann_fixed_sparsity_on_a_closed_pattern_is_the_series():
+    # lower-bidiagonal A_ff: its pattern is not closed, but a dense lower
+    # triangle is, so the masked powers are the exact powers there
+    rng_ = np.random.default_rng(12)
+    n = 8
+    M = np.diag(rng_.uniform(1.5, 2.5, n)) + np.tril(rng_.uniform(-0.5, 0.5, (n, n)), -1)
+    A = sp.csr_matrix(M)
+    D = np.diag(M)
+    N = np.eye(n) - M / D[:, None]
+    for d in (1, 2, 4):
+        want = sum(np.linalg.matrix_power(N, k) for k in range(d + 1)) / D[None, :]
+        got = oracle.hierarchy.neumann_fixed_sparsity(A, d).toarray()
+        assert np.allclose(got, want, rtol=1e-13, atol=1e-14)
+
+
+def test_nair_solves_to_tolerance():
+    p = workloads.fv_random(48, 0.3, True)
+    A = p.scipy()
+    for smoother in ("poly", "assembled"):
+        prm = oracle.Params(inverse_type="neumann", smoother=smoother)
+        x, its, rel, levels, _ = oracle.solve(A, p.b, prm)
+        u = oracle.sweep_solve(A, p.b, p.level)
+        assert rel <= 1e-10 and np.linalg.norm(x - u) <= 1e-8 * np.linalg.norm(u)
