@@ -380,7 +380,7 @@ def main():
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the solver has no multi-GPU "
-              "path in this build", file=sys.stderr)
+              "path", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -23,6 +23,6 @@ def gpu_available():
 
 @pytest.fixture(scope="session")
 def lib():
-    """The built C-ABI library (fails loudly when missing on a GPU machine)."""
+    """The built C-ABI library (fails loudly when it is missing on a machine with a GPU)."""
     from paper_2508_17517_amd import binding
     return binding.load()
