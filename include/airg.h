@@ -210,6 +210,12 @@ int airg_solve_batch(airg_handle h, const double* const* b, double* const* x,
 int airg_adjoint_solve(airg_handle h, int nrhs, const double* w, int64_t ldw,
                        double* lam, int64_t ldl, int use_guess, airg_solve_info* info);
 
+/* Free the Krylov workspaces that multi-column solves (nrhs > 1, forward or
+ * adjoint) keep in the handle for reuse (up to (2 restart + 1) n K doubles
+ * each); the next multi-column solve makes them again.  The hierarchies and
+ * the single-column workspace stay. */
+int airg_trim(airg_handle h);
+
 /* Hierarchy statistics. */
 int airg_get_stats(airg_handle h, airg_stats* s);
 

@@ -104,6 +104,10 @@ class Solver:
         """Solve A^T lam = w (the transpose hierarchy is built on first use)."""
         return self._solve(self.lib.airg_adjoint_solve, w, lam, guess)
 
+    def trim(self):
+        """Free the workspaces kept for multi-column solves (airg_trim)."""
+        binding.check(self.lib.airg_trim(self.h), self.lib)
+
     # ------------------------------------------------------------------ introspection
     def stats(self):
         s = binding.Stats()

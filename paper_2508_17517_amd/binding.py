@@ -119,6 +119,7 @@ SYMBOLS = {
     "airg_adjoint_solve": (c_i32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, c_i64,
                                    ctypes.c_void_p, c_i64, ctypes.c_int, P(SolveInfo)]),
     "airg_get_stats": (c_i32, [ctypes.c_void_p, P(Stats)]),
+    "airg_trim": (c_i32, [ctypes.c_void_p]),
     "airg_level_info_get": (c_i32, [ctypes.c_void_p, ctypes.c_int, P(LevelInfo)]),
     "airg_export_level": (c_i32, [ctypes.c_void_p, ctypes.c_int, P(LevelArrays)]),
     "airg_import_hierarchy": (c_i32, [P(ctypes.c_void_p), ctypes.c_int, P(LevelInfo),

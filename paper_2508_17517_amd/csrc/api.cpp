@@ -409,6 +409,16 @@ int airg_time_kernels(airg_handle h, int cls, int reps, airg_kernel_timing* out)
   });
 }
 
+int airg_trim(airg_handle h) {
+  return guard([&]() {
+    airg_ctx* c = handle_of(h);
+    AIRG_HIP(hipStreamSynchronize(c->H.s));
+    c->Wk.clear();
+    c->Wtk.clear();
+    return (int)AIRG_OK;
+  });
+}
+
 int airg_autotune(airg_handle h, int reps, airg_tune_entry* out, int max_out, int* n_out) {
   return guard([&]() {
     airg_ctx* c = handle_of(h);

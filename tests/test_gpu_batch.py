@@ -54,6 +54,10 @@ def test_column_batch_matches_single_solves():
     X, infos = s.solve(torch.from_numpy(B).cuda())
     single = [s.solve(torch.from_numpy(B[k]).cuda())[0].cpu().numpy() for k in range(11)]
     _check_columns(p, B, X.cpu().numpy(), infos, single)
+    # the workspaces come back after a trim, with the same results
+    s.trim()
+    X2, _ = s.solve(torch.from_numpy(B).cuda())
+    assert torch.equal(X, X2)
     s.close()
 
 
