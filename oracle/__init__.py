@@ -16,8 +16,11 @@ Modules:
   solve   -- V-cycle with up F-point smoothing (Eq. f_point), FGMRES, adjoint
   sweep   -- exact flow-order sweeps (Sec. 1.1), the ground truth
 
-Parity status per function is recorded in the design notes; the pinned
-properties live in tests/test_oracle_*.py.
+Every function is pinned by a test in tests/test_oracle_pins.py against what
+the paper and the mathematics fix (closed forms, invariants, exactness
+cases, brute force); what nothing outside the method fixes -- the exact CF
+split, level counts and iteration counts of the workloads -- is parity
+unpinned and is compared between the library and this oracle only.
 """
 from .params import Params  # noqa: F401
 from .hierarchy import setup, ZeroDiagonal  # noqa: F401
