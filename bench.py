@@ -179,6 +179,8 @@ def batched_legs(a, p, s64, value64, ip, ix, dv):
                        "ms_per_step": 1e3 * dt, "iterations": infos[0]["iterations"],
                        "max_rel_residual": max(i["rel_residual"] for i in infos),
                        "levels": st["levels"], "setup_s": round(setup_b, 3),
+                       "setup_component_ms": {k: round(v, 1) for k, v in
+                                              st["setup_component_ms"].items()},
                        "speedup_vs_fp64": v / value64}
     print(f"bench: problems {res['problems']}", file=sys.stderr, flush=True)
     sb.close()
