@@ -11,7 +11,8 @@
  *     relative drop and lumping, and automatic truncation with a high-order
  *     Newton-form coarse polynomial (Sec. 2.3, 2.4);
  *   - solve: V-cycles with only up F-point smoothing (Eq. f_point), the
- *     polynomials applied matrix-free.
+ *     polynomials applied matrix-free (or the assembled Ahat^{-1}), inside
+ *     FGMRES or the paper's undamped Richardson.
  *
  * Conventions
  *   - Every function returns an int status: AIRG_OK (0), a warning (> 0) or an
@@ -73,8 +74,8 @@ typedef struct {
   int32_t max_levels;        /* <= AIRG_MAX_LEVELS, 64 */
   int32_t added_roots;       /* extra copies of outlying Newton roots, 1 */
   int32_t precision;         /* airg_precision of the V-cycle storage, AIRG_FP64 */
-  int32_t max_it;            /* FGMRES iteration cap (V-cycles), 500 */
-  int32_t restart;           /* FGMRES restart length, 30 */
+  int32_t max_it;            /* outer iteration cap (V-cycles), 500 */
+  int32_t restart;           /* FGMRES restart length, 30 (unused by Richardson) */
   int32_t keep_setup_data;   /* keep level data in setup numbering for export, 0 */
   int32_t locality_order;    /* order each level's F points and the coarsest level's
                                 points in the solve numbering by a locality key of two
@@ -160,7 +161,9 @@ typedef struct {
   int32_t* fc_rowptr; int32_t* fc_col; double* fc_val;  /* A_fc */
   int32_t* z_rowptr; int32_t* z_col; double* z_val;     /* Z (n_c x n_f) */
   int32_t* cmap;                                   /* n_f: coarse index or -1 */
-  double* alpha;                                   /* poly_len smoother coefficients */
+  double* alpha;                                   /* poly_len smoother coefficients
+                                                      (zeros for AIRG_INVERSE_NEUMANN:
+                                                      only the degree counts) */
   double* roots_re; double* roots_im;              /* n_roots, applied order */
 } airg_level_arrays;
 
@@ -182,9 +185,9 @@ int airg_setup(airg_handle* out, int64_t n, int64_t nnz, const int32_t* rowptr,
  * column missed rtol within max_it.
  * Several columns are solved together, K at a time (K a power of two, at
  * most 64 and with n K < 2^31): every V-cycle kernel then reads each matrix
- * entry once for all K columns (SpMM on interleaved columns) and one FGMRES
- * process runs over the stacked columns, stopped only when every column has
- * |b_k - A x_k| <= rtol |b_k|.  The Krylov bases then hold (2 restart + 1)
+ * entry once for all K columns (SpMM on interleaved columns) and one outer
+ * process (FGMRES or Richardson) runs over the stacked columns, stopped only
+ * when every column has |b_k - A x_k| <= rtol |b_k|.  The Krylov bases then hold (2 restart + 1)
  * vectors of n K doubles (136 GB for n = 2048^2, K = 64, restart 30). */
 int airg_solve(airg_handle h, int nrhs, const double* b, int64_t ldb, double* x,
                int64_t ldx, int use_x_as_guess, airg_solve_info* info);
@@ -199,8 +202,8 @@ int airg_setup_batch(airg_handle* out, int nprob, const int64_t* n, const int64_
                      void* hip_stream);
 
 /* Solve every problem of a batch handle: b[p], x[p] device pointers of n[p]
- * doubles.  One FGMRES process runs over the block-diagonal system until
- * every problem has |b_p - A_p x_p| <= rtol |b_p|; info has nprob entries. */
+ * doubles.  One outer process runs over the block-diagonal system until every
+ * problem has |b_p - A_p x_p| <= rtol |b_p|; info has nprob entries. */
 int airg_solve_batch(airg_handle h, const double* const* b, double* const* x,
                      int use_x_as_guess, airg_solve_info* info);
 
@@ -236,7 +239,8 @@ int airg_import_hierarchy(airg_handle* out, int nlevels, const airg_level_info* 
 enum airg_kernel_class {
   AIRG_K_POLY = 0,      /* every polynomial SpMV of a V-cycle: Horner smoother steps on
                            all levels and the Newton steps of the coarse solve */
-  AIRG_K_HORNER = 1,    /* smoother steps only (Sec. 2.2) */
+  AIRG_K_HORNER = 1,    /* smoother products only: Horner or Neumann steps, or the
+                           assembled Ahat^{-1} (Sec. 2.2) */
   AIRG_K_NEWTON = 2,    /* coarse Newton steps only (Sec. 2.3) */
   AIRG_K_RESIDUAL = 3,  /* F-point residual s = r_f - (A_fc + A_ff W) e_c (Eq. f_point) */
   AIRG_K_RESTRICT = 4,  /* restriction r_c + Z r_f */
@@ -293,8 +297,9 @@ typedef struct {
 
 /* Launch-shape tuner: time every solve operator's single-column product with
  * 1, 2, ..., 64 lanes per row, the row-block kernel and the LDS-staged kernel
- * where they exist, each with and without the XCD mapping (`reps` launches each, HIP events on the
- * handle's stream), and keep the fastest per operator.  A row split over more
+ * where they exist, each with and without the XCD mapping (`reps` launches
+ * each, HIP events on the handle's stream), and keep the fastest per
+ * operator.  A row split over more
  * lanes sums in a different order, so solves after tuning agree with untuned
  * ones to rounding, not bit for bit; timings vary run to run, so a caller
  * that needs reproducible results pins the shapes with airg_set_lanes.
