@@ -248,3 +248,23 @@ def test_row_block_kernel_sums_like_one_lane_per_row():
     assert i0["iterations"] == i1["iterations"]
     assert torch.equal(x0, x1)
     s.close()
+
+
+@pytest.mark.parametrize("opts", [
+    dict(precision=1, smoother=1),
+    dict(precision=2, inverse_type=1),
+    dict(outer=1, smoother=1, inverse_type=1),
+    dict(outer=1, precision=1),
+])
+def test_option_combinations_on_column_batches(opts):
+    # every combination of storage precision, smoother, polynomial and outer
+    # loop reaches the FP64 tolerance on each of several columns
+    _needs_gpu()
+    from paper_2508_17517_amd import Solver
+    p = workloads.fv_random(64, 0.7, True)
+    B = workloads.rhs_batch(p, 3)
+    print("options", opts, flush=True)
+    s = Solver(p.indptr, p.indices, p.data, **opts)
+    X, infos = s.solve(torch.from_numpy(B).cuda())
+    _check_columns(p, B, X.cpu().numpy(), infos)
+    s.close()
