@@ -185,10 +185,13 @@ int airg_setup(airg_handle* out, int64_t n, int64_t nnz, const int32_t* rowptr,
  * column missed rtol within max_it.
  * Several columns are solved together, K at a time (K a power of two, at
  * most 64 and with n K < 2^31): every V-cycle kernel then reads each matrix
- * entry once for all K columns (SpMM on interleaved columns) and one outer
- * process (FGMRES or Richardson) runs over the stacked columns, stopped only
- * when every column has |b_k - A x_k| <= rtol |b_k|.  The Krylov bases then hold (2 restart + 1)
- * vectors of n K doubles (136 GB for n = 2048^2, K = 64, restart 30). */
+ * entry once for all K columns (SpMM on interleaved columns), and so do the
+ * top-level product and the orthogonalisation kernels, while each column
+ * runs its own outer process (FGMRES or Richardson) with its own stopping
+ * test |b_k - A x_k| <= rtol |b_k|, restarts and iteration count, as if it
+ * were solved alone; a column that has stopped rides along as zeros until
+ * the others stop.  The Krylov bases then hold (2 restart + 1) vectors of
+ * n K doubles (136 GB for n = 2048^2, K = 64, restart 30). */
 int airg_solve(airg_handle h, int nrhs, const double* b, int64_t ldb, double* x,
                int64_t ldx, int use_x_as_guess, airg_solve_info* info);
 

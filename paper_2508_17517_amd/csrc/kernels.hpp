@@ -34,6 +34,22 @@ void launch_basis_combine(double* x, const double* Z, int64_t ldz, const double*
 size_t dot_work_size(int64_t n, int nv);
 void launch_tree_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
                       double* out, double* work, hipStream_t s);
+// One FGMRES per column of K interleaved columns ([n0][K] arrays, K a power
+// of two, at most 64; h, y and out hold entry (k, c) at k K + c):
+//   w = w - sum_k h[k, c] V_k (k sequential per element),
+//   x = x + sum_k y[k, c] Z_k,
+//   y = x / d[c] column by column (0 where d[c] = 0),
+//   out[k, c] = V_k . w over column c (fixed order; `work` needs
+//   col_dots_work_size(n0, K) doubles).
+void launch_cgs_update_cols(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                            int64_t n0, int K, hipStream_t s);
+void launch_basis_combine_cols(double* x, const double* Z, int64_t ldz, const double* y, int nv,
+                               int64_t n0, int K, hipStream_t s);
+void launch_divide_cols(double* y, const double* x, const double* d, int64_t n0, int K,
+                        hipStream_t s);
+size_t col_dots_work_size(int64_t n0, int K);
+void launch_col_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n0, int K,
+                     double* out, double* work, hipStream_t s);
 // out[0] = sqrt(out[0]) on the device
 void launch_sqrt_inplace(double* v, hipStream_t s);
 

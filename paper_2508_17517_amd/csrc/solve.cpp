@@ -7,10 +7,13 @@
 //
 // Many right-hand sides are solved together as K interleaved columns: every
 // V-cycle kernel is then an SpMM that reads each matrix entry once for all
-// columns, and one Krylov process runs over the stacked columns (its
-// stopping test is tightened so that every column reaches the tolerance on
-// its own).  A block-diagonal batch of problems is solved the same way, each
-// problem being a convergence group.
+// columns, and the top-level product and the Gram-Schmidt, normalisation and
+// update kernels likewise cover all columns per launch, while each column
+// keeps its own FGMRES process (Hessenberg matrix, rotations, stopping test,
+// restarts) on the host.  A block-diagonal batch of problems is solved by one
+// Krylov process over the whole system, each problem being a convergence
+// group (its stopping test is tightened so that every problem reaches the
+// tolerance on its own).
 //
 // Mixed precision: with FP32 or BF16 storage the V-cycle runs on FP32 vectors
 // (matrices in the storage type, rows accumulated in FP32) between a
@@ -67,8 +70,12 @@ void workspace_init(const Hierarchy& H, Workspace& W, int K) {
   W.bperm.alloc(n, s);
   W.xperm.alloc(n, s);
   if (!H.seg.empty()) W.nat.alloc(H.n0, s);
-  W.hbuf.alloc(2 * (W.restart + 1) + 2, s);
-  W.ybuf.alloc(W.restart + 1, s);
+  W.hbuf.alloc((2 * (W.restart + 1) + 2) * (size_t)K, s);
+  W.ybuf.alloc((W.restart + 1) * (size_t)K, s);
+  if (K > 1) {
+    W.cdiv.alloc(K, s);
+    W.cdot_work.alloc(col_dots_work_size(H.n0, K), s);
+  }
   const size_t ng = std::max<size_t>((size_t)K, H.seg.empty() ? 1 : H.seg.size());
   W.gbuf.alloc(ng + 1, s);
   W.dot_work.alloc(dot_work_size(n, 64), s);
@@ -268,6 +275,217 @@ std::vector<double> group_norms(const Hierarchy& H, Workspace& W, const double* 
   return out;
 }
 
+// Givens-rotated Arnoldi state of one column's FGMRES cycle.
+struct ColumnCycle {
+  std::vector<double> Hm, g, cs, sn, y;
+  int k = 0;  // Arnoldi steps taken in this cycle
+  void reset(int R, double beta) {
+    Hm.assign((size_t)(R + 1) * R, 0.0);
+    g.assign(R + 1, 0.0);
+    cs.assign(R, 0.0);
+    sn.assign(R, 0.0);
+    y.assign(R, 0.0);
+    g[0] = beta;
+    k = 0;
+  }
+  // Append Hessenberg column j (h[i], i <= j, and h_{j+1,j} = hn), rotate it
+  // and return the residual estimate |g_{j+1}|.
+  double push(int R, int j, const double* h, double hn) {
+    for (int i = 0; i <= j; ++i) Hm[(size_t)i * R + j] = h[i];
+    Hm[(size_t)(j + 1) * R + j] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double a = Hm[(size_t)i * R + j], c = Hm[(size_t)(i + 1) * R + j];
+      Hm[(size_t)i * R + j] = cs[i] * a + sn[i] * c;
+      Hm[(size_t)(i + 1) * R + j] = -sn[i] * a + cs[i] * c;
+    }
+    const double a = Hm[(size_t)j * R + j], c = Hm[(size_t)(j + 1) * R + j];
+    const double rr = std::hypot(a, c);
+    if (rr > 0) {
+      cs[j] = a / rr;
+      sn[j] = c / rr;
+    } else {
+      cs[j] = 1.0;
+      sn[j] = 0.0;
+    }
+    Hm[(size_t)j * R + j] = rr;
+    Hm[(size_t)(j + 1) * R + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    k = j + 1;
+    return std::fabs(g[j + 1]);
+  }
+  // Back substitution for the k coefficients of the solution update.
+  void solve_upper(int R) {
+    for (int i = k - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int q = i + 1; q < k; ++q) t -= Hm[(size_t)i * R + q] * y[q];
+      y[i] = t / Hm[(size_t)i * R + i];
+    }
+  }
+};
+
+// K > 1 columns, one outer process per column (see fgmres_solve).  A column
+// that has stopped (converged, out of iterations, or at the end of its
+// Arnoldi process in this cycle) is carried through the shared launches as
+// zeros: its divisor is 0, so its next basis vector, V-cycle input and
+// products vanish, and it gets a zero weight in every solution update.
+void solve_columns(const Hierarchy& H, Workspace& W, std::vector<airg_solve_info>& out,
+                   bool& all_converged) {
+  hipStream_t s = H.s;
+  const int K = W.K;
+  const int64_t n0 = H.n0;
+  const int64_t n = n0 * K;
+  const int R = W.restart;
+  const int64_t ld = W.ld;
+  const double rtol = H.p.rtol;
+  const int max_it = H.p.max_it;
+  const OpView A = opview(H.Aperm);
+  double* V = W.V.get();
+  double* Zb = W.Zb.get();
+  double* dv = W.cdiv.get();
+
+  std::vector<double> bn = group_norms(H, W, W.bperm.get());
+  for (double v : bn)
+    if (!std::isfinite(v)) fail(AIRG_ERR_NONFINITE, "right-hand side is not finite");
+  std::vector<int> its(K, 0), rst(K, 0), done(K, 0);
+  std::vector<double> rn(K, 0.0), est(K, 0.0), ref = bn, dh(K), yh((size_t)R * K);
+  auto upload_div = [&]() { W.cdiv.from_host(dh.data(), K); };
+  auto residual = [&](double* r) {
+    spmv_t<double>(A, H.tpr_top, K, W.xperm.get(), W.w.get(), s);
+    launch_sub(r, W.bperm.get(), W.w.get(), n, s);
+    rn = group_norms(H, W, r);
+  };
+
+  if (H.p.outer == AIRG_OUTER_RICHARDSON) {
+    // x <- x + M (b - A x) for the columns still running; a column with b = 0
+    // is measured against its initial residual
+    double* r = V;
+    double* e = Zb;
+    residual(r);
+    for (int c = 0; c < K; ++c) {
+      if (ref[c] == 0.0) ref[c] = rn[c];
+      done[c] = rn[c] <= rtol * ref[c] || max_it <= 0;
+    }
+    for (;;) {
+      bool any = false;
+      for (int c = 0; c < K; ++c) {
+        dh[c] = done[c] ? 0.0 : 1.0;
+        any = any || !done[c];
+      }
+      if (!any) break;
+      vcycle(H, W, r, e);
+      W.ybuf.from_host(dh.data(), K);
+      launch_basis_combine_cols(W.xperm.get(), e, ld, W.ybuf.get(), 1, n0, K, s);
+      residual(r);
+      for (int c = 0; c < K; ++c) {
+        if (done[c]) continue;
+        ++its[c];
+        if (!std::isfinite(rn[c])) fail(AIRG_ERR_BREAKDOWN, "Richardson diverged (non-finite residual)");
+        if (rn[c] <= rtol * ref[c] || its[c] >= max_it) done[c] = 1;
+      }
+    }
+  } else {
+    // b = 0: the solution of A x = 0, whatever the guess
+    bool zero = false;
+    for (int c = 0; c < K; ++c) {
+      dh[c] = bn[c] == 0.0 ? 0.0 : 1.0;
+      zero = zero || bn[c] == 0.0;
+      done[c] = bn[c] == 0.0;
+    }
+    if (zero) {
+      upload_div();
+      launch_divide_cols(W.xperm.get(), W.xperm.get(), dv, n0, K, s);
+    }
+    std::vector<ColumnCycle> cyc(K);
+    std::vector<int> act(K, 0);
+    double* hd = W.hbuf.get();
+    std::vector<double> hh((size_t)(2 * (R + 1) + 1) * K), hc(R + 1);
+    for (;;) {
+      residual(V);
+      bool any = false;
+      for (int c = 0; c < K; ++c) {
+        act[c] = 0;
+        if (done[c]) continue;
+        if (rn[c] <= rtol * bn[c] || its[c] >= max_it) {
+          done[c] = 1;
+          continue;
+        }
+        if (!std::isfinite(rn[c])) fail(AIRG_ERR_BREAKDOWN, "FGMRES breakdown (non-finite residual)");
+        if (its[c] > 0) ++rst[c];
+        act[c] = 1;
+        any = true;
+      }
+      if (!any) break;
+      for (int c = 0; c < K; ++c) {
+        dh[c] = act[c] ? rn[c] : 0.0;
+        cyc[c].reset(R, act[c] ? rn[c] : 0.0);
+      }
+      upload_div();
+      launch_divide_cols(V, V, dv, n0, K, s);
+      for (int j = 0; j < R; ++j) {
+        double* vj = V + (int64_t)j * ld;
+        double* zj = Zb + (int64_t)j * ld;
+        vcycle(H, W, vj, zj);
+        spmv_t<double>(A, H.tpr_top, K, zj, W.w.get(), s);
+        double* h1 = hd;
+        double* h2 = hd + (size_t)(R + 1) * K;
+        double* hn2 = hd + (size_t)2 * (R + 1) * K;
+        launch_col_dots(V, ld, j + 1, W.w.get(), n0, K, h1, W.cdot_work.get(), s);
+        launch_cgs_update_cols(W.w.get(), V, ld, h1, j + 1, n0, K, s);
+        launch_col_dots(V, ld, j + 1, W.w.get(), n0, K, h2, W.cdot_work.get(), s);
+        launch_cgs_update_cols(W.w.get(), V, ld, h2, j + 1, n0, K, s);
+        launch_col_sumsq(W.w.get(), n0, K, hn2, W.col_work.get(), s);
+        W.hbuf.to_host(hh.data(), (size_t)(2 * (R + 1) + 1) * K);
+        AIRG_HIP(hipStreamSynchronize(s));
+        bool more = false;
+        for (int c = 0; c < K; ++c) {
+          dh[c] = 0.0;
+          if (!act[c]) continue;
+          for (int i = 0; i <= j; ++i)
+            hc[i] = hh[(size_t)i * K + c] + hh[(size_t)(R + 1) * K + (size_t)i * K + c];
+          const double hn = std::sqrt(hh[(size_t)2 * (R + 1) * K + c]);
+          ++its[c];
+          est[c] = cyc[c].push(R, j, hc.data(), hn);
+          if (!std::isfinite(est[c])) fail(AIRG_ERR_BREAKDOWN, "FGMRES breakdown (non-finite residual)");
+          if (est[c] <= rtol * bn[c] || its[c] >= max_it || hn == 0.0) {
+            act[c] = 0;
+            continue;
+          }
+          dh[c] = hn;
+          more = true;
+        }
+        if (!more || j + 1 == R) break;
+        upload_div();
+        launch_divide_cols(V + (int64_t)(j + 1) * ld, W.w.get(), dv, n0, K, s);
+      }
+      int kmax = 0;
+      std::fill(yh.begin(), yh.end(), 0.0);
+      for (int c = 0; c < K; ++c) {
+        ColumnCycle& cc = cyc[c];
+        if (cc.k == 0) continue;
+        cc.solve_upper(R);
+        for (int i = 0; i < cc.k; ++i) yh[(size_t)i * K + c] = cc.y[i];
+        kmax = std::max(kmax, cc.k);
+      }
+      W.ybuf.from_host(yh.data(), (size_t)kmax * K);
+      launch_basis_combine_cols(W.xperm.get(), Zb, ld, W.ybuf.get(), kmax, n0, K, s);
+    }
+  }
+  all_converged = true;
+  out.assign(K, airg_solve_info{});
+  for (int c = 0; c < K; ++c) {
+    airg_solve_info& o = out[c];
+    o.iterations = its[c];
+    o.restarts = rst[c];
+    o.converged = rn[c] <= rtol * ref[c] ? 1 : 0;
+    o.rel_residual = ref[c] > 0.0 ? rn[c] / ref[c] : 0.0;
+    o.rel_residual_estimate = H.p.outer == AIRG_OUTER_RICHARDSON
+                                  ? o.rel_residual
+                                  : (bn[c] > 0.0 ? est[c] / bn[c] : 0.0);
+    if (!o.converged) all_converged = false;
+  }
+}
+
 }  // namespace
 
 void vcycle(const Hierarchy& H, Workspace& W, const double* in, double* e) {
@@ -293,15 +511,28 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
   const int max_it = H.p.max_it;
   AIRG_HIP(hipEventRecord(W.ev0, s));
 
-  if (K == 1) {
-    launch_scatter(W.bperm.get(), b, pos, H.n0, s);
-    if (guess) launch_scatter(W.xperm.get(), x, pos, H.n0, s);
-    else launch_fill(W.xperm.get(), n, 0.0, s);
-  } else {
+  if (K > 1) {
     launch_scatter_cols(W.bperm.get(), b, ldb, pos, H.n0, K, kvalid, s);
     if (guess) launch_scatter_cols(W.xperm.get(), x, ldx, pos, H.n0, K, kvalid, s);
     else launch_fill(W.xperm.get(), n, 0.0, s);
+    std::vector<airg_solve_info> cols;
+    bool ok = false;
+    solve_columns(H, W, cols, ok);
+    launch_gather_cols(x, ldx, W.xperm.get(), pos, H.n0, K, kvalid, s);
+    AIRG_HIP(hipEventRecord(W.ev1, s));
+    AIRG_HIP(hipEventSynchronize(W.ev1));
+    float ms = 0.f;
+    AIRG_HIP(hipEventElapsedTime(&ms, W.ev0, W.ev1));
+    if (info)
+      for (int c = 0; c < kvalid; ++c) {
+        info[c] = cols[c];
+        info[c].solve_ms = ms;
+      }
+    return ok ? AIRG_OK : AIRG_NOT_CONVERGED;
   }
+  launch_scatter(W.bperm.get(), b, pos, H.n0, s);
+  if (guess) launch_scatter(W.xperm.get(), x, pos, H.n0, s);
+  else launch_fill(W.xperm.get(), n, 0.0, s);
   const std::vector<double> bn = group_norms(H, W, W.bperm.get());
   const size_t ng = bn.size();
   double bmin = 0.0, btot2 = 0.0;
@@ -433,8 +664,7 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
       launch_basis_combine(W.xperm.get(), Zb, ld, W.ybuf.get(), k, n, s);
     }
   }
-  if (K == 1) launch_gather(x, W.xperm.get(), pos, H.n0, s);
-  else launch_gather_cols(x, ldx, W.xperm.get(), pos, H.n0, K, kvalid, s);
+  launch_gather(x, W.xperm.get(), pos, H.n0, s);
   if (!converged) status = AIRG_NOT_CONVERGED;
   AIRG_HIP(hipEventRecord(W.ev1, s));
   AIRG_HIP(hipEventSynchronize(W.ev1));
@@ -448,10 +678,8 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
     out[q].rel_residual_estimate = est_rel;
     out[q].solve_ms = ms;
   }
-  if (info) {
-    const size_t nout = K > 1 ? (size_t)kvalid : ng;
-    for (size_t q = 0; q < nout; ++q) info[q] = out[q];
-  }
+  if (info)
+    for (size_t q = 0; q < ng; ++q) info[q] = out[q];
   return status;
 }
 

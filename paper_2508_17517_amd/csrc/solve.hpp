@@ -17,6 +17,7 @@ struct Workspace {
   DBuf<float> in32, e32, rr32, sv32, y032, y132, cw032, cw132, ct32;
   DBuf<double> bperm, xperm, nat;
   DBuf<double> hbuf, ybuf, gbuf, dot_work, col_work;
+  DBuf<double> cdiv, cdot_work;  // per-column divisors and dot partials (K > 1)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   ~Workspace();
 };
@@ -26,12 +27,15 @@ void workspace_init(const Hierarchy& H, Workspace& W, int K = 1);
 // One V-cycle: e = M r for a top-level vector `in` (nested numbering, W.K columns).
 void vcycle(const Hierarchy& H, Workspace& W, const double* in, double* e);
 
-// FGMRES on A x = b for W.K right-hand sides solved together: column c of b
-// starts at b + c ldb and of x at x + c ldx (setup numbering, device); only
-// the first kvalid columns are read and written.  With K = 1 and a batch of
-// problems (H.seg), each problem is a convergence group.  One Krylov process
-// runs over the stacked columns; every group must reach |r_g| <= rtol |b_g|.
-// info receives one entry per group.
+// The outer solve of A x = b for W.K right-hand sides solved together: column
+// c of b starts at b + c ldb and of x at x + c ldx (setup numbering, device);
+// only the first kvalid columns are read and written.  With K > 1 every
+// column runs its own FGMRES (or Richardson) process with its own stopping
+// test, iteration count and restarts, while the V-cycle, the top-level
+// product and the orthogonalisation kernels cover all K columns per launch.
+// With K = 1 and a batch of problems (H.seg), one process runs over the
+// block-diagonal system until every problem reaches |r_p| <= rtol |b_p|.
+// info receives one entry per column or problem.
 int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb, double* x,
                  int64_t ldx, int kvalid, bool guess, airg_solve_info* info);
 

@@ -235,6 +235,127 @@ void launch_sqrt_inplace(double* v, hipStream_t s) {
   AIRG_CHECK_LAUNCH();
 }
 
+// ------------------------------------------------------------------ per-column Krylov
+// K interleaved columns (element e = r K + c of an [n][K] array, K a power of
+// two): the orthogonalisation of one FGMRES per column, all columns per launch.
+__global__ void cgs_update_cols_kernel(double* w, const double* V, int64_t ldv, const double* h,
+                                       int nv, int64_t n, int K) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int c = (int)(e & (K - 1));
+  double acc = w[e];
+  for (int k = 0; k < nv; ++k) acc = acc - h[k * K + c] * V[(int64_t)k * ldv + e];
+  w[e] = acc;
+}
+__global__ void basis_combine_cols_kernel(double* x, const double* Z, int64_t ldz, const double* y,
+                                          int nv, int64_t n, int K) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int c = (int)(e & (K - 1));
+  double acc = x[e];
+  for (int k = 0; k < nv; ++k) acc = acc + y[k * K + c] * Z[(int64_t)k * ldz + e];
+  x[e] = acc;
+}
+__global__ void divide_cols_kernel(double* y, const double* x, const double* d, int64_t n, int K) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const double dc = d[e & (K - 1)];
+  y[e] = dc != 0.0 ? x[e] / dc : 0.0;
+}
+
+static void check_cols(int K) {
+  if (K < 1 || K > 64 || (K & (K - 1)) != 0) fail(AIRG_ERR_INTERNAL, "bad column count");
+}
+void launch_cgs_update_cols(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                            int64_t n0, int K, hipStream_t s) {
+  check_cols(K);
+  const int64_t n = n0 * K;
+  if (n <= 0 || nv <= 0) return;
+  cgs_update_cols_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(w, V, ldv, h, nv, n, K);
+  AIRG_CHECK_LAUNCH();
+}
+void launch_basis_combine_cols(double* x, const double* Z, int64_t ldz, const double* y, int nv,
+                               int64_t n0, int K, hipStream_t s) {
+  check_cols(K);
+  const int64_t n = n0 * K;
+  if (n <= 0 || nv <= 0) return;
+  basis_combine_cols_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(x, Z, ldz, y, nv, n, K);
+  AIRG_CHECK_LAUNCH();
+}
+void launch_divide_cols(double* y, const double* x, const double* d, int64_t n0, int K,
+                        hipStream_t s) {
+  check_cols(K);
+  const int64_t n = n0 * K;
+  if (n <= 0) return;
+  divide_cols_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, d, n, K);
+  AIRG_CHECK_LAUNCH();
+}
+
+// Per-column dot products out[k K + c] = sum_r V_k[r K + c] w[r K + c], up to
+// kColDotVecs vectors per pass.  Block b walks the 256-element slabs b, b + G,
+// b + 2G, ... of the array (a slab holds whole rows, so thread t always meets
+// column t mod K) adding its products in sequence; the lanes of a column then
+// combine by a shuffle tree, the four waves in order, and the G block
+// partials of each (k, c) by the tree sum.  w is read once per pass.
+constexpr int kColDotVecs = 16;
+constexpr int kColDotBlocks = 1024;
+
+static int64_t col_dot_blocks(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  return g < 1 ? 1 : (g > kColDotBlocks ? kColDotBlocks : g);
+}
+
+__global__ __launch_bounds__(256) void col_dots_stage1(const double* __restrict__ V, int64_t ldv,
+                                                       int nv, const double* __restrict__ w,
+                                                       int64_t n, int K, double* __restrict__ part) {
+  __shared__ double red[kColDotVecs][4][64];
+  const int t = threadIdx.x;
+  double acc[kColDotVecs];
+#pragma unroll
+  for (int k = 0; k < kColDotVecs; ++k) acc[k] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + t; e < n; e += stride) {
+    const double wv = w[e];
+#pragma unroll
+    for (int k = 0; k < kColDotVecs; ++k)
+      if (k < nv) acc[k] = acc[k] + V[(int64_t)k * ldv + e] * wv;
+  }
+  const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int k = 0; k < kColDotVecs; ++k) {
+    if (k < nv) {
+      double v = acc[k];
+      for (int o = K; o < 64; o <<= 1) v = v + __shfl_down(v, o, 64);
+      if (lane < K) red[k][wave][lane] = v;
+    }
+  }
+  __syncthreads();
+  for (int q = t; q < nv * K; q += 256) {
+    const int k = q / K, c = q % K;
+    part[(int64_t)q * gridDim.x + blockIdx.x] =
+        (red[k][0][c] + red[k][1][c]) + (red[k][2][c] + red[k][3][c]);
+  }
+}
+
+size_t col_dots_work_size(int64_t n0, int K) {
+  return (size_t)kColDotVecs * (size_t)K * (size_t)col_dot_blocks(n0 * K);
+}
+void launch_col_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n0, int K,
+                     double* out, double* work, hipStream_t s) {
+  check_cols(K);
+  if (nv <= 0) return;
+  const int64_t n = n0 * K;
+  const int64_t G = col_dot_blocks(n);
+  for (int k0 = 0; k0 < nv; k0 += kColDotVecs) {
+    const int cnt = nv - k0 < kColDotVecs ? nv - k0 : kColDotVecs;
+    col_dots_stage1<<<(unsigned)G, 256, 0, s>>>(V + (int64_t)k0 * ldv, ldv, cnt, w, n, K, work);
+    AIRG_CHECK_LAUNCH();
+    // G <= kDotChunk partials per (k, c): one tree stage per pair
+    tree_sum_stage<<<dim3(1u, (unsigned)(cnt * K)), 256, 0, s>>>(work, G, G, out + (int64_t)k0 * K, 1);
+    AIRG_CHECK_LAUNCH();
+  }
+}
+
 // ------------------------------------------------------------------ permutations
 __global__ void scatter_kernel(double* y, const double* x, const int32_t* perm, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

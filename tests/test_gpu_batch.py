@@ -1,8 +1,8 @@
 """Batched solves through the C ABI (needs an MI355X).
 
 Two kinds of batching: several right-hand sides of one matrix (K interleaved
-columns, one stacked Krylov process) and several independent problems in one
-block-diagonal hierarchy.  Every column or problem must reach the FP64
+columns, one FGMRES process per column over shared V-cycle launches) and
+several independent problems in one block-diagonal hierarchy.  Every column or problem must reach the FP64
 tolerance in its own residual, checked here on the CPU, and agree with the
 exact discrete solution from the oracle's sweep.
 """
@@ -52,12 +52,47 @@ def test_column_batch_matches_single_solves():
     print(f"fv96 perm, 11 columns", flush=True)
     s = Solver(p.indptr, p.indices, p.data)
     X, infos = s.solve(torch.from_numpy(B).cuda())
-    single = [s.solve(torch.from_numpy(B[k]).cuda())[0].cpu().numpy() for k in range(11)]
+    ones = [s.solve(torch.from_numpy(B[k]).cuda()) for k in range(11)]
+    single = [x.cpu().numpy() for x, _ in ones]
     _check_columns(p, B, X.cpu().numpy(), infos, single)
+    # each column runs its own FGMRES: the single solve's iteration count
+    assert [i["iterations"] for i in infos] == [i["iterations"] for _, i in ones]
     # the workspaces come back after a trim, with the same results
     s.trim()
     X2, _ = s.solve(torch.from_numpy(B).cuda())
     assert torch.equal(X, X2)
+    s.close()
+
+
+@pytest.mark.parametrize("outer", [0, 1])
+def test_each_column_iterates_like_the_oracle(outer):
+    # one outer process per column: every column stops at its own count, the
+    # one the oracle's single-column solve from the same guess takes
+    _needs_gpu()
+    from paper_2508_17517_amd import Solver
+    p = workloads.fv_random(64, 0.4, True)
+    A = p.scipy()
+    B = workloads.rhs_batch(p, 6)
+    B[4] *= 1e3
+    pr = oracle.Params(outer=("fgmres", "richardson")[outer])
+    levels = oracle.setup(A, pr)
+    X0 = np.zeros_like(B)
+    # a guess near column 2's solution and a rough one for column 5
+    u2 = oracle.sweep_solve(A, B[2], p.level)
+    X0[2] = u2 * (1.0 + 1e-7 * np.cos(np.arange(p.n)))
+    X0[5] = 0.5 * oracle.sweep_solve(A, B[5], p.level)
+    print(f"fv64 perm, 6 columns, outer {outer}", flush=True)
+    s = Solver(p.indptr, p.indices, p.data, outer=outer)
+    X, infos = s.solve(torch.from_numpy(B).cuda(), x=torch.from_numpy(X0).cuda(), guess=True)
+    Xh = X.cpu().numpy()
+    its = []
+    for k in range(B.shape[0]):
+        xo, ik, rel, _, _ = oracle.solve(A, B[k], pr, levels, x0=X0[k].copy())
+        its.append(ik)
+        assert infos[k]["converged"] == 1, k
+        assert infos[k]["iterations"] == ik, (k, infos[k]["iterations"], ik)
+        assert np.linalg.norm(Xh[k] - xo) <= 1e-9 * np.linalg.norm(xo), k
+    assert its[2] < its[0] and len(set(its)) >= 2
     s.close()
 
 
