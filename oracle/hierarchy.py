@@ -318,6 +318,9 @@ class Level:
     cmap: np.ndarray = None          # W: F point -> coarse index (or -1)
     alpha: np.ndarray = None         # smoother coefficients alpha_0..alpha_d
     Ahat: sp.csr_matrix = None       # the assembled fixed-sparsity Ahat^{-1} (Eq. fixed_sparsity)
+    Acc: sp.csr_matrix = None        # C-point smoothing only: A_cc,
+    alpha_c: np.ndarray = None       # its GMRES polynomial coefficients
+    Ahat_cc: sp.csr_matrix = None    # and its fixed-sparsity assembly
     roots: list = None               # Newton roots (coarsest level)
     trunc_rel: float = None          # truncation test result on this level
     info: dict = field(default_factory=dict)
@@ -376,7 +379,24 @@ def coarsen(A, level, p):
     diagonal_of(Ac)
     L.Aff, L.Afc, L.Acf, L.Z, L.cmap, L.alpha = Aff, Afc, Acf, Z, cmap, alpha
     L.Ahat = Ahat
+    if "c" in p.smooth_type:
+        c_point_smoother(A, L, level, p)
     return L, Ac
+
+
+def c_point_smoother(A, L, level, p):
+    """C-point smoothing (FC / FCF, Sec. 2 and Sec. 3.3): the paper names it and
+    its storage (A_cc and A_cf kept on every level) but not its inverse.
+    Reading: the same construction as the F-point smoother, on A_cc: the
+    GMRES polynomial of degree d from (d+1)-step Arnoldi with its own random
+    right-hand side, applied matrix-free or assembled on A_cc's pattern."""
+    if p.inverse_type != "arnoldi":
+        raise ValueError("C-point smoothing uses the GMRES polynomial")
+    Acc = _csr(A[L.C][:, L.C])
+    b = rng.uniform(p.seed, rng.CPOLY_RHS, level, len(L.C))
+    L.Acc = Acc
+    L.alpha_c = linalg.gmres_poly_coeffs(Acc, b, p.poly_order)
+    L.Ahat_cc = fixed_sparsity_inverse(Acc, L.alpha_c)
 
 
 def setup(A, p=None):

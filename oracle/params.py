@@ -29,5 +29,6 @@ class Params:
     outer: str = "fgmres"            # or "richardson": the paper's undamped Richardson (Sec. 3)
     smoother: str = "poly"           # or "assembled": F-smoothing with the assembled Ahat^{-1} (Sec. 2.2)
     inverse_type: str = "arnoldi"    # or "neumann": nAIR's Neumann polynomials (Sec. 3.3)
+    smooth_type: str = "f"           # up-smooths in order: "f", "fc" or "fcf" (Sec. 2, Sec. 3.3)
     # oracle-only knob for the exactness pins: solve the coarsest level by LU
     exact_coarse: bool = False

@@ -12,6 +12,7 @@ PMISR = 1
 POLY_RHS = 2
 COARSE_RHS = 3
 TRUNC_RHS = 4
+CPOLY_RHS = 5   # the C-point smoother's polynomial (FC / FCF smoothing)
 
 _GAMMA = np.uint64(0x9E3779B97F4A7C15)
 

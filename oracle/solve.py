@@ -4,7 +4,9 @@ V-cycle (Sec. 2): no down smoothing; restrict r_c' = Z r_f + r_c (R = [Z I]),
 recurse, prolong e_f = W e_c (P = [W; I]), then one up F-point smooth
 (Eq. f_point) with the smoother polynomial applied matrix-free by Horner:
 e_f += q(A_ff) (r_f - A_fc e_c - A_ff e_f).  The coarsest level applies its
-Newton polynomial.
+Newton polynomial.  The FC and FCF variants add a C-point smooth
+e_c += q_c(A_cc) (r_c - A_cf e_f - A_cc e_c) after it (and then a second F
+smooth), with a GMRES polynomial of A_cc built the same way.
 
 Outer loop: the paper uses undamped Richardson from an initial guess of one
 (Sec. 3), available as `richardson`; the default workloads use
@@ -23,11 +25,16 @@ from .params import Params
 from .hierarchy import setup
 
 
-def vcycle(levels, r, lvl=0, exact_coarse=False, assembled=False, neumann=False):
+def vcycle(levels, r, lvl=0, exact_coarse=False, assembled=False, neumann=False,
+           smooth_type="f"):
     """One V-cycle applied to r.  assembled: the F-point smoother applies the
     assembled fixed-sparsity Ahat^{-1} (one product, Sec. 2.2) instead of the
     polynomial matrix-free.  neumann: the matrix-free polynomial is nAIR's
-    Jacobi-scaled Neumann polynomial of the same degree."""
+    Jacobi-scaled Neumann polynomial of the same degree.  smooth_type: the
+    up-smooths after the coarse-grid correction, in order ("f", "fc", "fcf"):
+    an F smooth is e_f += Abar_ff^{-1} (r_f - A_ff e_f - A_fc e_c) (Eq. f_point),
+    a C smooth is e_c += Abar_cc^{-1} (r_c - A_cf e_f - A_cc e_c) with the
+    level's C-point polynomial (Sec. 2)."""
     L = levels[lvl]
     if L.coarsest:
         if exact_coarse:
@@ -36,15 +43,25 @@ def vcycle(levels, r, lvl=0, exact_coarse=False, assembled=False, neumann=False)
     rf = r[L.F]
     rc = r[L.C]
     rc2 = linalg.spmv(L.Z, rf) + rc
-    ec = vcycle(levels, rc2, lvl + 1, exact_coarse, assembled, neumann)
+    ec = vcycle(levels, rc2, lvl + 1, exact_coarse, assembled, neumann, smooth_type)
     ef = np.where(L.cmap >= 0, ec[np.maximum(L.cmap, 0)], 0.0)
-    s = rf - linalg.spmv(L.Afc, ec) - linalg.spmv(L.Aff, ef)
-    if assembled:
-        ef = ef + linalg.spmv(L.Ahat, s)
-    elif neumann:
-        ef = ef + linalg.neumann_apply(L.Aff, len(L.alpha) - 1, s)
-    else:
-        ef = ef + linalg.horner_apply(L.Aff, L.alpha, s)
+    for step in smooth_type:
+        if step == "f":
+            s = rf - linalg.spmv(L.Afc, ec) - linalg.spmv(L.Aff, ef)
+            if assembled:
+                ef = ef + linalg.spmv(L.Ahat, s)
+            elif neumann:
+                ef = ef + linalg.neumann_apply(L.Aff, len(L.alpha) - 1, s)
+            else:
+                ef = ef + linalg.horner_apply(L.Aff, L.alpha, s)
+        elif step == "c":
+            t = rc - linalg.spmv(L.Acf, ef) - linalg.spmv(L.Acc, ec)
+            if assembled:
+                ec = ec + linalg.spmv(L.Ahat_cc, t)
+            else:
+                ec = ec + linalg.horner_apply(L.Acc, L.alpha_c, t)
+        else:
+            raise ValueError(f"unknown smooth step {step!r}")
     e = np.zeros(len(r))
     e[L.F] = ef
     e[L.C] = ec
@@ -145,8 +162,10 @@ def solve(A, b, p=None, levels=None, x0=None):
         raise ValueError(f"unknown smoother {p.smoother!r}")
     if p.inverse_type not in ("arnoldi", "neumann"):
         raise ValueError(f"unknown inverse type {p.inverse_type!r}")
+    if p.smooth_type not in ("f", "fc", "fcf"):
+        raise ValueError(f"unknown smooth type {p.smooth_type!r}")
     M = lambda v: vcycle(levels, v, 0, p.exact_coarse, p.smoother == "assembled",  # noqa: E731
-                         p.inverse_type == "neumann")
+                         p.inverse_type == "neumann", p.smooth_type)
     if p.outer == "richardson":
         x, its, rel, hist = richardson(A, M, b, p.rtol, p.max_it, x0)
     elif p.outer == "fgmres":

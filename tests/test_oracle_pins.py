@@ -545,3 +545,103 @@ def test_nair_solves_to_tolerance():
         x, its, rel, levels, _ = oracle.solve(A, p.b, prm)
         u = oracle.sweep_solve(A, p.b, p.level)
         assert rel <= 1e-10 and np.linalg.norm(x - u) <= 1e-8 * np.linalg.norm(u)
+
+
+# --------------------------------------------------------------------- C-point smoothing (Sec. 2, Sec. 3.3)
+
+@pytest.mark.parametrize("smooth_type", ["fc", "fcf"])
+def test_c_smoothing_keeps_cyclic_reduction_exact(smooth_type):
+    # the F smooth already makes the cycle exact here (see the cyclic
+    # reduction pin), so a C residual r_c - A_cf e_f - A_cc e_c with every
+    # term and sign right is zero and the extra smooths change nothing
+    p = fv_advection(32, 0.0, np.random.default_rng(1).uniform(size=32), 0.0, perm_seed=4)
+    prm = Params(strong_threshold=0.0, r_drop=0.0, a_drop=0.0, ddc_its=0, trunc_tol=0.0,
+                 min_coarse_rows=40, exact_coarse=True, smooth_type=smooth_type)
+    x, its, rel, levels, _ = oracle.solve(p.scipy(), p.b, prm)
+    assert len(levels) >= 3 and all(L.Acc is not None for L in levels[:-1])
+    assert its == 1 and rel < 1e-12
+
+
+@pytest.mark.parametrize("smooth_type,assembled", [("fc", False), ("fcf", False), ("fcf", True)])
+def test_smooths_follow_the_global_relaxation_form(smooth_type, assembled):
+    # two levels, exact coarse solve: x = P A_c^{-1} R r, then for each step
+    # x_S += M_S (r - A x)_S on the F or C rows, with M_S the dense polynomial
+    # sum_i alpha_i A_SS^i (or the assembled matrix): an independent statement
+    # of the block formulas the oracle evaluates
+    p = workloads.fv_random(12, 0.7, True)
+    A = p.scipy()
+    prm = Params(max_levels=2, trunc_tol=0.0, smooth_type=smooth_type)
+    levels = oracle.setup(A, prm)
+    L0, L1 = levels
+    assert L1.coarsest
+    r = np.random.default_rng(3).standard_normal(p.n)
+    got = oracle.vcycle(levels, r, exact_coarse=True, assembled=assembled, smooth_type=smooth_type)
+    Ad = A.toarray()
+    F, C = L0.F, L0.C
+    nF, nC = len(F), len(C)
+
+    def poly(M, alpha):
+        out = np.zeros_like(M)
+        Pk = np.eye(M.shape[0])
+        for a in alpha:
+            out += a * Pk
+            Pk = Pk @ M
+        return out
+
+    if assembled:
+        Mf, Mc = L0.Ahat.toarray(), L0.Ahat_cc.toarray()
+    else:
+        Mf = poly(Ad[np.ix_(F, F)], L0.alpha)
+        Mc = poly(Ad[np.ix_(C, C)], L0.alpha_c)
+    R = np.zeros((nC, p.n))
+    R[:, F] = L0.Z.toarray()
+    R[np.arange(nC), C] = 1.0
+    P = np.zeros((p.n, nC))
+    w = L0.cmap >= 0
+    P[F[w], L0.cmap[w]] = 1.0
+    P[C, np.arange(nC)] = 1.0
+    x = P @ np.linalg.solve(L1.A.toarray(), R @ r)
+    for step in smooth_type:
+        res = r - Ad @ x
+        if step == "f":
+            x[F] += Mf @ res[F]
+        else:
+            x[C] += Mc @ res[C]
+    assert np.allclose(got, x, rtol=1e-11, atol=1e-11 * np.abs(x).max())
+
+
+def test_c_point_polynomial_minimises_the_residual_on_acc():
+    # alpha_c: the degree-d minimiser of |b - A_cc q(A_cc) b| for the C stream's
+    # b, checked by least squares on the explicit Krylov matrix of the dense A_cc
+    p = workloads.fv_random(16, 0.4, True)
+    A = p.scipy()
+    prm = Params(smooth_type="fc")
+    L, _ = S.coarsen(A, 0, prm)
+    Acc = A.toarray()[np.ix_(L.C, L.C)]
+    b = oracle.rng.uniform(prm.seed, 5, 0, len(L.C))
+    K = np.empty((len(b), prm.poly_order + 1))
+    v = b.copy()
+    for i in range(prm.poly_order + 1):
+        v = Acc @ v
+        K[:, i] = v
+    want, *_ = np.linalg.lstsq(K, b, rcond=None)
+    assert len(L.alpha_c) == prm.poly_order + 1
+    assert np.allclose(L.alpha_c, want, rtol=1e-7, atol=1e-9 * np.abs(want).max())
+    assert abs(L.Acc - sp.csr_matrix(Acc)).max() == 0.0
+
+
+@pytest.mark.parametrize("smooth_type", ["fc", "fcf"])
+@pytest.mark.parametrize("smoother", ["poly", "assembled"])
+def test_c_smoothing_solves_to_tolerance(smooth_type, smoother):
+    p = workloads.fv_random(48, 0.3, True)
+    A = p.scipy()
+    prm = oracle.Params(smooth_type=smooth_type, smoother=smoother)
+    x, its, rel, levels, _ = oracle.solve(A, p.b, prm)
+    u = oracle.sweep_solve(A, p.b, p.level)
+    assert rel <= 1e-10 and np.linalg.norm(x - u) <= 1e-8 * np.linalg.norm(u)
+
+
+def test_c_smoothing_needs_the_gmres_polynomial():
+    p = workloads.fv_random(16, 0.4, True)
+    with pytest.raises(ValueError):
+        oracle.setup(p.scipy(), oracle.Params(smooth_type="fc", inverse_type="neumann"))
