@@ -85,6 +85,8 @@ typedef struct {
   int32_t smoother;          /* airg_smoother: the F-point smoother, AIRG_SMOOTH_POLY */
   int32_t inverse_type;      /* airg_inverse: the polynomial approximating A_ff^{-1},
                                 AIRG_INVERSE_ARNOLDI */
+  int32_t smooth_type;       /* airg_smooth_type: the up-smooths of each level,
+                                AIRG_SMOOTH_TYPE_F */
 } airg_params;
 
 /* The polynomial approximation of A_ff^{-1} in the smoother and in Ahat^{-1}.
@@ -101,6 +103,21 @@ typedef enum { AIRG_INVERSE_ARNOLDI = 0, AIRG_INVERSE_NEUMANN = 1 } airg_inverse
  * the assembled fixed-sparsity Ahat^{-1} of Eq. fixed_sparsity (one product
  * with an operator of A_ff's pattern, kept per level). */
 typedef enum { AIRG_SMOOTH_POLY = 0, AIRG_SMOOTH_ASSEMBLED = 1 } airg_smoother;
+
+/* Up-smooths of each level after its coarse-grid correction (Sec. 2; the
+ * paper's option set uses F only and measures the storage of FC and FCF in
+ * Sec. 3.3).  F: one F-point smooth.  FC: then a C-point smooth
+ * e_c += q_c(A_cc) (r_c - A_cf e_f - A_cc e_c), q_c the GMRES polynomial of
+ * A_cc of degree poly_order from its own random right-hand side (matrix-free,
+ * or assembled on A_cc's pattern with AIRG_SMOOTH_ASSEMBLED); every level
+ * then also keeps A_cf and A_cc and the V-cycle keeps each level's residual.
+ * FCF: then a second F-point smooth with the updated e_c.  FC and FCF need
+ * AIRG_INVERSE_ARNOLDI and a hierarchy built by setup (not imported). */
+typedef enum {
+  AIRG_SMOOTH_TYPE_F = 0,
+  AIRG_SMOOTH_TYPE_FC = 1,
+  AIRG_SMOOTH_TYPE_FCF = 2
+} airg_smooth_type;
 
 /* Outer iterations.  AIRG_OUTER_RICHARDSON is the paper's undamped Richardson
  * x <- x + M (b - A x) with M one V-cycle (Sec. 3), stopped when the true
@@ -148,7 +165,7 @@ typedef struct {
   int32_t is_coarsest;
   int32_t poly_len;      /* number of smoother coefficients (degree + 1) */
   int32_t n_roots;       /* Newton roots (coarsest level) */
-  int32_t reserved;
+  int32_t c_poly_len;    /* C-point smoother coefficients (0 without FC / FCF) */
 } airg_level_info;
 
 /* Host arrays of one level in setup numbering: F and C points in ascending
@@ -165,6 +182,8 @@ typedef struct {
                                                       (zeros for AIRG_INVERSE_NEUMANN:
                                                       only the degree counts) */
   double* roots_re; double* roots_im;              /* n_roots, applied order */
+  double* alpha_c;                                 /* c_poly_len coefficients of the
+                                                      C-point smoother (export only) */
 } airg_level_arrays;
 
 /* Fill *p with the defaults above. */

@@ -180,14 +180,17 @@ class Solver:
                 arr.cmap = _np_ptr(cm, ctypes.c_int32)
                 out["cmap"] = cm[:li.n_f]
         al = np.zeros(max(li.poly_len, 1))
+        ac = np.zeros(max(li.c_poly_len, 1))
         re = np.zeros(max(li.n_roots, 1))
         im = np.zeros(max(li.n_roots, 1))
-        keep.extend([al, re, im])
+        keep.extend([al, ac, re, im])
         arr.alpha = _np_ptr(al, ctypes.c_double)
+        arr.alpha_c = _np_ptr(ac, ctypes.c_double)
         arr.roots_re = _np_ptr(re, ctypes.c_double)
         arr.roots_im = _np_ptr(im, ctypes.c_double)
         binding.check(self.lib.airg_export_level(self.h, level, ctypes.byref(arr)), self.lib)
         out["alpha"] = al[:li.poly_len]
+        out["alpha_c"] = ac[:li.c_poly_len]
         out["roots"] = re[:li.n_roots] + 1j * im[:li.n_roots]
         return out
 

@@ -17,6 +17,7 @@ FP64, FP32, BF16 = 0, 1, 2
 OUTER_FGMRES, OUTER_RICHARDSON = 0, 1
 SMOOTH_POLY, SMOOTH_ASSEMBLED = 0, 1
 INVERSE_ARNOLDI, INVERSE_NEUMANN = 0, 1
+SMOOTH_TYPE_F, SMOOTH_TYPE_FC, SMOOTH_TYPE_FCF = 0, 1, 2
 
 
 class Params(ctypes.Structure):
@@ -27,7 +28,7 @@ class Params(ctypes.Structure):
                 ("max_levels", c_i32), ("added_roots", c_i32), ("precision", c_i32),
                 ("max_it", c_i32), ("restart", c_i32), ("keep_setup_data", c_i32),
                 ("locality_order", c_i32), ("outer", c_i32), ("smoother", c_i32),
-                ("inverse_type", c_i32)]
+                ("inverse_type", c_i32), ("smooth_type", c_i32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -67,7 +68,7 @@ class Stats(ctypes.Structure):
 class LevelInfo(ctypes.Structure):
     _fields_ = [("n", c_i64), ("n_f", c_i64), ("n_c", c_i64), ("nnz_a", c_i64),
                 ("nnz_ff", c_i64), ("nnz_fc", c_i64), ("nnz_z", c_i64), ("is_coarsest", c_i32),
-                ("poly_len", c_i32), ("n_roots", c_i32), ("reserved", c_i32)]
+                ("poly_len", c_i32), ("n_roots", c_i32), ("c_poly_len", c_i32)]
 
 
 class LevelArrays(ctypes.Structure):
@@ -77,7 +78,7 @@ class LevelArrays(ctypes.Structure):
                 ("fc_rowptr", P(c_i32)), ("fc_col", P(c_i32)), ("fc_val", P(c_dbl)),
                 ("z_rowptr", P(c_i32)), ("z_col", P(c_i32)), ("z_val", P(c_dbl)),
                 ("cmap", P(c_i32)), ("alpha", P(c_dbl)), ("roots_re", P(c_dbl)),
-                ("roots_im", P(c_dbl))]
+                ("roots_im", P(c_dbl)), ("alpha_c", P(c_dbl))]
 
 
 class KernelTiming(ctypes.Structure):

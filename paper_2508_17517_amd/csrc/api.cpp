@@ -67,6 +67,9 @@ void check_params(const airg_params& p) {
   if (p.smoother != AIRG_SMOOTH_POLY && p.smoother != AIRG_SMOOTH_ASSEMBLED) bad("smoother");
   if (p.inverse_type != AIRG_INVERSE_ARNOLDI && p.inverse_type != AIRG_INVERSE_NEUMANN)
     bad("inverse_type");
+  if (p.smooth_type < AIRG_SMOOTH_TYPE_F || p.smooth_type > AIRG_SMOOTH_TYPE_FCF) bad("smooth_type");
+  if (p.smooth_type != AIRG_SMOOTH_TYPE_F && p.inverse_type != AIRG_INVERSE_ARNOLDI)
+    bad("smooth_type (C-point smoothing uses the GMRES polynomial)");
 }
 
 // Copy the caller's CSR (host or device) into library memory.
@@ -181,6 +184,7 @@ int airg_params_default(airg_params* p) {
   p->outer = AIRG_OUTER_FGMRES;
   p->smoother = AIRG_SMOOTH_POLY;
   p->inverse_type = AIRG_INVERSE_ARNOLDI;
+  p->smooth_type = AIRG_SMOOTH_TYPE_F;
   return AIRG_OK;
 }
 
@@ -337,6 +341,7 @@ int airg_level_info_get(airg_handle h, int level, airg_level_info* out) {
     out->is_coarsest = L.coarsest ? 1 : 0;
     out->poly_len = (int32_t)L.alpha.size();
     out->n_roots = (int32_t)L.roots.size();
+    out->c_poly_len = (int32_t)L.alpha_c.size();
     return (int)AIRG_OK;
   });
 }
@@ -372,6 +377,8 @@ int airg_export_level(airg_handle h, int level, airg_level_arrays* o) {
     AIRG_HIP(hipStreamSynchronize(s));
     if (o->alpha)
       for (size_t k = 0; k < L.alpha.size(); ++k) o->alpha[k] = L.alpha[k];
+    if (o->alpha_c)
+      for (size_t k = 0; k < L.alpha_c.size(); ++k) o->alpha_c[k] = L.alpha_c[k];
     for (size_t k = 0; k < L.roots.size(); ++k) {
       if (o->roots_re) o->roots_re[k] = L.roots[k].real();
       if (o->roots_im) o->roots_im[k] = L.roots[k].imag();
@@ -390,6 +397,8 @@ int airg_import_hierarchy(airg_handle* out, int nlevels, const airg_level_info* 
     if (p) prm = *p;
     else airg_params_default(&prm);
     check_params(prm);
+    if (prm.smooth_type != AIRG_SMOOTH_TYPE_F)
+      fail(AIRG_ERR_INVALID, "C-point smoothing needs a hierarchy built by airg_setup");
     std::unique_ptr<airg_ctx> c(new airg_ctx());
     c->H.p = prm;
     c->H.s = (hipStream_t)hip_stream;

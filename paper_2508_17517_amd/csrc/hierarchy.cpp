@@ -210,10 +210,10 @@ void cf_split(const CSR& A, const DBuf<double>& diag, int level, const airg_para
 }
 
 std::vector<double> smoother_coeffs(const CSR& Aff, int level, const airg_params& p,
-                                    hipStream_t s) {
+                                    hipStream_t s, int purpose = RNG_POLY_RHS) {
   const int64_t nf = Aff.rows;
   DBuf<double> b(nf, s);
-  launch_uniform(b.get(), nf, p.seed, RNG_POLY_RHS, level, s);
+  launch_uniform(b.get(), nf, p.seed, purpose, level, s);
   int m = (int)std::min<int64_t>((int64_t)p.poly_order + 1, nf);
   ArnoldiOut ar = arnoldi_dev(Aff, b.get(), m, s);
   return gmres_poly_coeffs(ar.H, ar.m, ar.steps, ar.beta);
@@ -236,11 +236,13 @@ bool coarsen(Hierarchy& H, int lvl, const CSR& A, Level& L, CSR& Anext) {
   L.nC = flag_scan(L.state, n, 2, L.cidx, s);
   if (L.nF == 0 || L.nC == 0) return false;
   CSR Acf;
+  const bool csmooth = p.smooth_type != AIRG_SMOOTH_TYPE_F;
   {
     Section t(H.comp_ms[C_EXTRACT], s);
     extract(A, L.state, 1, 1, L.fidx, L.cidx, L.nF, L.nF, L.Aff, s);
     extract(A, L.state, 1, 2, L.fidx, L.cidx, L.nF, L.nC, L.Afc_nat, s);
     extract(A, L.state, 2, 1, L.fidx, L.cidx, L.nC, L.nF, Acf, s);
+    if (csmooth) extract(A, L.state, 2, 2, L.fidx, L.cidx, L.nC, L.nC, L.Acc_nat, s);
   }
   const bool neumann = p.inverse_type == AIRG_INVERSE_NEUMANN;
   {
@@ -248,6 +250,8 @@ bool coarsen(Hierarchy& H, int lvl, const CSR& A, Level& L, CSR& Anext) {
     // nAIR's Neumann polynomial has no fitted coefficients: only its degree
     if (neumann) L.alpha.assign((size_t)p.poly_order + 1, 0.0);
     else L.alpha = smoother_coeffs(L.Aff, lvl, p, s);
+    // the C-point smoother: A_cc's GMRES polynomial from its own stream
+    if (csmooth) L.alpha_c = smoother_coeffs(L.Acc_nat, lvl, p, s, RNG_CPOLY_RHS);
   }
   {
     Section t(H.comp_ms[C_RSPGEMM], s);
@@ -257,6 +261,7 @@ bool coarsen(Hierarchy& H, int lvl, const CSR& A, Level& L, CSR& Anext) {
     spgemm(Acf, Ahat, Zfull, s);
     restrictor_drop(Zfull, p.r_drop, true, L.Z_nat, s);
   }
+  if (csmooth) L.Acf_nat = std::move(Acf);
   {
     Section t(H.comp_ms[C_PROLONG], s);
     L.cmap_nat.alloc(L.nF, s);
@@ -482,8 +487,9 @@ void finalize_hierarchy(Hierarchy& H) {
     }
     DBuf<double> dinv_setup;  // D^{-1} of A_ff for the matrix-free Neumann smoother
     if (neumann && !asm_smoother) diag_inverse(L.Aff, dinv_setup, s);
+    DBuf<int32_t> frank;
     if (order) {
-      DBuf<int32_t> frank(L.nF, s);
+      frank.alloc(L.nF, s);
       rank_f_points(L.state.get(), L.fidx.get(), key[l].get(), L.n, L.nF, frank.get(), s);
       if (asm_smoother) {
         permute_rows(Ahat_setup, frank.get(), frank.get(), L.nF, L.Ahat, s);
@@ -515,10 +521,35 @@ void finalize_hierarchy(Hierarchy& H) {
       permute_rows(L.Z_nat, N.pos.get(), nullptr, L.nF, L.Z, s);
       launch_remap(L.cmap_nat.get(), N.pos.get(), L.nF, L.cmap.get(), s);
     }
-    // the residual operator on e_c; A_fc itself is not needed by the solve
+    // the residual operator on e_c; A_fc itself is needed only by the second
+    // F smooth of FCF
     merge_fc_ffw(L.Afc, L.Aff, L.cmap.get(), L.B, s);
     L.nnz_fc = L.Afc.nnz;
+    if (H.p.smooth_type == AIRG_SMOOTH_TYPE_FCF) {
+      L.fc.m = std::move(L.Afc);
+      sort_rows(L.fc.m, s);
+      L.fc.tpr = pick_tpr(L.fc.m.rows, L.fc.m.nnz);
+    }
     L.Afc = CSR();
+    // C-point smoothing: A_cf and A_cc in the solve numbering, and A_cc's
+    // assembled polynomial
+    if (H.p.smooth_type != AIRG_SMOOTH_TYPE_F) {
+      if (L.Acf_nat.rows != L.nC || L.Acc_nat.rows != L.nC || L.alpha_c.empty())
+        fail(AIRG_ERR_INVALID, "C-point smoothing data missing on level " + std::to_string(l));
+      permute_rows(L.Acf_nat, N.pos.get(), order ? frank.get() : nullptr, L.nF, L.cf.m, s);
+      permute_rows(L.Acc_nat, N.pos.get(), N.pos.get(), L.nC, L.cc.m, s);
+      sort_rows(L.cf.m, s);
+      sort_rows(L.cc.m, s);
+      L.cf.tpr = pick_tpr(L.cf.m.rows, L.cf.m.nnz);
+      L.cc.tpr = pick_tpr(L.cc.m.rows, L.cc.m.nnz);
+      if (asm_smoother) {
+        CSR hc;
+        fixed_sparsity_inverse(L.Acc_nat, L.alpha_c, hc, s);
+        permute_rows(hc, N.pos.get(), N.pos.get(), L.nC, L.hat_cc.m, s);
+        sort_rows(L.hat_cc.m, s);
+        L.hat_cc.tpr = pick_tpr(L.hat_cc.m.rows, L.hat_cc.m.nnz);
+      }
+    }
     L.tpr_ff = pick_tpr(L.Aff.rows, L.Aff.nnz);
     L.tpr_b = pick_tpr(L.B.rows, L.B.nnz);
     L.tpr_z = pick_tpr(L.Z.rows, L.Z.nnz);
@@ -528,6 +559,12 @@ void finalize_hierarchy(Hierarchy& H) {
   for (Level& L : H.levels) {
     L.off = off;
     off += L.nF;
+  }
+  // segments of the stacked residual buffer, one per level below the top
+  H.stacked_len = 0;
+  for (size_t l = 1; l < H.levels.size(); ++l) {
+    H.levels[l].in_off = H.stacked_len;
+    H.stacked_len += H.levels[l].n;
   }
   permute_rows(H.A0, H.levels[0].pos.get(), H.levels[0].pos.get(), H.n0, H.Aperm, s);
   if (order) sort_rows(H.Aperm, s);
@@ -553,6 +590,8 @@ void finalize_hierarchy(Hierarchy& H) {
       lower(L.B, L.b32, L.b16);
       lower(L.Z, L.z32, L.z16);
       if (L.Ahat.rows > 0) lower(L.Ahat, L.hat32, L.hat16);
+      for (SolveOp* o : {&L.cf, &L.cc, &L.hat_cc, &L.fc})
+        if (o->m.rows > 0) lower(o->m, o->v32, o->v16);
       if (L.dinv.get()) {
         L.dinv32.alloc(L.nF, s);
         convert_d2f(L.dinv32.get(), L.dinv.get(), L.nF, s);
@@ -575,6 +614,8 @@ void finalize_hierarchy(Hierarchy& H) {
     prepare(L.B);
     prepare(L.Z);
     if (L.Ahat.rows > 0) prepare(L.Ahat);
+    for (SolveOp* o : {&L.cf, &L.cc, &L.hat_cc, &L.fc})
+      if (o->m.rows > 0) prepare(o->m);
   }
   // every solve-phase operator is checked once, so an inconsistent hierarchy
   // (for example a bad import) fails here instead of in a kernel
@@ -596,6 +637,16 @@ void finalize_hierarchy(Hierarchy& H) {
           fail(AIRG_ERR_INVALID, "assembled smoother missing on level " + std::to_string(l));
         launch_check_csr(L.Ahat, flags.get(), s);
       }
+      const int st = H.p.smooth_type;
+      if (st != AIRG_SMOOTH_TYPE_F) {
+        const bool asm_c = H.p.smoother == AIRG_SMOOTH_ASSEMBLED;
+        if (L.cf.m.rows != L.nC || L.cf.m.cols != L.nF || L.cc.m.rows != L.nC ||
+            L.cc.m.cols != L.nC || (asm_c && (L.hat_cc.m.rows != L.nC || L.hat_cc.m.cols != L.nC)) ||
+            (st == AIRG_SMOOTH_TYPE_FCF && (L.fc.m.rows != L.nF || L.fc.m.cols != L.nC)))
+          fail(AIRG_ERR_INVALID, "C-point smoothing operators missing on level " + std::to_string(l));
+        for (const SolveOp* o : {&L.cf, &L.cc, &L.hat_cc, &L.fc})
+          if (o->m.rows > 0) launch_check_csr(o->m, flags.get(), s);
+      }
       launch_check_map(L.cmap.get(), L.nF, -1, L.nC, flags.get(), s);
       launch_check_map(L.pos.get(), L.n, 0, L.n, flags.get(), s);
       if (L.Aff.rows != L.nF || L.Aff.cols != L.nF || L.B.rows != L.nF || L.B.cols != L.nC ||
@@ -615,6 +666,8 @@ void finalize_hierarchy(Hierarchy& H) {
       L.cidx.release();
       L.Afc_nat = CSR();
       L.Z_nat = CSR();
+      L.Acf_nat = CSR();
+      L.Acc_nat = CSR();
       L.cmap_nat.release();
     }
   }
@@ -742,6 +795,33 @@ void hierarchy_stats(const Hierarchy& H, airg_stats* st) {
         bytes += csr_bytes((double)L.nF, (double)L.Ahat.nnz) + 8.0 * 3 * L.nF + 12.0 * L.nF;
       else
         bytes += d * (csr_bytes((double)L.nF, (double)L.Aff.nnz) + 8.0 * 3 * L.nF) + 12.0 * L.nF;
+      if (H.p.smooth_type != AIRG_SMOOTH_TYPE_F) {
+        // C smooth: the residual r_c - A_cf e_f - A_cc e_c (two products), then
+        // d_c Horner steps with A_cc (or one product with its assembly), the
+        // last one updating e_c in place; storage gains A_cf and A_cc (and the
+        // assembly), as the paper counts for FC smoothing
+        const double ncf = (double)L.cf.m.nnz, ncc = (double)L.cc.m.nnz;
+        const int dc = (int)L.alpha_c.size() - 1;
+        const double nhc = (double)L.hat_cc.m.nnz;
+        cyc += ncf + ncc + (asm_smoother ? nhc : dc * ncc);
+        sto += ncf + ncc + (asm_smoother ? nhc : 0.0);
+        bytes += csr_bytes((double)L.nC, ncf) + 8.0 * (L.nF + 2 * L.nC);
+        bytes += csr_bytes((double)L.nC, ncc) + 8.0 * 3 * L.nC;
+        if (asm_smoother) bytes += csr_bytes((double)L.nC, nhc) + 8.0 * 3 * L.nC;
+        else bytes += dc * (csr_bytes((double)L.nC, ncc) + 8.0 * 3 * L.nC) + (dc > 0 ? 8.0 * L.nC : 0.0);
+        if (H.p.smooth_type == AIRG_SMOOTH_TYPE_FCF) {
+          // second F smooth: r_f - A_fc e_c - A_ff e_f, then the smoother
+          // accumulating into e_f
+          cyc += (double)L.nnz_fc + smooth;  // smooth counts A_ff's residual product
+          bytes += csr_bytes((double)L.nF, (double)L.nnz_fc) + 8.0 * (L.nC + 2 * L.nF);
+          bytes += csr_bytes((double)L.nF, (double)L.Aff.nnz) + 8.0 * 3 * L.nF;
+          if (asm_smoother)
+            bytes += csr_bytes((double)L.nF, (double)L.Ahat.nnz) + 8.0 * 3 * L.nF;
+          else
+            bytes += d * (csr_bytes((double)L.nF, (double)L.Aff.nnz) + 8.0 * 3 * L.nF) +
+                     (d > 0 ? 8.0 * L.nF : 0.0);
+        }
+      }
     }
   }
   st->grid_complexity = grid / (double)H.n0;

@@ -21,6 +21,17 @@
 
 namespace airg {
 
+OpView op_view(const CSR& A, const DBuf<float>& v32, const DBuf<bf16>& v16, int prec);
+
+// A solve-phase operator with its low-precision value copy and launch shape.
+struct SolveOp {
+  CSR m;
+  DBuf<float> v32;
+  DBuf<bf16> v16;
+  int tpr = 1;
+  OpView view(int prec) const { return op_view(m, v32, v16, prec); }
+};
+
 struct Level {
   int64_t n = 0, nF = 0, nC = 0;
   int64_t off = 0;
@@ -45,6 +56,14 @@ struct Level {
   DBuf<int32_t> pos;        // setup index -> nested position on this level
   std::vector<double> alpha;
   std::vector<cplx> roots;
+  // C-point smoothing (FC / FCF): A_cf and A_cc in setup numbering until
+  // finalize; then A_cf (rows in level l+1's nested order, columns in F
+  // order), A_cc (both in level l+1's nested order), its assembled
+  // approximate inverse (AIRG_SMOOTH_ASSEMBLED) and, for FCF, A_fc
+  CSR Acf_nat, Acc_nat;
+  SolveOp cf, cc, hat_cc, fc;
+  std::vector<double> alpha_c;  // GMRES polynomial coefficients of A_cc
+  int64_t in_off = 0;           // this level's segment of the stacked residuals (levels >= 1)
   // launch shapes of the products: lanes per row (bits 0-7, 0 = row-block
   // kernel) and the XCD mapping (bit 8)
   int tpr_ff = 1, tpr_b = 1, tpr_z = 1, tpr_a = 1, tpr_hat = 1;
@@ -69,6 +88,7 @@ struct Hierarchy {
   CSR Aperm;                // top matrix, nested numbering
   int tpr_top = 1;
   std::vector<Level> levels;
+  int64_t stacked_len = 0;  // sum of the level sizes below the top (C-point smoothing)
   double setup_ms = 0.0;
   double comp_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   // a block-diagonal batch of problems: block p holds setup-numbering rows

@@ -10,7 +10,13 @@ namespace airg {
 // Random draws of the setup: U[0,1) from counter-based SplitMix64, element i
 // of stream (purpose, level) being output c + 1 of `seed`, c = purpose << 56 |
 // level << 40 | i.
-enum RngPurpose { RNG_PMISR = 1, RNG_POLY_RHS = 2, RNG_COARSE_RHS = 3, RNG_TRUNC_RHS = 4 };
+enum RngPurpose {
+  RNG_PMISR = 1,
+  RNG_POLY_RHS = 2,
+  RNG_COARSE_RHS = 3,
+  RNG_TRUNC_RHS = 4,
+  RNG_CPOLY_RHS = 5  // the C-point smoother's polynomial
+};
 void launch_uniform(double* out, int64_t n, uint64_t seed, int purpose, int level, hipStream_t s);
 
 void launch_fill(double* x, int64_t n, double v, hipStream_t s);

@@ -44,8 +44,10 @@ void workspace_init(const Hierarchy& H, Workspace& W, int K) {
   W.V.alloc((size_t)(W.restart + 1) * W.ld, s);
   W.Zb.alloc((size_t)W.restart * W.ld, s);
   W.w.alloc(n, s);
+  // smoother scratch: F rows, and C rows too with C-point smoothing
+  const bool csm = H.p.smooth_type != AIRG_SMOOTH_TYPE_F;
   int64_t maxf = 1;
-  for (const Level& L : H.levels) maxf = std::max(maxf, L.nF);
+  for (const Level& L : H.levels) maxf = std::max(maxf, csm ? std::max(L.nF, L.nC) : L.nF);
   maxf *= K;
   const int64_t nc = std::max<int64_t>(1, H.levels.back().n) * K;
   if (H.p.precision == AIRG_FP64) {
@@ -56,6 +58,7 @@ void workspace_init(const Hierarchy& H, Workspace& W, int K) {
     W.cw0.alloc(nc, s);
     W.cw1.alloc(nc, s);
     W.ct.alloc(nc, s);
+    if (csm) W.rin.alloc(std::max<int64_t>(1, H.stacked_len) * K, s);
   } else {
     W.in32.alloc(n, s);
     W.e32.alloc(n, s);
@@ -66,6 +69,7 @@ void workspace_init(const Hierarchy& H, Workspace& W, int K) {
     W.cw032.alloc(nc, s);
     W.cw132.alloc(nc, s);
     W.ct32.alloc(nc, s);
+    if (csm) W.rin32.alloc(std::max<int64_t>(1, H.stacked_len) * K, s);
   }
   W.bperm.alloc(n, s);
   W.xperm.alloc(n, s);
@@ -98,14 +102,16 @@ struct VecSet {
   X* cw0;
   X* cw1;
   X* ct;        // Newton scratch
+  X* rin;       // stacked level residuals (C-point smoothing), or null
 };
 
 VecSet<double> vecs64(Workspace& W, const double* in, double* e) {
-  return {in, e, W.rr.get(), W.sv.get(), W.y0.get(), W.y1.get(), W.cw0.get(), W.cw1.get(), W.ct.get()};
+  return {in,        e,         W.rr.get(), W.sv.get(), W.y0.get(), W.y1.get(),
+          W.cw0.get(), W.cw1.get(), W.ct.get(), W.rin.get()};
 }
 VecSet<float> vecs32(Workspace& W) {
   return {W.in32.get(), W.e32.get(), W.rr32.get(), W.sv32.get(), W.y032.get(), W.y132.get(),
-          W.cw032.get(), W.cw132.get(), W.ct32.get()};
+          W.cw032.get(), W.cw132.get(), W.ct32.get(), W.rin32.get()};
 }
 
 struct LevelOps {
@@ -213,29 +219,88 @@ void smooth(const Level& L, const LevelOps& o, int K, const X* sv, const X* ec, 
   }
 }
 
+// out += q(A) s by Horner with the last product accumulating into out (the
+// C smooth, and the second F smooth of FCF): d products with A.
+template <class X>
+void horner_acc(const OpView& A, int tpr, const std::vector<double>& a, int64_t rows, int K,
+                const X* sv, X* out, X* y0, X* y1, hipStream_t s) {
+  const int d = (int)a.size() - 1;
+  if (d < 0) return;
+  if (d == 0) {
+    axpy_first_t<X>(out, sv, a[0], false, rows * K, s);
+    return;
+  }
+  if (d == 1) {
+    spmv_horner_t<X>(A, tpr, K, sv, sv, out, a[1], a[0], true, s);
+    return;
+  }
+  X* y[2] = {y0, y1};
+  int c = 0;
+  spmv_horner_t<X>(A, tpr, K, sv, sv, y[0], a[d], a[d - 1], false, s);
+  for (int k = d - 2; k >= 1; --k) {
+    spmv_horner_t<X>(A, tpr, K, y[c], sv, y[c ^ 1], 1.0, a[k], false, s);
+    c ^= 1;
+  }
+  spmv_horner_t<X>(A, tpr, K, y[c], sv, out, 1.0, a[0], true, s);
+}
+
+// After the first F smooth of level L: the C smooth
+//   t = r_c - A_cf e_f - A_cc e_c,  e_c += q_c(A_cc) t,
+// and for FCF a second F smooth with the updated e_c
+//   s = r_f - A_fc e_c - A_ff e_f,  e_f += q(A_ff) s
+// (the assembled inverses with AIRG_SMOOTH_ASSEMBLED).  rf is the level's
+// residual, its C part following its nF F rows.
+template <class X>
+void smooth_c(const Hierarchy& H, const Level& L, const LevelOps& o, int K, const X* rf, X* ec,
+              X* ef, const VecSet<X>& v, hipStream_t s) {
+  const int prec = H.p.precision;
+  const bool asm_smoother = H.p.smoother == AIRG_SMOOTH_ASSEMBLED;
+  const X* rc = rf + L.nF * K;
+  spmv_residual_t<X>(L.cf.view(prec), L.cf.tpr, K, ef, rc, v.y1, s);
+  spmv_residual_t<X>(L.cc.view(prec), L.cc.tpr, K, ec, v.y1, v.sv, s);
+  if (asm_smoother)
+    spmv_horner_t<X>(L.hat_cc.view(prec), L.hat_cc.tpr, K, v.sv, v.sv, ec, 1.0, 0.0, true, s);
+  else
+    horner_acc<X>(L.cc.view(prec), L.cc.tpr, L.alpha_c, L.nC, K, v.sv, ec, v.y0, v.y1, s);
+  if (H.p.smooth_type != AIRG_SMOOTH_TYPE_FCF) return;
+  spmv_residual_t<X>(L.fc.view(prec), L.fc.tpr, K, ec, rf, v.y1, s);
+  spmv_residual_t<X>(o.ff, L.tpr_ff, K, ef, v.y1, v.sv, s);
+  if (asm_smoother)
+    spmv_horner_t<X>(o.hat, L.tpr_hat, K, v.sv, v.sv, ef, 1.0, 0.0, true, s);
+  else
+    horner_acc<X>(o.ff, L.tpr_ff, L.alpha, L.nF, K, v.sv, ef, v.y0, v.y1, s);
+}
+
 template <class X>
 void vcycle_t(const Hierarchy& H, const VecSet<X>& v, int K) {
   hipStream_t s = H.s;
   const int prec = H.p.precision;
   const int L = (int)H.levels.size() - 1;
+  // level l's residual (l >= 1): the suffix at off_l of rr, each restriction
+  // overwriting the C part of the level above in place; with C-point
+  // smoothing, which reads r_c again on the way up, its own segment of rin
+  const bool csm = H.p.smooth_type != AIRG_SMOOTH_TYPE_F;
+  auto input = [&](int l) -> X* {
+    return csm ? v.rin + H.levels[l].in_off * K : v.rr + H.levels[l].off * K;
+  };
   for (int l = 0; l < L; ++l) {
     const Level& lv = H.levels[l];
-    const X* src = (l == 0 ? v.in : v.rr) + lv.off * K;
-    X* dst = v.rr + H.levels[l + 1].off * K;
-    spmv_restrict_t<X>(ops_of(lv, prec).z, lv.tpr_z, K, src, src + lv.nF * K, dst, s);
+    const X* src = l == 0 ? v.in : input(l);
+    spmv_restrict_t<X>(ops_of(lv, prec).z, lv.tpr_z, K, src, src + lv.nF * K, input(l + 1), s);
   }
   const Level& lc = H.levels[L];
-  const X* rc = (L == 0 ? v.in : v.rr) + lc.off * K;
+  const X* rc = L == 0 ? v.in : input(L);
   newton_apply_t<X>(ops_of(lc, prec).a, lc.tpr_a, K, lc.roots, rc, v.e + lc.off * K, v.cw0, v.cw1,
                     v.ct, s);
   for (int l = L - 1; l >= 0; --l) {
     const Level& lv = H.levels[l];
     const LevelOps o = ops_of(lv, prec);
-    const X* rf = (l == 0 ? v.in : v.rr) + lv.off * K;
+    const X* rf = l == 0 ? v.in : input(l);
     X* ef = v.e + lv.off * K;
-    const X* ec = v.e + H.levels[l + 1].off * K;
+    X* ec = v.e + H.levels[l + 1].off * K;
     spmv_residual_t<X>(o.b, lv.tpr_b, K, ec, rf, v.sv, s);
     smooth<X>(lv, o, K, v.sv, ec, ef, v.y0, v.y1, s);
+    if (csm) smooth_c<X>(H, lv, o, K, rf, ec, ef, v, s);
   }
 }
 

@@ -15,6 +15,9 @@ struct Workspace {
   DBuf<double> cw0, cw1, ct;
   // FP32 vectors of the mixed-precision V-cycle
   DBuf<float> in32, e32, rr32, sv32, y032, y132, cw032, cw132, ct32;
+  // each level's residual kept for C-point smoothing (stacked segments)
+  DBuf<double> rin;
+  DBuf<float> rin32;
   DBuf<double> bperm, xperm, nat;
   DBuf<double> hbuf, ybuf, gbuf, dot_work, col_work;
   DBuf<double> cdiv, cdot_work;  // per-column divisors and dot partials (K > 1)

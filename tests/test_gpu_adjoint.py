@@ -53,7 +53,7 @@ def _gpu_grads(n, gw, gs, theta, wfull):
     u = advect(tgw, tgs, tth, n, rtol=1e-13)
     loss = (u * torch.from_numpy(wfull).cuda()).sum()
     loss.backward()
-    return (float(loss), tgw.grad.cpu().numpy(), tgs.grad.cpu().numpy(), float(tth.grad))
+    return (float(loss.detach()), tgw.grad.cpu().numpy(), tgs.grad.cpu().numpy(), float(tth.grad))
 
 
 @pytest.mark.parametrize("n", [64, 256])

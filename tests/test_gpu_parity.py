@@ -410,3 +410,71 @@ def test_nair_matches_oracle(smoother):
     assert info["iterations"] == its
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
     s.close()
+
+
+C_SMOOTH = {
+    "fc_poly_fv96": (lambda: workloads.fv_random(96, 0.3, True), "fc", "poly", 0),
+    "fcf_poly_fv96": (lambda: workloads.fv_random(96, 0.3, True), "fcf", "poly", 0),
+    "fc_assembled_dg20": (lambda: workloads.dg_random(20, math.pi / 5, True), "fc", "assembled", 0),
+    "fcf_assembled_fv80x40": (lambda: workloads.fv_random(80, 0.7, True, ny=40), "fcf", "assembled", 0),
+    "fcf_poly_fv64_noorder": (lambda: workloads.fv_random(64, 1.1, True), "fcf", "poly", 1),
+}
+
+
+@pytest.mark.parametrize("case", list(C_SMOOTH))
+def test_c_point_smoothing_matches_oracle(case):
+    # FC / FCF up-smoothing (Sec. 2, Sec. 3.3): the same hierarchy (C-point
+    # coefficients bit for bit), the same iterations and solution as the oracle
+    _needs_gpu()
+    make, st, smoother, noorder = C_SMOOTH[case]
+    p = make()
+    print(f"case {case} n={p.n}", flush=True)
+    prm = oracle.Params(smooth_type=st, smoother=smoother)
+    xo, its, rel, levels, _ = oracle.solve(p.scipy(), p.b, prm)
+    s = _solver(p, smooth_type={"fc": 1, "fcf": 2}[st], smoother=int(smoother == "assembled"),
+                keep_setup_data=1, locality_order=0 if noorder else 1)
+    compare_hierarchy(s, levels)
+    for l, L in enumerate(levels[:-1]):
+        got = s.export_level(l, what=("alpha",))["alpha_c"]
+        assert np.array_equal(got, L.alpha_c), f"level {l}: C-point coefficients differ"
+    x, info = s.solve(torch.from_numpy(p.b).cuda())
+    assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
+    assert info["iterations"] == its
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    # storage in the paper's terms gains A_cf and A_cc on every level
+    s_f = _solver(p, smoother=int(smoother == "assembled"))
+    extra = sum(L.Acf.nnz + L.Acc.nnz + (L.Ahat_cc.nnz if smoother == "assembled" else 0)
+                for L in levels[:-1])
+    nnz0 = p.scipy().nnz
+    assert s.stats()["storage_complexity"] == pytest.approx(
+        s_f.stats()["storage_complexity"] + extra / nnz0, rel=1e-12)
+    s_f.close()
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_c_point_smoothing_mixed_precision_and_columns(prec):
+    _needs_gpu()
+    from paper_2508_17517_amd import Solver
+    p = workloads.fv_random(80, 0.4, True)
+    B = workloads.rhs_batch(p, 3)
+    s = Solver(p.indptr, p.indices, p.data, smooth_type=2, precision=prec)
+    x, info = s.solve(torch.from_numpy(p.b).cuda())
+    assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
+    X, infos = s.solve(torch.from_numpy(B).cuda())
+    A = p.scipy()
+    for k in range(3):
+        xk = X[k].cpu().numpy()
+        assert infos[k]["converged"] == 1
+        assert np.linalg.norm(B[k] - A @ xk) <= 1e-10 * (1 + 1e-6) * np.linalg.norm(B[k])
+    s.close()
+
+
+def test_c_point_smoothing_rejections():
+    _needs_gpu()
+    from paper_2508_17517_amd import AirgError, Solver
+    p = workloads.fv_random(32, 0.4, True)
+    with pytest.raises(AirgError):
+        Solver(p.indptr, p.indices, p.data, smooth_type=1, inverse_type=1)
+    with pytest.raises(AirgError):
+        Solver(p.indptr, p.indices, p.data, smooth_type=3)
