@@ -243,6 +243,10 @@ PAPER_SINGLE_GCD = {  # Sec. 3.1, one MI250X GCD, 13M unknowns, pi/4, d = 6
     # Sec. 3.4: 500 x N rectangles weak-scaled in y, m_c = 10 (constant over the runs)
     "rectangular_mc10": {"iterations": 6, "levels": 10, "cycle_complexity": 28.2,
                          "storage_complexity": 9.5},
+    # Sec. 3.3 (2 nodes): storage 10.5 with F smoothing, 17.2 with matrix-free
+    # C smoothing added, 20.2 with assembled F and C smoothing
+    "fc_truncated_mc10": {"storage_ratio_vs_f": round(17.2 / 10.5, 3)},
+    "fc_assembled_truncated_mc10": {"storage_ratio_vs_f": round(20.2 / 10.5, 3)},
 }
 
 
@@ -267,6 +271,13 @@ def paper_legs(a, side=3606):
             ("untruncated", dict(coarse_poly_order=10, trunc_tol=0.0)),
             ("nair_truncated_mc10", dict(coarse_poly_order=10, trunc_tol=0.1,
                                          inverse_type=binding.INVERSE_NEUMANN)),
+            ("fc_truncated_mc10", dict(coarse_poly_order=10, trunc_tol=0.1,
+                                       smooth_type=binding.SMOOTH_TYPE_FC)),
+            ("fcf_truncated_mc10", dict(coarse_poly_order=10, trunc_tol=0.1,
+                                        smooth_type=binding.SMOOTH_TYPE_FCF)),
+            ("fc_assembled_truncated_mc10", dict(coarse_poly_order=10, trunc_tol=0.1,
+                                                 smooth_type=binding.SMOOTH_TYPE_FC,
+                                                 smoother=binding.SMOOTH_ASSEMBLED)),
             ("rectangular_mc10", dict(coarse_poly_order=10, trunc_tol=0.1)))
     for name, over in legs:
         if name == "rectangular_mc10":
@@ -301,6 +312,9 @@ def paper_legs(a, side=3606):
                "dof_per_s_per_vcycle": p.n * info["iterations"] / dt}
         if name == "rectangular_mc10":
             leg["grid"] = "500 x 26000"
+        if "smooth_type" in over and "truncated_mc10" in res:
+            leg["storage_ratio_vs_f"] = round(
+                st["storage_complexity"] / res["truncated_mc10"]["storage_complexity"], 3)
         res[name] = leg
         print(f"bench: paper {name}: {leg}", file=sys.stderr, flush=True)
         sm.close()
