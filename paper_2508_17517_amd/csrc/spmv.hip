@@ -101,6 +101,100 @@ __device__ __forceinline__ X row_dot(const CSRT<MV, C16>& A, int s, int e, int b
   return row_dot_cols<TPR, U, K>(A, s, e, b, lane, x, c, idx, sum);
 }
 
+// Pair loads (K = 1, two or more lanes per row): a lane takes the aligned
+// entry pairs (2q, 2q+1), q = s/2 + lane, s/2 + lane + TPR, ..., and fetches
+// a pair's two values and two column indices with one wide load each, so the
+// load instructions per entry halve and more entries are in flight.  An entry
+// of a pair outside [s, e) is masked: a pair may straddle a row boundary, and
+// every array is padded past its end.  A lane adds its entries in ascending
+// order; the lanes of a row then combine by the shuffle tree.
+template <class X, class MV>
+__device__ __forceinline__ void load_pair(const MV* __restrict__ v, int q, X& a, X& b);
+template <>
+__device__ __forceinline__ void load_pair<double, double>(const double* __restrict__ v, int q,
+                                                          double& a, double& b) {
+  const double2 t = reinterpret_cast<const double2*>(v)[q];
+  a = t.x;
+  b = t.y;
+}
+template <>
+__device__ __forceinline__ void load_pair<float, float>(const float* __restrict__ v, int q, float& a,
+                                                        float& b) {
+  const float2 t = reinterpret_cast<const float2*>(v)[q];
+  a = t.x;
+  b = t.y;
+}
+template <>
+__device__ __forceinline__ void load_pair<float, bf16>(const bf16* __restrict__ v, int q, float& a,
+                                                       float& b) {
+  const uint32_t w = reinterpret_cast<const uint32_t*>(v)[q];
+  a = __uint_as_float(w << 16);
+  b = __uint_as_float(w & 0xffff0000u);
+}
+// the two columns of pair q in a row of base b (compressed form), or as stored
+template <class MV, bool C16>
+__device__ __forceinline__ void column_pair(const CSRT<MV, C16>& A, int q, int b, int& c0, int& c1) {
+  if constexpr (C16) {
+    const uint32_t w = reinterpret_cast<const uint32_t*>(A.col16)[q];
+    c0 = b + (int)(w & 0xffffu);
+    c1 = b + (int)(w >> 16);
+  } else {
+    const int2 w = reinterpret_cast<const int2*>(A.col)[q];
+    c0 = w.x;
+    c1 = w.y;
+  }
+}
+// The pairs of entries [s, e) that a lane owns, gathered through gx: with
+// OFF the gather index is the raw 16-bit offset (x staged in LDS from the
+// row's base), else the column.
+template <int TPR, int U, bool OFF, class MV, bool C16, class X>
+__device__ __forceinline__ X row_dot_pairs_cols(const CSRT<MV, C16>& A, int s, int e, int b,
+                                                int lane, const X* __restrict__ gx, X sum) {
+  const int qe = (e + 1) >> 1;
+  for (int q0 = (s >> 1) + lane; q0 < qe; q0 += TPR * U) {
+    int c0[U], c1[U];
+    X v0[U], v1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + u * TPR;
+      c0[u] = -1;
+      c1[u] = -1;
+      v0[u] = X(0);
+      v1[u] = X(0);
+      if (q < qe) {
+        load_pair<X>(A.val, q, v0[u], v1[u]);
+        column_pair(A, q, OFF ? 0 : b, c0[u], c1[u]);
+        if (2 * q < s) c0[u] = -1;
+        if (2 * q + 1 >= e) c1[u] = -1;
+      }
+    }
+    X x0[U], x1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      x0[u] = c0[u] >= 0 ? gx[c0[u]] : X(0);
+      x1[u] = c1[u] >= 0 ? gx[c1[u]] : X(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (c0[u] >= 0) sum = sum + v0[u] * x0[u];
+      if (c1[u] >= 0) sum = sum + v1[u] * x1[u];
+    }
+  }
+  return sum;
+}
+// global gathers; a negative base (int32 block) takes the int32 columns
+template <int TPR, int U, class MV, bool C16, class X>
+__device__ __forceinline__ X row_dot_pairs(const CSRT<MV, C16>& A, int s, int e, int b, int lane,
+                                           const X* __restrict__ x, X sum) {
+  if constexpr (C16) {
+    if (b < 0) {
+      const CSRT<MV, false> W{A.rowptr, A.col, nullptr, nullptr, A.val, A.rows};
+      return row_dot_pairs_cols<TPR, U, false>(W, s, e, 0, lane, x, sum);
+    }
+  }
+  return row_dot_pairs_cols<TPR, U, false>(A, s, e, b, lane, x, sum);
+}
+
 // Workgroups go to the 8 XCDs round robin (workgroup i to XCD i mod 8), and
 // each XCD has its own L2.  With the XCD mapping (launch shape bit 8) the grid
 // is padded to a multiple of 8 and workgroup i takes row block
@@ -128,9 +222,14 @@ __global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV, C16> A, const X* __r
   typename Epi::Pre pre{};
   if (live && lane == 0) pre = epi.pre(row);
   X sum = 0;
-  if (live)
-    sum = row_dot<TPR, unroll_for<TPR>(), 1>(A, A.rowptr[row], A.rowptr[row + 1], A.base(row), lane,
-                                             x, 0, IdxPlain{}, sum);
+  if (live) {
+    if constexpr (TPR >= 2)
+      sum = row_dot_pairs<TPR, unroll_for<TPR>()>(A, A.rowptr[row], A.rowptr[row + 1], A.base(row),
+                                                  lane, x, sum);
+    else
+      sum = row_dot<1, 4, 1>(A, A.rowptr[row], A.rowptr[row + 1], A.base(row), 0, x, 0, IdxPlain{},
+                             sum);
+  }
   if constexpr (TPR > 1) {
 #pragma unroll
     for (int o = TPR / 2; o > 0; o >>= 1) sum = sum + __shfl_down(sum, o, TPR);
@@ -217,26 +316,20 @@ __global__ __launch_bounds__(256) void spmv_rowblock_kernel(CSRT<MV, C16> A,
 // loads and gathers from LDS through the 16-bit column offsets.  Rows sum in
 // the order of the TPR-lane row kernel, so the results are the same bit for
 // bit.  A group that spans more than the LDS budget, or that kept int32
-// columns, gathers from global memory instead.
-constexpr int kLdsBytes = 64 * 1024;
-
-template <int TPR, int U, class MV, class X>
-__device__ __forceinline__ X row_dot_lds(const CSRT<MV, true>& A, int s, int e, int lane,
-                                         const X* xs, X sum) {
-  for (int p0 = s + lane; p0 < e; p0 += TPR * U) {
-    int c[U];
-    X v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int p = p0 + u * TPR;
-      c[u] = p < e ? (int)A.col16[p] : -1;
-      v[u] = p < e ? (X)ldv(A.val[p]) : X(0);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (c[u] >= 0) sum = sum + v[u] * xs[c[u]];
+// columns, gathers from global memory instead.  The budget is the device's
+// LDS per workgroup (160 KB on gfx950), 64 KB if the query fails.
+static int64_t lds_budget_bytes() {
+  static int64_t cached = 0;
+  if (cached == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        v >= 64 * 1024)
+      cached = v;
+    else
+      cached = 64 * 1024;
   }
-  return sum;
+  return cached;
 }
 
 template <int TPR, class MV, class X, class Epi>
@@ -270,14 +363,8 @@ __global__ __launch_bounds__(64 * TPR) void spmv_lds_kernel(CSRT<MV, true> A,
   X sum = 0;
   constexpr int U = unroll_for<TPR>();
   if (live) {
-    if (staged) {
-      sum = row_dot_lds<TPR, U>(A, s, e, lane, xs, sum);
-    } else if (base >= 0) {
-      sum = row_dot_cols<TPR, U, 1>(A, s, e, base, lane, x, 0, IdxPlain{}, sum);
-    } else {
-      const CSRT<MV, false> W{A.rowptr, A.col, nullptr, nullptr, A.val, A.rows};
-      sum = row_dot_cols<TPR, U, 1>(W, s, e, 0, lane, x, 0, IdxPlain{}, sum);
-    }
+    if (staged) sum = row_dot_pairs_cols<TPR, U, true>(A, s, e, 0, lane, (const X*)xs, sum);
+    else sum = row_dot_pairs<TPR, U>(A, s, e, base, lane, x, sum);
   }
   if constexpr (TPR > 1) {
 #pragma unroll
@@ -296,7 +383,7 @@ static void launch_spmv_t(const OpView& Av, int shape, int K, const X* x, Epi ep
   if (K == 1 && lds) {
     if constexpr (C16) {
       const int64_t ngroups = (Av.rows + 63) >> kColBlockShift;
-      const int cap = (int)std::min<int64_t>(Av.max_span, kLdsBytes / (int)sizeof(X));
+      const int cap = (int)std::min<int64_t>(Av.max_span, lds_budget_bytes() / (int64_t)sizeof(X));
       const size_t smem = (size_t)std::max(cap, 1) * sizeof(X);
       const unsigned nb = grid_for(ngroups, 1, xcd);
       switch (tpr) {
