@@ -460,10 +460,14 @@ void finalize_hierarchy(Hierarchy& H) {
       inherit_keys(key[l].get(), clist.get(), L.nC, key[l + 1].get(), s);
     }
   }
-  // the coarsest level: ordered by key too, its matrix permuted to match
+  // the coarsest level: ordered by keys of its own graph (its Newton steps
+  // are most of the V-cycle's products, and the couplings of a deep coarse
+  // matrix reach far beyond what the top grid's distances keep together),
+  // its matrix permuted to match
   Level& Lc = H.levels.back();
   Lc.pos.alloc(Lc.n, s);
   if (order) {
+    if (nl > 1) locality_keys(Lc.A, key[nl - 1].get(), s);
     rank_points(key[nl - 1].get(), Lc.n, Lc.pos.get(), s);
     CSR Ap;
     permute_rows(Lc.A, Lc.pos.get(), Lc.pos.get(), Lc.n, Ap, s);

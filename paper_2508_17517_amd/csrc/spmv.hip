@@ -361,7 +361,9 @@ __global__ __launch_bounds__(64 * TPR) void spmv_lds_kernel(CSRT<MV, true> A,
     __syncthreads();
   }
   X sum = 0;
-  constexpr int U = unroll_for<TPR>();
+  // LDS gathers are short: four pairs per lane in flight suffice (the order of
+  // a lane's entries, and so the result, does not depend on U)
+  constexpr int U = 4;
   if (live) {
     if (staged) sum = row_dot_pairs_cols<TPR, U, true>(A, s, e, 0, lane, (const X*)xs, sum);
     else sum = row_dot_pairs<TPR, U>(A, s, e, base, lane, x, sum);
