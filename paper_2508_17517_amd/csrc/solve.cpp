@@ -79,6 +79,8 @@ void workspace_init(const Hierarchy& H, Workspace& W, int K) {
   if (K > 1) {
     W.cdiv.alloc(K, s);
     W.cdot_work.alloc(col_dots_work_size(H.n0, K), s);
+  } else {
+    W.fused_work.alloc(cgs_fused_work_size(n), s);
   }
   const size_t ng = std::max<size_t>((size_t)K, H.seg.empty() ? 1 : H.seg.size());
   W.gbuf.alloc(ng + 1, s);
@@ -684,11 +686,19 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
         vcycle(H, W, vj, zj);
         spmv_t<double>(opview(H.Aperm), H.tpr_top, K, zj, W.w.get(), s);
         ++its;
+        // CGS2: h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; |w|^2, the
+        // second and third sweeps each fused with the reduction after them
         dots(V, ld, j + 1, W.w.get(), n, hd, W, s);
-        launch_cgs_update(W.w.get(), V, ld, hd, j + 1, n, s);
-        dots(V, ld, j + 1, W.w.get(), n, hd + (R + 1), W, s);
-        launch_cgs_update(W.w.get(), V, ld, hd + (R + 1), j + 1, n, s);
-        launch_tree_dots(W.w.get(), 0, 1, W.w.get(), n, hd + 2 * (R + 1), W.dot_work.get(), s);
+        if (j + 1 <= 32) {
+          launch_cgs_update_dots(W.w.get(), V, ld, hd, j + 1, n, hd + (R + 1), W.fused_work.get(), s);
+          launch_cgs_update_norm2(W.w.get(), V, ld, hd + (R + 1), j + 1, n, hd + 2 * (R + 1),
+                                  W.fused_work.get(), s);
+        } else {
+          launch_cgs_update(W.w.get(), V, ld, hd, j + 1, n, s);
+          dots(V, ld, j + 1, W.w.get(), n, hd + (R + 1), W, s);
+          launch_cgs_update(W.w.get(), V, ld, hd + (R + 1), j + 1, n, s);
+          launch_tree_dots(W.w.get(), 0, 1, W.w.get(), n, hd + 2 * (R + 1), W.dot_work.get(), s);
+        }
         W.hbuf.to_host(hh.data(), 2 * (R + 1) + 1);
         AIRG_HIP(hipStreamSynchronize(s));
         for (int i = 0; i <= j; ++i) Hm[(size_t)i * R + j] = hh[i] + hh[(R + 1) + i];

@@ -21,6 +21,7 @@ struct Workspace {
   DBuf<double> bperm, xperm, nat;
   DBuf<double> hbuf, ybuf, gbuf, dot_work, col_work;
   DBuf<double> cdiv, cdot_work;  // per-column divisors and dot partials (K > 1)
+  DBuf<double> fused_work;       // partials of the fused Gram-Schmidt sweeps (K = 1)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   ~Workspace();
 };

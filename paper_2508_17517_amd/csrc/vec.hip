@@ -235,6 +235,103 @@ void launch_sqrt_inplace(double* v, hipStream_t s) {
   AIRG_CHECK_LAUNCH();
 }
 
+// ------------------------------------------------------------------ fused Gram-Schmidt sweeps
+// The update of a classical Gram-Schmidt sweep fused with the reduction that
+// follows it: w = w - sum_k h[k] V_k (k ascending per element, as in
+// cgs_update_kernel), then either out[k] = V_k . w for k < nv (the next
+// sweep's coefficients) or out[0] = w . w (the new norm).  An element's V_k
+// values stay in registers between the update and the products, so the
+// basis is read once instead of twice.  One element per thread: block b
+// reduces elements b * 256 .. b * 256 + 255 by the shuffle tree and its four
+// waves in pairs, and the block partials of each k by the tree sum.
+constexpr int kFusedVecs = 32;
+
+// w = w - sum_k h[k] V_k, then the products V_k . w (DOTS) or w . w; NV basis
+// vectors, a compile-time count so that every load is issued unconditionally
+template <bool DOTS, int NV>
+__global__ __launch_bounds__(256) void cgs_fused_kernel(
+    double* __restrict__ w, const double* __restrict__ V, int64_t ldv, const double* __restrict__ h,
+    int64_t n, double* __restrict__ part, int64_t nb) {
+  constexpr int CNT = DOTS ? NV : 1;
+  __shared__ double red[CNT][4];
+  const int t = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 256 + t;
+  const bool in = i < n;
+  const int64_t ii = in ? i : 0;  // in-range address for the padding lanes
+  double v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = V[(int64_t)k * ldv + ii];
+  double wi = w[ii];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) wi = wi - h[k] * v[k];
+  if (in) w[i] = wi;
+  const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int k = 0; k < CNT; ++k) {
+    const double s = wave_tree(in ? (DOTS ? v[k] * wi : wi * wi) : 0.0);
+    if (lane == 0) red[k][wave] = s;
+  }
+  __syncthreads();
+  if (t < CNT) part[(int64_t)t * nb + blockIdx.x] = (red[t][0] + red[t][1]) + (red[t][2] + red[t][3]);
+}
+
+template <bool DOTS, int NV>
+static void launch_fused_nv(int nv, double* w, const double* V, int64_t ldv, const double* h,
+                            int64_t n, double* part, int64_t nb, hipStream_t s) {
+  if constexpr (NV > kFusedVecs) {
+    fail(AIRG_ERR_INTERNAL, "fused Gram-Schmidt takes 1 to 32 vectors");
+  } else {
+    if (nv != NV) return launch_fused_nv<DOTS, NV + 1>(nv, w, V, ldv, h, n, part, nb, s);
+    cgs_fused_kernel<DOTS, NV><<<(unsigned)nb, 256, 0, s>>>(w, V, ldv, h, n, part, nb);
+  }
+}
+
+static int64_t fused_blocks(int64_t n) { return n < 256 ? 1 : (n + 255) / 256; }
+
+size_t cgs_fused_work_size(int64_t n) {
+  const int64_t nb = fused_blocks(n);
+  const int64_t nb2 = (nb + kDotChunk - 1) / kDotChunk;
+  return (size_t)kFusedVecs * (size_t)(nb + nb2 + 2);
+}
+
+// out[k] = sum of the m partials a[k * m ...] by repeated tree stages (b: scratch)
+static void tree_reduce(double* a, int64_t m, int nv, double* out, double* b, hipStream_t s) {
+  int64_t stride = m;
+  for (;;) {
+    const int64_t mb = (m + kDotChunk - 1) / kDotChunk;
+    double* dst = (mb == 1) ? out : b;
+    const int64_t dstride = (mb == 1) ? 1 : mb;
+    tree_sum_stage<<<dim3((unsigned)mb, (unsigned)nv), 256, 0, s>>>(a, m, stride, dst, dstride);
+    AIRG_CHECK_LAUNCH();
+    if (mb == 1) return;
+    std::swap(a, b);
+    m = mb;
+    stride = dstride;
+  }
+}
+
+static void launch_cgs_fused(bool dots, double* w, const double* V, int64_t ldv, const double* h,
+                             int nv, int64_t n, double* out, double* work, hipStream_t s) {
+  if (nv < 1 || nv > kFusedVecs) fail(AIRG_ERR_INTERNAL, "fused Gram-Schmidt takes 1 to 32 vectors");
+  if (n <= 0) return;
+  const int64_t nb = fused_blocks(n);
+  const int cnt = dots ? nv : 1;
+  double* a = work;
+  double* b = work + (size_t)kFusedVecs * nb;
+  if (dots) launch_fused_nv<true, 1>(nv, w, V, ldv, h, n, a, nb, s);
+  else launch_fused_nv<false, 1>(nv, w, V, ldv, h, n, a, nb, s);
+  AIRG_CHECK_LAUNCH();
+  tree_reduce(a, nb, cnt, out, b, s);
+}
+void launch_cgs_update_dots(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                            int64_t n, double* out, double* work, hipStream_t s) {
+  launch_cgs_fused(true, w, V, ldv, h, nv, n, out, work, s);
+}
+void launch_cgs_update_norm2(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                             int64_t n, double* out, double* work, hipStream_t s) {
+  launch_cgs_fused(false, w, V, ldv, h, nv, n, out, work, s);
+}
+
 // ------------------------------------------------------------------ per-column Krylov
 // K interleaved columns (element e = r K + c of an [n][K] array, K a power of
 // two): the orthogonalisation of one FGMRES per column, all columns per launch.
