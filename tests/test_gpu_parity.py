@@ -478,3 +478,22 @@ def test_c_point_smoothing_rejections():
         Solver(p.indptr, p.indices, p.data, smooth_type=1, inverse_type=1)
     with pytest.raises(AirgError):
         Solver(p.indptr, p.indices, p.data, smooth_type=3)
+
+
+def test_long_arnoldi_cycle_past_the_fused_sweeps():
+    # a weak preconditioner (one level, degree-3 Newton polynomial) and
+    # restart 40: Arnoldi cycles pass 32 basis vectors, where the fused
+    # Gram-Schmidt sweeps give way to the separate ones, and then restart
+    _needs_gpu()
+    p = workloads.fv_random(64, 0.4, True)
+    kw = dict(max_levels=1, coarse_poly_order=3, restart=40)
+    xo, its, rel, levels, _ = oracle.solve(p.scipy(), p.b, oracle.Params(**kw))
+    assert its > 40
+    s = _solver(p, **kw)
+    x, info = s.solve(torch.from_numpy(p.b).cuda())
+    assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
+    assert info["restarts"] >= 1
+    # 40-step Arnoldi cycles amplify rounding differences: one iteration apart at most
+    assert abs(info["iterations"] - its) <= 1
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-9 * np.linalg.norm(xo)
+    s.close()
