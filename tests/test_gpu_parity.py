@@ -497,3 +497,28 @@ def test_long_arnoldi_cycle_past_the_fused_sweeps():
     assert abs(info["iterations"] - its) <= 1
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-9 * np.linalg.norm(xo)
     s.close()
+
+
+def test_c_point_smoothing_in_the_adjoint_and_problem_batches():
+    # the transpose hierarchy and a block-diagonal batch take the same smooth
+    # sequence: both reach the FP64 tolerance, and the adjoint takes the
+    # oracle's iterations on A^T
+    _needs_gpu()
+    from paper_2508_17517_amd import BatchSolver
+    p = workloads.fv_random(64, 0.8, True)
+    A = p.scipy()
+    w = np.random.default_rng(7).standard_normal(p.n)
+    lo, its, rel, _, _ = oracle.adjoint_solve(A, w, oracle.Params(smooth_type="fcf"))
+    s = _solver(p, smooth_type=2)
+    lam, info = s.adjoint_solve(torch.from_numpy(w).cuda())
+    assert info["converged"] == 1 and info["iterations"] == its
+    assert np.linalg.norm(lam.cpu().numpy() - lo) <= 1e-10 * np.linalg.norm(lo)
+    s.close()
+    probs = [workloads.fv_random(40, 0.3, True, seed=201), workloads.fv_random(24, 1.2, True, seed=202)]
+    sb = BatchSolver([(q.indptr, q.indices, q.data) for q in probs], smooth_type=1, precision=1)
+    xs, infos = sb.solve([torch.from_numpy(q.b).cuda() for q in probs])
+    for q, x, i in zip(probs, xs, infos):
+        xh = x.cpu().numpy()
+        assert i["converged"] == 1
+        assert np.linalg.norm(q.b - q.scipy() @ xh) <= 1e-10 * (1 + 1e-6) * np.linalg.norm(q.b)
+    sb.close()
