@@ -395,33 +395,6 @@ def test_fgmres_matches_brute_force_gmres_residuals():
     assert np.allclose(x, np.linalg.solve(Ad, b), rtol=1e-8)
 
 
-def test_fgmres_with_refined_sweeps_matches_gmres_residuals():
-    # A close to the identity: A v lies nearly in span(v), so the first
-    # Gram-Schmidt sweep cancels most of w and the second sweep is taken;
-    # the estimates must still be the GMRES residuals (projection residuals
-    # from a Householder QR of the Krylov matrix)
-    n = 60
-    B = sp.random(n, n, density=0.2, random_state=21)
-    A = sp.csr_matrix(sp.eye(n) + 1e-3 * B)
-    A.sort_indices()
-    b = np.random.default_rng(21).uniform(size=n)
-    v0 = b / np.linalg.norm(b)
-    w = A @ v0
-    h = v0 @ w
-    wp = w - h * v0
-    assert 2 * (wp @ wp) < (wp @ wp) + h * h      # the refined branch is live
-    x, its, rel, hist = oracle.fgmres(A, lambda v: v, b, rtol=1e-12)
-    Ad = A.toarray()
-    K = [b]
-    for k in range(1, min(its, 4) + 1):
-        K.append(Ad @ K[-1])
-        Q, _ = np.linalg.qr(np.array(K[1:]).T)
-        want = np.linalg.norm(b - Q @ (Q.T @ b)) / np.linalg.norm(b)
-        assert hist[k - 1] == pytest.approx(want, rel=1e-5, abs=1e-13)
-    assert rel <= 1e-12
-    assert np.allclose(x, np.linalg.solve(Ad, b), rtol=1e-10)
-
-
 # --------------------------------------------------------------------- adjoint (P11, P12)
 
 def test_adjoint_identity_and_adjoint_solve():
