@@ -152,6 +152,7 @@ def batched_legs(a, p, s64, value64, ip, ix, dv):
     v = p.n * k / dt
     res["columns"] = {"rhs": k, "value": v, "unit": "DOF/s", "ms_per_step": 1e3 * dt,
                       "iterations": max(i["iterations"] for i in infos),
+                      "iterations_min": min(i["iterations"] for i in infos),
                       "max_rel_residual": max(i["rel_residual"] for i in infos),
                       "rel_diff_vs_fp64_single": err, "speedup_vs_fp64": v / value64}
     print(f"bench: columns {res['columns']}", file=sys.stderr, flush=True)
@@ -176,7 +177,9 @@ def batched_legs(a, p, s64, value64, ip, ix, dv):
     st = sb.stats()
     v = ntot / dt
     res["problems"] = {"problems": q, "dofs": ntot, "value": v, "unit": "DOF/s",
-                       "ms_per_step": 1e3 * dt, "iterations": infos[0]["iterations"],
+                       "ms_per_step": 1e3 * dt,
+                       "iterations": max(i["iterations"] for i in infos),
+                       "iterations_min": min(i["iterations"] for i in infos),
                        "max_rel_residual": max(i["rel_residual"] for i in infos),
                        "levels": st["levels"], "setup_s": round(setup_b, 3),
                        "setup_component_ms": {k: round(v, 1) for k, v in

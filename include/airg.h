@@ -224,8 +224,14 @@ int airg_setup_batch(airg_handle* out, int nprob, const int64_t* n, const int64_
                      void* hip_stream);
 
 /* Solve every problem of a batch handle: b[p], x[p] device pointers of n[p]
- * doubles.  One outer process runs over the block-diagonal system until every
- * problem has |b_p - A_p x_p| <= rtol |b_p|; info has nprob entries. */
+ * doubles; info has nprob entries.  Each problem runs its own outer process
+ * (FGMRES or Richardson, with its own stopping test |b_p - A_p x_p| <=
+ * rtol |b_p|, restarts and iteration count), the V-cycle and every other
+ * kernel covering all problems per launch; the solve numbering orders each
+ * level problem-major for that.  (Should the problem-major keys not fit 31
+ * bits, or with locality_order = 0, one process runs over the block-diagonal
+ * system until every problem meets its test.)  A batch handle takes no
+ * airg_solve or airg_adjoint_solve call. */
 int airg_solve_batch(airg_handle h, const double* const* b, double* const* x,
                      int use_x_as_guess, airg_solve_info* info);
 

@@ -99,7 +99,8 @@ int solve_columns(Hierarchy& H, Workspace& W, std::map<int, std::unique_ptr<Work
   if (nrhs < 0) fail(AIRG_ERR_INVALID, "nrhs must be >= 0");
   if (nrhs > 0 && (!b || !x)) fail(AIRG_ERR_INVALID, "null vector pointer");
   if (nrhs > 1 && (ldb < H.n0 || ldx < H.n0)) fail(AIRG_ERR_INVALID, "leading dimension < n");
-  if (nrhs > 1 && !H.seg.empty()) fail(AIRG_ERR_INVALID, "a batch handle solves one column per problem");
+  if (!H.seg.empty())
+    fail(AIRG_ERR_INVALID, "a batch handle solves through airg_solve_batch (one entry per problem)");
   int status = AIRG_OK;
   for (int k0 = 0; k0 < nrhs;) {
     // K interleaved columns, with n K elements addressable by one launch
@@ -300,6 +301,7 @@ int airg_adjoint_solve(airg_handle h, int nrhs, const double* w, int64_t ldw, do
                        int64_t ldl, int use_guess, airg_solve_info* info) {
   return guard([&]() {
     airg_ctx* c = handle_of(h);
+    if (!c->H.seg.empty()) fail(AIRG_ERR_INVALID, "adjoint solves take a single-problem handle");
     if (!c->Ht) {
       std::unique_ptr<Hierarchy> Ht(new Hierarchy());
       Ht->p = c->H.p;

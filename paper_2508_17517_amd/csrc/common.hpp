@@ -152,6 +152,13 @@ struct CSRView {
 };
 inline CSRView view(const CSR& A) { return {A.rowptr.get(), A.col.get(), A.val.get(), A.rows}; }
 
+// A contiguous range of the nested numbering that belongs to one problem of
+// a block-diagonal batch.
+struct GroupRange {
+  int64_t start, len;
+  int32_t group;
+};
+
 inline unsigned blocks_for(int64_t n, int per_block) {
   int64_t b = (n + per_block - 1) / per_block;
   return (unsigned)(b < 1 ? 1 : b);

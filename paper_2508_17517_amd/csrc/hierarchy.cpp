@@ -449,9 +449,23 @@ void finalize_hierarchy(Hierarchy& H) {
   // locality keys, top down: two breadth-first distances on A_0 + A_0^T,
   // inherited by the coarse points
   std::vector<DBuf<int32_t>> key(nl);
+  // a batch orders every level problem-major (key = problem * mult + key), so
+  // that each problem's unknowns form ranges of the nested numbering; mult
+  // 0 where that would overflow the 31-bit keys (the batch then runs one
+  // outer process over all problems)
+  const int np = H.seg.empty() ? 0 : (int)H.seg.size() - 1;
+  int64_t mult = 0, mult_c = 0;
+  H.granges.clear();
   if (order) {
     key[0].alloc(H.n0, s);
     locality_keys(H.A0, key[0].get(), s);
+    if (np > 1) {
+      const int64_t m = (int64_t)max_key(key[0].get(), H.n0, s) + 1;
+      if ((int64_t)np * m <= (int64_t)INT32_MAX) {
+        problem_major_keys(key[0].get(), H.n0, H.seg, m, s);
+        mult = m;
+      }
+    }
     for (int l = 0; l + 1 < nl; ++l) {
       Level& L = H.levels[l];
       DBuf<int64_t> clist(L.nC, s);
@@ -467,7 +481,23 @@ void finalize_hierarchy(Hierarchy& H) {
   Level& Lc = H.levels.back();
   Lc.pos.alloc(Lc.n, s);
   if (order) {
-    if (nl > 1) locality_keys(Lc.A, key[nl - 1].get(), s);
+    if (nl > 1) {
+      DBuf<int32_t> pid;
+      if (mult) {
+        pid.alloc(Lc.n, s);
+        key_problems(key[nl - 1].get(), Lc.n, mult, pid.get(), s);
+      }
+      locality_keys(Lc.A, key[nl - 1].get(), s);
+      if (mult) {
+        const int64_t m = (int64_t)max_key(key[nl - 1].get(), Lc.n, s) + 1;
+        if ((int64_t)np * m <= (int64_t)INT32_MAX) {
+          problem_major_keys(key[nl - 1].get(), pid.get(), Lc.n, m, s);
+          mult_c = m;
+        }
+      }
+    } else {
+      mult_c = mult;
+    }
     rank_points(key[nl - 1].get(), Lc.n, Lc.pos.get(), s);
     CSR Ap;
     permute_rows(Lc.A, Lc.pos.get(), Lc.pos.get(), Lc.n, Ap, s);
@@ -563,6 +593,23 @@ void finalize_hierarchy(Hierarchy& H) {
   for (Level& L : H.levels) {
     L.off = off;
     off += L.nF;
+  }
+  // each problem's ranges of the nested numbering: its F points on every
+  // level, then its points of the coarsest level
+  if (mult && mult_c) {
+    for (int l = 0; l < nl; ++l) {
+      const Level& L = H.levels[l];
+      const std::vector<int32_t> cnt =
+          L.coarsest ? count_problems(nullptr, key[l].get(), L.n, mult_c, np, s)
+                     : count_problems(L.state.get(), key[l].get(), L.n, mult, np, s);
+      int64_t start = L.off;
+      for (int p = 0; p < np; ++p) {
+        if (cnt[p] > 0) H.granges.push_back({start, (int64_t)cnt[p], (int32_t)p});
+        start += cnt[p];
+      }
+      if (start != L.off + (L.coarsest ? L.n : L.nF))
+        fail(AIRG_ERR_INTERNAL, "problem ranges do not cover level " + std::to_string(l));
+    }
   }
   // segments of the stacked residual buffer, one per level below the top
   H.stacked_len = 0;

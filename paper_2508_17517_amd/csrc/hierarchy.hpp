@@ -94,6 +94,10 @@ struct Hierarchy {
   // a block-diagonal batch of problems: block p holds setup-numbering rows
   // seg[p] .. seg[p+1]-1 (empty for a single problem)
   std::vector<int64_t> seg;
+  // with a batch ordered problem-major, every problem's unknowns in the
+  // nested numbering as ranges (each level's F block, then the coarsest
+  // block, problems ascending inside each); empty otherwise
+  std::vector<GroupRange> granges;
 };
 
 // Build the hierarchy for A (device CSR, validated) with parameters p.

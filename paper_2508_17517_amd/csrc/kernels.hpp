@@ -64,6 +64,30 @@ void launch_divide_cols(double* y, const double* x, const double* d, int64_t n0,
 size_t col_dots_work_size(int64_t n0, int K);
 void launch_col_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n0, int K,
                      double* out, double* work, hipStream_t s);
+// One outer process per problem of a batch (see GroupRange): work items of
+// at most 1024 elements of one problem's range, and each problem's items in
+// a fixed order.  Coefficient arrays hold entry (k, g) at k G + g:
+//   out[k, g] = V_k . w over problem g (fixed order; `work` needs
+//   group_dots_work_size(items) doubles),
+//   w = w - sum_k h[k, g] V_k,  x = x + sum_k y[k, g] Z_k,
+//   y = x / d[g] problem by problem (0 where d[g] = 0).
+struct GroupItems {
+  DBuf<int64_t> start;
+  DBuf<int32_t> len, grp, gptr, glist;
+  int64_t n = 0;  // items
+  int G = 0;      // problems
+};
+void build_group_items(const std::vector<GroupRange>& ranges, int G, GroupItems& out,
+                       hipStream_t s);
+size_t group_dots_work_size(const GroupItems& it);
+void launch_group_dots(const double* V, int64_t ldv, int nv, const double* w, const GroupItems& it,
+                       double* out, double* work, hipStream_t s);
+void launch_group_update(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                         const GroupItems& it, hipStream_t s);
+void launch_group_combine(double* x, const double* Z, int64_t ldz, const double* y, int nv,
+                          const GroupItems& it, hipStream_t s);
+void launch_group_divide(double* y, const double* x, const double* d, const GroupItems& it,
+                         hipStream_t s);
 // out[0] = sqrt(out[0]) on the device
 void launch_sqrt_inplace(double* v, hipStream_t s);
 
@@ -236,6 +260,17 @@ void rank_points(const int32_t* key, int64_t n, int32_t* rank, hipStream_t s);
 void invert_perm(const int32_t* pos, int64_t n, int32_t* inv, hipStream_t s);
 // out[c] = key[clist[c]]
 void inherit_keys(const int32_t* key, const int64_t* clist, int64_t nc, int32_t* out, hipStream_t s);
+// Problem-major keys of a block-diagonal batch (key = p * mult + key), by the
+// row segments seg (problem p: rows seg[p] .. seg[p+1]-1) or by a problem per
+// point; the problem of each key (key / mult); the number of points of each
+// problem among all points, or among the F points when state is given.
+int32_t max_key(const int32_t* key, int64_t n, hipStream_t s);
+void problem_major_keys(int32_t* key, int64_t n, const std::vector<int64_t>& seg, int64_t mult,
+                        hipStream_t s);
+void problem_major_keys(int32_t* key, const int32_t* pid, int64_t n, int64_t mult, hipStream_t s);
+void key_problems(const int32_t* key, int64_t n, int64_t mult, int32_t* pid, hipStream_t s);
+std::vector<int32_t> count_problems(const int8_t* state, const int32_t* key, int64_t n,
+                                    int64_t mult, int np, hipStream_t s);
 // pos[i] = frank[fidx[i]] for F points, nF + pos_next[cidx[i]] for C points.
 void launch_nested_pos_ranked(const int8_t* state, const int64_t* fidx, const int64_t* cidx,
                               const int32_t* frank, int64_t nF, const int32_t* pos_next, int64_t n,

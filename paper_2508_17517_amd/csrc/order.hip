@@ -263,6 +263,72 @@ void inherit_keys(const int32_t* key, const int64_t* clist, int64_t nc, int32_t*
   AIRG_CHECK_LAUNCH();
 }
 
+// ------------------------------------------------------------------ problem-major keys
+// For a block-diagonal batch: key = p * mult + key with p the problem of the
+// point, so that every ordered block of points keeps each problem together.
+__global__ void problem_major_seg_kernel(int32_t* key, int64_t n, const int64_t* seg, int np,
+                                         int64_t mult) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int lo = 0, hi = np - 1;  // the largest p with seg[p] <= i
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (seg[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  key[i] = (int32_t)((int64_t)lo * mult + key[i]);
+}
+__global__ void problem_major_pid_kernel(int32_t* key, const int32_t* pid, int64_t n, int64_t mult) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) key[i] = (int32_t)((int64_t)pid[i] * mult + key[i]);
+}
+__global__ void key_problem_kernel(const int32_t* key, int64_t n, int64_t mult, int32_t* pid) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) pid[i] = (int32_t)(key[i] / mult);
+}
+__global__ void count_problems_kernel(const int8_t* state, const int32_t* key, int64_t n,
+                                      int64_t mult, int np, int32_t* counts) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || (state && state[i] != 1)) return;
+  const int64_t p = key[i] / mult;
+  if (p >= 0 && p < np) atomicAdd(&counts[p], 1);
+}
+
+int32_t max_key(const int32_t* key, int64_t n, hipStream_t s) {
+  if (n <= 0) return 0;
+  return fetch(key + far_node(key, n, s), s);
+}
+void problem_major_keys(int32_t* key, int64_t n, const std::vector<int64_t>& seg, int64_t mult,
+                        hipStream_t s) {
+  const int np = (int)seg.size() - 1;
+  if (n <= 0 || np < 1) return;
+  DBuf<int64_t> sd(seg.size(), s);
+  sd.from_host(seg.data(), seg.size());
+  problem_major_seg_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(key, n, sd.get(), np, mult);
+  AIRG_CHECK_LAUNCH();
+  AIRG_HIP(hipStreamSynchronize(s));
+}
+void problem_major_keys(int32_t* key, const int32_t* pid, int64_t n, int64_t mult, hipStream_t s) {
+  if (n <= 0) return;
+  problem_major_pid_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(key, pid, n, mult);
+  AIRG_CHECK_LAUNCH();
+}
+void key_problems(const int32_t* key, int64_t n, int64_t mult, int32_t* pid, hipStream_t s) {
+  if (n <= 0) return;
+  key_problem_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(key, n, mult, pid);
+  AIRG_CHECK_LAUNCH();
+}
+std::vector<int32_t> count_problems(const int8_t* state, const int32_t* key, int64_t n,
+                                    int64_t mult, int np, hipStream_t s) {
+  DBuf<int32_t> c(np, s);
+  launch_fill_i32(c.get(), np, 0, s);
+  if (n > 0) {
+    count_problems_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(state, key, n, mult, np, c.get());
+    AIRG_CHECK_LAUNCH();
+  }
+  return c.host(np);
+}
+
 // Nested positions with ordered F points, and the permuted prolongation map.
 __global__ void nested_pos_ranked_kernel(const int8_t* state, const int64_t* fidx,
                                          const int64_t* cidx, const int32_t* frank, int64_t nF,

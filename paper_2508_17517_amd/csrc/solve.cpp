@@ -10,10 +10,12 @@
 // columns, and the top-level product and the Gram-Schmidt, normalisation and
 // update kernels likewise cover all columns per launch, while each column
 // keeps its own FGMRES process (Hessenberg matrix, rotations, stopping test,
-// restarts) on the host.  A block-diagonal batch of problems is solved by one
-// Krylov process over the whole system, each problem being a convergence
-// group (its stopping test is tightened so that every problem reaches the
-// tolerance on its own).
+// restarts) on the host.  A block-diagonal batch of problems ordered
+// problem-major runs one process per problem in the same way, its
+// reductions and updates working on each problem's ranges of the nested
+// numbering; without that order, one Krylov process runs over the whole
+// system, each problem being a convergence group (its stopping test is
+// tightened so that every problem reaches the tolerance on its own).
 //
 // Mixed precision: with FP32 or BF16 storage the V-cycle runs on FP32 vectors
 // (matrices in the storage type, rows accumulated in FP32) between a
@@ -74,13 +76,21 @@ void workspace_init(const Hierarchy& H, Workspace& W, int K) {
   W.bperm.alloc(n, s);
   W.xperm.alloc(n, s);
   if (!H.seg.empty()) W.nat.alloc(H.n0, s);
-  W.hbuf.alloc((2 * (W.restart + 1) + 2) * (size_t)K, s);
-  W.ybuf.alloc((W.restart + 1) * (size_t)K, s);
+  const size_t G = std::max<size_t>((size_t)K, H.seg.empty() ? 1 : H.seg.size());
+  W.hbuf.alloc((2 * (W.restart + 1) + 2) * G, s);
+  W.ybuf.alloc((W.restart + 1) * G, s);
   if (K > 1) {
     W.cdiv.alloc(K, s);
     W.cdot_work.alloc(col_dots_work_size(H.n0, K), s);
   } else {
     W.fused_work.alloc(cgs_fused_work_size(n), s);
+  }
+  // a batch ordered problem-major: one outer process per problem
+  const int np = H.seg.empty() ? 0 : (int)H.seg.size() - 1;
+  if (K == 1 && np > 0 && !H.granges.empty()) {
+    build_group_items(H.granges, np, W.gitems, s);
+    W.gdot_work.alloc(group_dots_work_size(W.gitems), s);
+    W.cdiv.alloc(np, s);
   }
   const size_t ng = std::max<size_t>((size_t)K, H.seg.empty() ? 1 : H.seg.size());
   W.gbuf.alloc(ng + 1, s);
@@ -391,15 +401,54 @@ struct ColumnCycle {
   }
 };
 
-// K > 1 columns, one outer process per column (see fgmres_solve).  A column
-// that has stopped (converged, out of iterations, or at the end of its
-// Arnoldi process in this cycle) is carried through the shared launches as
-// zeros: its divisor is 0, so its next basis vector, V-cycle input and
-// products vanish, and it gets a zero weight in every solution update.
-void solve_columns(const Hierarchy& H, Workspace& W, std::vector<airg_solve_info>& out,
-                   bool& all_converged) {
+// The kernels of G independent outer processes run together: the K
+// interleaved columns of a multi-column solve (G = K), or the problems of a
+// batch ordered problem-major (G problems, ranges of one column).
+struct Procs {
+  const Hierarchy& H;
+  Workspace& W;
+  int G;
+  bool cols;
+  void dots(const double* V, int64_t ld, int nv, const double* w, double* out) {
+    if (cols) launch_col_dots(V, ld, nv, w, H.n0, W.K, out, W.cdot_work.get(), H.s);
+    else launch_group_dots(V, ld, nv, w, W.gitems, out, W.gdot_work.get(), H.s);
+  }
+  void update(double* w, const double* V, int64_t ld, const double* h, int nv) {
+    if (cols) launch_cgs_update_cols(w, V, ld, h, nv, H.n0, W.K, H.s);
+    else launch_group_update(w, V, ld, h, nv, W.gitems, H.s);
+  }
+  void sumsq(const double* v, double* out) {
+    if (cols) launch_col_sumsq(v, H.n0, W.K, out, W.col_work.get(), H.s);
+    else launch_group_dots(v, 0, 1, v, W.gitems, out, W.gdot_work.get(), H.s);
+  }
+  void divide(double* y, const double* x, const double* d) {
+    if (cols) launch_divide_cols(y, x, d, H.n0, W.K, H.s);
+    else launch_group_divide(y, x, d, W.gitems, H.s);
+  }
+  void combine(double* x, const double* Z, int64_t ld, const double* y, int nv) {
+    if (cols) launch_basis_combine_cols(x, Z, ld, y, nv, H.n0, W.K, H.s);
+    else launch_group_combine(x, Z, ld, y, nv, W.gitems, H.s);
+  }
+  std::vector<double> norms(const double* v) {
+    sumsq(v, W.gbuf.get());
+    std::vector<double> out(G);
+    W.gbuf.to_host(out.data(), G);
+    AIRG_HIP(hipStreamSynchronize(H.s));
+    for (double& x : out) x = std::sqrt(x);
+    return out;
+  }
+};
+
+// G outer processes at once (see fgmres_solve).  A process that has stopped
+// (converged, out of iterations, or at the end of its Arnoldi process in
+// this cycle) is carried through the shared launches as zeros: its divisor
+// is 0, so its next basis vector, V-cycle input and products vanish, and it
+// gets a zero weight in every solution update.
+void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<airg_solve_info>& out,
+                     bool& all_converged) {
   hipStream_t s = H.s;
   const int K = W.K;
+  const int G = P.G;
   const int64_t n0 = H.n0;
   const int64_t n = n0 * K;
   const int R = W.restart;
@@ -411,40 +460,39 @@ void solve_columns(const Hierarchy& H, Workspace& W, std::vector<airg_solve_info
   double* Zb = W.Zb.get();
   double* dv = W.cdiv.get();
 
-  std::vector<double> bn = group_norms(H, W, W.bperm.get());
+  std::vector<double> bn = P.norms(W.bperm.get());
   for (double v : bn)
     if (!std::isfinite(v)) fail(AIRG_ERR_NONFINITE, "right-hand side is not finite");
-  std::vector<int> its(K, 0), rst(K, 0), done(K, 0);
-  std::vector<double> rn(K, 0.0), est(K, 0.0), ref = bn, dh(K), yh((size_t)R * K);
-  auto upload_div = [&]() { W.cdiv.from_host(dh.data(), K); };
+  std::vector<int> its(G, 0), rst(G, 0), done(G, 0);
+  std::vector<double> rn(G, 0.0), est(G, 0.0), ref = bn, dh(G), yh((size_t)R * G);
+  auto upload_div = [&]() { W.cdiv.from_host(dh.data(), G); };
   auto residual = [&](double* r) {
     spmv_t<double>(A, H.tpr_top, K, W.xperm.get(), W.w.get(), s);
     launch_sub(r, W.bperm.get(), W.w.get(), n, s);
-    rn = group_norms(H, W, r);
+    rn = P.norms(r);
   };
-
   if (H.p.outer == AIRG_OUTER_RICHARDSON) {
     // x <- x + M (b - A x) for the columns still running; a column with b = 0
     // is measured against its initial residual
     double* r = V;
     double* e = Zb;
     residual(r);
-    for (int c = 0; c < K; ++c) {
+    for (int c = 0; c < G; ++c) {
       if (ref[c] == 0.0) ref[c] = rn[c];
       done[c] = rn[c] <= rtol * ref[c] || max_it <= 0;
     }
     for (;;) {
       bool any = false;
-      for (int c = 0; c < K; ++c) {
+      for (int c = 0; c < G; ++c) {
         dh[c] = done[c] ? 0.0 : 1.0;
         any = any || !done[c];
       }
       if (!any) break;
       vcycle(H, W, r, e);
-      W.ybuf.from_host(dh.data(), K);
-      launch_basis_combine_cols(W.xperm.get(), e, ld, W.ybuf.get(), 1, n0, K, s);
+      W.ybuf.from_host(dh.data(), G);
+      P.combine(W.xperm.get(), e, ld, W.ybuf.get(), 1);
       residual(r);
-      for (int c = 0; c < K; ++c) {
+      for (int c = 0; c < G; ++c) {
         if (done[c]) continue;
         ++its[c];
         if (!std::isfinite(rn[c])) fail(AIRG_ERR_BREAKDOWN, "Richardson diverged (non-finite residual)");
@@ -454,23 +502,23 @@ void solve_columns(const Hierarchy& H, Workspace& W, std::vector<airg_solve_info
   } else {
     // b = 0: the solution of A x = 0, whatever the guess
     bool zero = false;
-    for (int c = 0; c < K; ++c) {
+    for (int c = 0; c < G; ++c) {
       dh[c] = bn[c] == 0.0 ? 0.0 : 1.0;
       zero = zero || bn[c] == 0.0;
       done[c] = bn[c] == 0.0;
     }
     if (zero) {
       upload_div();
-      launch_divide_cols(W.xperm.get(), W.xperm.get(), dv, n0, K, s);
+      P.divide(W.xperm.get(), W.xperm.get(), dv);
     }
-    std::vector<ColumnCycle> cyc(K);
-    std::vector<int> act(K, 0);
+    std::vector<ColumnCycle> cyc(G);
+    std::vector<int> act(G, 0);
     double* hd = W.hbuf.get();
-    std::vector<double> hh((size_t)(2 * (R + 1) + 1) * K), hc(R + 1);
+    std::vector<double> hh((size_t)(2 * (R + 1) + 1) * G), hc(R + 1);
     for (;;) {
       residual(V);
       bool any = false;
-      for (int c = 0; c < K; ++c) {
+      for (int c = 0; c < G; ++c) {
         act[c] = 0;
         if (done[c]) continue;
         if (rn[c] <= rtol * bn[c] || its[c] >= max_it) {
@@ -483,34 +531,34 @@ void solve_columns(const Hierarchy& H, Workspace& W, std::vector<airg_solve_info
         any = true;
       }
       if (!any) break;
-      for (int c = 0; c < K; ++c) {
+      for (int c = 0; c < G; ++c) {
         dh[c] = act[c] ? rn[c] : 0.0;
         cyc[c].reset(R, act[c] ? rn[c] : 0.0);
       }
       upload_div();
-      launch_divide_cols(V, V, dv, n0, K, s);
+      P.divide(V, V, dv);
       for (int j = 0; j < R; ++j) {
         double* vj = V + (int64_t)j * ld;
         double* zj = Zb + (int64_t)j * ld;
         vcycle(H, W, vj, zj);
         spmv_t<double>(A, H.tpr_top, K, zj, W.w.get(), s);
         double* h1 = hd;
-        double* h2 = hd + (size_t)(R + 1) * K;
-        double* hn2 = hd + (size_t)2 * (R + 1) * K;
-        launch_col_dots(V, ld, j + 1, W.w.get(), n0, K, h1, W.cdot_work.get(), s);
-        launch_cgs_update_cols(W.w.get(), V, ld, h1, j + 1, n0, K, s);
-        launch_col_dots(V, ld, j + 1, W.w.get(), n0, K, h2, W.cdot_work.get(), s);
-        launch_cgs_update_cols(W.w.get(), V, ld, h2, j + 1, n0, K, s);
-        launch_col_sumsq(W.w.get(), n0, K, hn2, W.col_work.get(), s);
-        W.hbuf.to_host(hh.data(), (size_t)(2 * (R + 1) + 1) * K);
+        double* h2 = hd + (size_t)(R + 1) * G;
+        double* hn2 = hd + (size_t)2 * (R + 1) * G;
+        P.dots(V, ld, j + 1, W.w.get(), h1);
+        P.update(W.w.get(), V, ld, h1, j + 1);
+        P.dots(V, ld, j + 1, W.w.get(), h2);
+        P.update(W.w.get(), V, ld, h2, j + 1);
+        P.sumsq(W.w.get(), hn2);
+        W.hbuf.to_host(hh.data(), (size_t)(2 * (R + 1) + 1) * G);
         AIRG_HIP(hipStreamSynchronize(s));
         bool more = false;
-        for (int c = 0; c < K; ++c) {
+        for (int c = 0; c < G; ++c) {
           dh[c] = 0.0;
           if (!act[c]) continue;
           for (int i = 0; i <= j; ++i)
-            hc[i] = hh[(size_t)i * K + c] + hh[(size_t)(R + 1) * K + (size_t)i * K + c];
-          const double hn = std::sqrt(hh[(size_t)2 * (R + 1) * K + c]);
+            hc[i] = hh[(size_t)i * G + c] + hh[(size_t)(R + 1) * G + (size_t)i * G + c];
+          const double hn = std::sqrt(hh[(size_t)2 * (R + 1) * G + c]);
           ++its[c];
           est[c] = cyc[c].push(R, j, hc.data(), hn);
           if (!std::isfinite(est[c])) fail(AIRG_ERR_BREAKDOWN, "FGMRES breakdown (non-finite residual)");
@@ -523,24 +571,24 @@ void solve_columns(const Hierarchy& H, Workspace& W, std::vector<airg_solve_info
         }
         if (!more || j + 1 == R) break;
         upload_div();
-        launch_divide_cols(V + (int64_t)(j + 1) * ld, W.w.get(), dv, n0, K, s);
+        P.divide(V + (int64_t)(j + 1) * ld, W.w.get(), dv);
       }
       int kmax = 0;
       std::fill(yh.begin(), yh.end(), 0.0);
-      for (int c = 0; c < K; ++c) {
+      for (int c = 0; c < G; ++c) {
         ColumnCycle& cc = cyc[c];
         if (cc.k == 0) continue;
         cc.solve_upper(R);
-        for (int i = 0; i < cc.k; ++i) yh[(size_t)i * K + c] = cc.y[i];
+        for (int i = 0; i < cc.k; ++i) yh[(size_t)i * G + c] = cc.y[i];
         kmax = std::max(kmax, cc.k);
       }
-      W.ybuf.from_host(yh.data(), (size_t)kmax * K);
-      launch_basis_combine_cols(W.xperm.get(), Zb, ld, W.ybuf.get(), kmax, n0, K, s);
+      W.ybuf.from_host(yh.data(), (size_t)kmax * G);
+      P.combine(W.xperm.get(), Zb, ld, W.ybuf.get(), kmax);
     }
   }
   all_converged = true;
-  out.assign(K, airg_solve_info{});
-  for (int c = 0; c < K; ++c) {
+  out.assign(G, airg_solve_info{});
+  for (int c = 0; c < G; ++c) {
     airg_solve_info& o = out[c];
     o.iterations = its[c];
     o.restarts = rst[c];
@@ -578,23 +626,34 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
   const int max_it = H.p.max_it;
   AIRG_HIP(hipEventRecord(W.ev0, s));
 
-  if (K > 1) {
-    launch_scatter_cols(W.bperm.get(), b, ldb, pos, H.n0, K, kvalid, s);
-    if (guess) launch_scatter_cols(W.xperm.get(), x, ldx, pos, H.n0, K, kvalid, s);
-    else launch_fill(W.xperm.get(), n, 0.0, s);
-    std::vector<airg_solve_info> cols;
+  const bool groups = K == 1 && W.gitems.n > 0;
+  if (K > 1 || groups) {
+    if (K > 1) {
+      launch_scatter_cols(W.bperm.get(), b, ldb, pos, H.n0, K, kvalid, s);
+      if (guess) launch_scatter_cols(W.xperm.get(), x, ldx, pos, H.n0, K, kvalid, s);
+      else launch_fill(W.xperm.get(), n, 0.0, s);
+    } else {
+      launch_scatter(W.bperm.get(), b, pos, H.n0, s);
+      if (guess) launch_scatter(W.xperm.get(), x, pos, H.n0, s);
+      else launch_fill(W.xperm.get(), n, 0.0, s);
+    }
+    Procs P{H, W, groups ? W.gitems.G : K, !groups};
+    std::vector<airg_solve_info> res;
     bool ok = false;
-    solve_columns(H, W, cols, ok);
-    launch_gather_cols(x, ldx, W.xperm.get(), pos, H.n0, K, kvalid, s);
+    solve_processes(H, W, P, res, ok);
+    if (K > 1) launch_gather_cols(x, ldx, W.xperm.get(), pos, H.n0, K, kvalid, s);
+    else launch_gather(x, W.xperm.get(), pos, H.n0, s);
     AIRG_HIP(hipEventRecord(W.ev1, s));
     AIRG_HIP(hipEventSynchronize(W.ev1));
     float ms = 0.f;
     AIRG_HIP(hipEventElapsedTime(&ms, W.ev0, W.ev1));
-    if (info)
-      for (int c = 0; c < kvalid; ++c) {
-        info[c] = cols[c];
+    if (info) {
+      const int nout = groups ? P.G : kvalid;
+      for (int c = 0; c < nout; ++c) {
+        info[c] = res[c];
         info[c].solve_ms = ms;
       }
+    }
     return ok ? AIRG_OK : AIRG_NOT_CONVERGED;
   }
   launch_scatter(W.bperm.get(), b, pos, H.n0, s);

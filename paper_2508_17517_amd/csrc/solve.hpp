@@ -3,6 +3,7 @@
 #pragma once
 
 #include "hierarchy.hpp"
+#include "kernels.hpp"
 
 namespace airg {
 
@@ -22,6 +23,8 @@ struct Workspace {
   DBuf<double> hbuf, ybuf, gbuf, dot_work, col_work;
   DBuf<double> cdiv, cdot_work;  // per-column divisors and dot partials (K > 1)
   DBuf<double> fused_work;       // partials of the fused Gram-Schmidt sweeps (K = 1)
+  GroupItems gitems;             // per-problem work items of a batch (K = 1)
+  DBuf<double> gdot_work;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   ~Workspace();
 };
@@ -37,9 +40,11 @@ void vcycle(const Hierarchy& H, Workspace& W, const double* in, double* e);
 // column runs its own FGMRES (or Richardson) process with its own stopping
 // test, iteration count and restarts, while the V-cycle, the top-level
 // product and the orthogonalisation kernels cover all K columns per launch.
-// With K = 1 and a batch of problems (H.seg), one process runs over the
-// block-diagonal system until every problem reaches |r_p| <= rtol |b_p|.
-// info receives one entry per column or problem.
+// A batch of problems (H.seg) ordered problem-major (H.granges) likewise runs
+// one process per problem, with kernels over each problem's ranges of the
+// nested numbering; otherwise one process runs over the block-diagonal
+// system until every problem reaches |r_p| <= rtol |b_p|.  info receives
+// one entry per column or problem.
 int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb, double* x,
                  int64_t ldx, int kvalid, bool guess, airg_solve_info* info);
 

@@ -1,5 +1,6 @@
 // Vector kernels: counter-based random draws, elementwise updates, dot
 // products in a fixed binary-tree order, permutations and prefix scans.
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.hpp"
@@ -451,6 +452,160 @@ void launch_col_dots(const double* V, int64_t ldv, int nv, const double* w, int6
     tree_sum_stage<<<dim3(1u, (unsigned)(cnt * K)), 256, 0, s>>>(work, G, G, out + (int64_t)k0 * K, 1);
     AIRG_CHECK_LAUNCH();
   }
+}
+
+// ------------------------------------------------------------------ per-problem Krylov
+// One outer process per problem of a batch ordered problem-major: work item
+// q covers elements start[q] .. start[q] + len[q] - 1 (len <= kDotChunk) of
+// problem grp[q]; coefficient arrays hold entry (k, g) at k G + g.
+void build_group_items(const std::vector<GroupRange>& ranges, int G, GroupItems& out,
+                       hipStream_t s) {
+  std::vector<int64_t> st;
+  std::vector<int32_t> ln, gp;
+  for (const GroupRange& r : ranges)
+    for (int64_t a = 0; a < r.len; a += kDotChunk) {
+      st.push_back(r.start + a);
+      ln.push_back((int32_t)std::min<int64_t>(kDotChunk, r.len - a));
+      gp.push_back(r.group);
+    }
+  // items of each problem in list order: the fixed order of its sums
+  std::vector<int32_t> gptr(G + 1, 0), glist(gp.size());
+  for (int32_t g : gp) ++gptr[g + 1];
+  for (int g = 0; g < G; ++g) gptr[g + 1] += gptr[g];
+  std::vector<int32_t> fill(gptr.begin(), gptr.end() - 1);
+  for (size_t q = 0; q < gp.size(); ++q) glist[fill[gp[q]]++] = (int32_t)q;
+  out.n = (int64_t)st.size();
+  out.G = G;
+  out.start.alloc(st.size(), s);
+  out.len.alloc(ln.size(), s);
+  out.grp.alloc(gp.size(), s);
+  out.gptr.alloc(gptr.size(), s);
+  out.glist.alloc(glist.size(), s);
+  out.start.from_host(st.data(), st.size());
+  out.len.from_host(ln.data(), ln.size());
+  out.grp.from_host(gp.data(), gp.size());
+  out.gptr.from_host(gptr.data(), gptr.size());
+  out.glist.from_host(glist.data(), glist.size());
+  AIRG_HIP(hipStreamSynchronize(s));
+}
+
+// block q: partial products of its item, by the tree of tree_dot_stage1
+__global__ __launch_bounds__(256) void group_dots_stage1(const double* __restrict__ V, int64_t ldv,
+                                                         int nv, const double* __restrict__ w,
+                                                         const int64_t* __restrict__ start,
+                                                         const int32_t* __restrict__ len,
+                                                         double* __restrict__ part, int64_t nq) {
+  __shared__ double red[kMaxDotVecs][4];
+  const int t = threadIdx.x;
+  const int64_t b = start[blockIdx.x];
+  const int m = len[blockIdx.x];
+  double w4[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) w4[q] = (4 * t + q < m) ? w[b + 4 * t + q] : 0.0;
+  const int lane = t & 63, wave = t >> 6;
+  for (int k = 0; k < nv; ++k) {
+    const double* v = V + (int64_t)k * ldv + b;
+    double p[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[q] = (4 * t + q < m) ? v[4 * t + q] * w4[q] : 0.0;
+    const double ws = wave_tree((p[0] + p[1]) + (p[2] + p[3]));
+    if (lane == 0) red[k][wave] = ws;
+  }
+  __syncthreads();
+  if (t < nv) part[(int64_t)t * nq + blockIdx.x] = (red[t][0] + red[t][1]) + (red[t][2] + red[t][3]);
+}
+// block (g, k): out[k G + g] = the partials of problem g's items, each thread
+// adding its share of the list in order, then the shuffle tree and the waves
+__global__ __launch_bounds__(256) void group_sum_kernel(const double* __restrict__ part, int64_t nq,
+                                                        const int32_t* __restrict__ gptr,
+                                                        const int32_t* __restrict__ glist, int G,
+                                                        double* __restrict__ out) {
+  __shared__ double red[4];
+  const int g = blockIdx.x, k = blockIdx.y, t = threadIdx.x;
+  const double* src = part + (int64_t)k * nq;
+  double acc = 0.0;
+  for (int q = gptr[g] + t; q < gptr[g + 1]; q += 256) acc = acc + src[glist[q]];
+  const double ws = wave_tree(acc);
+  if ((t & 63) == 0) red[t >> 6] = ws;
+  __syncthreads();
+  if (t == 0) out[(int64_t)k * G + g] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+__global__ __launch_bounds__(256) void group_update_kernel(double* __restrict__ w,
+                                                           const double* __restrict__ V, int64_t ldv,
+                                                           const double* __restrict__ h, int nv,
+                                                           int G, const int64_t* __restrict__ start,
+                                                           const int32_t* __restrict__ len,
+                                                           const int32_t* __restrict__ grp) {
+  const int64_t b = start[blockIdx.x];
+  const int m = len[blockIdx.x], g = grp[blockIdx.x];
+  for (int e = threadIdx.x; e < m; e += 256) {
+    const int64_t i = b + e;
+    double acc = w[i];
+    for (int k = 0; k < nv; ++k) acc = acc - h[(int64_t)k * G + g] * V[(int64_t)k * ldv + i];
+    w[i] = acc;
+  }
+}
+__global__ __launch_bounds__(256) void group_combine_kernel(double* __restrict__ x,
+                                                            const double* __restrict__ Z, int64_t ldz,
+                                                            const double* __restrict__ y, int nv,
+                                                            int G, const int64_t* __restrict__ start,
+                                                            const int32_t* __restrict__ len,
+                                                            const int32_t* __restrict__ grp) {
+  const int64_t b = start[blockIdx.x];
+  const int m = len[blockIdx.x], g = grp[blockIdx.x];
+  for (int e = threadIdx.x; e < m; e += 256) {
+    const int64_t i = b + e;
+    double acc = x[i];
+    for (int k = 0; k < nv; ++k) acc = acc + y[(int64_t)k * G + g] * Z[(int64_t)k * ldz + i];
+    x[i] = acc;
+  }
+}
+__global__ __launch_bounds__(256) void group_divide_kernel(double* __restrict__ y,
+                                                           const double* __restrict__ x,
+                                                           const double* __restrict__ d,
+                                                           const int64_t* __restrict__ start,
+                                                           const int32_t* __restrict__ len,
+                                                           const int32_t* __restrict__ grp) {
+  const int64_t b = start[blockIdx.x];
+  const int m = len[blockIdx.x];
+  const double dg = d[grp[blockIdx.x]];
+  for (int e = threadIdx.x; e < m; e += 256) y[b + e] = dg != 0.0 ? x[b + e] / dg : 0.0;
+}
+
+size_t group_dots_work_size(const GroupItems& it) { return (size_t)kMaxDotVecs * (size_t)std::max<int64_t>(it.n, 1); }
+void launch_group_dots(const double* V, int64_t ldv, int nv, const double* w, const GroupItems& it,
+                       double* out, double* work, hipStream_t s) {
+  if (nv <= 0 || it.n <= 0) return;
+  for (int k0 = 0; k0 < nv; k0 += kMaxDotVecs) {
+    const int cnt = std::min(kMaxDotVecs, nv - k0);
+    group_dots_stage1<<<(unsigned)it.n, 256, 0, s>>>(V + (int64_t)k0 * ldv, ldv, cnt, w,
+                                                      it.start.get(), it.len.get(), work, it.n);
+    AIRG_CHECK_LAUNCH();
+    group_sum_kernel<<<dim3((unsigned)it.G, (unsigned)cnt), 256, 0, s>>>(
+        work, it.n, it.gptr.get(), it.glist.get(), it.G, out + (int64_t)k0 * it.G);
+    AIRG_CHECK_LAUNCH();
+  }
+}
+void launch_group_update(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                         const GroupItems& it, hipStream_t s) {
+  if (nv <= 0 || it.n <= 0) return;
+  group_update_kernel<<<(unsigned)it.n, 256, 0, s>>>(w, V, ldv, h, nv, it.G, it.start.get(),
+                                                      it.len.get(), it.grp.get());
+  AIRG_CHECK_LAUNCH();
+}
+void launch_group_combine(double* x, const double* Z, int64_t ldz, const double* y, int nv,
+                          const GroupItems& it, hipStream_t s) {
+  if (nv <= 0 || it.n <= 0) return;
+  group_combine_kernel<<<(unsigned)it.n, 256, 0, s>>>(x, Z, ldz, y, nv, it.G, it.start.get(),
+                                                       it.len.get(), it.grp.get());
+  AIRG_CHECK_LAUNCH();
+}
+void launch_group_divide(double* y, const double* x, const double* d, const GroupItems& it,
+                         hipStream_t s) {
+  if (it.n <= 0) return;
+  group_divide_kernel<<<(unsigned)it.n, 256, 0, s>>>(y, x, d, it.start.get(), it.len.get(),
+                                                      it.grp.get());
+  AIRG_CHECK_LAUNCH();
 }
 
 // ------------------------------------------------------------------ permutations

@@ -2,7 +2,8 @@
 
 Two kinds of batching: several right-hand sides of one matrix (K interleaved
 columns, one FGMRES process per column over shared V-cycle launches) and
-several independent problems in one block-diagonal hierarchy.  Every column or problem must reach the FP64
+several independent problems in one block-diagonal hierarchy (one process
+per problem).  Every column or problem must reach the FP64
 tolerance in its own residual, checked here on the CPU, and agree with the
 exact discrete solution from the oracle's sweep.
 """
@@ -171,6 +172,38 @@ def test_problem_batch_solves_every_problem():
     s.close()
 
 
+@pytest.mark.parametrize("outer", [0, 1])
+def test_problem_batch_runs_one_process_per_problem(outer):
+    # each problem stops at its own count: the oracle's solve of that
+    # problem alone (its right-hand side embedded, zeros elsewhere) with the
+    # V-cycle of the same block-diagonal hierarchy
+    _needs_gpu()
+    import scipy.sparse as sp
+    from paper_2508_17517_amd import BatchSolver
+    probs = _problems()
+    A = sp.csr_matrix(sp.block_diag([q.scipy() for q in probs]))
+    A.sort_indices()
+    pr = oracle.Params(outer=("fgmres", "richardson")[outer])
+    levels = oracle.setup(A, pr)
+    seg = np.concatenate([[0], np.cumsum([q.n for q in probs])])
+    its, xo = [], []
+    for k, q in enumerate(probs):
+        b = np.zeros(A.shape[0])
+        b[seg[k]:seg[k + 1]] = q.b
+        x, ik, rel, _, _ = oracle.solve(A, b, pr, levels)
+        its.append(ik)
+        xo.append(x[seg[k]:seg[k + 1]])
+    print("batch of", [q.n for q in probs], "outer", outer, "oracle its", its, flush=True)
+    s = BatchSolver([(q.indptr, q.indices, q.data) for q in probs], outer=outer)
+    xs, infos = s.solve([torch.from_numpy(q.b).cuda() for q in probs])
+    assert [i["iterations"] for i in infos] == its
+    for k, (x, i) in enumerate(zip(xs, infos)):
+        assert i["converged"] == 1
+        assert np.linalg.norm(x.cpu().numpy() - xo[k]) <= 1e-9 * np.linalg.norm(xo[k]), k
+    assert len(set(its)) >= 2
+    s.close()
+
+
 def test_problem_batch_of_one_matches_the_single_solver():
     # one problem: the same matrix, the same hierarchy, the same iterates
     _needs_gpu()
@@ -198,6 +231,13 @@ def test_batch_argument_errors():
     infos = (binding.SolveInfo * 2)()
     code = lib.airg_solve(s.h, 2, ctypes.c_void_p(B.data_ptr()), s.n,
                           ctypes.c_void_p(X.data_ptr()), s.n, 0, infos)
+    assert code == -1
+    # a batch handle takes its problems through airg_solve_batch only
+    code = lib.airg_solve(s.h, 1, ctypes.c_void_p(B.data_ptr()), s.n,
+                          ctypes.c_void_p(X.data_ptr()), s.n, 0, infos)
+    assert code == -1
+    code = lib.airg_adjoint_solve(s.h, 1, ctypes.c_void_p(B.data_ptr()), s.n,
+                                  ctypes.c_void_p(X.data_ptr()), s.n, 0, infos)
     assert code == -1
     q = probs[0]
     single = Solver(q.indptr, q.indices, q.data)
