@@ -458,7 +458,14 @@ void finalize_hierarchy(Hierarchy& H) {
   H.granges.clear();
   if (order) {
     key[0].alloc(H.n0, s);
-    locality_keys(H.A0, key[0].get(), s);
+    if (np > 1) {
+      // every problem of a batch at once
+      DBuf<int32_t> sid(H.n0, s);
+      segment_of_rows(H.seg, H.n0, sid.get(), s);
+      locality_keys_seg(H.A0, sid.get(), np, key[0].get(), s);
+    } else {
+      locality_keys(H.A0, key[0].get(), s);
+    }
     if (np > 1) {
       const int64_t m = (int64_t)max_key(key[0].get(), H.n0, s) + 1;
       if ((int64_t)np * m <= (int64_t)INT32_MAX) {
@@ -487,7 +494,8 @@ void finalize_hierarchy(Hierarchy& H) {
         pid.alloc(Lc.n, s);
         key_problems(key[nl - 1].get(), Lc.n, mult, pid.get(), s);
       }
-      locality_keys(Lc.A, key[nl - 1].get(), s);
+      if (mult) locality_keys_seg(Lc.A, pid.get(), np, key[nl - 1].get(), s);
+      else locality_keys(Lc.A, key[nl - 1].get(), s);
       if (mult) {
         const int64_t m = (int64_t)max_key(key[nl - 1].get(), Lc.n, s) + 1;
         if ((int64_t)np * m <= (int64_t)INT32_MAX) {

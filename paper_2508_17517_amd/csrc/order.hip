@@ -8,6 +8,8 @@
 // index), which keeps the gathers of every SpMV within a few neighbouring
 // stretches of the vector that stay in cache.  Coarse points inherit the key
 // of the fine point they are.
+#include <functional>
+
 #include "kernels.hpp"
 
 namespace airg {
@@ -261,6 +263,216 @@ void inherit_keys(const int32_t* key, const int64_t* clist, int64_t nc, int32_t*
   if (nc <= 0) return;
   inherit_key_kernel<<<blocks_for(nc, kBlock), kBlock, 0, s>>>(key, clist, nc, out);
   AIRG_CHECK_LAUNCH();
+}
+
+// ------------------------------------------------------------------ per-segment keys
+// The keys of a graph made of independent segments (the problems of a
+// batch: sid[i] is node i's segment, constant over long runs of indices)
+// are the keys above taken in every segment at once: each breadth-first
+// pass starts from one node per segment, and every choice of a start node
+// is made per segment.  The per-segment choices reduce packed (value,
+// index) words with atomics, first inside a wavefront whose lanes share a
+// segment, so the result does not depend on thread order.
+constexpr unsigned long long kNone = ~0ull;
+
+__device__ __forceinline__ void seg_atomic_min(unsigned long long* slot, int sid, unsigned long long v,
+                                               bool live) {
+  const int s0 = __shfl(sid, 0, 64);
+  const bool uniform = __all(sid == s0);
+  if (uniform) {
+    unsigned long long m = live ? v : kNone;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long u = __shfl_down(m, o, 64);
+      m = u < m ? u : m;
+    }
+    if ((threadIdx.x & 63) == 0 && m != kNone) atomicMin(slot + s0, m);
+  } else if (live) {
+    atomicMin(slot + sid, v);
+  }
+}
+__device__ __forceinline__ void seg_atomic_max(unsigned long long* slot, int sid, unsigned long long v,
+                                               bool live) {
+  const int s0 = __shfl(sid, 0, 64);
+  const bool uniform = __all(sid == s0);
+  if (uniform) {
+    unsigned long long m = live ? v : 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long u = __shfl_down(m, o, 64);
+      m = u > m ? u : m;
+    }
+    if ((threadIdx.x & 63) == 0 && m != 0ull) atomicMax(slot + s0, m);
+  } else if (live) {
+    atomicMax(slot + sid, v);
+  }
+}
+// smallest index per segment among the unreached nodes (all nodes when all)
+__global__ void seg_first_kernel(const int32_t* level, const int32_t* sid, int64_t n, int all,
+                                 unsigned long long* slot) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = i < n;
+  const int sg = in ? sid[i] : 0;
+  seg_atomic_min(slot, sg, (unsigned long long)i, in && (all || level[i] < 0));
+}
+// per segment, the node of largest level (ties: smallest index); with band,
+// only the nodes whose band value equals the segment's target count
+__global__ void seg_far_kernel(const int32_t* level, const int32_t* band, const int32_t* target,
+                               const int32_t* sid, int64_t n, unsigned long long* slot) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = i < n;
+  const int sg = in ? sid[i] : 0;
+  bool live = in && level[i] >= 0;
+  if (band && live) live = band[i] == target[sg];
+  const unsigned long long k =
+      live ? (((unsigned long long)(uint32_t)level[i] << 32) | (0xffffffffull - (uint64_t)i)) : 0ull;
+  seg_atomic_max(slot, sg, k, live);
+}
+// per segment, the smallest index on the segment's target level
+__global__ void seg_band_first_kernel(const int32_t* level, const int32_t* target, const int32_t* sid,
+                                      int64_t n, unsigned long long* slot) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = i < n;
+  const int sg = in ? sid[i] : 0;
+  seg_atomic_min(slot, sg, (unsigned long long)i, in && level[i] == target[sg]);
+}
+// start a frontier from a list of nodes at level v
+__global__ void seed_list_kernel(int32_t* level, const int32_t* seeds, int ns, int32_t v, int32_t* q,
+                                 int32_t* cnt, int slot) {
+  for (int t = threadIdx.x; t < ns; t += blockDim.x) {
+    level[seeds[t]] = v;
+    q[t] = seeds[t];
+  }
+  if (threadIdx.x == 0) {
+    cnt[0] = cnt[1] = cnt[2] = 0;
+    cnt[slot] = ns;
+  }
+}
+
+static std::vector<unsigned long long> seg_reduce(int nseg, unsigned long long init,
+                                                  const std::function<void(unsigned long long*)>& run,
+                                                  hipStream_t s) {
+  DBuf<unsigned long long> slot(nseg, s);
+  std::vector<unsigned long long> h(nseg, init);
+  slot.from_host(h.data(), nseg);
+  run(slot.get());
+  return slot.host(nseg);
+}
+
+// breadth-first levels from one start node per segment (none where -1);
+// unreached parts restart, every segment at once, from their smallest
+// index at the next step
+static void bfs_levels_seg(const CSR& A, const CSR& At, const std::vector<int32_t>& start,
+                           const int32_t* sid, int nseg, int32_t* level, hipStream_t s) {
+  const int64_t n = A.rows;
+  launch_fill_i32(level, n, -1, s);
+  DBuf<int32_t> qa(n, s), qb(n, s), cnt(3, s), sd(std::max(nseg, 1), s);
+  const unsigned nb = blocks_for(std::min<int64_t>(n, 256 * 1024), kBlock);
+  int32_t* q[2] = {qa.get(), qb.get()};
+  std::vector<int32_t> seeds;
+  for (int32_t v : start)
+    if (v >= 0) seeds.push_back(v);
+  int32_t d = 0;
+  for (;;) {
+    if (seeds.empty()) break;
+    sd.from_host(seeds.data(), seeds.size());
+    seed_list_kernel<<<1, 256, 0, s>>>(level, sd.get(), (int)seeds.size(), d, q[d & 1], cnt.get(),
+                                       d % 3);
+    AIRG_CHECK_LAUNCH();
+    for (;;) {
+      const int batch = 32;
+      for (int k = 0; k < batch; ++k, ++d) {
+        bfs_frontier_kernel<<<nb, kBlock, 0, s>>>(view(A), view(At), level, d, q[d & 1],
+                                                  q[(d + 1) & 1], cnt.get());
+        AIRG_CHECK_LAUNCH();
+      }
+      if (fetch(cnt.get() + d % 3, s) == 0) break;
+    }
+    // the frontier is empty: restart every segment that has unreached nodes
+    const std::vector<unsigned long long> first = seg_reduce(nseg, kNone, [&](unsigned long long* sl) {
+      seg_first_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(level, sid, n, 0, sl);
+      AIRG_CHECK_LAUNCH();
+    }, s);
+    seeds.clear();
+    for (unsigned long long f : first)
+      if (f != kNone) seeds.push_back((int32_t)f);
+  }
+}
+
+void locality_keys_seg(const CSR& A, const int32_t* sid, int nseg, int32_t* key, hipStream_t s) {
+  const int64_t n = A.rows;
+  if (n <= 0) return;
+  const unsigned nb = blocks_for(n, kBlock);
+  CSR At;
+  transpose(A, At, s);
+  DBuf<int32_t> d2(n, s), tgt(nseg, s);
+  auto unpack_index = [](unsigned long long k) { return (int32_t)(0xffffffffull - (k & 0xffffffffull)); };
+  auto far = [&](const int32_t* lv, const int32_t* band) {
+    return seg_reduce(nseg, 0ull, [&](unsigned long long* sl) {
+      seg_far_kernel<<<nb, kBlock, 0, s>>>(lv, band, tgt.get(), sid, n, sl);
+      AIRG_CHECK_LAUNCH();
+    }, s);
+  };
+  // from each segment's smallest index, then from the node farthest from it
+  std::vector<int32_t> start(nseg, -1);
+  {
+    const std::vector<unsigned long long> f = seg_reduce(nseg, kNone, [&](unsigned long long* sl) {
+      seg_first_kernel<<<nb, kBlock, 0, s>>>(key, sid, n, 1, sl);
+      AIRG_CHECK_LAUNCH();
+    }, s);
+    for (int g = 0; g < nseg; ++g) start[g] = f[g] == kNone ? -1 : (int32_t)f[g];
+  }
+  bfs_levels_seg(A, At, start, sid, nseg, key, s);
+  std::vector<unsigned long long> fk = far(key, nullptr);
+  for (int g = 0; g < nseg; ++g) start[g] = fk[g] ? unpack_index(fk[g]) : -1;
+  bfs_levels_seg(A, At, start, sid, nseg, key, s);  // d1
+  // an end of each segment's middle band
+  fk = far(key, nullptr);
+  std::vector<int32_t> mid(nseg, 0);
+  int32_t d1max = 0;
+  for (int g = 0; g < nseg; ++g) {
+    const int32_t m = fk[g] ? (int32_t)(fk[g] >> 32) : 0;
+    d1max = std::max(d1max, m);
+    mid[g] = m / 2;
+  }
+  tgt.from_host(mid.data(), nseg);
+  {
+    const std::vector<unsigned long long> f = seg_reduce(nseg, kNone, [&](unsigned long long* sl) {
+      seg_band_first_kernel<<<nb, kBlock, 0, s>>>(key, tgt.get(), sid, n, sl);
+      AIRG_CHECK_LAUNCH();
+    }, s);
+    for (int g = 0; g < nseg; ++g) start[g] = f[g] == kNone ? -1 : (int32_t)f[g];
+  }
+  bfs_levels_seg(A, At, start, sid, nseg, d2.get(), s);
+  fk = far(d2.get(), key);
+  for (int g = 0; g < nseg; ++g) start[g] = fk[g] ? unpack_index(fk[g]) : -1;
+  bfs_levels_seg(A, At, start, sid, nseg, d2.get(), s);  // d2
+  const int32_t d2max = fetch(d2.get() + far_node(d2.get(), n, s), s);
+  const int64_t mult = (int64_t)d2max + 1;
+  if (((int64_t)d1max + 1) * mult >= (int64_t)1 << 31) return;
+  combine_keys_kernel<<<nb, kBlock, 0, s>>>(key, d2.get(), n, mult);
+  AIRG_CHECK_LAUNCH();
+}
+
+__global__ void seg_of_rows_kernel(const int64_t* seg, int np, int64_t n, int32_t* sid) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int lo = 0, hi = np - 1;  // the largest p with seg[p] <= i
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (seg[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  sid[i] = lo;
+}
+void segment_of_rows(const std::vector<int64_t>& seg, int64_t n, int32_t* sid, hipStream_t s) {
+  const int np = (int)seg.size() - 1;
+  if (n <= 0 || np < 1) return;
+  DBuf<int64_t> sd(seg.size(), s);
+  sd.from_host(seg.data(), seg.size());
+  seg_of_rows_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(sd.get(), np, n, sid);
+  AIRG_CHECK_LAUNCH();
+  AIRG_HIP(hipStreamSynchronize(s));
 }
 
 // ------------------------------------------------------------------ problem-major keys
