@@ -132,9 +132,85 @@ __global__ void combine_keys_kernel(int32_t* d1, const int32_t* d2, int64_t n, i
   if (i < n) d1[i] = (int32_t)((int64_t)d1[i] * mult + d2[i]);
 }
 
+// Connected components of the graph of A + A^T: every node's label falls to
+// the smallest index of its component by hooking (an edge whose ends carry
+// different labels lowers the larger label's entry to the smaller) and
+// pointer jumping, repeated until no edge joins two labels.  The fixed point
+// does not depend on the order of the atomics.
+__global__ void cc_hook_kernel(CSRView A, int32_t* lab, int32_t* changed) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= A.rows) return;
+  bool any = false;
+  for (int p = A.rowptr[u]; p < A.rowptr[u + 1]; ++p) {
+    const int32_t lu = lab[u], lv = lab[A.col[p]];
+    if (lu == lv) continue;
+    atomicMin(&lab[lu > lv ? lu : lv], lu < lv ? lu : lv);
+    any = true;
+  }
+  if (any) atomicOr(changed, 1);
+}
+__global__ void cc_jump_kernel(int32_t* lab, int64_t n, int32_t* changed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t l = lab[i], ll = lab[l];
+  if (ll != l) {
+    lab[i] = ll;
+    atomicOr(changed, 1);
+  }
+}
+__global__ void cc_root_flag_kernel(const int32_t* lab, int64_t n, int64_t* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag[i] = lab[i] == i ? 1 : 0;
+}
+__global__ void cc_rank_kernel(const int32_t* lab, const int64_t* rank, int64_t n, int32_t* sid) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) sid[i] = (int32_t)rank[lab[i]];
+}
+// sid[i] = rank of i's component (components ordered by smallest index);
+// returns the number of components
+static int component_ids(const CSR& A, int32_t* sid, hipStream_t s) {
+  const int64_t n = A.rows;
+  const unsigned nb = blocks_for(n, kBlock);
+  DBuf<int32_t> flag(1, s);
+  launch_iota(sid, n, s);
+  for (;;) {
+    launch_fill_i32(flag.get(), 1, 0, s);
+    cc_hook_kernel<<<nb, kBlock, 0, s>>>(view(A), sid, flag.get());
+    AIRG_CHECK_LAUNCH();
+    const int32_t hooked = fetch(flag.get(), s);
+    for (;;) {
+      launch_fill_i32(flag.get(), 1, 0, s);
+      cc_jump_kernel<<<nb, kBlock, 0, s>>>(sid, n, flag.get());
+      AIRG_CHECK_LAUNCH();
+      if (!fetch(flag.get(), s)) break;
+    }
+    if (!hooked) break;
+  }
+  DBuf<int64_t> rk(n + 1, s), work(scan_work_size(n), s);
+  cc_root_flag_kernel<<<nb, kBlock, 0, s>>>(sid, n, rk.get());
+  AIRG_CHECK_LAUNCH();
+  launch_scan_i64(rk.get(), rk.get(), n, work.get(), s);
+  const int64_t nc = fetch(rk.get() + n, s);
+  cc_rank_kernel<<<nb, kBlock, 0, s>>>(sid, rk.get(), n, sid);
+  AIRG_CHECK_LAUNCH();
+  return (int)nc;
+}
+
 void locality_keys(const CSR& A, int32_t* key, hipStream_t s) {
   const int64_t n = A.rows;
   if (n <= 0) return;
+  // several components (a flow along the grid lines decouples them): the
+  // keys of every component at once, then component-major
+  {
+    DBuf<int32_t> sid(n, s);
+    const int nc = component_ids(A, sid.get(), s);
+    if (nc > 1) {
+      locality_keys_seg(A, sid.get(), nc, key, s);
+      const int64_t m = (int64_t)max_key(key, n, s) + 1;
+      if ((int64_t)nc * m <= (int64_t)INT32_MAX) problem_major_keys(key, sid.get(), n, m, s);
+      return;
+    }
+  }
   const unsigned nb = blocks_for(n, kBlock);
   CSR At;
   transpose(A, At, s);

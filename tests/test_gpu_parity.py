@@ -522,3 +522,27 @@ def test_c_point_smoothing_in_the_adjoint_and_problem_batches():
         assert i["converged"] == 1
         assert np.linalg.norm(q.b - q.scipy() @ xh) <= 1e-10 * (1 + 1e-6) * np.linalg.norm(q.b)
     sb.close()
+
+
+def test_decoupled_grid_lines_solve_exactly():
+    # theta = 0: every grid line is a separate component (the locality order
+    # handles them all at once).  The coarse spectrum is then one repeated
+    # block's, so the Newton roots are ill-conditioned and are not compared;
+    # the discrete setup decisions and the solve are
+    _needs_gpu()
+    p = workloads.fv_random(72, 0.0, True)
+    A = p.scipy()
+    xo, its, rel, levels, _ = oracle.solve(A, p.b)
+    s = _solver(p, keep_setup_data=1)
+    st = s.stats()
+    assert st["levels"] == len(levels)
+    for l, L in enumerate(levels[:-1]):
+        g = s.export_level(l)
+        assert np.array_equal(g["state"], L.state), f"level {l}: CF split differs"
+        _csr_equal("Z", g["z"], L.Z, l)
+    x, info = s.solve(torch.from_numpy(p.b).cuda())
+    assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
+    assert abs(info["iterations"] - its) <= 1
+    u = oracle.sweep_solve(A, p.b, p.level)
+    assert np.linalg.norm(x.cpu().numpy() - u) <= 1e-9 * np.linalg.norm(u)
+    s.close()
