@@ -459,10 +459,8 @@ void finalize_hierarchy(Hierarchy& H) {
   if (order) {
     key[0].alloc(H.n0, s);
     if (np > 1) {
-      // every problem of a batch at once
-      DBuf<int32_t> sid(H.n0, s);
-      segment_of_rows(H.seg, H.n0, sid.get(), s);
-      locality_keys_seg(H.A0, sid.get(), np, key[0].get(), s);
+      // every component of every problem at once
+      locality_keys_by_component(H.A0, key[0].get(), s);
     } else {
       locality_keys(H.A0, key[0].get(), s);
     }
@@ -494,7 +492,7 @@ void finalize_hierarchy(Hierarchy& H) {
         pid.alloc(Lc.n, s);
         key_problems(key[nl - 1].get(), Lc.n, mult, pid.get(), s);
       }
-      if (mult) locality_keys_seg(Lc.A, pid.get(), np, key[nl - 1].get(), s);
+      if (mult) locality_keys_by_component(Lc.A, key[nl - 1].get(), s);
       else locality_keys(Lc.A, key[nl - 1].get(), s);
       if (mult) {
         const int64_t m = (int64_t)max_key(key[nl - 1].get(), Lc.n, s) + 1;

@@ -261,10 +261,11 @@ void invert_perm(const int32_t* pos, int64_t n, int32_t* inv, hipStream_t s);
 // out[c] = key[clist[c]]
 void inherit_keys(const int32_t* key, const int64_t* clist, int64_t nc, int32_t* out, hipStream_t s);
 // The locality keys of a graph of independent segments (sid[i]: the segment
-// of node i), computed in every segment at once; the segment of every row
-// from the row segments seg.
+// of node i), computed in every segment at once.
 void locality_keys_seg(const CSR& A, const int32_t* sid, int nseg, int32_t* key, hipStream_t s);
-void segment_of_rows(const std::vector<int64_t>& seg, int64_t n, int32_t* sid, hipStream_t s);
+// The keys of every connected component at once, each component's from 0
+// (not component-major; a connected graph gets locality_keys).
+void locality_keys_by_component(const CSR& A, int32_t* key, hipStream_t s);
 // Problem-major keys of a block-diagonal batch (key = p * mult + key), by the
 // row segments seg (problem p: rows seg[p] .. seg[p+1]-1) or by a problem per
 // point; the problem of each key (key / mult); the number of points of each

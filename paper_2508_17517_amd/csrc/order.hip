@@ -530,25 +530,13 @@ void locality_keys_seg(const CSR& A, const int32_t* sid, int nseg, int32_t* key,
   AIRG_CHECK_LAUNCH();
 }
 
-__global__ void seg_of_rows_kernel(const int64_t* seg, int np, int64_t n, int32_t* sid) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int lo = 0, hi = np - 1;  // the largest p with seg[p] <= i
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (seg[mid] <= i) lo = mid;
-    else hi = mid - 1;
-  }
-  sid[i] = lo;
-}
-void segment_of_rows(const std::vector<int64_t>& seg, int64_t n, int32_t* sid, hipStream_t s) {
-  const int np = (int)seg.size() - 1;
-  if (n <= 0 || np < 1) return;
-  DBuf<int64_t> sd(seg.size(), s);
-  sd.from_host(seg.data(), seg.size());
-  seg_of_rows_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(sd.get(), np, n, sid);
-  AIRG_CHECK_LAUNCH();
-  AIRG_HIP(hipStreamSynchronize(s));
+void locality_keys_by_component(const CSR& A, int32_t* key, hipStream_t s) {
+  const int64_t n = A.rows;
+  if (n <= 0) return;
+  DBuf<int32_t> sid(n, s);
+  const int nc = component_ids(A, sid.get(), s);
+  if (nc > 1) locality_keys_seg(A, sid.get(), nc, key, s);
+  else locality_keys(A, key, s);
 }
 
 // ------------------------------------------------------------------ problem-major keys

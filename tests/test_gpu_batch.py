@@ -204,6 +204,24 @@ def test_problem_batch_runs_one_process_per_problem(outer):
     s.close()
 
 
+def test_problem_batch_with_decoupled_lines():
+    # a theta = 0 problem (one component per grid line) next to coupled ones:
+    # every problem still reaches the tolerance and its exact solution
+    _needs_gpu()
+    from paper_2508_17517_amd import BatchSolver
+    probs = [workloads.fv_random(96, 0.0, True, seed=301), workloads.fv_random(48, 0.5, True, seed=302),
+             workloads.fv_random(64, 0.0, False, seed=303, ny=40)]
+    s = BatchSolver([(q.indptr, q.indices, q.data) for q in probs])
+    xs, infos = s.solve([torch.from_numpy(q.b).cuda() for q in probs])
+    for q, x, i in zip(probs, xs, infos):
+        A = q.scipy()
+        xh = x.cpu().numpy()
+        assert i["converged"] == 1
+        u = oracle.sweep_solve(A, q.b, q.level)
+        assert np.linalg.norm(xh - u) <= 1e-8 * np.linalg.norm(u)
+    s.close()
+
+
 def test_problem_batch_of_one_matches_the_single_solver():
     # one problem: the same matrix, the same hierarchy, the same iterates
     _needs_gpu()
