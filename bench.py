@@ -96,15 +96,29 @@ def measured_traffic(workload):
     return float(vals["traffic_bytes_per_launch"])
 
 
-TUNE = {"on": True}
+TUNE = {"on": True, "file": None}
 
 
-def _tune(solver):
+def _tune(solver, main=False):
     """Pick the lanes per row of every solve operator by timing (airg_autotune)
-    unless --no-autotune; returns a summary."""
+    unless --no-autotune; returns a summary.  With --tune-file the main
+    solver's shapes are read from that file when it exists (and pinned, so a
+    profiled run launches the kernels an unprofiled run chose), else tuned
+    and written there."""
     if not TUNE["on"]:
         return None
+    path = TUNE["file"] if main else None
+    if path and os.path.exists(path):
+        with open(path) as f:
+            t = json.load(f)
+        for e in t:
+            solver.set_lanes(e["level"], e["op"], e["lanes"], e["xcd_map"], e["lds"])
+        print(f"bench: launch shapes pinned from {path}", file=sys.stderr, flush=True)
+        return {"operators": len(t), "pinned_from": os.path.basename(path)}
     t = solver.autotune(reps=10)
+    if path:
+        with open(path, "w") as f:
+            json.dump(t, f)
     for e in t:
         print(f"bench: tune level {e['level']:2d} {e['op']:3s} lanes {e['lanes']:2d} xcd {e['xcd_map']} "
               f"lds {e['lds']} {e['best_us']:8.2f} us (default {e['default_lanes']:2d}/"
@@ -394,6 +408,9 @@ def main():
     ap.add_argument("--no-dg", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-file", default=None,
+                    help="read the main solver's launch shapes from this JSON file if it "
+                         "exists, else tune and write them there")
     ap.add_argument("--batch-cols", type=int, default=64)
     ap.add_argument("--batch-problems", type=int, default=48)
     a = ap.parse_args()
@@ -423,7 +440,8 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     TUNE["on"] = not a.no_autotune
-    tune = _tune(s)
+    TUNE["file"] = a.tune_file
+    tune = _tune(s, main=True)
     print(f"bench: autotune {tune}", file=sys.stderr, flush=True)
     st = s.stats()
     for l in range(st["levels"]):
