@@ -52,7 +52,7 @@ static CSRT<MV, C16> csr_t(const OpView& A) {
 // so a row costs two dependent memory round trips per U entries instead of
 // two per entry.  The additions keep the lane's ascending entry order.
 template <int TPR>
-constexpr int unroll_for() { return TPR >= 16 ? 8 : 4; }
+constexpr int unroll_for() { return 4; }
 
 // Column index transforms for row_dot: the CSR column itself, or the column
 // looked up in a map (entries whose mapped index is negative are skipped).
@@ -146,7 +146,44 @@ __device__ __forceinline__ void column_pair(const CSRT<MV, C16>& A, int q, int b
 }
 // The pairs of entries [s, e) that a lane owns, gathered through gx: with
 // OFF the gather index is the raw 16-bit offset (x staged in LDS from the
-// row's base), else the column.
+// row's base), else the column.  load_pairs fetches the U pairs of one step
+// (q0, q0 + TPR, ...) and add_pairs gathers and adds them in ascending order.
+template <int TPR, int U, bool OFF, class MV, bool C16, class X>
+__device__ __forceinline__ void load_pairs(const CSRT<MV, C16>& A, int q0, int qe, int s, int e,
+                                           int b, int (&c0)[U], int (&c1)[U], X (&v0)[U],
+                                           X (&v1)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = q0 + u * TPR;
+    c0[u] = -1;
+    c1[u] = -1;
+    v0[u] = X(0);
+    v1[u] = X(0);
+    if (q < qe) {
+      load_pair<X>(A.val, q, v0[u], v1[u]);
+      column_pair(A, q, OFF ? 0 : b, c0[u], c1[u]);
+      if (2 * q < s) c0[u] = -1;
+      if (2 * q + 1 >= e) c1[u] = -1;
+    }
+  }
+}
+template <int U, class X>
+__device__ __forceinline__ X add_pairs(const X* __restrict__ gx, const int (&c0)[U],
+                                       const int (&c1)[U], const X (&v0)[U], const X (&v1)[U],
+                                       X sum) {
+  X x0[U], x1[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    x0[u] = c0[u] >= 0 ? gx[c0[u]] : X(0);
+    x1[u] = c1[u] >= 0 ? gx[c1[u]] : X(0);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (c0[u] >= 0) sum = sum + v0[u] * x0[u];
+    if (c1[u] >= 0) sum = sum + v1[u] * x1[u];
+  }
+  return sum;
+}
 template <int TPR, int U, bool OFF, class MV, bool C16, class X>
 __device__ __forceinline__ X row_dot_pairs_cols(const CSRT<MV, C16>& A, int s, int e, int b,
                                                 int lane, const X* __restrict__ gx, X sum) {
@@ -154,31 +191,8 @@ __device__ __forceinline__ X row_dot_pairs_cols(const CSRT<MV, C16>& A, int s, i
   for (int q0 = (s >> 1) + lane; q0 < qe; q0 += TPR * U) {
     int c0[U], c1[U];
     X v0[U], v1[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int q = q0 + u * TPR;
-      c0[u] = -1;
-      c1[u] = -1;
-      v0[u] = X(0);
-      v1[u] = X(0);
-      if (q < qe) {
-        load_pair<X>(A.val, q, v0[u], v1[u]);
-        column_pair(A, q, OFF ? 0 : b, c0[u], c1[u]);
-        if (2 * q < s) c0[u] = -1;
-        if (2 * q + 1 >= e) c1[u] = -1;
-      }
-    }
-    X x0[U], x1[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      x0[u] = c0[u] >= 0 ? gx[c0[u]] : X(0);
-      x1[u] = c1[u] >= 0 ? gx[c1[u]] : X(0);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (c0[u] >= 0) sum = sum + v0[u] * x0[u];
-      if (c1[u] >= 0) sum = sum + v1[u] * x1[u];
-    }
+    load_pairs<TPR, U, OFF>(A, q0, qe, s, e, b, c0, c1, v0, v1);
+    sum = add_pairs<U>(gx, c0, c1, v0, v1, sum);
   }
   return sum;
 }
@@ -356,17 +370,25 @@ __global__ __launch_bounds__(64 * TPR) void spmv_lds_kernel(CSRT<MV, true> A,
     s = A.rowptr[row];
     e = A.rowptr[row + 1];
   }
+  X sum = 0;
+  constexpr int U = unroll_for<TPR>();
   if (staged) {
+    // the lane's first U pairs are loaded before the x window, so the two
+    // memory round trips overlap; the LDS gathers wait for the barrier
+    const int qe = (e + 1) >> 1;
+    int q0 = (s >> 1) + lane;
+    int c0[U], c1[U];
+    X v0[U], v1[U];
+    load_pairs<TPR, U, true>(A, q0, qe, s, e, 0, c0, c1, v0, v1);
     for (int i = t; i < span; i += 64 * TPR) xs[i] = x[base + i];
     __syncthreads();
-  }
-  X sum = 0;
-  // LDS gathers are short: four pairs per lane in flight suffice (the order of
-  // a lane's entries, and so the result, does not depend on U)
-  constexpr int U = 4;
-  if (live) {
-    if (staged) sum = row_dot_pairs_cols<TPR, U, true>(A, s, e, 0, lane, (const X*)xs, sum);
-    else sum = row_dot_pairs<TPR, U>(A, s, e, base, lane, x, sum);
+    sum = add_pairs<U>((const X*)xs, c0, c1, v0, v1, sum);
+    for (q0 += TPR * U; q0 < qe; q0 += TPR * U) {
+      load_pairs<TPR, U, true>(A, q0, qe, s, e, 0, c0, c1, v0, v1);
+      sum = add_pairs<U>((const X*)xs, c0, c1, v0, v1, sum);
+    }
+  } else if (live) {
+    sum = row_dot_pairs<TPR, U>(A, s, e, base, lane, x, sum);
   }
   if constexpr (TPR > 1) {
 #pragma unroll
