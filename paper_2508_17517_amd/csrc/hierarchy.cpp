@@ -446,8 +446,8 @@ void finalize_hierarchy(Hierarchy& H) {
   hipStream_t s = H.s;
   const int nl = (int)H.levels.size();
   const bool order = H.p.locality_order != 0;
-  // locality keys, top down: two breadth-first distances on A_0 + A_0^T,
-  // inherited by the coarse points
+  // locality keys, top down: the Hilbert index of two breadth-first
+  // distances on A_0 + A_0^T, inherited by the coarse points
   std::vector<DBuf<int32_t>> key(nl);
   // a batch orders every level problem-major (key = problem * mult + key), so
   // that each problem's unknowns form ranges of the nested numbering; mult
@@ -460,9 +460,9 @@ void finalize_hierarchy(Hierarchy& H) {
     key[0].alloc(H.n0, s);
     if (np > 1) {
       // every component of every problem at once
-      locality_keys_by_component(H.A0, key[0].get(), s);
+      locality_keys_by_component(H.A0, key[0].get(), s, true);
     } else {
-      locality_keys(H.A0, key[0].get(), s);
+      locality_keys(H.A0, key[0].get(), s, true);
     }
     if (np > 1) {
       const int64_t m = (int64_t)max_key(key[0].get(), H.n0, s) + 1;
@@ -492,8 +492,8 @@ void finalize_hierarchy(Hierarchy& H) {
         pid.alloc(Lc.n, s);
         key_problems(key[nl - 1].get(), Lc.n, mult, pid.get(), s);
       }
-      if (mult) locality_keys_by_component(Lc.A, key[nl - 1].get(), s);
-      else locality_keys(Lc.A, key[nl - 1].get(), s);
+      if (mult) locality_keys_by_component(Lc.A, key[nl - 1].get(), s, false);
+      else locality_keys(Lc.A, key[nl - 1].get(), s, false);
       if (mult) {
         const int64_t m = (int64_t)max_key(key[nl - 1].get(), Lc.n, s) + 1;
         if ((int64_t)np * m <= (int64_t)INT32_MAX) {

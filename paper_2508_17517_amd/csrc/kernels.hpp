@@ -249,11 +249,15 @@ int64_t far_node(const int32_t* level, int64_t n, hipStream_t s);
 // rank[f] = position of F point f ordered by (key, F index).
 void rank_f_points(const int8_t* state, const int64_t* fidx, const int32_t* key, int64_t n,
                    int64_t nf, int32_t* rank, hipStream_t s);
-// Locality key of every node of A: with d1 the BFS distance from a far node
-// and d2 the distance from an end of d1's middle band, key = d1 * (max d2 + 1)
-// + d2 (d1 alone if that overflows 31 bits).  On a structured grid this
-// orders by anti-diagonal, then by position along it.
-void locality_keys(const CSR& A, int32_t* key, hipStream_t s);
+// Locality key of every node of A, from d1, the BFS distance from a far node,
+// and d2, the distance from an end of d1's middle band.  With hilbert the key
+// is the index of (d1, d2) along a Hilbert curve (distances below 2^15), which
+// keeps 2D neighbourhoods together at every scale: the order whose keys the
+// coarse levels inherit.  Otherwise, or when the distances are larger, key =
+// d1 * (max d2 + 1) + d2 (d1 alone if that overflows 31 bits): on a structured
+// grid, by anti-diagonal, then by position along it, which keeps the columns
+// of 64 consecutive rows in one narrow window.
+void locality_keys(const CSR& A, int32_t* key, hipStream_t s, bool hilbert);
 // rank[i] = position of node i ordered by (key, i).
 void rank_points(const int32_t* key, int64_t n, int32_t* rank, hipStream_t s);
 // inv[pos[i]] = i
@@ -262,10 +266,11 @@ void invert_perm(const int32_t* pos, int64_t n, int32_t* inv, hipStream_t s);
 void inherit_keys(const int32_t* key, const int64_t* clist, int64_t nc, int32_t* out, hipStream_t s);
 // The locality keys of a graph of independent segments (sid[i]: the segment
 // of node i), computed in every segment at once.
-void locality_keys_seg(const CSR& A, const int32_t* sid, int nseg, int32_t* key, hipStream_t s);
+void locality_keys_seg(const CSR& A, const int32_t* sid, int nseg, int32_t* key, hipStream_t s,
+                       bool hilbert);
 // The keys of every connected component at once, each component's from 0
 // (not component-major; a connected graph gets locality_keys).
-void locality_keys_by_component(const CSR& A, int32_t* key, hipStream_t s);
+void locality_keys_by_component(const CSR& A, int32_t* key, hipStream_t s, bool hilbert);
 // Problem-major keys of a block-diagonal batch (key = p * mult + key), by the
 // row segments seg (problem p: rows seg[p] .. seg[p+1]-1) or by a problem per
 // point; the problem of each key (key / mult); the number of points of each

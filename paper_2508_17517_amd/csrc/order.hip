@@ -7,7 +7,14 @@
 // made of two breadth-first distances on the graph of A + A^T (ties by
 // index), which keeps the gathers of every SpMV within a few neighbouring
 // stretches of the vector that stay in cache.  Coarse points inherit the key
-// of the fine point they are.
+// of the fine point they are.  The two distances act as coordinates of the
+// grid, and the inherited key is the point's index along a Hilbert curve
+// through them: points near each other in both distances stay near each
+// other in the order at every scale, so the rows of a coarse level, whose
+// couplings reach many fine grid lines, still gather from a few cache lines
+// each.  The coarsest level, ordered by its own graph for its LDS-staged
+// products, takes the anti-diagonal key, whose 64-row groups span one
+// narrow window of columns.
 #include <functional>
 
 #include "kernels.hpp"
@@ -131,6 +138,51 @@ __global__ void combine_keys_kernel(int32_t* d1, const int32_t* d2, int64_t n, i
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d1[i] = (int32_t)((int64_t)d1[i] * mult + d2[i]);
 }
+// Index of cell (x, y) along the Hilbert curve over a side x side square
+// (side a power of two): at each scale the quadrant's place in the curve's
+// visiting order is added, and the coordinates are turned into that
+// quadrant's frame (flipped and/or transposed), so that the curve enters
+// every sub-square where the previous one left it.
+__device__ __forceinline__ uint32_t hilbert_index(uint32_t side, uint32_t x, uint32_t y) {
+  uint32_t d = 0;
+  for (uint32_t h = side >> 1; h > 0; h >>= 1) {
+    const uint32_t rx = (x & h) ? 1u : 0u, ry = (y & h) ? 1u : 0u;
+    d += h * h * ((3u * rx) ^ ry);
+    if (ry == 0) {
+      if (rx == 1) {
+        x = side - 1 - x;
+        y = side - 1 - y;
+      }
+      const uint32_t t = x;
+      x = y;
+      y = t;
+    }
+  }
+  return d;
+}
+__global__ void hilbert_keys_kernel(int32_t* d1, const int32_t* d2, int64_t n, uint32_t side) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d1[i] = (int32_t)hilbert_index(side, (uint32_t)d1[i], (uint32_t)d2[i]);
+}
+// key = Hilbert index of (d1, d2) when asked for and both distances are below
+// 2^15 (the index then fits 30 bits), else d1 * (d2max + 1) + d2 when that
+// fits 31 bits; otherwise the key stays d1
+static void combine_keys(int32_t* key, const int32_t* d2, int64_t n, int32_t d1max,
+                         int32_t d2max, bool hilbert, hipStream_t s) {
+  const unsigned nb = blocks_for(n, kBlock);
+  const int32_t dm = std::max(d1max, d2max);
+  if (hilbert && dm < (1 << 15)) {
+    uint32_t side = 1;
+    while (side <= (uint32_t)dm) side <<= 1;
+    hilbert_keys_kernel<<<nb, kBlock, 0, s>>>(key, d2, n, side);
+    AIRG_CHECK_LAUNCH();
+    return;
+  }
+  const int64_t mult = (int64_t)d2max + 1;
+  if (((int64_t)d1max + 1) * mult >= (int64_t)1 << 31) return;
+  combine_keys_kernel<<<nb, kBlock, 0, s>>>(key, d2, n, mult);
+  AIRG_CHECK_LAUNCH();
+}
 
 // Connected components of the graph of A + A^T: every node's label falls to
 // the smallest index of its component by hooking (an edge whose ends carry
@@ -196,7 +248,7 @@ static int component_ids(const CSR& A, int32_t* sid, hipStream_t s) {
   return (int)nc;
 }
 
-void locality_keys(const CSR& A, int32_t* key, hipStream_t s) {
+void locality_keys(const CSR& A, int32_t* key, hipStream_t s, bool hilbert) {
   const int64_t n = A.rows;
   if (n <= 0) return;
   // several components (a flow along the grid lines decouples them): the
@@ -205,7 +257,7 @@ void locality_keys(const CSR& A, int32_t* key, hipStream_t s) {
     DBuf<int32_t> sid(n, s);
     const int nc = component_ids(A, sid.get(), s);
     if (nc > 1) {
-      locality_keys_seg(A, sid.get(), nc, key, s);
+      locality_keys_seg(A, sid.get(), nc, key, s, hilbert);
       const int64_t m = (int64_t)max_key(key, n, s) + 1;
       if ((int64_t)nc * m <= (int64_t)INT32_MAX) problem_major_keys(key, sid.get(), n, m, s);
       return;
@@ -238,10 +290,7 @@ void locality_keys(const CSR& A, int32_t* key, hipStream_t s) {
   const int64_t f2 = (int64_t)(0xffffffffull - (fetch(red.get(), s) & 0xffffffffull));
   bfs_levels(A, At, f2, d2.get(), s);
   const int32_t d2max = fetch(d2.get() + far_node(d2.get(), n, s), s);
-  const int64_t mult = (int64_t)d2max + 1;
-  if (((int64_t)d1max + 1) * mult >= (int64_t)1 << 31) return;
-  combine_keys_kernel<<<nb, kBlock, 0, s>>>(key, d2.get(), n, mult);
-  AIRG_CHECK_LAUNCH();
+  combine_keys(key, d2.get(), n, d1max, d2max, hilbert, s);
 }
 
 // ------------------------------------------------------------------ ranking
@@ -475,7 +524,8 @@ static void bfs_levels_seg(const CSR& A, const CSR& At, const std::vector<int32_
   }
 }
 
-void locality_keys_seg(const CSR& A, const int32_t* sid, int nseg, int32_t* key, hipStream_t s) {
+void locality_keys_seg(const CSR& A, const int32_t* sid, int nseg, int32_t* key, hipStream_t s,
+                       bool hilbert) {
   const int64_t n = A.rows;
   if (n <= 0) return;
   const unsigned nb = blocks_for(n, kBlock);
@@ -524,19 +574,16 @@ void locality_keys_seg(const CSR& A, const int32_t* sid, int nseg, int32_t* key,
   for (int g = 0; g < nseg; ++g) start[g] = fk[g] ? unpack_index(fk[g]) : -1;
   bfs_levels_seg(A, At, start, sid, nseg, d2.get(), s);  // d2
   const int32_t d2max = fetch(d2.get() + far_node(d2.get(), n, s), s);
-  const int64_t mult = (int64_t)d2max + 1;
-  if (((int64_t)d1max + 1) * mult >= (int64_t)1 << 31) return;
-  combine_keys_kernel<<<nb, kBlock, 0, s>>>(key, d2.get(), n, mult);
-  AIRG_CHECK_LAUNCH();
+  combine_keys(key, d2.get(), n, d1max, d2max, hilbert, s);
 }
 
-void locality_keys_by_component(const CSR& A, int32_t* key, hipStream_t s) {
+void locality_keys_by_component(const CSR& A, int32_t* key, hipStream_t s, bool hilbert) {
   const int64_t n = A.rows;
   if (n <= 0) return;
   DBuf<int32_t> sid(n, s);
   const int nc = component_ids(A, sid.get(), s);
-  if (nc > 1) locality_keys_seg(A, sid.get(), nc, key, s);
-  else locality_keys(A, key, s);
+  if (nc > 1) locality_keys_seg(A, sid.get(), nc, key, s, hilbert);
+  else locality_keys(A, key, s, hilbert);
 }
 
 // ------------------------------------------------------------------ problem-major keys
