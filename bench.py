@@ -64,6 +64,21 @@ def copy_bandwidth(nbytes=1 << 30, reps=10):
     return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
+def read_bandwidth(nbytes=1 << 31, reps=10):
+    """Read-only bandwidth of a plain device reduction over nbytes: the
+    practical ceiling of kernels that, like the products, mostly read."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    src.sum()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        src.sum()
+    e1.record()
+    e1.synchronize()
+    return 1.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fv2048_poly_hbm_traffic.md")
 # sources that decide the poly-SpMV launches and their operators
 TRAFFIC_SOURCES = ["spmv.hip", "hierarchy.cpp", "solve.cpp", "order.hip", "spgemm.hip",
@@ -527,7 +542,9 @@ def main():
     if not a.no_paper:
         out["paper_fd"] = optional("paper", paper_legs, a)
     out["hbm_copy_gbps"] = copy_bandwidth()
-    print(f"bench: copy kernel {out['hbm_copy_gbps']:.1f} GB/s", file=sys.stderr, flush=True)
+    out["hbm_read_gbps"] = read_bandwidth()
+    print(f"bench: copy kernel {out['hbm_copy_gbps']:.1f} GB/s, read-only reduction "
+          f"{out['hbm_read_gbps']:.1f} GB/s", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.cpu_sample)
