@@ -368,12 +368,26 @@ def test_assembled_smoother_matches_oracle(case):
     s.close()
 
 
+def _permuted_chain(n, seed):
+    r = np.random.default_rng(seed)
+    B = sp.diags([np.full(n, 2.0), np.full(n - 1, -1.0)], [0, -1]).tocsr()
+    q = r.permutation(n)
+    P = sp.csr_matrix((np.ones(n), (np.arange(n), q)), shape=(n, n))
+    return sp.csr_matrix(P @ B @ P.T), r.uniform(size=n)
+
+
 DEGENERATE = {
     "1x1": lambda: (sp.csr_matrix(np.array([[2.0]])), np.array([4.0])),
     "2x2_lower": lambda: (sp.csr_matrix(np.array([[2.0, 0.0], [-1.0, 3.0]])), np.array([1.0, 2.0])),
     "diagonal_100": lambda: (sp.diags(np.arange(1.0, 101.0)).tocsr(), np.ones(100)),
     "bidiagonal_300": lambda: (sp.csr_matrix(sp.diags([np.full(300, 2.0), np.full(299, -1.0)],
                                                        [0, -1])), np.ones(300)),
+    # permuted chains whose breadth-first distances pass 2^15: the locality
+    # key falls back from the Hilbert index to d1 (max d2 + 1) + d2 (40,000:
+    # d1 < 40,000, d2 < 20,001) and to d1 alone (70,000, where that product
+    # passes 2^31)
+    "chain_40000_perm": lambda: _permuted_chain(40000, 5),
+    "chain_70000_perm": lambda: _permuted_chain(70000, 6),
 }
 
 
