@@ -77,8 +77,10 @@ struct GroupItems {
   int64_t n = 0;  // items
   int G = 0;      // problems
 };
+// chunk: the item length (1024 for the dot and update kernels, 256 for the
+// fused sweeps)
 void build_group_items(const std::vector<GroupRange>& ranges, int G, GroupItems& out,
-                       hipStream_t s);
+                       hipStream_t s, int chunk = 1024);
 size_t group_dots_work_size(const GroupItems& it);
 void launch_group_dots(const double* V, int64_t ldv, int nv, const double* w, const GroupItems& it,
                        double* out, double* work, hipStream_t s);
@@ -88,6 +90,18 @@ void launch_group_combine(double* x, const double* Z, int64_t ldz, const double*
                           const GroupItems& it, hipStream_t s);
 void launch_group_divide(double* y, const double* x, const double* d, const GroupItems& it,
                          hipStream_t s);
+// Most basis vectors the fused Gram-Schmidt sweeps take (one register each).
+constexpr int kFusedVecs = 32;
+// The fused Gram-Schmidt sweeps per problem, on items of at most 256
+// elements (build_group_items with chunk 256): w = w - sum_k h[k, g] V_k,
+// then out[k, g] = V_k . w (update_dots) or out[0, g] = w . w (update_norm2)
+// over problem g, each summed in a fixed order.  1 to 32 basis vectors;
+// `work` needs group_fused_work_size(items) doubles.
+size_t group_fused_work_size(const GroupItems& it);
+void launch_group_update_dots(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                              const GroupItems& it, double* out, double* work, hipStream_t s);
+void launch_group_update_norm2(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                               const GroupItems& it, double* out, double* work, hipStream_t s);
 // out[0] = sqrt(out[0]) on the device
 void launch_sqrt_inplace(double* v, hipStream_t s);
 

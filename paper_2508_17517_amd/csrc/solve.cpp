@@ -90,6 +90,8 @@ void workspace_init(const Hierarchy& H, Workspace& W, int K) {
   if (K == 1 && np > 0 && !H.granges.empty()) {
     build_group_items(H.granges, np, W.gitems, s);
     W.gdot_work.alloc(group_dots_work_size(W.gitems), s);
+    build_group_items(H.granges, np, W.gitems_f, s, 256);
+    W.gfused_work.alloc(group_fused_work_size(W.gitems_f), s);
     W.cdiv.alloc(np, s);
   }
   const size_t ng = std::max<size_t>((size_t)K, H.seg.empty() ? 1 : H.seg.size());
@@ -417,6 +419,25 @@ struct Procs {
     if (cols) launch_cgs_update_cols(w, V, ld, h, nv, H.n0, W.K, H.s);
     else launch_group_update(w, V, ld, h, nv, W.gitems, H.s);
   }
+  // w = w - V h, then the next sweep's coefficients (one pass over the basis
+  // where a fused kernel exists)
+  void update_dots(double* w, const double* V, int64_t ld, const double* h, int nv, double* out) {
+    if (!cols && nv <= kFusedVecs) {
+      launch_group_update_dots(w, V, ld, h, nv, W.gitems_f, out, W.gfused_work.get(), H.s);
+      return;
+    }
+    update(w, V, ld, h, nv);
+    dots(V, ld, nv, w, out);
+  }
+  // w = w - V h, then w . w
+  void update_sumsq(double* w, const double* V, int64_t ld, const double* h, int nv, double* out) {
+    if (!cols && nv <= kFusedVecs) {
+      launch_group_update_norm2(w, V, ld, h, nv, W.gitems_f, out, W.gfused_work.get(), H.s);
+      return;
+    }
+    update(w, V, ld, h, nv);
+    sumsq(w, out);
+  }
   void sumsq(const double* v, double* out) {
     if (cols) launch_col_sumsq(v, H.n0, W.K, out, W.col_work.get(), H.s);
     else launch_group_dots(v, 0, 1, v, W.gitems, out, W.gdot_work.get(), H.s);
@@ -546,10 +567,8 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
         double* h2 = hd + (size_t)(R + 1) * G;
         double* hn2 = hd + (size_t)2 * (R + 1) * G;
         P.dots(V, ld, j + 1, W.w.get(), h1);
-        P.update(W.w.get(), V, ld, h1, j + 1);
-        P.dots(V, ld, j + 1, W.w.get(), h2);
-        P.update(W.w.get(), V, ld, h2, j + 1);
-        P.sumsq(W.w.get(), hn2);
+        P.update_dots(W.w.get(), V, ld, h1, j + 1, h2);
+        P.update_sumsq(W.w.get(), V, ld, h2, j + 1, hn2);
         W.hbuf.to_host(hh.data(), (size_t)(2 * (R + 1) + 1) * G);
         AIRG_HIP(hipStreamSynchronize(s));
         bool more = false;
@@ -748,7 +767,7 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
         // CGS2: h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; |w|^2, the
         // second and third sweeps each fused with the reduction after them
         dots(V, ld, j + 1, W.w.get(), n, hd, W, s);
-        if (j + 1 <= 32) {
+        if (j + 1 <= kFusedVecs) {
           launch_cgs_update_dots(W.w.get(), V, ld, hd, j + 1, n, hd + (R + 1), W.fused_work.get(), s);
           launch_cgs_update_norm2(W.w.get(), V, ld, hd + (R + 1), j + 1, n, hd + 2 * (R + 1),
                                   W.fused_work.get(), s);

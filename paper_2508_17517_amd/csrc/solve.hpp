@@ -25,6 +25,8 @@ struct Workspace {
   DBuf<double> fused_work;       // partials of the fused Gram-Schmidt sweeps (K = 1)
   GroupItems gitems;             // per-problem work items of a batch (K = 1)
   DBuf<double> gdot_work;
+  GroupItems gitems_f;           // the same ranges in items of 256, for the fused sweeps
+  DBuf<double> gfused_work;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   ~Workspace();
 };

@@ -245,7 +245,6 @@ void launch_sqrt_inplace(double* v, hipStream_t s) {
 // basis is read once instead of twice.  One element per thread: block b
 // reduces elements b * 256 .. b * 256 + 255 by the shuffle tree and its four
 // waves in pairs, and the block partials of each k by the tree sum.
-constexpr int kFusedVecs = 32;
 
 // w = w - sum_k h[k] V_k, then the products V_k . w (DOTS) or w . w; NV basis
 // vectors, a compile-time count so that every load is issued unconditionally
@@ -459,13 +458,14 @@ void launch_col_dots(const double* V, int64_t ldv, int nv, const double* w, int6
 // q covers elements start[q] .. start[q] + len[q] - 1 (len <= kDotChunk) of
 // problem grp[q]; coefficient arrays hold entry (k, g) at k G + g.
 void build_group_items(const std::vector<GroupRange>& ranges, int G, GroupItems& out,
-                       hipStream_t s) {
+                       hipStream_t s, int chunk) {
+  if (chunk < 1 || chunk > kDotChunk) fail(AIRG_ERR_INTERNAL, "item length must be 1..1024");
   std::vector<int64_t> st;
   std::vector<int32_t> ln, gp;
   for (const GroupRange& r : ranges)
-    for (int64_t a = 0; a < r.len; a += kDotChunk) {
+    for (int64_t a = 0; a < r.len; a += chunk) {
       st.push_back(r.start + a);
-      ln.push_back((int32_t)std::min<int64_t>(kDotChunk, r.len - a));
+      ln.push_back((int32_t)std::min<int64_t>(chunk, r.len - a));
       gp.push_back(r.group);
     }
   // items of each problem in list order: the fixed order of its sums
@@ -606,6 +606,76 @@ void launch_group_divide(double* y, const double* x, const double* d, const Grou
   group_divide_kernel<<<(unsigned)it.n, 256, 0, s>>>(y, x, d, it.start.get(), it.len.get(),
                                                       it.grp.get());
   AIRG_CHECK_LAUNCH();
+}
+
+// The fused sweeps of cgs_fused_kernel per problem: block q takes item q (at
+// most 256 elements of problem grp[q], one per thread), updates w with that
+// problem's coefficients, and leaves the item's partial products, which
+// group_sum_kernel adds per problem in list order.
+template <bool DOTS, int NV>
+__global__ __launch_bounds__(256) void group_fused_kernel(
+    double* __restrict__ w, const double* __restrict__ V, int64_t ldv, const double* __restrict__ h,
+    int G, const int64_t* __restrict__ start, const int32_t* __restrict__ len,
+    const int32_t* __restrict__ grp, double* __restrict__ part, int64_t nq) {
+  constexpr int CNT = DOTS ? NV : 1;
+  __shared__ double red[CNT][4];
+  const int t = threadIdx.x;
+  const int64_t b = start[blockIdx.x];
+  const int g = grp[blockIdx.x];
+  const bool in = t < len[blockIdx.x];
+  const int64_t i = in ? b + t : b;  // in-range address for the padding lanes
+  double v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = V[(int64_t)k * ldv + i];
+  double wi = w[i];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) wi = wi - h[(int64_t)k * G + g] * v[k];
+  if (in) w[i] = wi;
+  const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int k = 0; k < CNT; ++k) {
+    const double s = wave_tree(in ? (DOTS ? v[k] * wi : wi * wi) : 0.0);
+    if (lane == 0) red[k][wave] = s;
+  }
+  __syncthreads();
+  if (t < CNT) part[(int64_t)t * nq + blockIdx.x] = (red[t][0] + red[t][1]) + (red[t][2] + red[t][3]);
+}
+
+template <bool DOTS, int NV>
+static void launch_group_fused_nv(int nv, double* w, const double* V, int64_t ldv, const double* h,
+                                  const GroupItems& it, double* part, hipStream_t s) {
+  if constexpr (NV > kFusedVecs) {
+    fail(AIRG_ERR_INTERNAL, "fused Gram-Schmidt takes 1 to 32 vectors");
+  } else {
+    if (nv != NV) return launch_group_fused_nv<DOTS, NV + 1>(nv, w, V, ldv, h, it, part, s);
+    group_fused_kernel<DOTS, NV><<<(unsigned)it.n, 256, 0, s>>>(
+        w, V, ldv, h, it.G, it.start.get(), it.len.get(), it.grp.get(), part, it.n);
+  }
+}
+
+size_t group_fused_work_size(const GroupItems& it) {
+  return (size_t)kFusedVecs * (size_t)std::max<int64_t>(it.n, 1);
+}
+
+static void launch_group_fused(bool dots, double* w, const double* V, int64_t ldv, const double* h,
+                               int nv, const GroupItems& it, double* out, double* work,
+                               hipStream_t s) {
+  if (nv < 1 || nv > kFusedVecs) fail(AIRG_ERR_INTERNAL, "fused Gram-Schmidt takes 1 to 32 vectors");
+  if (it.n <= 0) return;
+  if (dots) launch_group_fused_nv<true, 1>(nv, w, V, ldv, h, it, work, s);
+  else launch_group_fused_nv<false, 1>(nv, w, V, ldv, h, it, work, s);
+  AIRG_CHECK_LAUNCH();
+  group_sum_kernel<<<dim3((unsigned)it.G, (unsigned)(dots ? nv : 1)), 256, 0, s>>>(
+      work, it.n, it.gptr.get(), it.glist.get(), it.G, out);
+  AIRG_CHECK_LAUNCH();
+}
+void launch_group_update_dots(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                              const GroupItems& it, double* out, double* work, hipStream_t s) {
+  launch_group_fused(true, w, V, ldv, h, nv, it, out, work, s);
+}
+void launch_group_update_norm2(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                               const GroupItems& it, double* out, double* work, hipStream_t s) {
+  launch_group_fused(false, w, V, ldv, h, nv, it, out, work, s);
 }
 
 // ------------------------------------------------------------------ permutations
