@@ -92,6 +92,16 @@ void launch_group_divide(double* y, const double* x, const double* d, const Grou
                          hipStream_t s);
 // Most basis vectors the fused Gram-Schmidt sweeps take (one register each).
 constexpr int kFusedVecs = 32;
+// The fused Gram-Schmidt sweeps per column of K interleaved columns:
+// w = w - sum_k h[k K + c] V_k, then out[k K + c] = V_k . w over column c
+// (update_dots, summed as launch_col_dots sums) or out[c] = w . w
+// (update_norm2).  1 to 32 basis vectors; `work` needs
+// col_fused_work_size(n0, K) doubles.
+size_t col_fused_work_size(int64_t n0, int K);
+void launch_cols_update_dots(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                             int64_t n0, int K, double* out, double* work, hipStream_t s);
+void launch_cols_update_norm2(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                              int64_t n0, int K, double* out, double* work, hipStream_t s);
 // The fused Gram-Schmidt sweeps per problem, on items of at most 256
 // elements (build_group_items with chunk 256): w = w - sum_k h[k, g] V_k,
 // then out[k, g] = V_k . w (update_dots) or out[0, g] = w . w (update_norm2)

@@ -82,6 +82,7 @@ void workspace_init(const Hierarchy& H, Workspace& W, int K) {
   if (K > 1) {
     W.cdiv.alloc(K, s);
     W.cdot_work.alloc(col_dots_work_size(H.n0, K), s);
+    W.cfused_work.alloc(col_fused_work_size(H.n0, K), s);
   } else {
     W.fused_work.alloc(cgs_fused_work_size(n), s);
   }
@@ -422,8 +423,11 @@ struct Procs {
   // w = w - V h, then the next sweep's coefficients (one pass over the basis
   // where a fused kernel exists)
   void update_dots(double* w, const double* V, int64_t ld, const double* h, int nv, double* out) {
-    if (!cols && nv <= kFusedVecs) {
-      launch_group_update_dots(w, V, ld, h, nv, W.gitems_f, out, W.gfused_work.get(), H.s);
+    if (nv <= kFusedVecs) {
+      if (cols)
+        launch_cols_update_dots(w, V, ld, h, nv, H.n0, W.K, out, W.cfused_work.get(), H.s);
+      else
+        launch_group_update_dots(w, V, ld, h, nv, W.gitems_f, out, W.gfused_work.get(), H.s);
       return;
     }
     update(w, V, ld, h, nv);
@@ -431,8 +435,11 @@ struct Procs {
   }
   // w = w - V h, then w . w
   void update_sumsq(double* w, const double* V, int64_t ld, const double* h, int nv, double* out) {
-    if (!cols && nv <= kFusedVecs) {
-      launch_group_update_norm2(w, V, ld, h, nv, W.gitems_f, out, W.gfused_work.get(), H.s);
+    if (nv <= kFusedVecs) {
+      if (cols)
+        launch_cols_update_norm2(w, V, ld, h, nv, H.n0, W.K, out, W.cfused_work.get(), H.s);
+      else
+        launch_group_update_norm2(w, V, ld, h, nv, W.gitems_f, out, W.gfused_work.get(), H.s);
       return;
     }
     update(w, V, ld, h, nv);

@@ -22,6 +22,7 @@ struct Workspace {
   DBuf<double> bperm, xperm, nat;
   DBuf<double> hbuf, ybuf, gbuf, dot_work, col_work;
   DBuf<double> cdiv, cdot_work;  // per-column divisors and dot partials (K > 1)
+  DBuf<double> cfused_work;      // partials of the fused per-column sweeps (K > 1)
   DBuf<double> fused_work;       // partials of the fused Gram-Schmidt sweeps (K = 1)
   GroupItems gitems;             // per-problem work items of a batch (K = 1)
   DBuf<double> gdot_work;

@@ -453,6 +453,95 @@ void launch_col_dots(const double* V, int64_t ldv, int nv, const double* w, int6
   }
 }
 
+// The fused sweeps of cgs_fused_kernel per column: the update of
+// cgs_update_cols_kernel, then the products of col_dots_stage1 (DOTS, the
+// same walk and sum order) or the column sums of squares, with the element's
+// basis values kept in registers in between.  The coefficients h[k K + c]
+// sit in LDS.
+template <bool DOTS, int NV>
+__global__ __launch_bounds__(256) void col_fused_kernel(double* __restrict__ w,
+                                                        const double* __restrict__ V, int64_t ldv,
+                                                        const double* __restrict__ h, int64_t n,
+                                                        int K, double* __restrict__ part) {
+  constexpr int CNT = DOTS ? NV : 1;
+  __shared__ double hs[NV][64];
+  __shared__ double red[4][64];
+  const int t = threadIdx.x;
+  for (int q = t; q < NV * K; q += 256) hs[q / K][q % K] = h[q];
+  __syncthreads();
+  const int c = t & (K - 1);  // every element a thread meets is in column c
+  double acc[CNT];
+#pragma unroll
+  for (int k = 0; k < CNT; ++k) acc[k] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + t; e < n; e += stride) {
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = V[(int64_t)k * ldv + e];
+    double wi = w[e];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) wi = wi - hs[k][c] * v[k];
+    w[e] = wi;
+    if constexpr (DOTS) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) acc[k] = acc[k] + v[k] * wi;
+    } else {
+      acc[0] = acc[0] + wi * wi;
+    }
+  }
+  // one k at a time through a small LDS buffer (the sums of col_dots_stage1)
+  const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int k = 0; k < CNT; ++k) {
+    double v = acc[k];
+    for (int o = K; o < 64; o <<= 1) v = v + __shfl_down(v, o, 64);
+    if (lane < K) red[wave][lane] = v;
+    __syncthreads();
+    if (t < K)
+      part[(int64_t)(k * K + t) * gridDim.x + blockIdx.x] =
+          (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+    __syncthreads();
+  }
+}
+
+template <bool DOTS, int NV>
+static void launch_col_fused_nv(int nv, double* w, const double* V, int64_t ldv, const double* h,
+                                int64_t n, int K, double* part, int64_t G, hipStream_t s) {
+  if constexpr (NV > kFusedVecs) {
+    fail(AIRG_ERR_INTERNAL, "fused Gram-Schmidt takes 1 to 32 vectors");
+  } else {
+    if (nv != NV) return launch_col_fused_nv<DOTS, NV + 1>(nv, w, V, ldv, h, n, K, part, G, s);
+    col_fused_kernel<DOTS, NV><<<(unsigned)G, 256, 0, s>>>(w, V, ldv, h, n, K, part);
+  }
+}
+
+size_t col_fused_work_size(int64_t n0, int K) {
+  return (size_t)kFusedVecs * (size_t)K * (size_t)col_dot_blocks(n0 * K);
+}
+
+static void launch_col_fused(bool dots, double* w, const double* V, int64_t ldv, const double* h,
+                             int nv, int64_t n0, int K, double* out, double* work, hipStream_t s) {
+  check_cols(K);
+  if (nv < 1 || nv > kFusedVecs) fail(AIRG_ERR_INTERNAL, "fused Gram-Schmidt takes 1 to 32 vectors");
+  const int64_t n = n0 * K;
+  if (n <= 0) return;
+  const int64_t G = col_dot_blocks(n);
+  if (dots) launch_col_fused_nv<true, 1>(nv, w, V, ldv, h, n, K, work, G, s);
+  else launch_col_fused_nv<false, 1>(nv, w, V, ldv, h, n, K, work, G, s);
+  AIRG_CHECK_LAUNCH();
+  // G <= kDotChunk partials per (k, c): one tree stage per pair
+  tree_sum_stage<<<dim3(1u, (unsigned)((dots ? nv : 1) * K)), 256, 0, s>>>(work, G, G, out, 1);
+  AIRG_CHECK_LAUNCH();
+}
+void launch_cols_update_dots(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                             int64_t n0, int K, double* out, double* work, hipStream_t s) {
+  launch_col_fused(true, w, V, ldv, h, nv, n0, K, out, work, s);
+}
+void launch_cols_update_norm2(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                              int64_t n0, int K, double* out, double* work, hipStream_t s) {
+  launch_col_fused(false, w, V, ldv, h, nv, n0, K, out, work, s);
+}
+
 // ------------------------------------------------------------------ per-problem Krylov
 // One outer process per problem of a batch ordered problem-major: work item
 // q covers elements start[q] .. start[q] + len[q] - 1 (len <= kDotChunk) of
