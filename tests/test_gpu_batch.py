@@ -361,3 +361,50 @@ def test_option_combinations_on_column_batches(opts):
     X, infos = s.solve(torch.from_numpy(B).cuda())
     _check_columns(p, B, X.cpu().numpy(), infos)
     s.close()
+
+
+def test_long_arnoldi_cycles_in_column_and_problem_batches():
+    # a weak preconditioner (one level, degree-3 Newton polynomial) and
+    # restart 40: every process's Arnoldi cycle passes 32 basis vectors,
+    # where the fused per-column and per-problem Gram-Schmidt sweeps give
+    # way to the separate ones, and then restarts
+    _needs_gpu()
+    import scipy.sparse as sp
+    from paper_2508_17517_amd import BatchSolver, Solver
+    kw = dict(max_levels=1, coarse_poly_order=3, restart=40)
+    pr = oracle.Params(**kw)
+    p = workloads.fv_random(64, 0.4, True)
+    A = p.scipy()
+    B = workloads.rhs_batch(p, 2)
+    print("fv64 perm, 2 columns, restart 40", flush=True)
+    s = Solver(p.indptr, p.indices, p.data, **kw)
+    X, infos = s.solve(torch.from_numpy(B).cuda())
+    Xh = X.cpu().numpy()
+    levels = oracle.setup(A, pr)
+    for k in range(2):
+        xo, ik, rel, _, _ = oracle.solve(A, B[k], pr, levels)
+        assert ik > 40
+        assert infos[k]["converged"] == 1 and infos[k]["restarts"] >= 1, k
+        # 40-step Arnoldi cycles amplify rounding differences: one iteration apart at most
+        assert abs(infos[k]["iterations"] - ik) <= 1, (k, infos[k]["iterations"], ik)
+        assert np.linalg.norm(Xh[k] - xo) <= 1e-9 * np.linalg.norm(xo), k
+    s.close()
+    probs = [workloads.fv_random(48, 0.4, True, seed=311), workloads.fv_random(64, 0.9, True, seed=312)]
+    Ab = sp.csr_matrix(sp.block_diag([q.scipy() for q in probs]))
+    Ab.sort_indices()
+    levels = oracle.setup(Ab, pr)
+    seg = np.concatenate([[0], np.cumsum([q.n for q in probs])])
+    print("batch of", [q.n for q in probs], "restart 40", flush=True)
+    sb = BatchSolver([(q.indptr, q.indices, q.data) for q in probs], **kw)
+    xs, infos = sb.solve([torch.from_numpy(q.b).cuda() for q in probs])
+    for k, q in enumerate(probs):
+        b = np.zeros(Ab.shape[0])
+        b[seg[k]:seg[k + 1]] = q.b
+        xo, ik, rel, _, _ = oracle.solve(Ab, b, pr, levels)
+        xo = xo[seg[k]:seg[k + 1]]
+        assert ik > 32
+        assert infos[k]["converged"] == 1, k
+        assert infos[k]["restarts"] >= (1 if ik > 41 else 0), k
+        assert abs(infos[k]["iterations"] - ik) <= 1, (k, infos[k]["iterations"], ik)
+        assert np.linalg.norm(xs[k].cpu().numpy() - xo) <= 1e-9 * np.linalg.norm(xo), k
+    sb.close()
