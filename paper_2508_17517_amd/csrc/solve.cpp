@@ -35,6 +35,17 @@ namespace airg {
 Workspace::~Workspace() {
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
+  if (pin) (void)hipHostFree(pin);
+}
+
+// The outer loop reads a few coefficients back every iteration and waits for
+// them; from pinned memory the copy needs no staging through pageable memory.
+static void read_small(Workspace& W, const double* dev, double* host, size_t n, hipStream_t s) {
+  if (n > W.pin_n) fail(AIRG_ERR_INTERNAL, "pinned staging buffer too small");
+  if (n == 0) return;
+  AIRG_HIP(hipMemcpyAsync(W.pin, dev, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  AIRG_HIP(hipStreamSynchronize(s));
+  std::memcpy(host, W.pin, n * sizeof(double));
 }
 
 void workspace_init(const Hierarchy& H, Workspace& W, int K) {
@@ -97,6 +108,10 @@ void workspace_init(const Hierarchy& H, Workspace& W, int K) {
   }
   const size_t ng = std::max<size_t>((size_t)K, H.seg.empty() ? 1 : H.seg.size());
   W.gbuf.alloc(ng + 1, s);
+  W.pin_n = std::max((2 * (size_t)(W.restart + 1) + 2) * G, ng + 1);
+  if (W.pin) (void)hipHostFree(W.pin);
+  W.pin = nullptr;
+  AIRG_HIP(hipHostMalloc((void**)&W.pin, W.pin_n * sizeof(double), hipHostMallocDefault));
   W.dot_work.alloc(dot_work_size(n, 64), s);
   W.col_work.alloc(col_sumsq_work_size(H.n0, K), s);
   AIRG_HIP(hipEventCreate(&W.ev0));
@@ -349,8 +364,7 @@ std::vector<double> group_norms(const Hierarchy& H, Workspace& W, const double* 
     launch_tree_dots(v, 0, 1, v, H.n0, g, W.dot_work.get(), s);
   }
   std::vector<double> out(ng);
-  W.gbuf.to_host(out.data(), ng);
-  AIRG_HIP(hipStreamSynchronize(s));
+  read_small(W, W.gbuf.get(), out.data(), ng, s);
   for (double& x : out) x = std::sqrt(x);
   return out;
 }
@@ -460,8 +474,7 @@ struct Procs {
   std::vector<double> norms(const double* v) {
     sumsq(v, W.gbuf.get());
     std::vector<double> out(G);
-    W.gbuf.to_host(out.data(), G);
-    AIRG_HIP(hipStreamSynchronize(H.s));
+    read_small(W, W.gbuf.get(), out.data(), G, H.s);
     for (double& x : out) x = std::sqrt(x);
     return out;
   }
@@ -576,8 +589,7 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
         P.dots(V, ld, j + 1, W.w.get(), h1);
         P.update_dots(W.w.get(), V, ld, h1, j + 1, h2);
         P.update_sumsq(W.w.get(), V, ld, h2, j + 1, hn2);
-        W.hbuf.to_host(hh.data(), (size_t)(2 * (R + 1) + 1) * G);
-        AIRG_HIP(hipStreamSynchronize(s));
+        read_small(W, W.hbuf.get(), hh.data(), (size_t)(2 * (R + 1) + 1) * G, s);
         bool more = false;
         for (int c = 0; c < G; ++c) {
           dh[c] = 0.0;
@@ -784,8 +796,7 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
           launch_cgs_update(W.w.get(), V, ld, hd + (R + 1), j + 1, n, s);
           launch_tree_dots(W.w.get(), 0, 1, W.w.get(), n, hd + 2 * (R + 1), W.dot_work.get(), s);
         }
-        W.hbuf.to_host(hh.data(), 2 * (R + 1) + 1);
-        AIRG_HIP(hipStreamSynchronize(s));
+        read_small(W, W.hbuf.get(), hh.data(), 2 * (R + 1) + 1, s);
         for (int i = 0; i <= j; ++i) Hm[(size_t)i * R + j] = hh[i] + hh[(R + 1) + i];
         const double hn = std::sqrt(hh[2 * (R + 1)]);
         Hm[(size_t)(j + 1) * R + j] = hn;

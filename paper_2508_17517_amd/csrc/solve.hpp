@@ -29,6 +29,9 @@ struct Workspace {
   GroupItems gitems_f;           // the same ranges in items of 256, for the fused sweeps
   DBuf<double> gfused_work;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // pinned host staging for the small per-iteration reads of the outer loop
+  double* pin = nullptr;
+  size_t pin_n = 0;
   ~Workspace();
 };
 
