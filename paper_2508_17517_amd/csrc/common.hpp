@@ -103,6 +103,9 @@ struct CSR {
   // rblk[b] .. rblk[b+1]-1 (see build_row_blocks)
   DBuf<int32_t> rblk;
   int64_t nrblk = 0;
+  // in a problem batch: the first of this operator's 64-row groups in the
+  // batch's activity masks (-1: not masked)
+  int64_t mask_off = -1;
   void alloc(int64_t r, int64_t c, int64_t nz, hipStream_t s) {
     rows = r; cols = c; nnz = nz;
     rowptr.alloc(r + 1, s);
@@ -114,6 +117,7 @@ struct CSR {
     max_span = 0;
     rblk.release();
     nrblk = 0;
+    mask_off = -1;
   }
 };
 
@@ -137,10 +141,14 @@ struct OpView {
   int64_t nrblk;
   const int32_t* cspan;   // column span per 64-row group (with col16)
   int64_t max_span;
+  // per 64-row group, 0 where every row belongs to a problem whose input is
+  // zero in this product (its rows then skip the matrix: their sums are 0);
+  // null: every row is computed
+  const uint8_t* gmask;
 };
 inline OpView opview(const CSR& A) {
   return {A.rowptr.get(), A.col.get(), A.val.get(), VT_F64, A.rows, A.nnz, A.col16.get(),
-          A.cbase.get(), A.rblk.get(), A.nrblk, A.cspan.get(), A.max_span};
+          A.cbase.get(), A.rblk.get(), A.nrblk, A.cspan.get(), A.max_span, nullptr};
 }
 
 // Read-only view passed to kernels.

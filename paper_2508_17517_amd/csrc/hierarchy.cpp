@@ -714,6 +714,51 @@ void finalize_hierarchy(Hierarchy& H) {
       fail(AIRG_ERR_INVALID, "coarsest matrix does not match its level size");
     if (fetch(flags.get(), s)) fail(AIRG_ERR_INVALID, "hierarchy operators fail the index check");
   }
+  // the problems of every 64-row group of the solve operators, for the
+  // activity masks of a batch's per-problem processes: rows of A_ff and B
+  // are level l's F block at off_l, rows of Z level l + 1's points at
+  // off_{l+1}, the coarsest matrix's at its off, the top matrix's all of them
+  H.mgroups = 0;
+  if (!H.granges.empty()) {
+    std::vector<int32_t> pp((size_t)H.n0, -1);
+    for (const GroupRange& r : H.granges)
+      std::fill(pp.begin() + r.start, pp.begin() + r.start + r.len, r.group);
+    for (int32_t v : pp)
+      if (v < 0) fail(AIRG_ERR_INTERNAL, "problem ranges do not cover the nested numbering");
+    std::vector<int32_t> g0, g1;
+    auto add = [&](CSR& A, int64_t first) {
+      A.mask_off = -1;
+      if (A.rows <= 0) return;
+      if (first < 0 || first + A.rows > H.n0) fail(AIRG_ERR_INTERNAL, "operator rows outside the numbering");
+      A.mask_off = (int64_t)g0.size();
+      for (int64_t r0 = 0; r0 < A.rows; r0 += 64) {
+        int32_t lo = pp[first + r0], hi = lo;
+        for (int64_t r = r0 + 1; r < std::min(A.rows, r0 + 64); ++r) {
+          lo = std::min(lo, pp[first + r]);
+          hi = std::max(hi, pp[first + r]);
+        }
+        g0.push_back(lo);
+        g1.push_back(hi);
+      }
+    };
+    for (int l = 0; l < nl; ++l) {
+      Level& L = H.levels[l];
+      if (L.coarsest) {
+        add(L.A, L.off);
+      } else {
+        add(L.Aff, L.off);
+        add(L.B, L.off);
+        add(L.Z, L.off + L.nF);
+      }
+    }
+    add(H.Aperm, 0);
+    H.mgroups = (int64_t)g0.size();
+    H.mgp0.alloc(g0.size(), s);
+    H.mgp1.alloc(g1.size(), s);
+    H.mgp0.from_host(g0.data(), g0.size());
+    H.mgp1.from_host(g1.data(), g1.size());
+    AIRG_HIP(hipStreamSynchronize(s));  // g0 and g1 go out of scope
+  }
   if (!H.p.keep_setup_data) {
     for (int l = 0; l < nl; ++l) {
       Level& L = H.levels[l];

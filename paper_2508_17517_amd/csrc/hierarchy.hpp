@@ -98,6 +98,12 @@ struct Hierarchy {
   // nested numbering as ranges (each level's F block, then the coarsest
   // block, problems ascending inside each); empty otherwise
   std::vector<GroupRange> granges;
+  // with granges: for every 64-row group of the masked solve operators
+  // (A_ff, B and Z of each level, the coarsest matrix, the top matrix; each
+  // CSR's mask_off is its first group), the lowest and highest problem of
+  // its rows
+  DBuf<int32_t> mgp0, mgp1;
+  int64_t mgroups = 0;
 };
 
 // Build the hierarchy for A (device CSR, validated) with parameters p.

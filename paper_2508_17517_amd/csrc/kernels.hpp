@@ -90,6 +90,10 @@ void launch_group_combine(double* x, const double* Z, int64_t ldz, const double*
                           const GroupItems& it, hipStream_t s);
 void launch_group_divide(double* y, const double* x, const double* d, const GroupItems& it,
                          hipStream_t s);
+// Activity masks of a problem batch: mask[i] = 1 where any of the problems
+// g0[i] .. g1[i] of 64-row group i has active[p] != 0.
+void launch_group_mask(const int32_t* g0, const int32_t* g1, const uint8_t* active, int64_t n,
+                       uint8_t* mask, hipStream_t s);
 // Most basis vectors the fused Gram-Schmidt sweeps take (one register each).
 constexpr int kFusedVecs = 32;
 // The fused Gram-Schmidt sweeps per column of K interleaved columns:

@@ -104,6 +104,10 @@ void workspace_init(const Hierarchy& H, Workspace& W, int K) {
     W.gdot_work.alloc(group_dots_work_size(W.gitems), s);
     build_group_items(H.granges, np, W.gitems_f, s, 256);
     W.gfused_work.alloc(group_fused_work_size(W.gitems_f), s);
+    if (H.mgroups > 0) {
+      W.active.alloc(np, s);
+      W.gmask.alloc(H.mgroups, s);
+    }
     W.cdiv.alloc(np, s);
   }
   const size_t ng = std::max<size_t>((size_t)K, H.seg.empty() ? 1 : H.seg.size());
@@ -133,15 +137,17 @@ struct VecSet {
   X* cw1;
   X* ct;        // Newton scratch
   X* rin;       // stacked level residuals (C-point smoothing), or null
+  const uint8_t* gmask;  // activity masks of a problem batch, or null
 };
 
 VecSet<double> vecs64(Workspace& W, const double* in, double* e) {
   return {in,        e,         W.rr.get(), W.sv.get(), W.y0.get(), W.y1.get(),
-          W.cw0.get(), W.cw1.get(), W.ct.get(), W.rin.get()};
+          W.cw0.get(), W.cw1.get(), W.ct.get(), W.rin.get(), W.mask_on ? W.gmask.get() : nullptr};
 }
 VecSet<float> vecs32(Workspace& W) {
   return {W.in32.get(), W.e32.get(), W.rr32.get(), W.sv32.get(), W.y032.get(), W.y132.get(),
-          W.cw032.get(), W.cw132.get(), W.ct32.get(), W.rin32.get()};
+          W.cw032.get(), W.cw132.get(), W.ct32.get(), W.rin32.get(),
+          W.mask_on ? W.gmask.get() : nullptr};
 }
 
 struct LevelOps {
@@ -151,6 +157,23 @@ LevelOps ops_of(const Level& L, int prec) {
   return {op_view(L.Aff, L.ff32, L.ff16, prec), op_view(L.B, L.b32, L.b16, prec),
           op_view(L.Z, L.z32, L.z16, prec), op_view(L.A, L.a32, L.a16, prec),
           op_view(L.Ahat, L.hat32, L.hat16, prec)};
+}
+// the view of A with the activity masks gm (null: unmasked)
+OpView masked(OpView v, const CSR& A, const uint8_t* gm) {
+  if (gm && A.mask_off >= 0) v.gmask = gm + A.mask_off;
+  return v;
+}
+// The operators of a V-cycle over a problem batch's per-problem processes:
+// A_ff, B, Z and the coarsest matrix skip the row groups whose problems are
+// inactive.  Their input there is exactly zero, so the skipped sums (0) are
+// the ones the products would give.
+LevelOps ops_of(const Level& L, int prec, const uint8_t* gm) {
+  LevelOps o = ops_of(L, prec);
+  o.ff = masked(o.ff, L.Aff, gm);
+  o.b = masked(o.b, L.B, gm);
+  o.z = masked(o.z, L.Z, gm);
+  o.a = masked(o.a, L.A, gm);
+  return o;
 }
 
 double vt_bytes(ValType vt) { return vt == VT_F64 ? 8.0 : vt == VT_F32 ? 4.0 : 2.0; }
@@ -316,15 +339,16 @@ void vcycle_t(const Hierarchy& H, const VecSet<X>& v, int K) {
   for (int l = 0; l < L; ++l) {
     const Level& lv = H.levels[l];
     const X* src = l == 0 ? v.in : input(l);
-    spmv_restrict_t<X>(ops_of(lv, prec).z, lv.tpr_z, K, src, src + lv.nF * K, input(l + 1), s);
+    spmv_restrict_t<X>(ops_of(lv, prec, v.gmask).z, lv.tpr_z, K, src, src + lv.nF * K,
+                       input(l + 1), s);
   }
   const Level& lc = H.levels[L];
   const X* rc = L == 0 ? v.in : input(L);
-  newton_apply_t<X>(ops_of(lc, prec).a, lc.tpr_a, K, lc.roots, rc, v.e + lc.off * K, v.cw0, v.cw1,
-                    v.ct, s);
+  newton_apply_t<X>(ops_of(lc, prec, v.gmask).a, lc.tpr_a, K, lc.roots, rc, v.e + lc.off * K,
+                    v.cw0, v.cw1, v.ct, s);
   for (int l = L - 1; l >= 0; --l) {
     const Level& lv = H.levels[l];
-    const LevelOps o = ops_of(lv, prec);
+    const LevelOps o = ops_of(lv, prec, v.gmask);
     const X* rf = l == 0 ? v.in : input(l);
     X* ef = v.e + lv.off * K;
     X* ec = v.e + H.levels[l + 1].off * K;
@@ -578,11 +602,32 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
       }
       upload_div();
       P.divide(V, V, dv);
+      // problems of a batch whose processes are not running have a zero
+      // basis vector: the V-cycle and the top product skip their rows
+      const bool mask = !P.cols && W.gmask.size() > 0;
+      std::vector<uint8_t> amask(mask ? G : 0, 2);  // last uploaded activity (2: none yet)
+      OpView Am = A;
+      if (mask) Am = masked(A, H.Aperm, W.gmask.get());
       for (int j = 0; j < R; ++j) {
         double* vj = V + (int64_t)j * ld;
         double* zj = Zb + (int64_t)j * ld;
+        if (mask) {
+          bool changed = false;
+          for (int c = 0; c < G; ++c) {
+            const uint8_t a = act[c] ? 1 : 0;
+            changed = changed || amask[c] != a;
+            amask[c] = a;
+          }
+          if (changed) {
+            W.active.from_host(amask.data(), G);
+            launch_group_mask(H.mgp0.get(), H.mgp1.get(), W.active.get(), H.mgroups,
+                              W.gmask.get(), s);
+          }
+          W.mask_on = true;
+        }
         vcycle(H, W, vj, zj);
-        spmv_t<double>(A, H.tpr_top, K, zj, W.w.get(), s);
+        W.mask_on = false;
+        spmv_t<double>(mask ? Am : A, H.tpr_top, K, zj, W.w.get(), s);
         double* h1 = hd;
         double* h2 = hd + (size_t)(R + 1) * G;
         double* hn2 = hd + (size_t)2 * (R + 1) * G;

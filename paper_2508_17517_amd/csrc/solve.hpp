@@ -28,6 +28,10 @@ struct Workspace {
   DBuf<double> gdot_work;
   GroupItems gitems_f;           // the same ranges in items of 256, for the fused sweeps
   DBuf<double> gfused_work;
+  // activity of the problems and its 64-row-group masks (Hierarchy::mgp0);
+  // with mask_on the V-cycle's masked products skip the inactive groups
+  DBuf<uint8_t> active, gmask;
+  bool mask_on = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // pinned host staging for the small per-iteration reads of the outer loop
   double* pin = nullptr;

@@ -31,6 +31,11 @@ struct CSRT {
   const int32_t* __restrict__ cbase;
   const MV* __restrict__ val;
   int64_t rows;
+  const uint8_t* __restrict__ gmask;  // see OpView::gmask
+  // false where the row's 64-row group is masked off: its sum is 0
+  __device__ __forceinline__ bool computed(int64_t row) const {
+    return gmask == nullptr || gmask[row >> kColBlockShift] != 0;
+  }
   __device__ __forceinline__ int base(int64_t row) const {
     if constexpr (C16) return cbase[row >> kColBlockShift];
     return 0;
@@ -44,7 +49,7 @@ struct CSRT {
 
 template <class MV, bool C16>
 static CSRT<MV, C16> csr_t(const OpView& A) {
-  return {A.rowptr, A.col, A.col16, A.cbase, (const MV*)A.val, A.rows};
+  return {A.rowptr, A.col, A.col16, A.cbase, (const MV*)A.val, A.rows, A.gmask};
 }
 
 // Entries in flight per lane: every lane first loads the column indices and
@@ -94,7 +99,7 @@ __device__ __forceinline__ X row_dot(const CSRT<MV, C16>& A, int s, int e, int b
                                      const X* __restrict__ x, int c, Idx idx, X sum) {
   if constexpr (C16) {
     if (b < 0) {
-      const CSRT<MV, false> W{A.rowptr, A.col, nullptr, nullptr, A.val, A.rows};
+      const CSRT<MV, false> W{A.rowptr, A.col, nullptr, nullptr, A.val, A.rows, nullptr};
       return row_dot_cols<TPR, U, K>(W, s, e, 0, lane, x, c, idx, sum);
     }
   }
@@ -202,7 +207,7 @@ __device__ __forceinline__ X row_dot_pairs(const CSRT<MV, C16>& A, int s, int e,
                                            const X* __restrict__ x, X sum) {
   if constexpr (C16) {
     if (b < 0) {
-      const CSRT<MV, false> W{A.rowptr, A.col, nullptr, nullptr, A.val, A.rows};
+      const CSRT<MV, false> W{A.rowptr, A.col, nullptr, nullptr, A.val, A.rows, nullptr};
       return row_dot_pairs_cols<TPR, U, false>(W, s, e, 0, lane, x, sum);
     }
   }
@@ -227,7 +232,7 @@ static unsigned grid_for(int64_t rows, int rows_per_block, int xcd) {
 }
 
 // lanes-per-row kernel (K = 1)
-template <int TPR, class MV, bool C16, class X, class Epi>
+template <int TPR, class MV, bool C16, class X, class Epi, bool MASK>
 __global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV, C16> A, const X* __restrict__ x,
                                                    Epi epi, int xcd) {
   const int lane = threadIdx.x & (TPR - 1);
@@ -237,12 +242,12 @@ __global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV, C16> A, const X* __r
   if (live && lane == 0) pre = epi.pre(row);
   X sum = 0;
   if (live) {
+    const int rs = A.rowptr[row];
+    const int re = (!MASK || A.computed(row)) ? A.rowptr[row + 1] : rs;
     if constexpr (TPR >= 2)
-      sum = row_dot_pairs<TPR, unroll_for<TPR>()>(A, A.rowptr[row], A.rowptr[row + 1], A.base(row),
-                                                  lane, x, sum);
+      sum = row_dot_pairs<TPR, unroll_for<TPR>()>(A, rs, re, A.base(row), lane, x, sum);
     else
-      sum = row_dot<1, 4, 1>(A, A.rowptr[row], A.rowptr[row + 1], A.base(row), 0, x, 0, IdxPlain{},
-                             sum);
+      sum = row_dot<1, 4, 1>(A, rs, re, A.base(row), 0, x, 0, IdxPlain{}, sum);
   }
   if constexpr (TPR > 1) {
 #pragma unroll
@@ -275,7 +280,7 @@ __global__ __launch_bounds__(256) void spmm_kernel(CSRT<MV, C16> A, const X* __r
 // memory round trips for all of its rows, which suits long rows.
 constexpr int kRowBlockNnz = 2048;
 
-template <class MV, bool C16, class X, class Epi>
+template <class MV, bool C16, class X, class Epi, bool MASK>
 __global__ __launch_bounds__(256) void spmv_rowblock_kernel(CSRT<MV, C16> A,
                                                             const int32_t* __restrict__ rblk,
                                                             int64_t nblk, const X* __restrict__ x,
@@ -294,7 +299,7 @@ __global__ __launch_bounds__(256) void spmv_rowblock_kernel(CSRT<MV, C16> A,
     rs = A.rowptr[row];
     re = A.rowptr[row + 1];
   }
-  const int p0 = A.rowptr[r0], p1 = A.rowptr[r1];
+  const int p0 = A.rowptr[r0], p1 = (!MASK || A.computed(r0)) ? A.rowptr[r1] : p0;
   const int base = A.base(r0);  // one 64-row group per block
   X sum = 0;
   for (int c0 = p0; c0 < p1; c0 += kRowBlockNnz) {  // one pass unless a single long row
@@ -346,7 +351,7 @@ static int64_t lds_budget_bytes() {
   return cached;
 }
 
-template <int TPR, class MV, class X, class Epi>
+template <int TPR, class MV, class X, class Epi, bool MASK>
 __global__ __launch_bounds__(64 * TPR) void spmv_lds_kernel(CSRT<MV, true> A,
                                                             const int32_t* __restrict__ cspan,
                                                             int64_t ngroups, int lds_cap,
@@ -362,13 +367,15 @@ __global__ __launch_bounds__(64 * TPR) void spmv_lds_kernel(CSRT<MV, true> A,
   const bool live = row < A.rows;
   const int base = A.cbase[g];
   const int span = cspan[g];
-  const bool staged = base >= 0 && span <= lds_cap;  // the same for the whole workgroup
+  const bool on = !MASK || A.computed(g << kColBlockShift);
+  // the same for the whole workgroup
+  const bool staged = on && base >= 0 && span <= lds_cap;
   typename Epi::Pre pre{};
   if (live && lane == 0) pre = epi.pre(row);
   int s = 0, e = 0;
   if (live) {
     s = A.rowptr[row];
-    e = A.rowptr[row + 1];
+    e = on ? A.rowptr[row + 1] : s;
   }
   X sum = 0;
   constexpr int U = unroll_for<TPR>();
@@ -399,7 +406,9 @@ __global__ __launch_bounds__(64 * TPR) void spmv_lds_kernel(CSRT<MV, true> A,
 
 // shape: lanes per row in bits 0-7 (0: the row-block kernel), the XCD
 // mapping in bit 8, the LDS-staged kernel in bit 9
-template <class MV, bool C16, class X, class Epi>
+// MASK: the launch honours Av.gmask (a separate instantiation, so that the
+// unmasked products carry no test)
+template <class MV, bool C16, bool MASK, class X, class Epi>
 static void launch_spmv_t(const OpView& Av, int shape, int K, const X* x, Epi epi, hipStream_t s) {
   if (Av.rows <= 0) return;
   const int tpr = shape & 0xff, xcd = (shape >> 8) & 1, lds = (shape >> 9) & 1;
@@ -411,10 +420,10 @@ static void launch_spmv_t(const OpView& Av, int shape, int K, const X* x, Epi ep
       const size_t smem = (size_t)std::max(cap, 1) * sizeof(X);
       const unsigned nb = grid_for(ngroups, 1, xcd);
       switch (tpr) {
-        case 2: spmv_lds_kernel<2, MV, X, Epi><<<nb, 128, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
-        case 4: spmv_lds_kernel<4, MV, X, Epi><<<nb, 256, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
-        case 8: spmv_lds_kernel<8, MV, X, Epi><<<nb, 512, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
-        case 16: spmv_lds_kernel<16, MV, X, Epi><<<nb, 1024, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
+        case 2: spmv_lds_kernel<2, MV, X, Epi, MASK><<<nb, 128, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
+        case 4: spmv_lds_kernel<4, MV, X, Epi, MASK><<<nb, 256, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
+        case 8: spmv_lds_kernel<8, MV, X, Epi, MASK><<<nb, 512, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
+        case 16: spmv_lds_kernel<16, MV, X, Epi, MASK><<<nb, 1024, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
         default: fail(AIRG_ERR_INTERNAL, "LDS-staged product takes 2, 4, 8 or 16 lanes per row");
       }
       AIRG_CHECK_LAUNCH();
@@ -425,7 +434,7 @@ static void launch_spmv_t(const OpView& Av, int shape, int K, const X* x, Epi ep
   }
   if (K == 1 && tpr == 0) {
     if (!Av.rblk) fail(AIRG_ERR_INTERNAL, "row-block product without row blocks");
-    spmv_rowblock_kernel<MV, C16, X, Epi><<<grid_for(Av.nrblk, 1, xcd), 256, 0, s>>>(
+    spmv_rowblock_kernel<MV, C16, X, Epi, MASK><<<grid_for(Av.nrblk, 1, xcd), 256, 0, s>>>(
         A, Av.rblk, Av.nrblk, x, epi, xcd);
     AIRG_CHECK_LAUNCH();
     return;
@@ -435,13 +444,13 @@ static void launch_spmv_t(const OpView& Av, int shape, int K, const X* x, Epi ep
   if (K == 1) {
     unsigned nb = grid_for(Av.rows, 256 / tpr, xcd);
     switch (tpr) {
-      case 1: spmv_kernel<1, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 2: spmv_kernel<2, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 4: spmv_kernel<4, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 8: spmv_kernel<8, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 16: spmv_kernel<16, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 32: spmv_kernel<32, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 64: spmv_kernel<64, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 1: spmv_kernel<1, MV, C16, X, Epi, MASK><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 2: spmv_kernel<2, MV, C16, X, Epi, MASK><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 4: spmv_kernel<4, MV, C16, X, Epi, MASK><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 8: spmv_kernel<8, MV, C16, X, Epi, MASK><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 16: spmv_kernel<16, MV, C16, X, Epi, MASK><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 32: spmv_kernel<32, MV, C16, X, Epi, MASK><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 64: spmv_kernel<64, MV, C16, X, Epi, MASK><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
       default: fail(AIRG_ERR_INTERNAL, "bad lanes-per-row");
     }
   } else {
@@ -463,8 +472,13 @@ static void launch_spmv_t(const OpView& Av, int shape, int K, const X* x, Epi ep
 // vectors, FP32 and BF16 values with FP32 vectors
 template <class MV, class X, class Epi>
 static void launch_cols(const OpView& A, int tpr, int K, const X* x, Epi epi, hipStream_t s) {
-  if (A.col16) launch_spmv_t<MV, true>(A, tpr, K, x, epi, s);
-  else launch_spmv_t<MV, false>(A, tpr, K, x, epi, s);
+  if (A.gmask && K == 1) {
+    if (A.col16) launch_spmv_t<MV, true, true>(A, tpr, K, x, epi, s);
+    else launch_spmv_t<MV, false, true>(A, tpr, K, x, epi, s);
+    return;
+  }
+  if (A.col16) launch_spmv_t<MV, true, false>(A, tpr, K, x, epi, s);
+  else launch_spmv_t<MV, false, false>(A, tpr, K, x, epi, s);
 }
 template <class Epi>
 static void launch_spmv(const OpView& A, int tpr, int K, const double* x, Epi epi, hipStream_t s) {

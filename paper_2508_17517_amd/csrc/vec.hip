@@ -767,6 +767,23 @@ void launch_group_update_norm2(double* w, const double* V, int64_t ldv, const do
   launch_group_fused(false, w, V, ldv, h, nv, it, out, work, s);
 }
 
+// mask[i] = 1 where any problem g0[i] .. g1[i] of 64-row group i is active
+__global__ void group_mask_kernel(const int32_t* __restrict__ g0, const int32_t* __restrict__ g1,
+                                  const uint8_t* __restrict__ active, int64_t n,
+                                  uint8_t* __restrict__ mask) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint8_t m = 0;
+  for (int32_t p = g0[i]; p <= g1[i]; ++p) m |= active[p];
+  mask[i] = m != 0 ? 1 : 0;
+}
+void launch_group_mask(const int32_t* g0, const int32_t* g1, const uint8_t* active, int64_t n,
+                       uint8_t* mask, hipStream_t s) {
+  if (n <= 0) return;
+  group_mask_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(g0, g1, active, n, mask);
+  AIRG_CHECK_LAUNCH();
+}
+
 // ------------------------------------------------------------------ permutations
 __global__ void scatter_kernel(double* y, const double* x, const int32_t* perm, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
