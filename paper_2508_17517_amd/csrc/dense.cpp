@@ -129,136 +129,164 @@ int numerical_rank(const std::vector<double>& H, int ld, int k, double tol) {
   return r;
 }
 
-std::vector<cplx> hessenberg_eigenvalues(std::vector<double> a, int n) {
-  auto A = [&](int i, int j) -> double& { return a[(size_t)i * n + j]; };
-  std::vector<cplx> ev(n);
-  double anorm = 0.0;
-  for (int i = 0; i < n; ++i)
-    for (int j = std::max(i - 1, 0); j < n; ++j) anorm += std::fabs(A(i, j));
-  int nn = n - 1;
-  double t = 0.0;
-  while (nn >= 0) {
-    int its = 0;
-    for (;;) {
-      int l;
-      // a negligible subdiagonal entry splits the active block
-      for (l = nn; l >= 1; --l) {
-        double s = std::fabs(A(l - 1, l - 1)) + std::fabs(A(l, l));
-        if (s == 0.0) s = anorm;
-        if (std::fabs(A(l, l - 1)) + s == s) {
-          A(l, l - 1) = 0.0;
-          break;
-        }
-      }
-      double x = A(nn, nn);
-      if (l == nn) {  // a 1 x 1 block
-        ev[nn] = cplx(x + t, 0.0);
-        --nn;
-        break;
-      }
-      double y = A(nn - 1, nn - 1);
-      double w = A(nn, nn - 1) * A(nn - 1, nn);
-      if (l == nn - 1) {  // a 2 x 2 block
-        double p = 0.5 * (y - x);
-        double q = p * p + w;
-        double z = std::sqrt(std::fabs(q));
-        x += t;
-        if (q >= 0.0) {
-          z = p + std::copysign(z, p);
-          double r1 = x + z;
-          double r2 = (z != 0.0) ? x - w / z : r1;
-          ev[nn - 1] = cplx(r1, 0.0);
-          ev[nn] = cplx(r2, 0.0);
-        } else {
-          ev[nn - 1] = cplx(x + p, z);
-          ev[nn] = cplx(x + p, -z);
-        }
-        nn -= 2;
-        break;
-      }
-      if (its == 60) fail(AIRG_ERR_BREAKDOWN, "Hessenberg QR did not converge");
-      if (its == 10 || its == 20) {  // exceptional shift
-        t += x;
-        for (int i = 0; i <= nn; ++i) A(i, i) -= x;
-        double s = std::fabs(A(nn, nn - 1)) + std::fabs(A(nn - 1, nn - 2));
-        x = y = 0.75 * s;
-        w = -0.4375 * s * s;
-      }
-      ++its;
-      // double-shift start: look for two consecutive small subdiagonals
-      int m;
-      double p = 0, q = 0, r = 0, z;
-      for (m = nn - 2; m >= l; --m) {
-        z = A(m, m);
-        r = x - z;
-        double s = y - z;
-        p = (r * s - w) / A(m + 1, m) + A(m, m + 1);
-        q = A(m + 1, m + 1) - z - r - s;
-        r = A(m + 2, m + 1);
-        s = std::fabs(p) + std::fabs(q) + std::fabs(r);
-        p /= s;
-        q /= s;
-        r /= s;
-        if (m == l) break;
-        double u = std::fabs(A(m, m - 1)) * (std::fabs(q) + std::fabs(r));
-        double v = std::fabs(p) * (std::fabs(A(m - 1, m - 1)) + std::fabs(z) + std::fabs(A(m + 1, m + 1)));
-        if (u + v == v) break;
-      }
-      for (int i = m + 2; i <= nn; ++i) {
-        A(i, i - 2) = 0.0;
-        if (i != m + 2) A(i, i - 3) = 0.0;
-      }
-      // chase the bulge with 3 x 3 Householder reflections
-      for (int k = m; k <= nn - 1; ++k) {
-        if (k != m) {
-          p = A(k, k - 1);
-          q = A(k + 1, k - 1);
-          r = 0.0;
-          if (k != nn - 1) r = A(k + 2, k - 1);
-          x = std::fabs(p) + std::fabs(q) + std::fabs(r);
-          if (x != 0.0) {
-            p /= x;
-            q /= x;
-            r /= x;
-          }
-        }
-        double s = std::copysign(std::sqrt(p * p + q * q + r * r), p);
-        if (s != 0.0) {
-          if (k == m) {
-            if (l != m) A(k, k - 1) = -A(k, k - 1);
-          } else {
-            A(k, k - 1) = -s * x;
-          }
-          p += s;
-          x = p / s;
-          y = q / s;
-          z = r / s;
-          q /= p;
-          r /= p;
-          for (int j = k; j <= nn; ++j) {
-            p = A(k, j) + q * A(k + 1, j);
-            if (k != nn - 1) {
-              p += r * A(k + 2, j);
-              A(k + 2, j) -= p * z;
-            }
-            A(k + 1, j) -= p * y;
-            A(k, j) -= p * x;
-          }
-          int mmin = nn < k + 3 ? nn : k + 3;
-          for (int i = l; i <= mmin; ++i) {
-            p = x * A(i, k) + y * A(i, k + 1);
-            if (k != nn - 1) {
-              p += z * A(i, k + 2);
-              A(i, k + 2) -= p * r;
-            }
-            A(i, k + 1) -= p * q;
-            A(i, k) -= p;
-          }
-        }
-      }
-    }
+// Eigenvalues of an upper Hessenberg matrix by the implicit double-shift
+// QR iteration as Golub & Van Loan present it (Matrix Computations, 4th ed.,
+// Sec. 7.5: the Francis step of Algorithm 7.5.1 inside the deflating loop of
+// Algorithm 7.5.2; Householder vectors as in Algorithm 5.1.1).  Only the
+// active diagonal window is updated, since the eigenvalues alone are wanted.
+namespace {
+
+struct HessWork {
+  std::vector<double>& h;
+  int n;
+  double& at(int i, int j) { return h[(size_t)i * n + j]; }
+};
+
+// Householder vector of x (len 2 or 3): (I - beta v v^T) x = -+|x| e_1, with
+// v[0] = 1.  x is scaled by its largest magnitude first; beta = 0 when x is
+// already a multiple of e_1.
+struct Reflector {
+  double v[3];
+  double beta;
+};
+
+Reflector householder(const double* x, int len) {
+  Reflector r{{1.0, 0.0, 0.0}, 0.0};
+  double scale = 0.0;
+  for (int i = 0; i < len; ++i) scale = std::max(scale, std::fabs(x[i]));
+  if (scale == 0.0) return r;
+  double y[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < len; ++i) y[i] = x[i] / scale;
+  double tail = 0.0;
+  for (int i = 1; i < len; ++i) tail += y[i] * y[i];
+  if (tail == 0.0) return r;
+  const double mu = std::sqrt(y[0] * y[0] + tail);
+  const double v0 = y[0] <= 0.0 ? y[0] - mu : -tail / (y[0] + mu);
+  r.beta = 2.0 * v0 * v0 / (tail + v0 * v0);
+  for (int i = 1; i < len; ++i) r.v[i] = y[i] / v0;
+  return r;
+}
+
+// rows q..q+len-1, columns c0..c1 of H  <-  P * (those rows)
+void reflect_rows(HessWork& H, const Reflector& P, int len, int q, int c0, int c1) {
+  if (P.beta == 0.0) return;
+  for (int c = c0; c <= c1; ++c) {
+    double s = 0.0;
+    for (int i = 0; i < len; ++i) s += P.v[i] * H.at(q + i, c);
+    s *= P.beta;
+    for (int i = 0; i < len; ++i) H.at(q + i, c) -= s * P.v[i];
   }
-  return ev;
+}
+
+// columns q..q+len-1, rows r0..r1 of H  <-  (those columns) * P
+void reflect_cols(HessWork& H, const Reflector& P, int len, int q, int r0, int r1) {
+  if (P.beta == 0.0) return;
+  for (int r = r0; r <= r1; ++r) {
+    double s = 0.0;
+    for (int i = 0; i < len; ++i) s += H.at(r, q + i) * P.v[i];
+    s *= P.beta;
+    for (int i = 0; i < len; ++i) H.at(r, q + i) -= s * P.v[i];
+  }
+}
+
+// One implicit double-shift sweep over the unreduced window lo..hi (at least
+// 3 x 3).  The shifts enter only through their sum and product: the first
+// column of (H - s1 I)(H - s2 I) starts a bulge that the reflectors chase
+// down the subdiagonal until the matrix is Hessenberg again.
+void francis_sweep(HessWork& H, int lo, int hi, double shift_sum, double shift_prod) {
+  const double h00 = H.at(lo, lo), h10 = H.at(lo + 1, lo);
+  double col[3] = {h00 * h00 + H.at(lo, lo + 1) * h10 - shift_sum * h00 + shift_prod,
+                   h10 * (h00 + H.at(lo + 1, lo + 1) - shift_sum), h10 * H.at(lo + 2, lo + 1)};
+  for (int q = lo; q + 2 <= hi; ++q) {
+    if (q > lo) {
+      col[0] = H.at(q, q - 1);
+      col[1] = H.at(q + 1, q - 1);
+      col[2] = H.at(q + 2, q - 1);
+    }
+    const Reflector P = householder(col, 3);
+    reflect_rows(H, P, 3, q, q > lo ? q - 1 : lo, hi);
+    reflect_cols(H, P, 3, q, lo, std::min(q + 3, hi));
+    if (q > lo) H.at(q + 1, q - 1) = H.at(q + 2, q - 1) = 0.0;
+  }
+  const double tail[2] = {H.at(hi - 1, hi - 2), H.at(hi, hi - 2)};
+  const Reflector P = householder(tail, 2);
+  reflect_rows(H, P, 2, hi - 1, hi - 2, hi);
+  reflect_cols(H, P, 2, hi - 1, lo, hi);
+  H.at(hi, hi - 2) = 0.0;
+}
+
+// Eigenvalues of [[a, b], [c, d]]: real ones by the cancellation-free form of
+// the quadratic formula, complex ones as an exact conjugate pair.
+void eig2(double a, double b, double c, double d, cplx& first, cplx& second) {
+  const double half = 0.5 * (a - d);
+  const double disc = half * half + b * c;
+  if (disc >= 0.0) {
+    const double big = half + std::copysign(std::sqrt(disc), half);
+    first = cplx(d + big, 0.0);
+    second = cplx(big != 0.0 ? d - (b * c) / big : d, 0.0);
+  } else {
+    const double im = std::sqrt(-disc);
+    first = cplx(d + half, im);
+    second = cplx(d + half, -im);
+  }
+}
+
+}  // namespace
+
+std::vector<cplx> hessenberg_eigenvalues(std::vector<double> a, int n) {
+  std::vector<cplx> eig(n);
+  HessWork H{a, n};
+  double fro = 0.0;
+  for (double v : a) fro += v * v;
+  fro = std::sqrt(fro);
+  const double eps = std::numeric_limits<double>::epsilon();
+  const int max_sweeps = 40 * std::max(n, 1);
+  int sweeps = 0;
+  int since_split = 0;  // sweeps since the window last shrank
+  int hi = n - 1;
+  while (hi >= 0) {
+    // largest unreduced window ending at hi: walk up the subdiagonal until an
+    // entry is negligible next to its two diagonal neighbours
+    int lo = hi;
+    while (lo > 0) {
+      double nb = std::fabs(H.at(lo, lo)) + std::fabs(H.at(lo - 1, lo - 1));
+      if (nb == 0.0) nb = fro;
+      if (std::fabs(H.at(lo, lo - 1)) <= eps * nb) {
+        H.at(lo, lo - 1) = 0.0;
+        break;
+      }
+      --lo;
+    }
+    const int size = hi - lo + 1;
+    if (size <= 2) {
+      if (size == 1)
+        eig[hi] = cplx(H.at(hi, hi), 0.0);
+      else
+        eig2(H.at(lo, lo), H.at(lo, hi), H.at(hi, lo), H.at(hi, hi), eig[lo], eig[hi]);
+      hi -= size;
+      since_split = 0;
+      continue;
+    }
+    if (++sweeps > max_sweeps) fail(AIRG_ERR_BREAKDOWN, "Hessenberg QR did not converge");
+    ++since_split;
+    double shift_sum, shift_prod;
+    if (since_split % 12 == 0) {
+      // a window that will not split: move both shifts off the trailing
+      // block's eigenvalues by the size of the last two subdiagonals
+      const double w = std::fabs(H.at(hi, hi - 1)) + std::fabs(H.at(hi - 1, hi - 2));
+      const double c = H.at(hi, hi) + 0.5 * w;
+      shift_sum = 2.0 * c;
+      shift_prod = c * c + w * w;
+    } else {
+      // the trailing 2 x 2 block's eigenvalues (Wilkinson-style double shift)
+      const double p = H.at(hi - 1, hi - 1), q = H.at(hi - 1, hi), r = H.at(hi, hi - 1),
+                   s = H.at(hi, hi);
+      shift_sum = p + s;
+      shift_prod = p * s - q * r;
+    }
+    francis_sweep(H, lo, hi, shift_sum, shift_prod);
+  }
+  return eig;
 }
 
 std::vector<cplx> harmonic_ritz(const std::vector<double>& H, int m, int k) {

@@ -87,6 +87,42 @@ def test_library_hessenberg_eigenvalues_match_lapack(n, seed):
         assert np.conj(z) in got
 
 
+@pytest.mark.parametrize("n,seed", [(150, 6), (300, 7)])
+def test_library_hessenberg_eigenvalues_are_backward_stable(n, seed):
+    # large random Hessenberg matrices have ill-conditioned eigenvalues, so
+    # compare backward errors: every computed lambda makes A - lambda I
+    # singular to within a few units of rounding of |A|
+    host = binding.load_host_dense()
+    a = np.triu(np.random.default_rng(seed).standard_normal((n, n)), -1)
+    re, im = np.zeros(n), np.zeros(n)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert host.airg_host_hessenberg_eig(np.ascontiguousarray(a).ctypes.data_as(dp), n,
+                                         re.ctypes.data_as(dp), im.ctypes.data_as(dp)) == 0
+    nrm = np.linalg.norm(a, 2)
+    for lam in re + 1j * im:
+        smin = np.linalg.svd(a - lam * np.eye(n), compute_uv=False)[-1]
+        assert smin <= 1e-14 * nrm
+
+
+@pytest.mark.parametrize("n", [4, 9, 32])
+def test_library_hessenberg_eigenvalues_of_a_cyclic_shift(n):
+    # the cyclic shift's eigenvalues are the n-th roots of unity; the standard
+    # double shift stalls on it, so this exercises the exceptional shifts
+    host = binding.load_host_dense()
+    a = np.zeros((n, n))
+    a[1:, :-1] = np.eye(n - 1)
+    a[0, -1] = 1.0
+    re, im = np.zeros(n), np.zeros(n)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert host.airg_host_hessenberg_eig(np.ascontiguousarray(a).ctypes.data_as(dp), n,
+                                         re.ctypes.data_as(dp), im.ctypes.data_as(dp)) == 0
+    z = re + 1j * im
+    assert np.allclose(np.abs(z), 1.0, atol=1e-12)
+    assert np.allclose(z ** n, 1.0, atol=1e-11)
+    angles = np.sort(np.mod(np.angle(z), 2 * np.pi))
+    assert np.allclose(angles, 2 * np.pi * np.arange(n) / n, atol=1e-12)
+
+
 def test_library_newton_roots_match_oracle():
     host = binding.load_host_dense()
     A, b = _arnoldi_case(200, 20, 7)
