@@ -370,6 +370,28 @@ int airg_fv_gradients(int64_t nx, int64_t ny, double theta, const int32_t* rowpt
                       const double* u, const double* lam, double* dg_west, double* dg_south,
                       double* dtheta, void* hip_stream);
 
+/* airg_fv_gradients without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and the same kernels,
+ * bit for bit the same results; the theta terms and the partial sums of the
+ * contraction live in one static device array of the library (about 34 MB,
+ * held by each device that runs this call until the process ends), whose
+ * address is looked up once per device on the first call there.
+ *   - n = nx ny must be at most 4194304 (2048 x 2048); larger grids get
+ *     AIRG_ERR_INVALID and nothing is enqueued.
+ *   - The work is enqueued on hip_stream and the call returns without
+ *     waiting: dg_west, dg_south and *dtheta are complete when the stream
+ *     reaches that point.
+ *   - Every call on one device shares that device's array, which keeps the
+ *     last call's contents: calls whose work can overlap on one device (other
+ *     streams, other threads, before the stream has drained the previous
+ *     call) race and must be serialised by the caller. */
+int airg_fv_gradients_noalloc(int64_t nx, int64_t ny, double theta, const int32_t* rowptr,
+                              const int32_t* col, const double* dval_dtheta,
+                              const double* db_dtheta, const double* u, const double* lam,
+                              double* dg_west, double* dg_south, double* dtheta,
+                              void* hip_stream);
+
 /* Release the handle and all its device memory (NULL is a no-op). */
 void airg_destroy(airg_handle h);
 

@@ -132,6 +132,7 @@ SYMBOLS = {
     "airg_fv_nnz": (c_i32, [c_i64, c_i64, c_dbl, P(c_i64)]),
     "airg_fv_assemble": (c_i32, [c_i64, c_i64, c_dbl] + [ctypes.c_void_p] * 9),
     "airg_fv_gradients": (c_i32, [c_i64, c_i64, c_dbl] + [ctypes.c_void_p] * 10),
+    "airg_fv_gradients_noalloc": (c_i32, [c_i64, c_i64, c_dbl] + [ctypes.c_void_p] * 10),
     "airg_destroy": (None, [ctypes.c_void_p]),
     "airg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "airg_last_error": (ctypes.c_char_p, []),

@@ -488,6 +488,22 @@ int airg_fv_gradients(int64_t nx, int64_t ny, double theta, const int32_t* rowpt
   });
 }
 
+int airg_fv_gradients_noalloc(int64_t nx, int64_t ny, double theta, const int32_t* rowptr,
+                              const int32_t* col, const double* dval_dtheta,
+                              const double* db_dtheta, const double* u, const double* lam,
+                              double* dg_west, double* dg_south, double* dtheta,
+                              void* hip_stream) {
+  return guard([&]() {
+    if (nx < 1 || ny < 1) fail(AIRG_ERR_INVALID, "bad grid");
+    if (!rowptr || !col || !dval_dtheta || !db_dtheta || !u || !lam || !dg_west || !dg_south ||
+        !dtheta)
+      fail(AIRG_ERR_INVALID, "null pointer");
+    fv_gradients_noalloc(nx, ny, theta, rowptr, col, dval_dtheta, db_dtheta, u, lam, dg_west,
+                         dg_south, dtheta, (hipStream_t)hip_stream);
+    return (int)AIRG_OK;
+  });
+}
+
 void airg_destroy(airg_handle h) {
   if (!h) return;
   hipStream_t s = h->H.s;

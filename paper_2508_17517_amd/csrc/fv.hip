@@ -7,6 +7,7 @@
 // - vy u_{k-nx} [j > 0]; b_k = vx g_W(j) [i = 0] + vy g_S(i) [j = 0], with
 // v = (cos theta, sin theta).  Entries with a zero coefficient are not stored.
 #include <cmath>
+#include <mutex>
 
 #include "kernels.hpp"
 
@@ -104,6 +105,55 @@ void fv_gradients(int64_t nx, int64_t ny, double theta, const int32_t* rowptr, c
   AIRG_CHECK_LAUNCH();
   launch_tree_dots(lam, 0, 1, r.get(), n, dtheta, work.get(), s);
   AIRG_HIP(hipStreamSynchronize(s));
+}
+
+// ---- the same gradients without allocating --------------------------------
+// The theta terms r (n doubles) and the partial sums of lam . r live in one
+// file-scope device array instead of stream-ordered allocations.  Every
+// device that runs the entry point holds its own copy until the process
+// ends; host code reaches it only through the address hipGetSymbolAddress
+// returns on that device (the array's name is a host-side stand-in).
+constexpr int64_t kNoallocWorkDoubles = 2 * ((kFvNoallocMaxN + 1023) / 1024) + 8;
+static __device__ __align__(256) double scratch[kFvNoallocMaxN + kNoallocWorkDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch address on the current device, looked up once per device.
+double* scratch_on_current_device() {
+  int dev = 0;
+  AIRG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(AIRG_ERR_INVALID, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    AIRG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(AIRG_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+void fv_gradients_noalloc(int64_t nx, int64_t ny, double theta, const int32_t* rowptr,
+                          const int32_t* col, const double* dval, const double* db, const double* u,
+                          const double* lam, double* dgw, double* dgs, double* dtheta, hipStream_t s) {
+  const int64_t n = nx * ny;
+  if (n > kFvNoallocMaxN) fail(AIRG_ERR_INVALID, "grid beyond the no-allocation limit of 4194304 unknowns");
+  if (dot_work_size(n, 1) > (size_t)kNoallocWorkDoubles)
+    fail(AIRG_ERR_INTERNAL, "no-allocation scratch too small for the dot partials");
+  double* base = scratch_on_current_device();
+  double* r = base;
+  double* work = base + kFvNoallocMaxN;
+  const double vx = std::cos(theta), vy = std::sin(theta);
+  const int64_t m = nx > ny ? nx : ny;
+  fv_inflow_grads_kernel<<<blocks_for(m, kBlock), kBlock, 0, s>>>(nx, ny, vx, vy, lam, dgw, dgs);
+  AIRG_CHECK_LAUNCH();
+  fv_theta_terms_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(rowptr, col, dval, db, u, n, r);
+  AIRG_CHECK_LAUNCH();
+  launch_tree_dots(lam, 0, 1, r, n, dtheta, work, s);
 }
 
 }  // namespace airg

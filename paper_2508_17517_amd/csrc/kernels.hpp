@@ -326,6 +326,12 @@ void fv_assemble(int64_t nx, int64_t ny, double theta, const double* gw, const d
 void fv_gradients(int64_t nx, int64_t ny, double theta, const int32_t* rowptr, const int32_t* col,
                   const double* dval, const double* db, const double* u, const double* lam,
                   double* dgw, double* dgs, double* dtheta, hipStream_t s);
+// The same launches with r and the dot partials in the file-scope scratch
+// array of fv.hip (no allocation, no wait); n = nx ny <= kFvNoallocMaxN.
+constexpr int64_t kFvNoallocMaxN = int64_t(1) << 22;
+void fv_gradients_noalloc(int64_t nx, int64_t ny, double theta, const int32_t* rowptr,
+                          const int32_t* col, const double* dval, const double* db, const double* u,
+                          const double* lam, double* dgw, double* dgs, double* dtheta, hipStream_t s);
 
 // ---------------------------------------------------------------- spgemm.hip
 // C = A B with c_ij accumulated over k ascending from 0.0, exact zeros dropped.
