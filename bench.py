@@ -126,10 +126,9 @@ def _tune(solver, main=False):
     if path and os.path.exists(path):
         with open(path) as f:
             t = json.load(f)
-        for e in t:
-            solver.set_lanes(e["level"], e["op"], e["lanes"], e["xcd_map"], e["lds"])
+        solver.pin_shapes(t)
         print(f"bench: launch shapes pinned from {path}", file=sys.stderr, flush=True)
-        return {"operators": len(t), "pinned_from": os.path.basename(path)}
+        return {"operators": len(t), "pinned_from": os.path.relpath(path, ROOT)}
     t = solver.autotune(reps=10)
     if path:
         with open(path, "w") as f:
@@ -425,7 +424,11 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tune-file", default=None,
                     help="read the main solver's launch shapes from this JSON file if it "
-                         "exists, else tune and write them there")
+                         "exists, else tune and write them there (default: the shapes kept "
+                         "for the workload in paper_2508_17517_amd/shapes/, which the "
+                         "full-size parity test pins too; none kept: tune)")
+    ap.add_argument("--retune", action="store_true",
+                    help="tune the main solver's shapes instead of pinning the kept ones")
     ap.add_argument("--batch-cols", type=int, default=64)
     ap.add_argument("--batch-problems", type=int, default=48)
     a = ap.parse_args()
@@ -455,7 +458,8 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     TUNE["on"] = not a.no_autotune
-    TUNE["file"] = a.tune_file
+    kept = os.path.join(ROOT, "paper_2508_17517_amd", "shapes", f"{a.workload}_fp64.json")
+    TUNE["file"] = a.tune_file or (kept if os.path.exists(kept) and not a.retune else None)
     tune = _tune(s, main=True)
     print(f"bench: autotune {tune}", file=sys.stderr, flush=True)
     st = s.stats()

@@ -10,6 +10,8 @@ the setup and solve runs in the library's HIP kernels.
     lam, info = s.adjoint_solve(w)             # A^T lam = w on a transpose hierarchy
 """
 import ctypes
+import json
+import os
 
 import numpy as np
 
@@ -17,6 +19,19 @@ from . import binding
 from .binding import AirgError, FP64, FP32, BF16, default_params  # noqa: F401
 
 __all__ = ["Solver", "BatchSolver", "AirgError", "default_params", "FP64", "FP32", "BF16"]
+
+
+SHAPES_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "shapes")
+
+
+def load_shapes(name):
+    """Launch shapes kept for a named workload (shapes/<name>.json, e.g.
+    "fv2048_fp64"): one entry per solve operator with its level, operator,
+    lanes per row, XCD mapping and LDS staging, as airg_autotune chose them on
+    an MI355X.  Pinning them with Solver.pin_shapes makes a solve launch
+    exactly those kernels, so its rounding (and its results) are reproducible."""
+    with open(os.path.join(SHAPES_DIR, name + ".json")) as f:
+        return json.load(f)
 
 
 def _torch():
@@ -136,6 +151,12 @@ class Solver:
         lanes per row (0 = row-block kernel), the XCD mapping and LDS staging."""
         binding.check(self.lib.airg_set_lanes(self.h, level, binding.OPERATORS[op], lanes, xcd_map,
                                               lds), self.lib)
+
+    def pin_shapes(self, shapes):
+        """Pin every operator's launch shape from a list of entries (as
+        load_shapes or autotune return them)."""
+        for e in shapes:
+            self.set_lanes(e["level"], e["op"], e["lanes"], e["xcd_map"], e["lds"])
 
     def level_info(self, level):
         li = binding.LevelInfo()

@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 from airg_inputs import workloads
+from parity import assert_elementwise
 
 pytestmark = pytest.mark.gpu
 
@@ -92,7 +93,8 @@ def test_each_column_iterates_like_the_oracle(outer):
         its.append(ik)
         assert infos[k]["converged"] == 1, k
         assert infos[k]["iterations"] == ik, (k, infos[k]["iterations"], ik)
-        assert np.linalg.norm(Xh[k] - xo) <= 1e-9 * np.linalg.norm(xo), k
+        assert np.linalg.norm(Xh[k] - xo) <= 1e-10 * np.linalg.norm(xo), k
+        assert_elementwise(Xh[k], xo)
     assert its[2] < its[0] and len(set(its)) >= 2
     s.close()
 
@@ -199,7 +201,8 @@ def test_problem_batch_runs_one_process_per_problem(outer):
     assert [i["iterations"] for i in infos] == its
     for k, (x, i) in enumerate(zip(xs, infos)):
         assert i["converged"] == 1
-        assert np.linalg.norm(x.cpu().numpy() - xo[k]) <= 1e-9 * np.linalg.norm(xo[k]), k
+        assert np.linalg.norm(x.cpu().numpy() - xo[k]) <= 1e-10 * np.linalg.norm(xo[k]), k
+        assert_elementwise(x.cpu().numpy(), xo[k])
     assert len(set(its)) >= 2
     s.close()
 
@@ -288,8 +291,11 @@ def test_autotuned_shapes_keep_the_solution_and_can_be_pinned():
     assert all(t["xcd_map"] in (0, 1) for t in tuned)
     assert all(t["best_us"] <= t["default_us"] for t in tuned)
     x1, i1 = s.solve(b)
-    assert i1["converged"] == 1 and abs(i1["iterations"] - i0["iterations"]) <= 1
-    assert float(torch.linalg.norm(x1 - x0) / torch.linalg.norm(x0)) <= 1e-8
+    # tuned shapes sum rows in another order: the same iterations, the
+    # solution to rounding
+    assert i1["converged"] == 1 and i1["iterations"] == i0["iterations"]
+    assert float(torch.linalg.norm(x1 - x0) / torch.linalg.norm(x0)) <= 1e-10
+    assert_elementwise(x1.cpu().numpy(), x0.cpu().numpy())
     # pinned shapes give bit-identical solves
     for t in tuned:
         s.set_lanes(t["level"], t["op"], 64 if t["op"] == "a" else 1, t["xcd_map"])
@@ -312,6 +318,56 @@ def test_autotuned_shapes_keep_the_solution_and_can_be_pinned():
     assert torch.equal(x4, x5)
     with pytest.raises(AirgError):
         s.set_lanes(0, "ff", 3)
+    s.close()
+
+
+def test_masked_row_block_and_staged_kernels_on_a_problem_batch():
+    # problems that stop at different counts switch the V-cycle's products to
+    # their masked versions (rows of stopped problems skipped); pinned to the
+    # row-block kernel or to LDS staging, those versions must sum like the
+    # one-lane and the row kernels with the same lanes, bit for bit, and
+    # every problem must keep the oracle's iteration count
+    _needs_gpu()
+    import scipy.sparse as sp
+    from paper_2508_17517_amd import AirgError, BatchSolver
+    probs = _problems()
+    A = sp.csr_matrix(sp.block_diag([q.scipy() for q in probs]))
+    A.sort_indices()
+    pr = oracle.Params()
+    levels = oracle.setup(A, pr)
+    seg = np.concatenate([[0], np.cumsum([q.n for q in probs])])
+    its = []
+    for k, q in enumerate(probs):
+        b = np.zeros(A.shape[0])
+        b[seg[k]:seg[k + 1]] = q.b
+        its.append(oracle.solve(A, b, pr, levels)[1])
+    assert len(set(its)) >= 2
+    s = BatchSolver([(q.indptr, q.indices, q.data) for q in probs])
+    bs = [torch.from_numpy(q.b).cuda() for q in probs]
+    ops = [(e["level"], e["op"]) for e in s.autotune(reps=1)]
+
+    def run(lanes, xcd, lds, fallback_lanes=None):
+        switched = 0
+        for l, op in ops:
+            try:
+                s.set_lanes(l, op, lanes, xcd, lds)
+                switched += 1
+            except AirgError:
+                s.set_lanes(l, op, fallback_lanes if fallback_lanes is not None else lanes, xcd, 0)
+        xs, infos = s.solve(bs)
+        assert [i["iterations"] for i in infos] == its
+        return [x.clone() for x in xs], switched
+
+    x1, _ = run(1, 0, 0)
+    x0, nrb = run(0, 1, 0, fallback_lanes=1)
+    assert nrb >= 1, "no operator took the row-block kernel"
+    for a, b in zip(x0, x1):
+        assert torch.equal(a, b)
+    x4, _ = run(4, 1, 0)
+    x4s, nlds = run(4, 1, 1)
+    assert nlds >= 1, "no operator took the LDS-staged kernel"
+    for a, b in zip(x4s, x4):
+        assert torch.equal(a, b)
     s.close()
 
 
@@ -385,9 +441,9 @@ def test_long_arnoldi_cycles_in_column_and_problem_batches():
         xo, ik, rel, _, _ = oracle.solve(A, B[k], pr, levels)
         assert ik > 40
         assert infos[k]["converged"] == 1 and infos[k]["restarts"] >= 1, k
-        # 40-step Arnoldi cycles amplify rounding differences: one iteration apart at most
-        assert abs(infos[k]["iterations"] - ik) <= 1, (k, infos[k]["iterations"], ik)
-        assert np.linalg.norm(Xh[k] - xo) <= 1e-9 * np.linalg.norm(xo), k
+        assert infos[k]["iterations"] == ik, (k, infos[k]["iterations"], ik)
+        assert np.linalg.norm(Xh[k] - xo) <= 1e-10 * np.linalg.norm(xo), k
+        assert_elementwise(Xh[k], xo)
     s.close()
     probs = [workloads.fv_random(48, 0.4, True, seed=311), workloads.fv_random(64, 0.9, True, seed=312)]
     Ab = sp.csr_matrix(sp.block_diag([q.scipy() for q in probs]))
@@ -405,6 +461,7 @@ def test_long_arnoldi_cycles_in_column_and_problem_batches():
         assert ik > 32
         assert infos[k]["converged"] == 1, k
         assert infos[k]["restarts"] >= (1 if ik > 41 else 0), k
-        assert abs(infos[k]["iterations"] - ik) <= 1, (k, infos[k]["iterations"], ik)
-        assert np.linalg.norm(xs[k].cpu().numpy() - xo) <= 1e-9 * np.linalg.norm(xo), k
+        assert infos[k]["iterations"] == ik, (k, infos[k]["iterations"], ik)
+        assert np.linalg.norm(xs[k].cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo), k
+        assert_elementwise(xs[k].cpu().numpy(), xo)
     sb.close()

@@ -1,11 +1,20 @@
 """Full-size checks at the benchmark workload (FV 2048 x 2048, theta 0.3,
 permuted, g ~ U(0,1)) in the launch configuration bench.py times.
 
-The oracle computes level 0 of the hierarchy at full size in seconds, so the
-CF split, A_ff, A_fc, the smoother coefficients, Z, the prolongator and A_1
-are compared bit for bit; the whole oracle solve is too slow at this size, so
-the GPU solution is checked against properties that hold at any size: the
-true residual and the distance to the exact sweep solution."""
+* Level 0 of the hierarchy at full size (the oracle computes it in seconds):
+  the CF split, A_ff, A_fc, the smoother coefficients, Z, the prolongator and
+  A_1 bit for bit.
+* The whole oracle solve, stored by tests/golden/make_fv2048_golden.py (a few
+  minutes on one core): with the launch shapes the benchmark pins
+  (paper_2508_17517_amd/shapes/fv2048_fp64.json), the GPU solve takes the
+  oracle's iteration count, every level has the oracle's size and smoother
+  coefficients, and the solution at 2048 sampled unknowns agrees element by
+  element to 1e-10 of max |x|.
+* Properties that hold at any size: the true residual and the distance to the
+  exact sweep solution."""
+import json
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -16,6 +25,8 @@ from airg_inputs import workloads
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fv2048_oracle.json")
 
 
 @pytest.fixture(scope="module")
@@ -75,4 +86,43 @@ def test_full_size_solve_properties(big):
     x2, info2 = s.solve(b)
     assert info2["iterations"] == info["iterations"]
     assert torch.equal(x, x2)
+    s.close()
+
+
+def test_full_size_solve_is_the_oracles_in_the_timed_launch_shapes(big):
+    from paper_2508_17517_amd import Solver, load_shapes
+    with open(GOLDEN) as f:
+        g = json.load(f)
+    assert g["n"] == big.n and g["nnz"] == big.nnz
+    s = Solver(big.indptr, big.indices, big.data)
+    s.pin_shapes(load_shapes("fv2048_fp64"))
+    st = s.stats()
+    lv = g["levels"]
+    assert st["levels"] == len(lv)
+    for l, L in enumerate(lv):
+        assert st["n"][l] == L["n"] and st["nnz"][l] == L["nnz"], l
+        if L["trunc_rel"] is not None:
+            assert st["trunc_rel"][l] == pytest.approx(float.fromhex(L["trunc_rel"]), rel=1e-8), l
+        e = s.export_level(l, what=("alpha", "roots"))
+        if L["coarsest"]:
+            want = np.array([complex(float.fromhex(a), float.fromhex(b)) for a, b in L["roots"]])
+            assert len(e["roots"]) == len(want)
+            assert np.allclose(np.sort_complex(e["roots"]), np.sort_complex(want), rtol=1e-9,
+                               atol=1e-12)
+        else:
+            assert st["n_f"][l] == L["n_f"], l
+            assert np.array_equal(e["alpha"], np.array([float.fromhex(a) for a in L["alpha"]])), l
+    b = torch.from_numpy(big.b).cuda()
+    x, info = s.solve(b)
+    print(f"fv2048 pinned shapes: gpu {info['iterations']} iterations, rel {info['rel_residual']:.3e}; "
+          f"oracle {g['iterations']}, rel {float.fromhex(g['rel_residual']):.3e}", flush=True)
+    assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
+    assert info["iterations"] == g["iterations"]
+    idx = np.array(g["sample_index"])
+    xo = np.array([float.fromhex(v) for v in g["sample_x"]])
+    xg = x.cpu().numpy()[idx]
+    xmax = float.fromhex(g["x_max_abs"])
+    err = np.abs(xg - xo).max()
+    print(f"max |x_gpu - x_oracle| over {len(idx)} samples: {err:.3e} (max |x| {xmax:.3e})", flush=True)
+    assert err <= 1e-10 * xmax
     s.close()

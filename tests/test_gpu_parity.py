@@ -14,6 +14,7 @@ import scipy.sparse as sp
 
 import oracle
 from airg_inputs import workloads, fv_advection, fd_advection
+from parity import assert_elementwise, mmatrix_inverse_inf_norm
 
 pytestmark = pytest.mark.gpu
 
@@ -101,6 +102,7 @@ def test_solve_matches_oracle(case):
     assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
     assert info["iterations"] == its
     assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+    assert_elementwise(xg, xo)
     # against the exact discrete solution too
     u = oracle.sweep_solve(p.scipy(), p.b, p.level)
     assert np.linalg.norm(xg - u) <= 1e-8 * np.linalg.norm(u)
@@ -134,6 +136,7 @@ def test_imported_oracle_hierarchy_solves_like_the_oracle():
     x, info = s.solve(torch.from_numpy(p.b).cuda())
     assert info["iterations"] == its
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    assert_elementwise(x.cpu().numpy(), xo)
     s.close()
 
 
@@ -168,6 +171,7 @@ def test_adjoint_solve_matches_oracle_and_sweep():
     lg = lam.cpu().numpy()
     assert info["converged"] == 1 and info["iterations"] == its
     assert np.linalg.norm(lg - lo) <= 1e-10 * np.linalg.norm(lo)
+    assert_elementwise(lg, lo, what="adjoint solution")
     ls = oracle.sweep_solve(A, w, p.level, transpose=True)
     assert np.linalg.norm(lg - ls) <= 1e-8 * np.linalg.norm(ls)
     s.close()
@@ -282,24 +286,54 @@ def test_grid_aligned_flow(theta):
     x, info = s.solve(torch.from_numpy(p.b).cuda())
     assert info["iterations"] == its
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    assert_elementwise(x.cpu().numpy(), xo)
     s.close()
 
 
-@pytest.mark.parametrize("prec,name", [(1, "fp32"), (2, "bf16")])
-def test_mixed_precision_reaches_the_fp64_tolerance(prec, name):
-    # FP32 / BF16 storage in the V-cycle, FP64 outer FGMRES: the true FP64
-    # residual still reaches 1e-10 and the solution matches the FP64 oracle's
+MIXED_CASES = {
+    "fv128_fp32": (lambda: workloads.fv_random(128, 0.3, True), 1),
+    "fv128_bf16": (lambda: workloads.fv_random(128, 0.3, True), 2),
+    "dg32_fp32": (lambda: workloads.dg_random(32, math.pi / 5, True), 1),
+    "dg32_bf16": (lambda: workloads.dg_random(32, math.pi / 5, True), 2),
+}
+
+
+@pytest.mark.parametrize("case", list(MIXED_CASES))
+def test_mixed_precision_reaches_the_fp64_tolerance(case):
+    # FP32 / BF16 storage in the V-cycle, FP64 outer FGMRES (iterative
+    # refinement): the true FP64 residual reaches 1e-10 and the solution
+    # agrees with the FP64 oracle's within the bound the two residuals give.
+    # Both satisfy A x = b - r, so x_g - x_o = A^{-1}(r_o - r_g) and
+    # |x_g - x_o|_inf <= |A^{-1}|_inf |r_o - r_g|_inf.  |A^{-1}|_inf is one
+    # sweep away for the FV system (a triangular M-matrix: A^{-1} >= 0, so it
+    # is max(A^{-1} 1)) and comes from the dense inverse for the small DG
+    # system.  The perturbation of the V-cycle (FP32 rounding 6e-8, BF16
+    # 4e-3 relative) leaves the iteration count of these cases equal to the
+    # FP64 oracle's.
     _needs_gpu()
-    p = workloads.fv_random(128, 0.3, True)
-    xo, its, rel, _, _ = oracle.solve(p.scipy(), p.b)
+    make, prec = MIXED_CASES[case]
+    p = make()
+    A = p.scipy()
+    xo, its, rel, _, _ = oracle.solve(A, p.b)
     s = _solver(p, precision=prec)
     x, info = s.solve(torch.from_numpy(p.b).cuda())
     xg = x.cpu().numpy()
-    err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
-    print(f"{name}: iterations {info['iterations']} (fp64 oracle {its}), rel err vs oracle {err:.2e}")
+    rg = p.b - A @ xg
+    ro = p.b - A @ xo
+    if case.startswith("fv"):
+        ainv = mmatrix_inverse_inf_norm(A, p.level)
+    else:
+        ainv = float(np.abs(np.linalg.inv(A.toarray())).sum(axis=1).max())
+    bound = ainv * np.abs(ro - rg).max()
+    err = np.abs(xg - xo).max()
+    print(f"{case}: iterations {info['iterations']} (fp64 oracle {its}), max |x - x_oracle| "
+          f"{err:.2e}, bound {bound:.2e} (|A^-1|_inf {ainv:.1f}), relative to max |x| "
+          f"{err / np.abs(xo).max():.2e}")
     assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
-    assert err <= 1e-8
-    assert info["iterations"] <= its + 6
+    assert np.linalg.norm(rg) <= 1e-10 * (1 + 1e-6) * np.linalg.norm(p.b)
+    assert info["iterations"] == its
+    # the bound, with room for the rounding of the residuals computed here
+    assert err <= 1.01 * bound + 1e-14 * np.abs(xo).max()
     s.close()
 
 
@@ -349,6 +383,8 @@ def test_richardson_matches_oracle(case):
     assert abs(info["rel_residual"] - rel) <= 1e-3 * rel + 1e-16
     scale = max(np.linalg.norm(xo), np.linalg.norm(x0))
     assert np.linalg.norm(xg - xo) <= 1e-10 * scale
+    # g = 0: the solution is zero, so the error is measured against x0's scale
+    assert np.abs(xg - xo).max() <= 1e-10 * max(np.abs(xo).max(), 1.0)
     s.close()
 
 
@@ -365,6 +401,7 @@ def test_assembled_smoother_matches_oracle(case):
     assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
     assert info["iterations"] == its
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    assert_elementwise(x.cpu().numpy(), xo)
     s.close()
 
 
@@ -407,6 +444,7 @@ def test_degenerate_systems_match_oracle(case):
     x, info = s.solve(torch.from_numpy(b).cuda())
     assert info["converged"] == 1 and info["iterations"] == its
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * max(np.linalg.norm(xo), 1.0)
+    assert_elementwise(x.cpu().numpy(), xo)
     s.close()
 
 
@@ -423,6 +461,7 @@ def test_nair_matches_oracle(smoother):
     assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
     assert info["iterations"] == its
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    assert_elementwise(x.cpu().numpy(), xo)
     s.close()
 
 
@@ -455,6 +494,7 @@ def test_c_point_smoothing_matches_oracle(case):
     assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
     assert info["iterations"] == its
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    assert_elementwise(x.cpu().numpy(), xo)
     # storage in the paper's terms gains A_cf and A_cc on every level
     s_f = _solver(p, smoother=int(smoother == "assembled"))
     extra = sum(L.Acf.nnz + L.Acc.nnz + (L.Ahat_cc.nnz if smoother == "assembled" else 0)
@@ -507,9 +547,10 @@ def test_long_arnoldi_cycle_past_the_fused_sweeps():
     x, info = s.solve(torch.from_numpy(p.b).cuda())
     assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
     assert info["restarts"] >= 1
-    # 40-step Arnoldi cycles amplify rounding differences: one iteration apart at most
-    assert abs(info["iterations"] - its) <= 1
-    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-9 * np.linalg.norm(xo)
+    assert info["iterations"] == its
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    assert_elementwise(x.cpu().numpy(), xo)
+    assert_elementwise(x.cpu().numpy(), xo)
     s.close()
 
 
@@ -527,6 +568,7 @@ def test_c_point_smoothing_in_the_adjoint_and_problem_batches():
     lam, info = s.adjoint_solve(torch.from_numpy(w).cuda())
     assert info["converged"] == 1 and info["iterations"] == its
     assert np.linalg.norm(lam.cpu().numpy() - lo) <= 1e-10 * np.linalg.norm(lo)
+    assert_elementwise(lam.cpu().numpy(), lo)
     s.close()
     probs = [workloads.fv_random(40, 0.3, True, seed=201), workloads.fv_random(24, 1.2, True, seed=202)]
     sb = BatchSolver([(q.indptr, q.indices, q.data) for q in probs], smooth_type=1, precision=1)
@@ -556,7 +598,8 @@ def test_decoupled_grid_lines_solve_exactly():
         _csr_equal("Z", g["z"], L.Z, l)
     x, info = s.solve(torch.from_numpy(p.b).cuda())
     assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
-    assert abs(info["iterations"] - its) <= 1
+    assert info["iterations"] == its
+    assert_elementwise(x.cpu().numpy(), xo)
     u = oracle.sweep_solve(A, p.b, p.level)
     assert np.linalg.norm(x.cpu().numpy() - u) <= 1e-9 * np.linalg.norm(u)
     s.close()
