@@ -293,6 +293,19 @@ typedef struct {
  * bytes and flops per launch.  Does not change the solver's state. */
 int airg_time_kernels(airg_handle h, int cls, int reps, airg_kernel_timing* out);
 
+/* Streaming probe, for benchmarks: the average device time (*avg_ms) of one
+ * pass of the library's streaming read (kind 0: reads `bytes` from src,
+ * writes nothing to dst, which must still be a valid device pointer of 8
+ * bytes or more) or copy (kind 1: src to dst, `bytes` each) kernel, with
+ * `blocks` workgroups of 256 threads, 16-byte loads and stores, timed with
+ * HIP events over `reps` back-to-back launches on hip_stream after one
+ * warm-up launch.  Device pointers, 16-byte aligned; bytes a positive
+ * multiple of 16.  It gives the bandwidth a plain stream reaches on this
+ * device (from HBM for buffers far above the on-die caches, from the caches
+ * for small ones), the ceiling the sparse products are compared with. */
+int airg_stream_probe(int kind, const void* src, void* dst, int64_t bytes, int reps, int blocks,
+                      double* avg_ms, void* hip_stream);
+
 /* Solve operators, for the launch-shape tuner. */
 enum airg_operator {
   AIRG_OP_FF = 0,   /* A_ff of a level (smoother steps) */

@@ -133,6 +133,8 @@ SYMBOLS = {
     "airg_fv_assemble": (c_i32, [c_i64, c_i64, c_dbl] + [ctypes.c_void_p] * 9),
     "airg_fv_gradients": (c_i32, [c_i64, c_i64, c_dbl] + [ctypes.c_void_p] * 10),
     "airg_fv_gradients_noalloc": (c_i32, [c_i64, c_i64, c_dbl] + [ctypes.c_void_p] * 10),
+    "airg_stream_probe": (c_i32, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, c_i64, ctypes.c_int,
+                                  ctypes.c_int, P(c_dbl), ctypes.c_void_p]),
     "airg_destroy": (None, [ctypes.c_void_p]),
     "airg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "airg_last_error": (ctypes.c_char_p, []),

@@ -21,8 +21,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libairg.so")
 HOST_LIB = os.path.join(HERE, "libairg_dense_host.so")
 
-HIP_SOURCES = ["vec.hip", "spmv.hip", "cf.hip", "spgemm.hip", "order.hip", "fv.hip", "dense.cpp", "hierarchy.cpp",
-               "solve.cpp", "api.cpp"]
+HIP_SOURCES = ["vec.hip", "spmv.hip", "cf.hip", "spgemm.hip", "order.hip", "fv.hip", "probe.hip",
+               "dense.cpp", "hierarchy.cpp", "solve.cpp", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("AIRG_OFFLOAD_ARCH", "gfx950")
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -488,6 +488,20 @@ int airg_fv_gradients(int64_t nx, int64_t ny, double theta, const int32_t* rowpt
   });
 }
 
+int airg_stream_probe(int kind, const void* src, void* dst, int64_t bytes, int reps, int blocks,
+                      double* avg_ms, void* hip_stream) {
+  return guard([&]() {
+    if (kind != 0 && kind != 1) fail(AIRG_ERR_INVALID, "kind must be 0 (read) or 1 (copy)");
+    if (!src || !dst || !avg_ms) fail(AIRG_ERR_INVALID, "null pointer");
+    if (bytes < 16 || bytes % 16 != 0) fail(AIRG_ERR_INVALID, "bytes must be a positive multiple of 16");
+    if (reps < 1 || blocks < 1 || blocks > (1 << 20)) fail(AIRG_ERR_INVALID, "bad reps or blocks");
+    if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
+      fail(AIRG_ERR_INVALID, "buffers must be 16-byte aligned");
+    *avg_ms = stream_probe(kind, src, dst, bytes, reps, blocks, (hipStream_t)hip_stream);
+    return (int)AIRG_OK;
+  });
+}
+
 int airg_fv_gradients_noalloc(int64_t nx, int64_t ny, double theta, const int32_t* rowptr,
                               const int32_t* col, const double* dval_dtheta,
                               const double* db_dtheta, const double* u, const double* lam,

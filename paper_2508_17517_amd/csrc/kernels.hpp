@@ -333,6 +333,14 @@ void fv_gradients_noalloc(int64_t nx, int64_t ny, double theta, const int32_t* r
                           const int32_t* col, const double* dval, const double* db, const double* u,
                           const double* lam, double* dgw, double* dgs, double* dtheta, hipStream_t s);
 
+// ---------------------------------------------------------------- probe.hip
+// Average device time (ms) of one pass of a streaming read (kind 0: src only,
+// dst receives nothing unless the sum is -1e300) or copy (kind 1) of `bytes`
+// bytes, over `reps` back-to-back launches of `blocks` workgroups after one
+// warm-up launch, timed with HIP events on s.
+double stream_probe(int kind, const void* src, void* dst, int64_t bytes, int reps, int blocks,
+                    hipStream_t s);
+
 // ---------------------------------------------------------------- spgemm.hip
 // C = A B with c_ij accumulated over k ascending from 0.0, exact zeros dropped.
 void spgemm(const CSR& A, const CSR& B, CSR& C, hipStream_t s);
