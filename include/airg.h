@@ -87,6 +87,14 @@ typedef struct {
                                 AIRG_INVERSE_ARNOLDI */
   int32_t smooth_type;       /* airg_smooth_type: the up-smooths of each level,
                                 AIRG_SMOOTH_TYPE_F */
+  double atol;               /* absolute tolerance of the outer loop: a residual norm at
+                                or below max(rtol |b|, atol) stops it, 1e-50 (Sec. 3
+                                option set) */
+  int32_t graph;             /* 1: replay each V-cycle from a captured HIP graph (captured
+                                on first use per pair of vectors, recaptured after a
+                                launch-shape change; the same launches, bit for bit the
+                                same results); 0: launch its kernels one by one, 0 */
+  int32_t reserved;          /* must be 0 */
 } airg_params;
 
 /* The polynomial approximation of A_ff^{-1} in the smoother and in Ahat^{-1}.

@@ -24,6 +24,7 @@ class Params:
     added_roots: bool = True         # extra copies of outlying roots (Loe & Morgan 2022)
     seed: int = 17517
     rtol: float = 1e-10
+    atol: float = 1e-50              # absolute residual tolerance of the outer loop (Sec. 3 option set)
     max_it: int = 500
     restart: int = 30
     outer: str = "fgmres"            # or "richardson": the paper's undamped Richardson (Sec. 3)

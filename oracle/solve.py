@@ -68,19 +68,22 @@ def vcycle(levels, r, lvl=0, exact_coarse=False, assembled=False, neumann=False,
     return e
 
 
-def fgmres(A, precond, b, rtol=1e-10, max_it=500, restart=30, x0=None):
-    """Returns (x, iterations, true relative residual, estimate history)."""
+def fgmres(A, precond, b, rtol=1e-10, max_it=500, restart=30, x0=None, atol=0.0):
+    """Returns (x, iterations, true relative residual, estimate history).  A
+    residual norm at or below max(rtol |b|, atol) stops the iteration (the
+    paper's option set has both tolerances, Sec. 3)."""
     n = len(b)
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
     bnorm = linalg.norm(b)
     hist = []
     if bnorm == 0.0:
         return np.zeros(n), 0, 0.0, hist
+    tol = max(rtol * bnorm, atol)
     its = 0
     while True:
         r = b - linalg.spmv(A, x)
         beta = linalg.norm(r)
-        if beta <= rtol * bnorm or its >= max_it:
+        if beta <= tol or its >= max_it:
             return x, its, beta / bnorm, hist
         V = [r / beta]
         Zs = []
@@ -115,7 +118,7 @@ def fgmres(A, precond, b, rtol=1e-10, max_it=500, restart=30, x0=None):
             k = j + 1
             est = abs(g[j + 1])
             hist.append(est / bnorm)
-            if est <= rtol * bnorm or its >= max_it:
+            if est <= tol or its >= max_it:
                 break
             hn = linalg.norm(w)
             V.append(w / hn)
@@ -126,7 +129,7 @@ def fgmres(A, precond, b, rtol=1e-10, max_it=500, restart=30, x0=None):
             x = x + y[i] * Zs[i]
 
 
-def richardson(A, precond, b, rtol=1e-10, max_it=500, x0=None):
+def richardson(A, precond, b, rtol=1e-10, max_it=500, x0=None, atol=0.0):
     """Undamped Richardson, x <- x + M (b - A x), the paper's outer loop (Sec. 3),
     stopped on the unpreconditioned residual: |b - A x| <= rtol |b|, or
     rtol |b - A x0| when b = 0 (the paper's runs have g = 0 and x0 = 1).
@@ -141,7 +144,7 @@ def richardson(A, precond, b, rtol=1e-10, max_it=500, x0=None):
     if ref == 0.0:
         return x, 0, 0.0, hist
     its = 0
-    while rn > rtol * ref and its < max_it:
+    while rn > max(rtol * ref, atol) and its < max_it:
         x = x + precond(r)
         r = b - linalg.spmv(A, x)
         rn = linalg.norm(r)
@@ -167,9 +170,9 @@ def solve(A, b, p=None, levels=None, x0=None):
     M = lambda v: vcycle(levels, v, 0, p.exact_coarse, p.smoother == "assembled",  # noqa: E731
                          p.inverse_type == "neumann", p.smooth_type)
     if p.outer == "richardson":
-        x, its, rel, hist = richardson(A, M, b, p.rtol, p.max_it, x0)
+        x, its, rel, hist = richardson(A, M, b, p.rtol, p.max_it, x0, p.atol)
     elif p.outer == "fgmres":
-        x, its, rel, hist = fgmres(A, M, b, p.rtol, p.max_it, p.restart, x0)
+        x, its, rel, hist = fgmres(A, M, b, p.rtol, p.max_it, p.restart, x0, p.atol)
     else:
         raise ValueError(f"unknown outer loop {p.outer!r}")
     return x, its, rel, levels, hist

@@ -28,7 +28,8 @@ class Params(ctypes.Structure):
                 ("max_levels", c_i32), ("added_roots", c_i32), ("precision", c_i32),
                 ("max_it", c_i32), ("restart", c_i32), ("keep_setup_data", c_i32),
                 ("locality_order", c_i32), ("outer", c_i32), ("smoother", c_i32),
-                ("inverse_type", c_i32), ("smooth_type", c_i32)]
+                ("inverse_type", c_i32), ("smooth_type", c_i32), ("atol", c_dbl), ("graph", c_i32),
+                ("reserved", c_i32)]
 
 
 class SolveInfo(ctypes.Structure):

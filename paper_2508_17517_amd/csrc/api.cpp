@@ -61,6 +61,9 @@ void check_params(const airg_params& p) {
   if (p.min_coarse_rows < 1) bad("min_coarse_rows");
   if (p.precision != AIRG_FP64 && p.precision != AIRG_FP32 && p.precision != AIRG_BF16) bad("precision");
   if (!(p.rtol > 0.0 && p.rtol < 1.0)) bad("rtol");
+  if (!(p.atol >= 0.0 && std::isfinite(p.atol))) bad("atol");
+  if (p.graph != 0 && p.graph != 1) bad("graph");
+  if (p.reserved != 0) bad("reserved (must be 0)");
   if (p.max_it < 0) bad("max_it");
   if (p.restart < 1 || p.restart > 512) bad("restart");
   if (p.outer != AIRG_OUTER_FGMRES && p.outer != AIRG_OUTER_RICHARDSON) bad("outer");
@@ -186,6 +189,9 @@ int airg_params_default(airg_params* p) {
   p->smoother = AIRG_SMOOTH_POLY;
   p->inverse_type = AIRG_INVERSE_ARNOLDI;
   p->smooth_type = AIRG_SMOOTH_TYPE_F;
+  p->atol = 1e-50;
+  p->graph = 0;
+  p->reserved = 0;
   return AIRG_OK;
 }
 

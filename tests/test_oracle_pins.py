@@ -395,6 +395,45 @@ def test_fgmres_matches_brute_force_gmres_residuals():
     assert np.allclose(x, np.linalg.solve(Ad, b), rtol=1e-8)
 
 
+def test_fgmres_absolute_tolerance_stops_at_the_first_small_residual():
+    # a residual at or below max(rtol |b|, atol) stops the outer loop (the
+    # paper's option set has both, Sec. 3): with rtol negligible, atol = c |b|
+    # stops where rtol = c would, at the first brute-force GMRES residual
+    # below c |b|; with atol 0 nothing changes
+    A = _rand_diag_dominant(80, 12, dom=1.1)
+    b = np.random.default_rng(1).uniform(size=80)
+    bn = np.linalg.norm(b)
+    Ad = A.toarray()
+    K, res = [b], []
+    for k in range(1, 9):
+        K.append(Ad @ K[-1])
+        Km = np.array(K[1:]).T
+        c, *_ = np.linalg.lstsq(Km, b, rcond=None)
+        res.append(np.linalg.norm(b - Km @ c) / bn)
+    for c in (1e-1, 1e-2, 1e-3):
+        first = next(k + 1 for k, r in enumerate(res) if r <= c)
+        x, its, rel, hist = oracle.fgmres(A, lambda v: v, b, rtol=1e-300, atol=c * bn)
+        assert its == first, (c, its, first)
+        x2, its2, _, _ = oracle.fgmres(A, lambda v: v, b, rtol=c, atol=0.0)
+        assert its2 == its and np.array_equal(x, x2)
+    # the absolute test is on the residual norm itself, not relative to |b|
+    x, its, rel, hist = oracle.fgmres(A, lambda v: v, 1e4 * b, rtol=1e-300, atol=10.0 * bn)
+    assert its == next(k + 1 for k, r in enumerate(res) if r <= 1e-3)
+
+
+def test_richardson_absolute_tolerance():
+    p = workloads.fv_random(12, 1.0, True)
+    A = p.scipy()
+    levels = oracle.setup(A)
+    M = lambda v: oracle.vcycle(levels, v)  # noqa: E731
+    x, its, rel, hist = oracle.richardson(A, M, p.b, rtol=1e-12)
+    bn = np.linalg.norm(p.b)
+    for k in range(1, its):
+        c = hist[k] / bn * 1.0000001
+        x2, its2, _, h2 = oracle.richardson(A, M, p.b, rtol=1e-300, atol=c * bn)
+        assert its2 == next(j for j, h in enumerate(hist) if h <= c * bn)
+
+
 # --------------------------------------------------------------------- adjoint (P11, P12)
 
 def test_adjoint_identity_and_adjoint_solve():
