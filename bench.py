@@ -48,35 +48,23 @@ def cpu_baseline(sample_side=1024):
                       f"{os.cpu_count()} cores, the oracle's sparse kernels run on one thread"}
 
 
-def copy_bandwidth(nbytes=1 << 30, reps=10):
-    """Read + write bandwidth of a plain device copy of nbytes (the calibration
-    kernel for the HBM byte counters)."""
+def stream_bandwidth(kind, nbytes, blocks=8192, reps=20):
+    """GB/s of the library's hand-written streaming kernels (airg_stream_probe):
+    kind "read" reads nbytes, "copy" reads and writes nbytes each (16-byte
+    accesses, `blocks` workgroups of 256 threads).  Far above the on-die caches
+    this is the practical HBM ceiling the sparse products are compared with."""
+    import ctypes
     import torch
+    from paper_2508_17517_amd import binding, _ptr, _stream_ptr
+    lib = binding.load()
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    e1.synchronize()
-    return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
-
-
-def read_bandwidth(nbytes=1 << 31, reps=10):
-    """Read-only bandwidth of a plain device reduction over nbytes: the
-    practical ceiling of kernels that, like the products, mostly read."""
-    import torch
-    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
-    src.sum()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        src.sum()
-    e1.record()
-    e1.synchronize()
-    return 1.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    dst = torch.empty_like(src) if kind == "copy" else torch.zeros(8, dtype=torch.float64, device="cuda")
+    ms = ctypes.c_double()
+    binding.check(lib.airg_stream_probe(0 if kind == "read" else 1, _ptr(src), _ptr(dst), nbytes, reps,
+                                        blocks, ctypes.byref(ms), _stream_ptr(None)), lib)
+    moved = (2 if kind == "copy" else 1) * nbytes
+    del src, dst
+    return moved / (ms.value * 1e-3) / 1e9
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fv2048_poly_hbm_traffic.md")
@@ -112,6 +100,8 @@ def measured_traffic(workload):
 
 
 TUNE = {"on": True, "file": None}
+# solver options every leg uses (set from the command line)
+SOLVER_OPTS = {}
 
 
 def _tune(solver, main=False):
@@ -166,7 +156,7 @@ def batched_legs(a, p, s64, value64, ip, ix, dv):
     k = a.batch_cols
     print(f"bench: batch: {k} right-hand sides, FP32 V-cycle", file=sys.stderr, flush=True)
     B = torch.from_numpy(workloads.rhs_batch(p, k)).cuda()
-    sm = Solver(ip, ix, dv, precision=binding.FP32)
+    sm = Solver(ip, ix, dv, precision=binding.FP32, **SOLVER_OPTS)
     _tune(sm)
     X = torch.zeros_like(B)
     dt, (X, infos) = _timed(lambda: sm.solve(B, X), 1, max(1, min(a.steps, 3)))
@@ -195,7 +185,7 @@ def batched_legs(a, p, s64, value64, ip, ix, dv):
     bs = [torch.from_numpy(pr.b).cuda() for pr in probs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sb = BatchSolver(mats, precision=binding.FP32)
+    sb = BatchSolver(mats, precision=binding.FP32, **SOLVER_OPTS)
     torch.cuda.synchronize()
     setup_b = time.perf_counter() - t0
     _tune(sb)
@@ -238,7 +228,7 @@ def dg_legs(a, side=1024):
     for name, prec in (("fp64", binding.FP64), ("fp32", binding.FP32), ("bf16", binding.BF16)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sm = Solver(ip, ix, dv, precision=prec)
+        sm = Solver(ip, ix, dv, precision=prec, **SOLVER_OPTS)
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         _tune(sm)
@@ -323,7 +313,7 @@ def paper_legs(a, side=3606):
             p = q
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sm = Solver(ip, ix, dv, poly_order=6, outer=binding.OUTER_RICHARDSON, **over)
+        sm = Solver(ip, ix, dv, poly_order=6, outer=binding.OUTER_RICHARDSON, **over, **SOLVER_OPTS)
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         _tune(sm)
@@ -360,7 +350,7 @@ def mixed_legs(a, p, x64, value64, ip, ix, dv, b):
     res = {}
     xref = x64.clone()
     for name, prec in (("fp32", binding.FP32), ("bf16", binding.BF16)):
-        sm = Solver(ip, ix, dv, precision=prec)
+        sm = Solver(ip, ix, dv, precision=prec, **SOLVER_OPTS)
         _tune(sm)
         xm = torch.zeros_like(b)
         dtm, (xm, im) = _timed(lambda: sm.solve(b, xm), a.warmup, a.steps)
@@ -381,7 +371,7 @@ def assembled_leg(a, p, value64, ip, ix, dv, b):
     product per level instead of d matrix-free ones), FP64, same tolerance."""
     import torch
     from paper_2508_17517_amd import Solver, binding
-    sm = Solver(ip, ix, dv, smoother=binding.SMOOTH_ASSEMBLED)
+    sm = Solver(ip, ix, dv, smoother=binding.SMOOTH_ASSEMBLED, **SOLVER_OPTS)
     _tune(sm)
     xm = torch.zeros_like(b)
     dt, (xm, im) = _timed(lambda: sm.solve(b, xm), a.warmup, a.steps)
@@ -429,6 +419,9 @@ def main():
                          "full-size parity test pins too; none kept: tune)")
     ap.add_argument("--retune", action="store_true",
                     help="tune the main solver's shapes instead of pinning the kept ones")
+    ap.add_argument("--graph", type=int, default=None, choices=(0, 1),
+                    help="replay V-cycles from captured HIP graphs (1) or launch them kernel by "
+                         "kernel (0); default: the library's default")
     ap.add_argument("--batch-cols", type=int, default=64)
     ap.add_argument("--batch-problems", type=int, default=48)
     a = ap.parse_args()
@@ -442,6 +435,8 @@ def main():
     from airg_inputs import workloads
     from paper_2508_17517_amd import Solver, binding
 
+    if a.graph is not None:
+        SOLVER_OPTS["graph"] = a.graph
     side, theta, perm = WORKLOADS[a.workload]
     print(f"bench: generating {a.workload}", file=sys.stderr, flush=True)
     p = workloads.fv_random(side, theta, perm)
@@ -454,7 +449,7 @@ def main():
     torch.cuda.synchronize()
     print("bench: setup", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    s = Solver(ip, ix, dv)
+    s = Solver(ip, ix, dv, **SOLVER_OPTS)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     TUNE["on"] = not a.no_autotune
@@ -545,10 +540,12 @@ def main():
         out["dg_q1"] = optional("dg", dg_legs, a)
     if not a.no_paper:
         out["paper_fd"] = optional("paper", paper_legs, a)
-    out["hbm_copy_gbps"] = copy_bandwidth()
-    out["hbm_read_gbps"] = read_bandwidth()
-    print(f"bench: copy kernel {out['hbm_copy_gbps']:.1f} GB/s, read-only reduction "
-          f"{out['hbm_read_gbps']:.1f} GB/s", file=sys.stderr, flush=True)
+    # the practical ceilings, from the library's own streaming kernels
+    out["hbm_read_gbps"] = stream_bandwidth("read", 1 << 31)
+    out["hbm_copy_gbps"] = stream_bandwidth("copy", 1 << 30, blocks=16384)
+    out["roofline"]["frac_of_read_ceiling"] = dom["gbps"] / out["hbm_read_gbps"]
+    print(f"bench: streaming read {out['hbm_read_gbps']:.1f} GB/s, copy {out['hbm_copy_gbps']:.1f} GB/s "
+          f"(library probes)", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.cpu_sample)

@@ -104,6 +104,9 @@ struct Hierarchy {
   // its rows
   DBuf<int32_t> mgp0, mgp1;
   int64_t mgroups = 0;
+  // bumped whenever a solve operator's launch shape changes (captured
+  // V-cycles of an older epoch are stale)
+  uint64_t shape_epoch = 0;
 };
 
 // Build the hierarchy for A (device CSR, validated) with parameters p.

@@ -33,6 +33,8 @@
 namespace airg {
 
 Workspace::~Workspace() {
+  for (const VcycleGraph& g : graphs) (void)hipGraphExecDestroy(g.exec);
+  if (cap) (void)hipStreamDestroy(cap);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
   if (pin) (void)hipHostFree(pin);
@@ -50,6 +52,9 @@ static void read_small(Workspace& W, const double* dev, double* host, size_t n, 
 
 void workspace_init(const Hierarchy& H, Workspace& W, int K) {
   hipStream_t s = H.s;
+  // captured V-cycles hold the old buffers' addresses
+  for (const VcycleGraph& g : W.graphs) (void)hipGraphExecDestroy(g.exec);
+  W.graphs.clear();
   const int64_t n = H.n0 * K;
   W.K = K;
   W.ld = (n + 63) / 64 * 64;
@@ -325,8 +330,7 @@ void smooth_c(const Hierarchy& H, const Level& L, const LevelOps& o, int K, cons
 }
 
 template <class X>
-void vcycle_t(const Hierarchy& H, const VecSet<X>& v, int K) {
-  hipStream_t s = H.s;
+void vcycle_t(const Hierarchy& H, const VecSet<X>& v, int K, hipStream_t s) {
   const int prec = H.p.precision;
   const int L = (int)H.levels.size() - 1;
   // level l's residual (l >= 1): the suffix at off_l of rr, each restriction
@@ -450,9 +454,12 @@ struct Procs {
   Workspace& W;
   int G;
   bool cols;
+  // the problems' activity on the device while the Arnoldi step's w is zero
+  // on the stopped problems (null: every item is computed)
+  const uint8_t* act = nullptr;
   void dots(const double* V, int64_t ld, int nv, const double* w, double* out) {
     if (cols) launch_col_dots(V, ld, nv, w, H.n0, W.K, out, W.cdot_work.get(), H.s);
-    else launch_group_dots(V, ld, nv, w, W.gitems, out, W.gdot_work.get(), H.s);
+    else launch_group_dots(V, ld, nv, w, W.gitems, out, W.gdot_work.get(), H.s, act);
   }
   void update(double* w, const double* V, int64_t ld, const double* h, int nv) {
     if (cols) launch_cgs_update_cols(w, V, ld, h, nv, H.n0, W.K, H.s);
@@ -465,7 +472,7 @@ struct Procs {
       if (cols)
         launch_cols_update_dots(w, V, ld, h, nv, H.n0, W.K, out, W.cfused_work.get(), H.s);
       else
-        launch_group_update_dots(w, V, ld, h, nv, W.gitems_f, out, W.gfused_work.get(), H.s);
+        launch_group_update_dots(w, V, ld, h, nv, W.gitems_f, out, W.gfused_work.get(), H.s, act);
       return;
     }
     update(w, V, ld, h, nv);
@@ -477,7 +484,7 @@ struct Procs {
       if (cols)
         launch_cols_update_norm2(w, V, ld, h, nv, H.n0, W.K, out, W.cfused_work.get(), H.s);
       else
-        launch_group_update_norm2(w, V, ld, h, nv, W.gitems_f, out, W.gfused_work.get(), H.s);
+        launch_group_update_norm2(w, V, ld, h, nv, W.gitems_f, out, W.gfused_work.get(), H.s, act);
       return;
     }
     update(w, V, ld, h, nv);
@@ -518,7 +525,9 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
   const int64_t n = n0 * K;
   const int R = W.restart;
   const int64_t ld = W.ld;
-  const double rtol = H.p.rtol;
+  const double rtol = H.p.rtol, atol = H.p.atol;
+  // a residual is small enough at rtol times its reference norm or at atol
+  auto tol = [&](double ref) { return std::max(rtol * ref, atol); };
   const int max_it = H.p.max_it;
   const OpView A = opview(H.Aperm);
   double* V = W.V.get();
@@ -544,7 +553,7 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
     residual(r);
     for (int c = 0; c < G; ++c) {
       if (ref[c] == 0.0) ref[c] = rn[c];
-      done[c] = rn[c] <= rtol * ref[c] || max_it <= 0;
+      done[c] = rn[c] <= tol(ref[c]) || max_it <= 0;
     }
     for (;;) {
       bool any = false;
@@ -561,7 +570,7 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
         if (done[c]) continue;
         ++its[c];
         if (!std::isfinite(rn[c])) fail(AIRG_ERR_BREAKDOWN, "Richardson diverged (non-finite residual)");
-        if (rn[c] <= rtol * ref[c] || its[c] >= max_it) done[c] = 1;
+        if (rn[c] <= tol(ref[c]) || its[c] >= max_it) done[c] = 1;
       }
     }
   } else {
@@ -586,7 +595,7 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
       for (int c = 0; c < G; ++c) {
         act[c] = 0;
         if (done[c]) continue;
-        if (rn[c] <= rtol * bn[c] || its[c] >= max_it) {
+        if (rn[c] <= tol(bn[c]) || its[c] >= max_it) {
           done[c] = 1;
           continue;
         }
@@ -631,9 +640,13 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
         double* h1 = hd;
         double* h2 = hd + (size_t)(R + 1) * G;
         double* hn2 = hd + (size_t)2 * (R + 1) * G;
+        // a stopped problem's basis vector was zero, so its V-cycle output,
+        // product and every Gram-Schmidt term are zero: the sweeps skip it
+        if (mask) P.act = W.active.get();
         P.dots(V, ld, j + 1, W.w.get(), h1);
         P.update_dots(W.w.get(), V, ld, h1, j + 1, h2);
         P.update_sumsq(W.w.get(), V, ld, h2, j + 1, hn2);
+        P.act = nullptr;
         read_small(W, W.hbuf.get(), hh.data(), (size_t)(2 * (R + 1) + 1) * G, s);
         bool more = false;
         for (int c = 0; c < G; ++c) {
@@ -645,7 +658,7 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
           ++its[c];
           est[c] = cyc[c].push(R, j, hc.data(), hn);
           if (!std::isfinite(est[c])) fail(AIRG_ERR_BREAKDOWN, "FGMRES breakdown (non-finite residual)");
-          if (est[c] <= rtol * bn[c] || its[c] >= max_it || hn == 0.0) {
+          if (est[c] <= tol(bn[c]) || its[c] >= max_it || hn == 0.0) {
             act[c] = 0;
             continue;
           }
@@ -675,7 +688,7 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
     airg_solve_info& o = out[c];
     o.iterations = its[c];
     o.restarts = rst[c];
-    o.converged = rn[c] <= rtol * ref[c] ? 1 : 0;
+    o.converged = rn[c] <= tol(ref[c]) ? 1 : 0;
     o.rel_residual = ref[c] > 0.0 ? rn[c] / ref[c] : 0.0;
     o.rel_residual_estimate = H.p.outer == AIRG_OUTER_RICHARDSON
                                   ? o.rel_residual
@@ -686,15 +699,61 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
 
 }  // namespace
 
-void vcycle(const Hierarchy& H, Workspace& W, const double* in, double* e) {
+// The launches of one V-cycle, enqueued on s.
+void vcycle_launches(const Hierarchy& H, Workspace& W, const double* in, double* e, hipStream_t s) {
   const int64_t n = H.n0 * W.K;
   if (H.p.precision == AIRG_FP64) {
-    vcycle_t<double>(H, vecs64(W, in, e), W.K);
+    vcycle_t<double>(H, vecs64(W, in, e), W.K, s);
     return;
   }
-  convert_d2f(W.in32.get(), in, n, H.s);
-  vcycle_t<float>(H, vecs32(W), W.K);
-  convert_f2d(e, W.e32.get(), n, H.s);
+  convert_d2f(W.in32.get(), in, n, s);
+  vcycle_t<float>(H, vecs32(W), W.K, s);
+  convert_f2d(e, W.e32.get(), n, s);
+}
+
+// The V-cycle from `in` to `e` as an instantiated HIP graph: captured once
+// per (in, e, activity masks on or off) and launch-shape epoch on the
+// workspace's own capture stream (capture needs a stream other than the null
+// stream; capturing executes nothing), then replayed on the hierarchy's
+// stream.  The V-cycle's kernels take every coefficient and pointer as a
+// launch argument and no memset or copy is among them, so a replay repeats
+// exactly the launches of the direct path.
+hipGraphExec_t vcycle_graph(const Hierarchy& H, Workspace& W, const double* in, double* e) {
+  const bool mask = W.mask_on;
+  for (const VcycleGraph& g : W.graphs)
+    if (g.in == in && g.e == e && g.mask == mask && g.epoch == H.shape_epoch) return g.exec;
+  if (!W.cap) AIRG_HIP(hipStreamCreateWithFlags(&W.cap, hipStreamNonBlocking));
+  AIRG_HIP(hipStreamBeginCapture(W.cap, hipStreamCaptureModeThreadLocal));
+  hipGraph_t graph = nullptr;
+  try {
+    vcycle_launches(H, W, in, e, W.cap);
+  } catch (...) {
+    (void)hipStreamEndCapture(W.cap, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  AIRG_HIP(hipStreamEndCapture(W.cap, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  AIRG_HIP(err);
+  // graphs of an older launch-shape epoch are stale: drop them
+  std::vector<VcycleGraph> keep;
+  for (const VcycleGraph& g : W.graphs) {
+    if (g.epoch == H.shape_epoch) keep.push_back(g);
+    else (void)hipGraphExecDestroy(g.exec);
+  }
+  keep.push_back({in, e, mask, H.shape_epoch, exec});
+  W.graphs.swap(keep);
+  return exec;
+}
+
+void vcycle(const Hierarchy& H, Workspace& W, const double* in, double* e) {
+  if (H.p.graph) {
+    AIRG_HIP(hipGraphLaunch(vcycle_graph(H, W, in, e), H.s));
+    return;
+  }
+  vcycle_launches(H, W, in, e, H.s);
 }
 
 int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb, double* x,
@@ -705,7 +764,8 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
   const int R = W.restart;
   const int64_t ld = W.ld;
   const int32_t* pos = H.levels[0].pos.get();
-  const double rtol = H.p.rtol;
+  const double rtol = H.p.rtol, atol = H.p.atol;
+  auto tol = [&](double ref) { return std::max(rtol * ref, atol); };
   const int max_it = H.p.max_it;
   AIRG_HIP(hipEventRecord(W.ev0, s));
 
@@ -751,9 +811,10 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
     if (v > 0.0 && (bmin == 0.0 || v < bmin)) bmin = v;
   }
   const double bnorm = std::sqrt(btot2);
-  // stopping test of the stacked Krylov process: |r| <= rtol min_g |b_g| makes
-  // every group's residual small enough (it equals rtol |b| for one group)
-  const double thr = rtol * bmin;
+  // stopping test of the stacked Krylov process: |r| <= rtol min_g |b_g| (or
+  // atol) makes every group's residual small enough (it equals rtol |b| for
+  // one group)
+  const double thr = tol(bmin);
 
   std::vector<airg_solve_info> out(ng);
   for (auto& o : out) std::memset(&o, 0, sizeof(o));
@@ -779,7 +840,7 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
     };
     auto done = [&]() {
       for (size_t q = 0; q < ng; ++q)
-        if (!(rn[q] <= rtol * ref[q])) return false;
+        if (!(rn[q] <= tol(ref[q]))) return false;
       return true;
     };
     residual();
@@ -811,7 +872,7 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
       double beta2 = 0.0;
       for (size_t q = 0; q < ng; ++q) {
         beta2 += rn[q] * rn[q];
-        if (!(rn[q] <= rtol * bn[q])) converged = false;
+        if (!(rn[q] <= tol(bn[q]))) converged = false;
       }
       const double beta = std::sqrt(beta2);
       if (converged || its >= max_it) break;
@@ -889,7 +950,7 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
   for (size_t q = 0; q < ng; ++q) {
     out[q].iterations = its;
     out[q].restarts = restarts;
-    out[q].converged = rn[q] <= rtol * ref[q] ? 1 : 0;
+    out[q].converged = rn[q] <= tol(ref[q]) ? 1 : 0;
     out[q].rel_residual = ref[q] > 0.0 ? rn[q] / ref[q] : 0.0;
     out[q].rel_residual_estimate = est_rel;
     out[q].solve_ms = ms;
@@ -1020,6 +1081,7 @@ struct TuneTarget {
 int autotune(Hierarchy& H, Workspace& W, int reps, std::vector<airg_tune_entry>& out) {
   if (reps < 1) fail(AIRG_ERR_INVALID, "reps must be >= 1");
   if (W.K != 1) fail(AIRG_ERR_INTERNAL, "tuning uses the single-column workspace");
+  ++H.shape_epoch;
   hipStream_t s = H.s;
   const int prec = H.p.precision;
   const bool low = prec != AIRG_FP64;
@@ -1086,6 +1148,7 @@ void set_lanes(Hierarchy& H, int level, int op, int lanes, int xcd_map, int lds)
   if (lds != 0 && lds != 1) fail(AIRG_ERR_INVALID, "lds must be 0 or 1");
   if (lds && (lanes < 2 || lanes > 16))
     fail(AIRG_ERR_INVALID, "the LDS-staged product takes 2, 4, 8 or 16 lanes per row");
+  ++H.shape_epoch;
   const int L = (int)H.levels.size() - 1;
   const CSR* A = nullptr;
   int* tpr = nullptr;

@@ -7,6 +7,16 @@
 
 namespace airg {
 
+// One captured V-cycle (see vcycle): its input and output vectors, whether
+// the activity masks were on, and the launch-shape epoch it was captured in.
+struct VcycleGraph {
+  const double* in;
+  double* e;
+  bool mask;
+  uint64_t epoch;
+  hipGraphExec_t exec;
+};
+
 struct Workspace {
   int K = 1;           // interleaved columns (right-hand sides solved together)
   int64_t ld = 0;      // leading dimension of the Krylov bases (>= n K)
@@ -36,12 +46,17 @@ struct Workspace {
   // pinned host staging for the small per-iteration reads of the outer loop
   double* pin = nullptr;
   size_t pin_n = 0;
+  // captured V-cycles (params.graph) and the stream they are captured on
+  std::vector<VcycleGraph> graphs;
+  hipStream_t cap = nullptr;
   ~Workspace();
 };
 
 void workspace_init(const Hierarchy& H, Workspace& W, int K = 1);
 
-// One V-cycle: e = M r for a top-level vector `in` (nested numbering, W.K columns).
+// One V-cycle: e = M r for a top-level vector `in` (nested numbering, W.K
+// columns), launched kernel by kernel, or replayed from a captured HIP graph
+// with params.graph.
 void vcycle(const Hierarchy& H, Workspace& W, const double* in, double* e);
 
 // The outer solve of A x = b for W.K right-hand sides solved together: column
