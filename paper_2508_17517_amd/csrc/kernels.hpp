@@ -82,8 +82,11 @@ struct GroupItems {
 void build_group_items(const std::vector<GroupRange>& ranges, int G, GroupItems& out,
                        hipStream_t s, int chunk = 1024);
 size_t group_dots_work_size(const GroupItems& it);
+// With `active` (one byte per problem), the items of problems whose byte is
+// 0 are skipped and give zero products (callers pass it only where those
+// problems' w is zero).
 void launch_group_dots(const double* V, int64_t ldv, int nv, const double* w, const GroupItems& it,
-                       double* out, double* work, hipStream_t s);
+                       double* out, double* work, hipStream_t s, const uint8_t* active = nullptr);
 void launch_group_update(double* w, const double* V, int64_t ldv, const double* h, int nv,
                          const GroupItems& it, hipStream_t s);
 void launch_group_combine(double* x, const double* Z, int64_t ldz, const double* y, int nv,
@@ -112,10 +115,14 @@ void launch_cols_update_norm2(double* w, const double* V, int64_t ldv, const dou
 // over problem g, each summed in a fixed order.  1 to 32 basis vectors;
 // `work` needs group_fused_work_size(items) doubles.
 size_t group_fused_work_size(const GroupItems& it);
+// `active` as in launch_group_dots (skipped items leave w unchanged: their
+// w and coefficients are zero).
 void launch_group_update_dots(double* w, const double* V, int64_t ldv, const double* h, int nv,
-                              const GroupItems& it, double* out, double* work, hipStream_t s);
+                              const GroupItems& it, double* out, double* work, hipStream_t s,
+                              const uint8_t* active = nullptr);
 void launch_group_update_norm2(double* w, const double* V, int64_t ldv, const double* h, int nv,
-                               const GroupItems& it, double* out, double* work, hipStream_t s);
+                               const GroupItems& it, double* out, double* work, hipStream_t s,
+                               const uint8_t* active = nullptr);
 // out[0] = sqrt(out[0]) on the device
 void launch_sqrt_inplace(double* v, hipStream_t s);
 

@@ -578,14 +578,23 @@ void build_group_items(const std::vector<GroupRange>& ranges, int G, GroupItems&
   AIRG_HIP(hipStreamSynchronize(s));
 }
 
-// block q: partial products of its item, by the tree of tree_dot_stage1
+// block q: partial products of its item, by the tree of tree_dot_stage1; an
+// item of a problem whose process is not running (active[grp] == 0, when
+// active is given) leaves zero partials without reading anything: its w is
+// zero there, so its products would be zero too
 __global__ __launch_bounds__(256) void group_dots_stage1(const double* __restrict__ V, int64_t ldv,
                                                          int nv, const double* __restrict__ w,
                                                          const int64_t* __restrict__ start,
                                                          const int32_t* __restrict__ len,
+                                                         const int32_t* __restrict__ grp,
+                                                         const uint8_t* __restrict__ active,
                                                          double* __restrict__ part, int64_t nq) {
   __shared__ double red[kMaxDotVecs][4];
   const int t = threadIdx.x;
+  if (active && !active[grp[blockIdx.x]]) {
+    if (t < nv) part[(int64_t)t * nq + blockIdx.x] = 0.0;
+    return;
+  }
   const int64_t b = start[blockIdx.x];
   const int m = len[blockIdx.x];
   double w4[4];
@@ -663,12 +672,13 @@ __global__ __launch_bounds__(256) void group_divide_kernel(double* __restrict__ 
 
 size_t group_dots_work_size(const GroupItems& it) { return (size_t)kMaxDotVecs * (size_t)std::max<int64_t>(it.n, 1); }
 void launch_group_dots(const double* V, int64_t ldv, int nv, const double* w, const GroupItems& it,
-                       double* out, double* work, hipStream_t s) {
+                       double* out, double* work, hipStream_t s, const uint8_t* active) {
   if (nv <= 0 || it.n <= 0) return;
   for (int k0 = 0; k0 < nv; k0 += kMaxDotVecs) {
     const int cnt = std::min(kMaxDotVecs, nv - k0);
     group_dots_stage1<<<(unsigned)it.n, 256, 0, s>>>(V + (int64_t)k0 * ldv, ldv, cnt, w,
-                                                      it.start.get(), it.len.get(), work, it.n);
+                                                      it.start.get(), it.len.get(), it.grp.get(),
+                                                      active, work, it.n);
     AIRG_CHECK_LAUNCH();
     group_sum_kernel<<<dim3((unsigned)it.G, (unsigned)cnt), 256, 0, s>>>(
         work, it.n, it.gptr.get(), it.glist.get(), it.G, out + (int64_t)k0 * it.G);
@@ -700,17 +710,24 @@ void launch_group_divide(double* y, const double* x, const double* d, const Grou
 // The fused sweeps of cgs_fused_kernel per problem: block q takes item q (at
 // most 256 elements of problem grp[q], one per thread), updates w with that
 // problem's coefficients, and leaves the item's partial products, which
-// group_sum_kernel adds per problem in list order.
+// group_sum_kernel adds per problem in list order.  An item of a problem whose
+// process is not running (active given and active[grp] == 0) has w = 0 and
+// coefficients 0: it leaves w as it is and zero partials, reading nothing.
 template <bool DOTS, int NV>
 __global__ __launch_bounds__(256) void group_fused_kernel(
     double* __restrict__ w, const double* __restrict__ V, int64_t ldv, const double* __restrict__ h,
     int G, const int64_t* __restrict__ start, const int32_t* __restrict__ len,
-    const int32_t* __restrict__ grp, double* __restrict__ part, int64_t nq) {
+    const int32_t* __restrict__ grp, const uint8_t* __restrict__ active, double* __restrict__ part,
+    int64_t nq) {
   constexpr int CNT = DOTS ? NV : 1;
   __shared__ double red[CNT][4];
   const int t = threadIdx.x;
-  const int64_t b = start[blockIdx.x];
   const int g = grp[blockIdx.x];
+  if (active && !active[g]) {
+    if (t < CNT) part[(int64_t)t * nq + blockIdx.x] = 0.0;
+    return;
+  }
+  const int64_t b = start[blockIdx.x];
   const bool in = t < len[blockIdx.x];
   const int64_t i = in ? b + t : b;  // in-range address for the padding lanes
   double v[NV];
@@ -732,13 +749,15 @@ __global__ __launch_bounds__(256) void group_fused_kernel(
 
 template <bool DOTS, int NV>
 static void launch_group_fused_nv(int nv, double* w, const double* V, int64_t ldv, const double* h,
-                                  const GroupItems& it, double* part, hipStream_t s) {
+                                  const GroupItems& it, const uint8_t* active, double* part,
+                                  hipStream_t s) {
   if constexpr (NV > kFusedVecs) {
     fail(AIRG_ERR_INTERNAL, "fused Gram-Schmidt takes 1 to 32 vectors");
   } else {
-    if (nv != NV) return launch_group_fused_nv<DOTS, NV + 1>(nv, w, V, ldv, h, it, part, s);
+    if (nv != NV)
+      return launch_group_fused_nv<DOTS, NV + 1>(nv, w, V, ldv, h, it, active, part, s);
     group_fused_kernel<DOTS, NV><<<(unsigned)it.n, 256, 0, s>>>(
-        w, V, ldv, h, it.G, it.start.get(), it.len.get(), it.grp.get(), part, it.n);
+        w, V, ldv, h, it.G, it.start.get(), it.len.get(), it.grp.get(), active, part, it.n);
   }
 }
 
@@ -748,23 +767,25 @@ size_t group_fused_work_size(const GroupItems& it) {
 
 static void launch_group_fused(bool dots, double* w, const double* V, int64_t ldv, const double* h,
                                int nv, const GroupItems& it, double* out, double* work,
-                               hipStream_t s) {
+                               hipStream_t s, const uint8_t* active) {
   if (nv < 1 || nv > kFusedVecs) fail(AIRG_ERR_INTERNAL, "fused Gram-Schmidt takes 1 to 32 vectors");
   if (it.n <= 0) return;
-  if (dots) launch_group_fused_nv<true, 1>(nv, w, V, ldv, h, it, work, s);
-  else launch_group_fused_nv<false, 1>(nv, w, V, ldv, h, it, work, s);
+  if (dots) launch_group_fused_nv<true, 1>(nv, w, V, ldv, h, it, active, work, s);
+  else launch_group_fused_nv<false, 1>(nv, w, V, ldv, h, it, active, work, s);
   AIRG_CHECK_LAUNCH();
   group_sum_kernel<<<dim3((unsigned)it.G, (unsigned)(dots ? nv : 1)), 256, 0, s>>>(
       work, it.n, it.gptr.get(), it.glist.get(), it.G, out);
   AIRG_CHECK_LAUNCH();
 }
 void launch_group_update_dots(double* w, const double* V, int64_t ldv, const double* h, int nv,
-                              const GroupItems& it, double* out, double* work, hipStream_t s) {
-  launch_group_fused(true, w, V, ldv, h, nv, it, out, work, s);
+                              const GroupItems& it, double* out, double* work, hipStream_t s,
+                              const uint8_t* active) {
+  launch_group_fused(true, w, V, ldv, h, nv, it, out, work, s, active);
 }
 void launch_group_update_norm2(double* w, const double* V, int64_t ldv, const double* h, int nv,
-                               const GroupItems& it, double* out, double* work, hipStream_t s) {
-  launch_group_fused(false, w, V, ldv, h, nv, it, out, work, s);
+                               const GroupItems& it, double* out, double* work, hipStream_t s,
+                               const uint8_t* active) {
+  launch_group_fused(false, w, V, ldv, h, nv, it, out, work, s, active);
 }
 
 // mask[i] = 1 where any problem g0[i] .. g1[i] of 64-row group i is active
