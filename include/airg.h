@@ -334,9 +334,13 @@ typedef struct {
                           row on average) */
   int32_t xcd_map;     /* 1: workgroups of one XCD take one contiguous eighth of the rows
                           (each XCD has its own L2); 0: workgroup i takes row block i */
-  int32_t lds;         /* 1: the LDS-staged kernel (a workgroup per 64-row group copies the
-                          group's window of x to LDS and gathers there; operators with
-                          compressed columns; lanes 2..16) */
+  int32_t lds;         /* what the product stages in LDS.  0: nothing.  1: the window of x
+                          (a workgroup per 64-row group copies the group's window of x to
+                          LDS and gathers there; operators with compressed columns; lanes
+                          2..16).  2: the entries (a workgroup per 256 consecutive rows
+                          loads their entries at consecutive addresses and leaves the
+                          products in LDS, where each row's thread adds its own in order:
+                          the one-lane kernel's sums, bit for bit; lanes 1) */
   int32_t default_lanes;
   int32_t default_xcd_map;
   int32_t default_lds;
@@ -346,7 +350,8 @@ typedef struct {
 
 /* Launch-shape tuner: time every solve operator's single-column product with
  * 1, 2, ..., 64 lanes per row, the row-block kernel and the LDS-staged kernel
- * where they exist, each with and without the XCD mapping (`reps` launches
+ * where they exist and the entry-staged kernel, each with and without the XCD
+ * mapping (`reps` launches
  * each, HIP events on the handle's stream), and keep the fastest per
  * operator.  A row split over more
  * lanes sums in a different order, so solves after tuning agree with untuned
@@ -359,9 +364,9 @@ int airg_autotune(airg_handle h, int reps, airg_tune_entry* out, int max_out, in
 /* Set the launch shape (lanes per row, XCD mapping and LDS staging, as in
  * airg_tune_entry) of one solve operator (level is ignored for AIRG_OP_TOP
  * and AIRG_OP_A).  AIRG_ERR_INVALID for an unknown operator, lanes not 0 or a
- * power of two in 1..64, 0 for an operator without row blocks, xcd_map or lds
- * not 0 or 1, or lds = 1 with lanes outside 2..16 or for an operator without
- * compressed columns. */
+ * power of two in 1..64, 0 for an operator without row blocks, xcd_map not 0
+ * or 1, lds not 0, 1 or 2, lds = 1 with lanes outside 2..16 or for an operator
+ * without compressed columns, or lds = 2 with lanes other than 1. */
 int airg_set_lanes(airg_handle h, int level, int op, int lanes, int xcd_map, int lds);
 
 /* ---- differentiable advection solve -------------------------------------

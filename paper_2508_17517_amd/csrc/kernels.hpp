@@ -156,9 +156,12 @@ void launch_offsets_to_i32(const int64_t* off, int32_t* rowptr, int64_t n1, int3
 // Rows-per-thread-group shape of a CSR kernel (lanes per row, power of 2).
 int pick_tpr(int64_t rows, int64_t nnz);
 // Launch shape of a product: lanes per row in bits 0-7 (0: row-block kernel),
-// the XCD mapping in bit 8, the LDS-staged kernel in bit 9.
+// the XCD mapping in bit 8, the LDS-staged kernel in bit 9, the
+// entry-staged kernel (256 consecutive rows per workgroup, one lane per row)
+// in bit 10.
 constexpr int kShapeXcd = 1 << 8;
 constexpr int kShapeLds = 1 << 9;
+constexpr int kShapeEntries = 1 << 10;
 // y = A x, every row summed left to right from 0.0 by one lane (setup order).
 void spmv_seq(const CSR& A, const double* x, double* y, hipStream_t s);
 // y = A x with `tpr` lanes per row.

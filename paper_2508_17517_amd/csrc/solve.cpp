@@ -1110,7 +1110,7 @@ int autotune(Hierarchy& H, Workspace& W, int reps, std::vector<airg_tune_entry>&
     e.op = g.op;
     e.default_lanes = *g.tpr & 0xff;
     e.default_xcd_map = (*g.tpr >> 8) & 1;
-    e.default_lds = (*g.tpr >> 9) & 1;
+    e.default_lds = (*g.tpr & kShapeEntries) ? 2 : (*g.tpr >> 9) & 1;
     e.best_us = 1e300;
     e.default_us = 1e300;
     int best = *g.tpr;
@@ -1121,6 +1121,7 @@ int autotune(Hierarchy& H, Workspace& W, int reps, std::vector<airg_tune_entry>&
     }
     if (g.A.col16)  // LDS-staged kernel: 64-row groups, 2..16 lanes per row
       for (int tpr = 2; tpr <= 16; tpr <<= 1) shapes.push_back(tpr | kShapeLds);
+    shapes.push_back(1 | kShapeEntries);  // entry-staged kernel, one lane per row
     for (int base : shapes)
       for (int xcd = 0; xcd < 2; ++xcd) {
         const int shape = base | (xcd << 8);
@@ -1134,7 +1135,7 @@ int autotune(Hierarchy& H, Workspace& W, int reps, std::vector<airg_tune_entry>&
       }
     e.lanes = best & 0xff;
     e.xcd_map = (best >> 8) & 1;
-    e.lds = (best >> 9) & 1;
+    e.lds = (best & kShapeEntries) ? 2 : (best >> 9) & 1;
     *g.tpr = best;
     out.push_back(e);
   }
@@ -1145,9 +1146,11 @@ void set_lanes(Hierarchy& H, int level, int op, int lanes, int xcd_map, int lds)
   if (lanes < 0 || lanes > 64 || (lanes & (lanes - 1)))
     fail(AIRG_ERR_INVALID, "lanes must be 0 or a power of two in 1..64");
   if (xcd_map != 0 && xcd_map != 1) fail(AIRG_ERR_INVALID, "xcd_map must be 0 or 1");
-  if (lds != 0 && lds != 1) fail(AIRG_ERR_INVALID, "lds must be 0 or 1");
-  if (lds && (lanes < 2 || lanes > 16))
+  if (lds < 0 || lds > 2) fail(AIRG_ERR_INVALID, "lds must be 0, 1 or 2");
+  if (lds == 1 && (lanes < 2 || lanes > 16))
     fail(AIRG_ERR_INVALID, "the LDS-staged product takes 2, 4, 8 or 16 lanes per row");
+  if (lds == 2 && lanes != 1)
+    fail(AIRG_ERR_INVALID, "the entry-staged product takes one lane per row");
   ++H.shape_epoch;
   const int L = (int)H.levels.size() - 1;
   const CSR* A = nullptr;
@@ -1175,9 +1178,9 @@ void set_lanes(Hierarchy& H, int level, int op, int lanes, int xcd_map, int lds)
   }
   if (lanes == 0 && !A->rblk.get())
     fail(AIRG_ERR_INVALID, "this operator has no row blocks (rows shorter than 8 on average)");
-  if (lds && !A->col16.get())
+  if (lds == 1 && !A->col16.get())
     fail(AIRG_ERR_INVALID, "this operator has no compressed columns for the LDS-staged product");
-  *tpr = lanes | (xcd_map << 8) | (lds ? kShapeLds : 0);
+  *tpr = lanes | (xcd_map << 8) | (lds == 1 ? kShapeLds : lds == 2 ? kShapeEntries : 0);
 }
 
 }  // namespace airg

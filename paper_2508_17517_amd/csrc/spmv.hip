@@ -329,6 +329,81 @@ __global__ __launch_bounds__(256) void spmv_rowblock_kernel(CSRT<MV, C16> A,
   if (mine) epi(row, sum, pre);
 }
 
+// Entry-staged kernel (K = 1, shape bit 10): a workgroup takes 256
+// consecutive rows, one thread per row.  Short rows make the one-lane kernel's
+// loads scattered (each lane walks its own few entries); here the workgroup
+// loads the entries of its rows in chunks of 1024, thread t taking entries
+// t, t + 256, ... so that every load instruction reads consecutive addresses,
+// gathers x for each, and leaves the products in LDS; each row's thread then
+// adds its products left to right from 0.  The products and the order of the
+// sum are those of the one-lane kernel, so the results are the same bit for
+// bit.  The rows span four 64-row groups, each with its own column base (and
+// activity mask) in the compressed form; an entry's group comes from the
+// groups' first entries.
+constexpr int kEntryChunk = 1024;
+
+template <class MV, bool C16, class X, class Epi, bool MASK>
+__global__ __launch_bounds__(256) void spmv_entries_kernel(CSRT<MV, C16> A, const X* __restrict__ x,
+                                                           Epi epi, int xcd) {
+  __shared__ X prod[kEntryChunk];
+  const int64_t r0 = row_block_index(xcd) * 256;
+  if (r0 >= A.rows) return;  // the same for the whole workgroup
+  const int t = threadIdx.x;
+  const int64_t row = r0 + t;
+  const bool live = row < A.rows;
+  const int64_t rend = r0 + 256 < A.rows ? r0 + 256 : A.rows;
+  typename Epi::Pre pre{};
+  int rs = 0, re = 0;
+  if (live) {
+    pre = epi.pre(row);
+    rs = A.rowptr[row];
+    re = (!MASK || A.computed(row)) ? A.rowptr[row + 1] : rs;
+  }
+  // first entry of each 64-row group of the block (gstart[4]: the block's end),
+  // the group's column base and whether it is computed
+  int gstart[5], gbase[4];
+  bool gon[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int64_t gr = r0 + 64 * g;
+    gstart[g] = A.rowptr[gr < rend ? gr : rend];
+    gbase[g] = gr < rend ? A.base(gr) : 0;
+    gon[g] = gr < rend && (!MASK || A.computed(gr));
+  }
+  gstart[4] = A.rowptr[rend];
+  X sum = 0;
+  for (int c0 = gstart[0]; c0 < gstart[4]; c0 += kEntryChunk) {
+    const int c1 = c0 + kEntryChunk < gstart[4] ? c0 + kEntryChunk : gstart[4];
+    int col[4];
+    X v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int p = c0 + t + 256 * u;
+      const int g = (p >= gstart[1]) + (p >= gstart[2]) + (p >= gstart[3]);
+      col[u] = -1;
+      v[u] = X(0);
+      if (p < c1 && gon[g]) {
+        if constexpr (C16) col[u] = gbase[g] >= 0 ? A.column(p, gbase[g]) : A.col[p];
+        else col[u] = A.col[p];
+        v[u] = (X)ldv(A.val[p]);
+      }
+    }
+    X xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xv[u] = col[u] >= 0 ? x[col[u]] : X(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (col[u] >= 0) prod[t + 256 * u] = v[u] * xv[u];
+    __syncthreads();
+    if (live) {
+      const int e = re < c1 ? re : c1;
+      for (int p = rs > c0 ? rs : c0; p < e; ++p) sum = sum + prod[p - c0];
+    }
+    __syncthreads();
+  }
+  if (live) epi(row, sum, pre);
+}
+
 // LDS-staged kernel (K = 1, shape bit 9, operators with compressed columns):
 // a workgroup of 64 TPR threads takes one 64-row group, copies the group's
 // window of x (columns cbase .. cbase + span - 1) into LDS with coalesced
@@ -405,7 +480,8 @@ __global__ __launch_bounds__(64 * TPR) void spmv_lds_kernel(CSRT<MV, true> A,
 }
 
 // shape: lanes per row in bits 0-7 (0: the row-block kernel), the XCD
-// mapping in bit 8, the LDS-staged kernel in bit 9
+// mapping in bit 8, the LDS-staged kernel in bit 9, the entry-staged kernel in
+// bit 10
 // MASK: the launch honours Av.gmask (a separate instantiation, so that the
 // unmasked products carry no test)
 template <class MV, bool C16, bool MASK, class X, class Epi>
@@ -413,6 +489,12 @@ static void launch_spmv_t(const OpView& Av, int shape, int K, const X* x, Epi ep
   if (Av.rows <= 0) return;
   const int tpr = shape & 0xff, xcd = (shape >> 8) & 1, lds = (shape >> 9) & 1;
   CSRT<MV, C16> A = csr_t<MV, C16>(Av);
+  if (K == 1 && (shape & kShapeEntries)) {
+    spmv_entries_kernel<MV, C16, X, Epi, MASK><<<grid_for(Av.rows, 256, xcd), 256, 0, s>>>(A, x, epi,
+                                                                                         xcd);
+    AIRG_CHECK_LAUNCH();
+    return;
+  }
   if (K == 1 && lds) {
     if constexpr (C16) {
       const int64_t ngroups = (Av.rows + 63) >> kColBlockShift;

@@ -368,6 +368,11 @@ def test_masked_row_block_and_staged_kernels_on_a_problem_batch():
     assert nlds >= 1, "no operator took the LDS-staged kernel"
     for a, b in zip(x4s, x4):
         assert torch.equal(a, b)
+    # the entry-staged kernel sums like the one-lane kernel
+    xe, ne = run(1, 1, 2)
+    assert ne == len(ops)
+    for a, b in zip(xe, x1):
+        assert torch.equal(a, b)
     s.close()
 
 
@@ -396,6 +401,28 @@ def test_row_block_kernel_sums_like_one_lane_per_row():
     x0, i0 = s.solve(b)
     assert i0["iterations"] == i1["iterations"]
     assert torch.equal(x0, x1)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_entry_staged_kernel_sums_like_one_lane_per_row(prec):
+    # the entry-staged product (256 rows per workgroup, entries loaded at
+    # consecutive addresses, products in LDS) adds each row's products in the
+    # one-lane order: pinning it on every operator changes no bit of the solve
+    _needs_gpu()
+    from paper_2508_17517_amd import Solver
+    p = workloads.fv_random(150, 0.4, True, ny=97)
+    b = torch.from_numpy(p.b).cuda()
+    s = Solver(p.indptr, p.indices, p.data, precision=prec)
+    ops = [(e["level"], e["op"]) for e in s.autotune(reps=1)]
+    for l, op in ops:
+        s.set_lanes(l, op, 1, 0, 0)
+    x1, i1 = s.solve(b)
+    for l, op in ops:
+        s.set_lanes(l, op, 1, 1, 2)
+    x2, i2 = s.solve(b)
+    assert i2["iterations"] == i1["iterations"]
+    assert torch.equal(x1, x2)
     s.close()
 
 
