@@ -24,14 +24,18 @@ void launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s);
 void launch_zero_bytes(void* p, size_t bytes, hipStream_t s);
 void launch_copy(double* y, const double* x, int64_t n, hipStream_t s);
 void launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t s);   // y = a x
-void launch_divide(double* y, const double* x, double d, int64_t n, hipStream_t s);  // y = x / d
+// y = x / d, and y32 = (float) y when y32 is given
+void launch_divide(double* y, const double* x, double d, int64_t n, hipStream_t s,
+                   float* y32 = nullptr);
 void launch_divide_dev(double* y, const double* x, const double* d, int64_t n, hipStream_t s);
 void launch_sub(double* z, const double* x, const double* y, int64_t n, hipStream_t s);  // z = x - y
 // w = w - h[0] V_0 - h[1] V_1 - ... (k sequential per element; V_k = V + k ldv)
 void launch_cgs_update(double* w, const double* V, int64_t ldv, const double* h, int nv,
                        int64_t n, hipStream_t s);
-// x = x + sum_k y[k] Z_k (y on device)
+// x = x + sum_k y[k] Z_k (y on device; Z in FP64 or FP32)
 void launch_basis_combine(double* x, const double* Z, int64_t ldz, const double* y, int nv,
+                          int64_t n, hipStream_t s);
+void launch_basis_combine(double* x, const float* Z, int64_t ldz, const double* y, int nv,
                           int64_t n, hipStream_t s);
 
 // Dot products by the perfect binary tree over the index range (adjacent pairs
@@ -52,15 +56,18 @@ void launch_cgs_update_norm2(double* w, const double* V, int64_t ldv, const doub
 // of two, at most 64; h, y and out hold entry (k, c) at k K + c):
 //   w = w - sum_k h[k, c] V_k (k sequential per element),
 //   x = x + sum_k y[k, c] Z_k,
-//   y = x / d[c] column by column (0 where d[c] = 0),
+//   y = x / d[c] column by column (0 where d[c] = 0; also y32 = (float) y
+//   when y32 is given),
 //   out[k, c] = V_k . w over column c (fixed order; `work` needs
 //   col_dots_work_size(n0, K) doubles).
 void launch_cgs_update_cols(double* w, const double* V, int64_t ldv, const double* h, int nv,
                             int64_t n0, int K, hipStream_t s);
 void launch_basis_combine_cols(double* x, const double* Z, int64_t ldz, const double* y, int nv,
                                int64_t n0, int K, hipStream_t s);
+void launch_basis_combine_cols(double* x, const float* Z, int64_t ldz, const double* y, int nv,
+                               int64_t n0, int K, hipStream_t s);
 void launch_divide_cols(double* y, const double* x, const double* d, int64_t n0, int K,
-                        hipStream_t s);
+                        hipStream_t s, float* y32 = nullptr);
 size_t col_dots_work_size(int64_t n0, int K);
 void launch_col_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n0, int K,
                      double* out, double* work, hipStream_t s);
@@ -70,7 +77,8 @@ void launch_col_dots(const double* V, int64_t ldv, int nv, const double* w, int6
 //   out[k, g] = V_k . w over problem g (fixed order; `work` needs
 //   group_dots_work_size(items) doubles),
 //   w = w - sum_k h[k, g] V_k,  x = x + sum_k y[k, g] Z_k,
-//   y = x / d[g] problem by problem (0 where d[g] = 0).
+//   y = x / d[g] problem by problem (0 where d[g] = 0; also y32 = (float) y
+//   when y32 is given).
 struct GroupItems {
   DBuf<int64_t> start;
   DBuf<int32_t> len, grp, gptr, glist;
@@ -91,8 +99,10 @@ void launch_group_update(double* w, const double* V, int64_t ldv, const double* 
                          const GroupItems& it, hipStream_t s);
 void launch_group_combine(double* x, const double* Z, int64_t ldz, const double* y, int nv,
                           const GroupItems& it, hipStream_t s);
+void launch_group_combine(double* x, const float* Z, int64_t ldz, const double* y, int nv,
+                          const GroupItems& it, hipStream_t s);
 void launch_group_divide(double* y, const double* x, const double* d, const GroupItems& it,
-                         hipStream_t s);
+                         hipStream_t s, float* y32 = nullptr);
 // Activity masks of a problem batch: mask[i] = 1 where any of the problems
 // g0[i] .. g1[i] of 64-row group i has active[p] != 0.
 void launch_group_mask(const int32_t* g0, const int32_t* g1, const uint8_t* active, int64_t n,
@@ -172,6 +182,8 @@ void spmv(const CSR& A, int tpr, const double* x, double* y, hipStream_t s);
 // interleaved columns (element (row, c) at row * K + c; K a power of two <= 64).
 template <class X>
 void spmv_t(const OpView& A, int tpr, int K, const X* x, X* y, hipStream_t s);
+// y = A x with FP64 values and row sums, x in FP32 (widened as it is gathered).
+void spmv_x32(const OpView& A, int tpr, int K, const float* x, double* y, hipStream_t s);
 // Horner step of the smoother: out = (acc ? out : 0) + a (A y) + b s
 template <class X>
 void spmv_horner_t(const OpView& A, int tpr, int K, const X* y, const X* sv, X* out, double a,

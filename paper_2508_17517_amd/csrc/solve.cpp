@@ -60,7 +60,12 @@ void workspace_init(const Hierarchy& H, Workspace& W, int K) {
   W.ld = (n + 63) / 64 * 64;
   W.restart = H.p.restart;
   W.V.alloc((size_t)(W.restart + 1) * W.ld, s);
-  W.Zb.alloc((size_t)W.restart * W.ld, s);
+  // the FGMRES Z basis: FP64, or FP32 with lower-precision storage (the
+  // V-cycle's output is FP32 there, so an FP32 copy holds it exactly);
+  // Richardson keeps its one correction in FP64
+  W.z32 = H.p.precision != AIRG_FP64 && H.p.outer == AIRG_OUTER_FGMRES;
+  if (W.z32) W.Zb32.alloc((size_t)W.restart * W.ld, s);
+  else W.Zb.alloc((size_t)(H.p.outer == AIRG_OUTER_RICHARDSON ? 1 : W.restart) * W.ld, s);
   W.w.alloc(n, s);
   // smoother scratch: F rows, and C rows too with C-point smoothing
   const bool csm = H.p.smooth_type != AIRG_SMOOTH_TYPE_F;
@@ -149,8 +154,8 @@ VecSet<double> vecs64(Workspace& W, const double* in, double* e) {
   return {in,        e,         W.rr.get(), W.sv.get(), W.y0.get(), W.y1.get(),
           W.cw0.get(), W.cw1.get(), W.ct.get(), W.rin.get(), W.mask_on ? W.gmask.get() : nullptr};
 }
-VecSet<float> vecs32(Workspace& W) {
-  return {W.in32.get(), W.e32.get(), W.rr32.get(), W.sv32.get(), W.y032.get(), W.y132.get(),
+VecSet<float> vecs32(Workspace& W, float* e) {
+  return {W.in32.get(), e, W.rr32.get(), W.sv32.get(), W.y032.get(), W.y132.get(),
           W.cw032.get(), W.cw132.get(), W.ct32.get(), W.rin32.get(),
           W.mask_on ? W.gmask.get() : nullptr};
 }
@@ -494,11 +499,13 @@ struct Procs {
     if (cols) launch_col_sumsq(v, H.n0, W.K, out, W.col_work.get(), H.s);
     else launch_group_dots(v, 0, 1, v, W.gitems, out, W.gdot_work.get(), H.s);
   }
-  void divide(double* y, const double* x, const double* d) {
-    if (cols) launch_divide_cols(y, x, d, H.n0, W.K, H.s);
-    else launch_group_divide(y, x, d, W.gitems, H.s);
+  // y = x / d per process (and y32 = (float) y when given)
+  void divide(double* y, const double* x, const double* d, float* y32 = nullptr) {
+    if (cols) launch_divide_cols(y, x, d, H.n0, W.K, H.s, y32);
+    else launch_group_divide(y, x, d, W.gitems, H.s, y32);
   }
-  void combine(double* x, const double* Z, int64_t ld, const double* y, int nv) {
+  template <class ZT>
+  void combine(double* x, const ZT* Z, int64_t ld, const double* y, int nv) {
     if (cols) launch_basis_combine_cols(x, Z, ld, y, nv, H.n0, W.K, H.s);
     else launch_group_combine(x, Z, ld, y, nv, W.gitems, H.s);
   }
@@ -532,6 +539,10 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
   const OpView A = opview(H.Aperm);
   double* V = W.V.get();
   double* Zb = W.Zb.get();
+  // with an FP32 Z basis: the V-cycle reads (float) V_j, which every
+  // normalisation also writes to W.in32, and leaves z_j in FP32
+  float* Zb32 = W.z32 ? W.Zb32.get() : nullptr;
+  float* in32 = W.z32 ? W.in32.get() : nullptr;
   double* dv = W.cdiv.get();
 
   std::vector<double> bn = P.norms(W.bperm.get());
@@ -610,7 +621,7 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
         cyc[c].reset(R, act[c] ? rn[c] : 0.0);
       }
       upload_div();
-      P.divide(V, V, dv);
+      P.divide(V, V, dv, in32);
       // problems of a batch whose processes are not running have a zero
       // basis vector: the V-cycle and the top product skip their rows
       const bool mask = !P.cols && W.gmask.size() > 0;
@@ -634,9 +645,16 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
           }
           W.mask_on = true;
         }
-        vcycle(H, W, vj, zj);
-        W.mask_on = false;
-        spmv_t<double>(mask ? Am : A, H.tpr_top, K, zj, W.w.get(), s);
+        if (Zb32) {
+          float* zj32 = Zb32 + (int64_t)j * ld;
+          vcycle(H, W, vj, nullptr, zj32, true);
+          W.mask_on = false;
+          spmv_x32(mask ? Am : A, H.tpr_top, K, zj32, W.w.get(), s);
+        } else {
+          vcycle(H, W, vj, zj);
+          W.mask_on = false;
+          spmv_t<double>(mask ? Am : A, H.tpr_top, K, zj, W.w.get(), s);
+        }
         double* h1 = hd;
         double* h2 = hd + (size_t)(R + 1) * G;
         double* hn2 = hd + (size_t)2 * (R + 1) * G;
@@ -667,7 +685,7 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
         }
         if (!more || j + 1 == R) break;
         upload_div();
-        P.divide(V + (int64_t)(j + 1) * ld, W.w.get(), dv);
+        P.divide(V + (int64_t)(j + 1) * ld, W.w.get(), dv, in32);
       }
       int kmax = 0;
       std::fill(yh.begin(), yh.end(), 0.0);
@@ -679,7 +697,8 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
         kmax = std::max(kmax, cc.k);
       }
       W.ybuf.from_host(yh.data(), (size_t)kmax * G);
-      P.combine(W.xperm.get(), Zb, ld, W.ybuf.get(), kmax);
+      if (Zb32) P.combine(W.xperm.get(), Zb32, ld, W.ybuf.get(), kmax);
+      else P.combine(W.xperm.get(), Zb, ld, W.ybuf.get(), kmax);
     }
   }
   all_converged = true;
@@ -699,34 +718,41 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
 
 }  // namespace
 
-// The launches of one V-cycle, enqueued on s.
-void vcycle_launches(const Hierarchy& H, Workspace& W, const double* in, double* e, hipStream_t s) {
+// The launches of one V-cycle, enqueued on s: e64 = M in, or with
+// lower-precision storage e32 = M in when e32 is given (the V-cycle's FP32
+// output kept as it is); in32_ready: the caller already wrote (float) in to
+// W.in32.
+void vcycle_launches(const Hierarchy& H, Workspace& W, const double* in, double* e64, float* e32,
+                     bool in32_ready, hipStream_t s) {
   const int64_t n = H.n0 * W.K;
   if (H.p.precision == AIRG_FP64) {
-    vcycle_t<double>(H, vecs64(W, in, e), W.K, s);
+    vcycle_t<double>(H, vecs64(W, in, e64), W.K, s);
     return;
   }
-  convert_d2f(W.in32.get(), in, n, s);
-  vcycle_t<float>(H, vecs32(W), W.K, s);
-  convert_f2d(e, W.e32.get(), n, s);
+  if (!in32_ready) convert_d2f(W.in32.get(), in, n, s);
+  vcycle_t<float>(H, vecs32(W, e32 ? e32 : W.e32.get()), W.K, s);
+  if (!e32) convert_f2d(e64, W.e32.get(), n, s);
 }
 
-// The V-cycle from `in` to `e` as an instantiated HIP graph: captured once
-// per (in, e, activity masks on or off) and launch-shape epoch on the
-// workspace's own capture stream (capture needs a stream other than the null
-// stream; capturing executes nothing), then replayed on the hierarchy's
-// stream.  The V-cycle's kernels take every coefficient and pointer as a
-// launch argument and no memset or copy is among them, so a replay repeats
-// exactly the launches of the direct path.
-hipGraphExec_t vcycle_graph(const Hierarchy& H, Workspace& W, const double* in, double* e) {
+// The V-cycle as an instantiated HIP graph: captured once per set of vectors
+// (in, e64, e32, whether in32 is ready, activity masks on or off) and
+// launch-shape epoch on the workspace's own capture stream (capture needs a
+// stream other than the null stream; capturing executes nothing), then
+// replayed on the hierarchy's stream.  The V-cycle's kernels take every
+// coefficient and pointer as a launch argument and no memset or copy is among
+// them, so a replay repeats exactly the launches of the direct path.
+hipGraphExec_t vcycle_graph(const Hierarchy& H, Workspace& W, const double* in, double* e64,
+                            float* e32, bool in32_ready) {
   const bool mask = W.mask_on;
   for (const VcycleGraph& g : W.graphs)
-    if (g.in == in && g.e == e && g.mask == mask && g.epoch == H.shape_epoch) return g.exec;
+    if (g.in == in && g.e64 == e64 && g.e32 == e32 && g.in32_ready == in32_ready &&
+        g.mask == mask && g.epoch == H.shape_epoch)
+      return g.exec;
   if (!W.cap) AIRG_HIP(hipStreamCreateWithFlags(&W.cap, hipStreamNonBlocking));
   AIRG_HIP(hipStreamBeginCapture(W.cap, hipStreamCaptureModeThreadLocal));
   hipGraph_t graph = nullptr;
   try {
-    vcycle_launches(H, W, in, e, W.cap);
+    vcycle_launches(H, W, in, e64, e32, in32_ready, W.cap);
   } catch (...) {
     (void)hipStreamEndCapture(W.cap, &graph);
     if (graph) (void)hipGraphDestroy(graph);
@@ -743,17 +769,18 @@ hipGraphExec_t vcycle_graph(const Hierarchy& H, Workspace& W, const double* in, 
     if (g.epoch == H.shape_epoch) keep.push_back(g);
     else (void)hipGraphExecDestroy(g.exec);
   }
-  keep.push_back({in, e, mask, H.shape_epoch, exec});
+  keep.push_back({in, e64, e32, in32_ready, mask, H.shape_epoch, exec});
   W.graphs.swap(keep);
   return exec;
 }
 
-void vcycle(const Hierarchy& H, Workspace& W, const double* in, double* e) {
+void vcycle(const Hierarchy& H, Workspace& W, const double* in, double* e64, float* e32,
+            bool in32_ready) {
   if (H.p.graph) {
-    AIRG_HIP(hipGraphLaunch(vcycle_graph(H, W, in, e), H.s));
+    AIRG_HIP(hipGraphLaunch(vcycle_graph(H, W, in, e64, e32, in32_ready), H.s));
     return;
   }
-  vcycle_launches(H, W, in, e, H.s);
+  vcycle_launches(H, W, in, e64, e32, in32_ready, H.s);
 }
 
 int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb, double* x,
@@ -863,6 +890,8 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
     std::vector<double> Hm((size_t)(R + 1) * R), g(R + 1), cs(R), sn(R), hh(2 * (R + 1) + 2), y(R);
     double* V = W.V.get();
     double* Zb = W.Zb.get();
+    float* Zb32 = W.z32 ? W.Zb32.get() : nullptr;  // FP32 Z basis (see solve_processes)
+    float* in32 = W.z32 ? W.in32.get() : nullptr;
     double* hd = W.hbuf.get();
     for (;;) {
       spmv_t<double>(opview(H.Aperm), H.tpr_top, K, W.xperm.get(), W.w.get(), s);
@@ -878,16 +907,22 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
       if (converged || its >= max_it) break;
       if (!std::isfinite(beta)) fail(AIRG_ERR_BREAKDOWN, "FGMRES breakdown (non-finite residual)");
       if (its > 0) ++restarts;
-      launch_divide(V, V, beta, n, s);
+      launch_divide(V, V, beta, n, s, in32);
       std::fill(Hm.begin(), Hm.end(), 0.0);
       std::fill(g.begin(), g.end(), 0.0);
       g[0] = beta;
       int k = 0;
       for (int j = 0; j < R; ++j) {
         double* vj = V + (int64_t)j * ld;
-        double* zj = Zb + (int64_t)j * ld;
-        vcycle(H, W, vj, zj);
-        spmv_t<double>(opview(H.Aperm), H.tpr_top, K, zj, W.w.get(), s);
+        if (Zb32) {
+          float* zj32 = Zb32 + (int64_t)j * ld;
+          vcycle(H, W, vj, nullptr, zj32, true);
+          spmv_x32(opview(H.Aperm), H.tpr_top, K, zj32, W.w.get(), s);
+        } else {
+          double* zj = Zb + (int64_t)j * ld;
+          vcycle(H, W, vj, zj);
+          spmv_t<double>(opview(H.Aperm), H.tpr_top, K, zj, W.w.get(), s);
+        }
         ++its;
         // CGS2: h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; |w|^2, the
         // second and third sweeps each fused with the reduction after them
@@ -930,7 +965,7 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
         if (!std::isfinite(est)) fail(AIRG_ERR_BREAKDOWN, "FGMRES breakdown (non-finite residual)");
         if (est <= thr || its >= max_it) break;
         if (hn == 0.0) break;
-        launch_divide(V + (int64_t)(j + 1) * ld, W.w.get(), hn, n, s);
+        launch_divide(V + (int64_t)(j + 1) * ld, W.w.get(), hn, n, s, in32);
       }
       for (int i = k - 1; i >= 0; --i) {
         double t = g[i];
@@ -938,7 +973,8 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
         y[i] = t / Hm[(size_t)i * R + i];
       }
       W.ybuf.from_host(y.data(), k);
-      launch_basis_combine(W.xperm.get(), Zb, ld, W.ybuf.get(), k, n, s);
+      if (Zb32) launch_basis_combine(W.xperm.get(), Zb32, ld, W.ybuf.get(), k, n, s);
+      else launch_basis_combine(W.xperm.get(), Zb, ld, W.ybuf.get(), k, n, s);
     }
   }
   launch_gather(x, W.xperm.get(), pos, H.n0, s);
@@ -1029,7 +1065,7 @@ int time_kernels(const Hierarchy& H, Workspace& W, int cls, int reps, airg_kerne
       return;
     }
     if (f64) time_pass<double>(H, vecs64(W, in, W.Zb.get()), cls, t);
-    else time_pass<float>(H, vecs32(W), cls, t);
+    else time_pass<float>(H, vecs32(W, W.e32.get()), cls, t);
   };
   LaunchTally tally;
   pass(&tally);  // warm-up pass, also counts the launches and bytes

@@ -11,7 +11,9 @@ namespace airg {
 // the activity masks were on, and the launch-shape epoch it was captured in.
 struct VcycleGraph {
   const double* in;
-  double* e;
+  double* e64;
+  float* e32;
+  bool in32_ready;
   bool mask;
   uint64_t epoch;
   hipGraphExec_t exec;
@@ -22,6 +24,9 @@ struct Workspace {
   int64_t ld = 0;      // leading dimension of the Krylov bases (>= n K)
   int restart = 0;
   DBuf<double> V, Zb;  // (restart + 1) and restart basis vectors
+  // the Z basis in FP32 (FGMRES with FP32 or BF16 storage in the V-cycle)
+  DBuf<float> Zb32;
+  bool z32 = false;
   DBuf<double> w, rr, sv, y0, y1;
   DBuf<double> cw0, cw1, ct;
   // FP32 vectors of the mixed-precision V-cycle
@@ -56,8 +61,11 @@ void workspace_init(const Hierarchy& H, Workspace& W, int K = 1);
 
 // One V-cycle: e = M r for a top-level vector `in` (nested numbering, W.K
 // columns), launched kernel by kernel, or replayed from a captured HIP graph
-// with params.graph.
-void vcycle(const Hierarchy& H, Workspace& W, const double* in, double* e);
+// with params.graph.  The output goes to e64, or with FP32 or BF16 storage
+// to e32 in FP32 when e32 is given; in32_ready says that W.in32 already holds
+// (float) in.
+void vcycle(const Hierarchy& H, Workspace& W, const double* in, double* e64,
+            float* e32 = nullptr, bool in32_ready = false);
 
 // The outer solve of A x = b for W.K right-hand sides solved together: column
 // c of b starts at b + c ldb and of x at x + c ldx (setup numbering, device);

@@ -70,9 +70,9 @@ struct IdxMap {
 };
 
 // sum over entries p = s + lane, s + lane + TPR, ... < e of val[p] * x[idx(col[p]) * K + c]
-template <int TPR, int U, int K, class MV, bool C16, class X, class Idx>
+template <int TPR, int U, int K, class MV, bool C16, class X, class XI, class Idx>
 __device__ __forceinline__ X row_dot_cols(const CSRT<MV, C16>& A, int s, int e, int b, int lane,
-                                          const X* __restrict__ x, int c, Idx idx, X sum) {
+                                          const XI* __restrict__ x, int c, Idx idx, X sum) {
   for (int p0 = s + lane; p0 < e; p0 += TPR * U) {
     int col[U];
     X v[U];
@@ -84,7 +84,7 @@ __device__ __forceinline__ X row_dot_cols(const CSRT<MV, C16>& A, int s, int e, 
     }
     X xv[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) xv[u] = col[u] >= 0 ? x[(int64_t)col[u] * K + c] : X(0);
+    for (int u = 0; u < U; ++u) xv[u] = col[u] >= 0 ? (X)x[(int64_t)col[u] * K + c] : X(0);
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (col[u] >= 0) sum = sum + v[u] * xv[u];
@@ -94,9 +94,9 @@ __device__ __forceinline__ X row_dot_cols(const CSRT<MV, C16>& A, int s, int e, 
 // b: the row's column base in the compressed form; a negative base (a block
 // that kept int32 columns) takes the int32 path.  Rows of one wavefront lie
 // in one 64-row block, so the branch is uniform.
-template <int TPR, int U, int K, class MV, bool C16, class X, class Idx>
+template <int TPR, int U, int K, class MV, bool C16, class X, class XI, class Idx>
 __device__ __forceinline__ X row_dot(const CSRT<MV, C16>& A, int s, int e, int b, int lane,
-                                     const X* __restrict__ x, int c, Idx idx, X sum) {
+                                     const XI* __restrict__ x, int c, Idx idx, X sum) {
   if constexpr (C16) {
     if (b < 0) {
       const CSRT<MV, false> W{A.rowptr, A.col, nullptr, nullptr, A.val, A.rows, nullptr};
@@ -172,15 +172,15 @@ __device__ __forceinline__ void load_pairs(const CSRT<MV, C16>& A, int q0, int q
     }
   }
 }
-template <int U, class X>
-__device__ __forceinline__ X add_pairs(const X* __restrict__ gx, const int (&c0)[U],
+template <int U, class X, class XI>
+__device__ __forceinline__ X add_pairs(const XI* __restrict__ gx, const int (&c0)[U],
                                        const int (&c1)[U], const X (&v0)[U], const X (&v1)[U],
                                        X sum) {
   X x0[U], x1[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    x0[u] = c0[u] >= 0 ? gx[c0[u]] : X(0);
-    x1[u] = c1[u] >= 0 ? gx[c1[u]] : X(0);
+    x0[u] = c0[u] >= 0 ? (X)gx[c0[u]] : X(0);
+    x1[u] = c1[u] >= 0 ? (X)gx[c1[u]] : X(0);
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -189,9 +189,9 @@ __device__ __forceinline__ X add_pairs(const X* __restrict__ gx, const int (&c0)
   }
   return sum;
 }
-template <int TPR, int U, bool OFF, class MV, bool C16, class X>
+template <int TPR, int U, bool OFF, class MV, bool C16, class X, class XI>
 __device__ __forceinline__ X row_dot_pairs_cols(const CSRT<MV, C16>& A, int s, int e, int b,
-                                                int lane, const X* __restrict__ gx, X sum) {
+                                                int lane, const XI* __restrict__ gx, X sum) {
   const int qe = (e + 1) >> 1;
   for (int q0 = (s >> 1) + lane; q0 < qe; q0 += TPR * U) {
     int c0[U], c1[U];
@@ -202,9 +202,9 @@ __device__ __forceinline__ X row_dot_pairs_cols(const CSRT<MV, C16>& A, int s, i
   return sum;
 }
 // global gathers; a negative base (int32 block) takes the int32 columns
-template <int TPR, int U, class MV, bool C16, class X>
+template <int TPR, int U, class MV, bool C16, class X, class XI>
 __device__ __forceinline__ X row_dot_pairs(const CSRT<MV, C16>& A, int s, int e, int b, int lane,
-                                           const X* __restrict__ x, X sum) {
+                                           const XI* __restrict__ x, X sum) {
   if constexpr (C16) {
     if (b < 0) {
       const CSRT<MV, false> W{A.rowptr, A.col, nullptr, nullptr, A.val, A.rows, nullptr};
@@ -232,8 +232,8 @@ static unsigned grid_for(int64_t rows, int rows_per_block, int xcd) {
 }
 
 // lanes-per-row kernel (K = 1)
-template <int TPR, class MV, bool C16, class X, class Epi, bool MASK>
-__global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV, C16> A, const X* __restrict__ x,
+template <int TPR, class MV, bool C16, class X, class Epi, bool MASK, class XI>
+__global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV, C16> A, const XI* __restrict__ x,
                                                    Epi epi, int xcd) {
   const int lane = threadIdx.x & (TPR - 1);
   const int64_t row = row_block_index(xcd) * (256 / TPR) + threadIdx.x / TPR;
@@ -258,8 +258,8 @@ __global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV, C16> A, const X* __r
 
 // column-per-lane kernel (K > 1 interleaved columns): each column's row sum
 // runs left to right from 0, as the TPR = 1 kernel does
-template <int K, class MV, bool C16, class X, class Epi>
-__global__ __launch_bounds__(256) void spmm_kernel(CSRT<MV, C16> A, const X* __restrict__ x,
+template <int K, class MV, bool C16, class X, class Epi, class XI>
+__global__ __launch_bounds__(256) void spmm_kernel(CSRT<MV, C16> A, const XI* __restrict__ x,
                                                    Epi epi, int xcd) {
   const int c = threadIdx.x & (K - 1);
   const int64_t row = row_block_index(xcd) * (256 / K) + threadIdx.x / K;
@@ -280,10 +280,10 @@ __global__ __launch_bounds__(256) void spmm_kernel(CSRT<MV, C16> A, const X* __r
 // memory round trips for all of its rows, which suits long rows.
 constexpr int kRowBlockNnz = 2048;
 
-template <class MV, bool C16, class X, class Epi, bool MASK>
+template <class MV, bool C16, class X, class Epi, bool MASK, class XI>
 __global__ __launch_bounds__(256) void spmv_rowblock_kernel(CSRT<MV, C16> A,
                                                             const int32_t* __restrict__ rblk,
-                                                            int64_t nblk, const X* __restrict__ x,
+                                                            int64_t nblk, const XI* __restrict__ x,
                                                             Epi epi, int xcd) {
   __shared__ X prod[kRowBlockNnz];
   const int64_t b = row_block_index(xcd);
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(256) void spmv_rowblock_kernel(CSRT<MV, C16> A,
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int p = c0 + t + 256 * u;
-      if (p < c1) prod[p - c0] = v[u] * x[col[u]];
+      if (p < c1) prod[p - c0] = v[u] * (X)x[col[u]];
     }
     __syncthreads();
     if (mine) {
@@ -342,8 +342,8 @@ __global__ __launch_bounds__(256) void spmv_rowblock_kernel(CSRT<MV, C16> A,
 // groups' first entries.
 constexpr int kEntryChunk = 1024;
 
-template <class MV, bool C16, class X, class Epi, bool MASK>
-__global__ __launch_bounds__(256) void spmv_entries_kernel(CSRT<MV, C16> A, const X* __restrict__ x,
+template <class MV, bool C16, class X, class Epi, bool MASK, class XI>
+__global__ __launch_bounds__(256) void spmv_entries_kernel(CSRT<MV, C16> A, const XI* __restrict__ x,
                                                            Epi epi, int xcd) {
   __shared__ X prod[kEntryChunk];
   const int64_t r0 = row_block_index(xcd) * 256;
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(256) void spmv_entries_kernel(CSRT<MV, C16> A, cons
     }
     X xv[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) xv[u] = col[u] >= 0 ? x[col[u]] : X(0);
+    for (int u = 0; u < 4; ++u) xv[u] = col[u] >= 0 ? (X)x[col[u]] : X(0);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (col[u] >= 0) prod[t + 256 * u] = v[u] * xv[u];
@@ -426,11 +426,11 @@ static int64_t lds_budget_bytes() {
   return cached;
 }
 
-template <int TPR, class MV, class X, class Epi, bool MASK>
+template <int TPR, class MV, class X, class Epi, bool MASK, class XI>
 __global__ __launch_bounds__(64 * TPR) void spmv_lds_kernel(CSRT<MV, true> A,
                                                             const int32_t* __restrict__ cspan,
                                                             int64_t ngroups, int lds_cap,
-                                                            const X* __restrict__ x, Epi epi,
+                                                            const XI* __restrict__ x, Epi epi,
                                                             int xcd) {
   extern __shared__ unsigned char smem_raw[];
   X* xs = reinterpret_cast<X*>(smem_raw);
@@ -462,7 +462,7 @@ __global__ __launch_bounds__(64 * TPR) void spmv_lds_kernel(CSRT<MV, true> A,
     int c0[U], c1[U];
     X v0[U], v1[U];
     load_pairs<TPR, U, true>(A, q0, qe, s, e, 0, c0, c1, v0, v1);
-    for (int i = t; i < span; i += 64 * TPR) xs[i] = x[base + i];
+    for (int i = t; i < span; i += 64 * TPR) xs[i] = (X)x[base + i];
     __syncthreads();
     sum = add_pairs<U>((const X*)xs, c0, c1, v0, v1, sum);
     for (q0 += TPR * U; q0 < qe; q0 += TPR * U) {
@@ -484,14 +484,14 @@ __global__ __launch_bounds__(64 * TPR) void spmv_lds_kernel(CSRT<MV, true> A,
 // bit 10
 // MASK: the launch honours Av.gmask (a separate instantiation, so that the
 // unmasked products carry no test)
-template <class MV, bool C16, bool MASK, class X, class Epi>
-static void launch_spmv_t(const OpView& Av, int shape, int K, const X* x, Epi epi, hipStream_t s) {
+template <class MV, bool C16, bool MASK, class X, class XI, class Epi>
+static void launch_spmv_t(const OpView& Av, int shape, int K, const XI* x, Epi epi, hipStream_t s) {
   if (Av.rows <= 0) return;
   const int tpr = shape & 0xff, xcd = (shape >> 8) & 1, lds = (shape >> 9) & 1;
   CSRT<MV, C16> A = csr_t<MV, C16>(Av);
   if (K == 1 && (shape & kShapeEntries)) {
-    spmv_entries_kernel<MV, C16, X, Epi, MASK><<<grid_for(Av.rows, 256, xcd), 256, 0, s>>>(A, x, epi,
-                                                                                         xcd);
+    spmv_entries_kernel<MV, C16, X, Epi, MASK, XI><<<grid_for(Av.rows, 256, xcd), 256, 0, s>>>(
+        A, x, epi, xcd);
     AIRG_CHECK_LAUNCH();
     return;
   }
@@ -502,10 +502,10 @@ static void launch_spmv_t(const OpView& Av, int shape, int K, const X* x, Epi ep
       const size_t smem = (size_t)std::max(cap, 1) * sizeof(X);
       const unsigned nb = grid_for(ngroups, 1, xcd);
       switch (tpr) {
-        case 2: spmv_lds_kernel<2, MV, X, Epi, MASK><<<nb, 128, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
-        case 4: spmv_lds_kernel<4, MV, X, Epi, MASK><<<nb, 256, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
-        case 8: spmv_lds_kernel<8, MV, X, Epi, MASK><<<nb, 512, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
-        case 16: spmv_lds_kernel<16, MV, X, Epi, MASK><<<nb, 1024, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
+        case 2: spmv_lds_kernel<2, MV, X, Epi, MASK, XI><<<nb, 128, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
+        case 4: spmv_lds_kernel<4, MV, X, Epi, MASK, XI><<<nb, 256, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
+        case 8: spmv_lds_kernel<8, MV, X, Epi, MASK, XI><<<nb, 512, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
+        case 16: spmv_lds_kernel<16, MV, X, Epi, MASK, XI><<<nb, 1024, smem, s>>>(A, Av.cspan, ngroups, cap, x, epi, xcd); break;
         default: fail(AIRG_ERR_INTERNAL, "LDS-staged product takes 2, 4, 8 or 16 lanes per row");
       }
       AIRG_CHECK_LAUNCH();
@@ -516,7 +516,7 @@ static void launch_spmv_t(const OpView& Av, int shape, int K, const X* x, Epi ep
   }
   if (K == 1 && tpr == 0) {
     if (!Av.rblk) fail(AIRG_ERR_INTERNAL, "row-block product without row blocks");
-    spmv_rowblock_kernel<MV, C16, X, Epi, MASK><<<grid_for(Av.nrblk, 1, xcd), 256, 0, s>>>(
+    spmv_rowblock_kernel<MV, C16, X, Epi, MASK, XI><<<grid_for(Av.nrblk, 1, xcd), 256, 0, s>>>(
         A, Av.rblk, Av.nrblk, x, epi, xcd);
     AIRG_CHECK_LAUNCH();
     return;
@@ -526,24 +526,24 @@ static void launch_spmv_t(const OpView& Av, int shape, int K, const X* x, Epi ep
   if (K == 1) {
     unsigned nb = grid_for(Av.rows, 256 / tpr, xcd);
     switch (tpr) {
-      case 1: spmv_kernel<1, MV, C16, X, Epi, MASK><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 2: spmv_kernel<2, MV, C16, X, Epi, MASK><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 4: spmv_kernel<4, MV, C16, X, Epi, MASK><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 8: spmv_kernel<8, MV, C16, X, Epi, MASK><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 16: spmv_kernel<16, MV, C16, X, Epi, MASK><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 32: spmv_kernel<32, MV, C16, X, Epi, MASK><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 64: spmv_kernel<64, MV, C16, X, Epi, MASK><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 1: spmv_kernel<1, MV, C16, X, Epi, MASK, XI><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 2: spmv_kernel<2, MV, C16, X, Epi, MASK, XI><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 4: spmv_kernel<4, MV, C16, X, Epi, MASK, XI><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 8: spmv_kernel<8, MV, C16, X, Epi, MASK, XI><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 16: spmv_kernel<16, MV, C16, X, Epi, MASK, XI><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 32: spmv_kernel<32, MV, C16, X, Epi, MASK, XI><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 64: spmv_kernel<64, MV, C16, X, Epi, MASK, XI><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
       default: fail(AIRG_ERR_INTERNAL, "bad lanes-per-row");
     }
   } else {
     unsigned nb = grid_for(Av.rows, 256 / K, xcd);
     switch (K) {
-      case 2: spmm_kernel<2, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 4: spmm_kernel<4, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 8: spmm_kernel<8, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 16: spmm_kernel<16, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 32: spmm_kernel<32, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
-      case 64: spmm_kernel<64, MV, C16, X, Epi><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 2: spmm_kernel<2, MV, C16, X, Epi, XI><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 4: spmm_kernel<4, MV, C16, X, Epi, XI><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 8: spmm_kernel<8, MV, C16, X, Epi, XI><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 16: spmm_kernel<16, MV, C16, X, Epi, XI><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 32: spmm_kernel<32, MV, C16, X, Epi, XI><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
+      case 64: spmm_kernel<64, MV, C16, X, Epi, XI><<<nb, 256, 0, s>>>(A, x, epi, xcd); break;
       default: fail(AIRG_ERR_INTERNAL, "column count must be a power of two <= 64");
     }
   }
@@ -552,26 +552,26 @@ static void launch_spmv_t(const OpView& Av, int shape, int K, const X* x, Epi ep
 
 // dispatch on the matrix storage and column form: FP64 values go with FP64
 // vectors, FP32 and BF16 values with FP32 vectors
-template <class MV, class X, class Epi>
-static void launch_cols(const OpView& A, int tpr, int K, const X* x, Epi epi, hipStream_t s) {
+template <class MV, class X, class XI, class Epi>
+static void launch_cols(const OpView& A, int tpr, int K, const XI* x, Epi epi, hipStream_t s) {
   if (A.gmask && K == 1) {
-    if (A.col16) launch_spmv_t<MV, true, true>(A, tpr, K, x, epi, s);
-    else launch_spmv_t<MV, false, true>(A, tpr, K, x, epi, s);
+    if (A.col16) launch_spmv_t<MV, true, true, X>(A, tpr, K, x, epi, s);
+    else launch_spmv_t<MV, false, true, X>(A, tpr, K, x, epi, s);
     return;
   }
-  if (A.col16) launch_spmv_t<MV, true, false>(A, tpr, K, x, epi, s);
-  else launch_spmv_t<MV, false, false>(A, tpr, K, x, epi, s);
+  if (A.col16) launch_spmv_t<MV, true, false, X>(A, tpr, K, x, epi, s);
+  else launch_spmv_t<MV, false, false, X>(A, tpr, K, x, epi, s);
 }
 template <class Epi>
 static void launch_spmv(const OpView& A, int tpr, int K, const double* x, Epi epi, hipStream_t s) {
   if (A.vt != VT_F64) fail(AIRG_ERR_INTERNAL, "FP64 vectors need FP64 values");
-  launch_cols<double>(A, tpr, K, x, epi, s);
+  launch_cols<double, double>(A, tpr, K, x, epi, s);
 }
 template <class Epi>
 static void launch_spmv(const OpView& A, int tpr, int K, const float* x, Epi epi, hipStream_t s) {
   switch (A.vt) {
-    case VT_F32: launch_cols<float>(A, tpr, K, x, epi, s); break;
-    case VT_BF16: launch_cols<bf16>(A, tpr, K, x, epi, s); break;
+    case VT_F32: launch_cols<float, float>(A, tpr, K, x, epi, s); break;
+    case VT_BF16: launch_cols<bf16, float>(A, tpr, K, x, epi, s); break;
     default: fail(AIRG_ERR_INTERNAL, "FP32 vectors need FP32 or BF16 values");
   }
 }
@@ -890,6 +890,13 @@ void axpy_first_t(X* x, const X* w, double a, bool first, int64_t n, hipStream_t
 AIRG_INSTANTIATE(double)
 AIRG_INSTANTIATE(float)
 #undef AIRG_INSTANTIATE
+
+// y = A x with FP64 values and rows, x in FP32 (the outer loop's product with
+// a basis kept in FP32): every x element is widened to FP64 as it is gathered
+void spmv_x32(const OpView& A, int tpr, int K, const float* x, double* y, hipStream_t s) {
+  if (A.vt != VT_F64) fail(AIRG_ERR_INTERNAL, "the FP32-vector product of the outer loop needs FP64 values");
+  launch_cols<double, double>(A, tpr, K, x, EpiStore<double>{y}, s);
+}
 
 // ------------------------------------------------------------------ FP64 wrappers
 void spmv_seq(const CSR& A, const double* x, double* y, hipStream_t s) {

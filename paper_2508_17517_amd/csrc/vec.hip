@@ -52,9 +52,12 @@ __global__ void scale_kernel(double* y, const double* x, double a, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = a * x[i];
 }
-__global__ void divide_kernel(double* y, const double* x, double d, int64_t n) {
+__global__ void divide_kernel(double* y, const double* x, double d, int64_t n, float* y32) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = x[i] / d;
+  if (i >= n) return;
+  const double v = x[i] / d;
+  y[i] = v;
+  if (y32) y32[i] = (float)v;
 }
 __global__ void divide_dev_kernel(double* y, const double* x, const double* d, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -90,9 +93,9 @@ void launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t s
   scale_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, a, n);
   AIRG_CHECK_LAUNCH();
 }
-void launch_divide(double* y, const double* x, double d, int64_t n, hipStream_t s) {
+void launch_divide(double* y, const double* x, double d, int64_t n, hipStream_t s, float* y32) {
   if (n <= 0) return;
-  divide_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, d, n);
+  divide_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, d, n, y32);
   AIRG_CHECK_LAUNCH();
 }
 void launch_divide_dev(double* y, const double* x, const double* d, int64_t n, hipStream_t s) {
@@ -121,19 +124,30 @@ void launch_cgs_update(double* w, const double* V, int64_t ldv, const double* h,
   AIRG_CHECK_LAUNCH();
 }
 
-__global__ void basis_combine_kernel(double* x, const double* Z, int64_t ldz, const double* y,
-                                     int nv, int64_t n) {
+// Z in FP64, or in FP32 (widened to FP64 as it is read)
+template <class ZT>
+__global__ void basis_combine_kernel(double* x, const ZT* Z, int64_t ldz, const double* y, int nv,
+                                     int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double acc = x[i];
-  for (int k = 0; k < nv; ++k) acc = acc + y[k] * Z[(int64_t)k * ldz + i];
+  for (int k = 0; k < nv; ++k) acc = acc + y[k] * (double)Z[(int64_t)k * ldz + i];
   x[i] = acc;
+}
+template <class ZT>
+static void launch_basis_combine_t(double* x, const ZT* Z, int64_t ldz, const double* y, int nv,
+                                   int64_t n, hipStream_t s) {
+  if (n <= 0 || nv <= 0) return;
+  basis_combine_kernel<ZT><<<blocks_for(n, kBlock), kBlock, 0, s>>>(x, Z, ldz, y, nv, n);
+  AIRG_CHECK_LAUNCH();
 }
 void launch_basis_combine(double* x, const double* Z, int64_t ldz, const double* y, int nv,
                           int64_t n, hipStream_t s) {
-  if (n <= 0 || nv <= 0) return;
-  basis_combine_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(x, Z, ldz, y, nv, n);
-  AIRG_CHECK_LAUNCH();
+  launch_basis_combine_t(x, Z, ldz, y, nv, n, s);
+}
+void launch_basis_combine(double* x, const float* Z, int64_t ldz, const double* y, int nv,
+                          int64_t n, hipStream_t s) {
+  launch_basis_combine_t(x, Z, ldz, y, nv, n, s);
 }
 
 // ------------------------------------------------------------------ tree dots
@@ -344,20 +358,24 @@ __global__ void cgs_update_cols_kernel(double* w, const double* V, int64_t ldv, 
   for (int k = 0; k < nv; ++k) acc = acc - h[k * K + c] * V[(int64_t)k * ldv + e];
   w[e] = acc;
 }
-__global__ void basis_combine_cols_kernel(double* x, const double* Z, int64_t ldz, const double* y,
+template <class ZT>
+__global__ void basis_combine_cols_kernel(double* x, const ZT* Z, int64_t ldz, const double* y,
                                           int nv, int64_t n, int K) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   const int c = (int)(e & (K - 1));
   double acc = x[e];
-  for (int k = 0; k < nv; ++k) acc = acc + y[k * K + c] * Z[(int64_t)k * ldz + e];
+  for (int k = 0; k < nv; ++k) acc = acc + y[k * K + c] * (double)Z[(int64_t)k * ldz + e];
   x[e] = acc;
 }
-__global__ void divide_cols_kernel(double* y, const double* x, const double* d, int64_t n, int K) {
+__global__ void divide_cols_kernel(double* y, const double* x, const double* d, int64_t n, int K,
+                                   float* y32) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   const double dc = d[e & (K - 1)];
-  y[e] = dc != 0.0 ? x[e] / dc : 0.0;
+  const double v = dc != 0.0 ? x[e] / dc : 0.0;
+  y[e] = v;
+  if (y32) y32[e] = (float)v;
 }
 
 static void check_cols(int K) {
@@ -371,20 +389,29 @@ void launch_cgs_update_cols(double* w, const double* V, int64_t ldv, const doubl
   cgs_update_cols_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(w, V, ldv, h, nv, n, K);
   AIRG_CHECK_LAUNCH();
 }
-void launch_basis_combine_cols(double* x, const double* Z, int64_t ldz, const double* y, int nv,
-                               int64_t n0, int K, hipStream_t s) {
+template <class ZT>
+static void launch_basis_combine_cols_t(double* x, const ZT* Z, int64_t ldz, const double* y,
+                                        int nv, int64_t n0, int K, hipStream_t s) {
   check_cols(K);
   const int64_t n = n0 * K;
   if (n <= 0 || nv <= 0) return;
-  basis_combine_cols_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(x, Z, ldz, y, nv, n, K);
+  basis_combine_cols_kernel<ZT><<<blocks_for(n, kBlock), kBlock, 0, s>>>(x, Z, ldz, y, nv, n, K);
   AIRG_CHECK_LAUNCH();
 }
+void launch_basis_combine_cols(double* x, const double* Z, int64_t ldz, const double* y, int nv,
+                               int64_t n0, int K, hipStream_t s) {
+  launch_basis_combine_cols_t(x, Z, ldz, y, nv, n0, K, s);
+}
+void launch_basis_combine_cols(double* x, const float* Z, int64_t ldz, const double* y, int nv,
+                               int64_t n0, int K, hipStream_t s) {
+  launch_basis_combine_cols_t(x, Z, ldz, y, nv, n0, K, s);
+}
 void launch_divide_cols(double* y, const double* x, const double* d, int64_t n0, int K,
-                        hipStream_t s) {
+                        hipStream_t s, float* y32) {
   check_cols(K);
   const int64_t n = n0 * K;
   if (n <= 0) return;
-  divide_cols_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, d, n, K);
+  divide_cols_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, d, n, K, y32);
   AIRG_CHECK_LAUNCH();
 }
 
@@ -643,8 +670,9 @@ __global__ __launch_bounds__(256) void group_update_kernel(double* __restrict__ 
     w[i] = acc;
   }
 }
+template <class ZT>
 __global__ __launch_bounds__(256) void group_combine_kernel(double* __restrict__ x,
-                                                            const double* __restrict__ Z, int64_t ldz,
+                                                            const ZT* __restrict__ Z, int64_t ldz,
                                                             const double* __restrict__ y, int nv,
                                                             int G, const int64_t* __restrict__ start,
                                                             const int32_t* __restrict__ len,
@@ -654,7 +682,8 @@ __global__ __launch_bounds__(256) void group_combine_kernel(double* __restrict__
   for (int e = threadIdx.x; e < m; e += 256) {
     const int64_t i = b + e;
     double acc = x[i];
-    for (int k = 0; k < nv; ++k) acc = acc + y[(int64_t)k * G + g] * Z[(int64_t)k * ldz + i];
+    for (int k = 0; k < nv; ++k)
+      acc = acc + y[(int64_t)k * G + g] * (double)Z[(int64_t)k * ldz + i];
     x[i] = acc;
   }
 }
@@ -663,11 +692,16 @@ __global__ __launch_bounds__(256) void group_divide_kernel(double* __restrict__ 
                                                            const double* __restrict__ d,
                                                            const int64_t* __restrict__ start,
                                                            const int32_t* __restrict__ len,
-                                                           const int32_t* __restrict__ grp) {
+                                                           const int32_t* __restrict__ grp,
+                                                           float* __restrict__ y32) {
   const int64_t b = start[blockIdx.x];
   const int m = len[blockIdx.x];
   const double dg = d[grp[blockIdx.x]];
-  for (int e = threadIdx.x; e < m; e += 256) y[b + e] = dg != 0.0 ? x[b + e] / dg : 0.0;
+  for (int e = threadIdx.x; e < m; e += 256) {
+    const double v = dg != 0.0 ? x[b + e] / dg : 0.0;
+    y[b + e] = v;
+    if (y32) y32[b + e] = (float)v;
+  }
 }
 
 size_t group_dots_work_size(const GroupItems& it) { return (size_t)kMaxDotVecs * (size_t)std::max<int64_t>(it.n, 1); }
@@ -692,18 +726,27 @@ void launch_group_update(double* w, const double* V, int64_t ldv, const double* 
                                                       it.len.get(), it.grp.get());
   AIRG_CHECK_LAUNCH();
 }
-void launch_group_combine(double* x, const double* Z, int64_t ldz, const double* y, int nv,
-                          const GroupItems& it, hipStream_t s) {
+template <class ZT>
+static void launch_group_combine_t(double* x, const ZT* Z, int64_t ldz, const double* y, int nv,
+                                   const GroupItems& it, hipStream_t s) {
   if (nv <= 0 || it.n <= 0) return;
-  group_combine_kernel<<<(unsigned)it.n, 256, 0, s>>>(x, Z, ldz, y, nv, it.G, it.start.get(),
-                                                       it.len.get(), it.grp.get());
+  group_combine_kernel<ZT><<<(unsigned)it.n, 256, 0, s>>>(x, Z, ldz, y, nv, it.G, it.start.get(),
+                                                           it.len.get(), it.grp.get());
   AIRG_CHECK_LAUNCH();
 }
+void launch_group_combine(double* x, const double* Z, int64_t ldz, const double* y, int nv,
+                          const GroupItems& it, hipStream_t s) {
+  launch_group_combine_t(x, Z, ldz, y, nv, it, s);
+}
+void launch_group_combine(double* x, const float* Z, int64_t ldz, const double* y, int nv,
+                          const GroupItems& it, hipStream_t s) {
+  launch_group_combine_t(x, Z, ldz, y, nv, it, s);
+}
 void launch_group_divide(double* y, const double* x, const double* d, const GroupItems& it,
-                         hipStream_t s) {
+                         hipStream_t s, float* y32) {
   if (it.n <= 0) return;
   group_divide_kernel<<<(unsigned)it.n, 256, 0, s>>>(y, x, d, it.start.get(), it.len.get(),
-                                                      it.grp.get());
+                                                      it.grp.get(), y32);
   AIRG_CHECK_LAUNCH();
 }
 
