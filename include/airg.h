@@ -94,7 +94,11 @@ typedef struct {
                                 on first use per pair of vectors, recaptured after a
                                 launch-shape change; the same launches, bit for bit the
                                 same results); 0: launch its kernels one by one, 0 */
-  int32_t reserved;          /* must be 0 */
+  int32_t stagnation_check;  /* 1: a process (right-hand side, problem) whose true residual
+                                norm falls by less than 1% over a restart cycle (Richardson:
+                                over `restart` steps) stops there, not converged, with
+                                airg_solve_info.stagnated set; 0: only rtol, atol and max_it
+                                stop it, 0 */
 } airg_params;
 
 /* The polynomial approximation of A_ff^{-1} in the smoother and in Ahat^{-1}.
@@ -135,9 +139,10 @@ typedef enum { AIRG_OUTER_FGMRES = 0, AIRG_OUTER_RICHARDSON = 1 } airg_outer;
 
 typedef struct {
   int32_t iterations;        /* V-cycles applied */
-  int32_t converged;         /* 1 when the true relative residual <= rtol */
+  int32_t converged;         /* 1 when the true relative residual <= rtol (or the residual
+                                norm <= atol) */
   int32_t restarts;
-  int32_t reserved;
+  int32_t stagnated;         /* 1 when the stagnation check stopped it (stagnation_check) */
   double rel_residual;       /* true |b - A x| / |b| at exit (Richardson with b = 0:
                                 relative to |b - A x0|) */
   double rel_residual_estimate; /* Arnoldi estimate at exit */
@@ -417,6 +422,15 @@ int airg_fv_gradients_noalloc(int64_t nx, int64_t ny, double theta, const int32_
                               const double* db_dtheta, const double* u, const double* lam,
                               double* dg_west, double* dg_south, double* dtheta,
                               void* hip_stream);
+
+/* Failure-handling hook (for tests and for callers that cap the library's
+ * memory): from now on, a device allocation of the library that would take
+ * the bytes its buffers hold past `bytes` fails with AIRG_ERR_NOMEM, as if
+ * the device were out of memory (the call that needed it returns that code
+ * and releases what it had allocated).  bytes <= 0 removes the budget.
+ * *in_use (may be NULL) receives the bytes the library's buffers hold now,
+ * over every handle of the process. */
+int airg_set_alloc_budget(int64_t bytes, int64_t* in_use);
 
 /* Release the handle and all its device memory (NULL is a no-op). */
 void airg_destroy(airg_handle h);

@@ -29,16 +29,16 @@ class Params(ctypes.Structure):
                 ("max_it", c_i32), ("restart", c_i32), ("keep_setup_data", c_i32),
                 ("locality_order", c_i32), ("outer", c_i32), ("smoother", c_i32),
                 ("inverse_type", c_i32), ("smooth_type", c_i32), ("atol", c_dbl), ("graph", c_i32),
-                ("reserved", c_i32)]
+                ("stagnation_check", c_i32)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", c_i32), ("converged", c_i32), ("restarts", c_i32),
-                ("reserved", c_i32), ("rel_residual", c_dbl), ("rel_residual_estimate", c_dbl),
+                ("stagnated", c_i32), ("rel_residual", c_dbl), ("rel_residual_estimate", c_dbl),
                 ("solve_ms", c_dbl)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Stats(ctypes.Structure):
@@ -136,6 +136,7 @@ SYMBOLS = {
     "airg_fv_gradients_noalloc": (c_i32, [c_i64, c_i64, c_dbl] + [ctypes.c_void_p] * 10),
     "airg_stream_probe": (c_i32, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, c_i64, ctypes.c_int,
                                   ctypes.c_int, P(c_dbl), ctypes.c_void_p]),
+    "airg_set_alloc_budget": (c_i32, [c_i64, P(c_i64)]),
     "airg_destroy": (None, [ctypes.c_void_p]),
     "airg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "airg_last_error": (ctypes.c_char_p, []),

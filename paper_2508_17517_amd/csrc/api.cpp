@@ -1,5 +1,6 @@
 // C ABI of the AIRG library (declared in include/airg.h).  Every entry point
 // catches the library's exceptions and turns them into status codes.
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -13,6 +14,25 @@
 #include "solve.hpp"
 
 using namespace airg;
+
+namespace airg {
+
+namespace {
+std::atomic<int64_t> g_device_bytes{0};
+std::atomic<int64_t> g_device_budget{0};
+}  // namespace
+
+void account_device_bytes(int64_t delta) { g_device_bytes += delta; }
+void check_device_budget(size_t bytes) {
+  const int64_t budget = g_device_budget.load();
+  if (budget > 0 && g_device_bytes.load() + (int64_t)bytes > budget)
+    fail(AIRG_ERR_NOMEM, "device allocation of " + std::to_string(bytes) +
+                             " bytes would pass the allocation budget of " +
+                             std::to_string(budget) + " bytes");
+}
+void set_device_budget(int64_t bytes) { g_device_budget = bytes > 0 ? bytes : 0; }
+
+}  // namespace airg
 
 struct airg_ctx {
   Hierarchy H;
@@ -63,7 +83,7 @@ void check_params(const airg_params& p) {
   if (!(p.rtol > 0.0 && p.rtol < 1.0)) bad("rtol");
   if (!(p.atol >= 0.0 && std::isfinite(p.atol))) bad("atol");
   if (p.graph != 0 && p.graph != 1) bad("graph");
-  if (p.reserved != 0) bad("reserved (must be 0)");
+  if (p.stagnation_check != 0 && p.stagnation_check != 1) bad("stagnation_check");
   if (p.max_it < 0) bad("max_it");
   if (p.restart < 1 || p.restart > 512) bad("restart");
   if (p.outer != AIRG_OUTER_FGMRES && p.outer != AIRG_OUTER_RICHARDSON) bad("outer");
@@ -191,7 +211,7 @@ int airg_params_default(airg_params* p) {
   p->smooth_type = AIRG_SMOOTH_TYPE_F;
   p->atol = 1e-50;
   p->graph = 0;
-  p->reserved = 0;
+  p->stagnation_check = 0;
   return AIRG_OK;
 }
 
@@ -520,6 +540,14 @@ int airg_fv_gradients_noalloc(int64_t nx, int64_t ny, double theta, const int32_
       fail(AIRG_ERR_INVALID, "null pointer");
     fv_gradients_noalloc(nx, ny, theta, rowptr, col, dval_dtheta, db_dtheta, u, lam, dg_west,
                          dg_south, dtheta, (hipStream_t)hip_stream);
+    return (int)AIRG_OK;
+  });
+}
+
+int airg_set_alloc_budget(int64_t bytes, int64_t* in_use) {
+  return guard([&]() {
+    set_device_budget(bytes);
+    if (in_use) *in_use = g_device_bytes.load();
     return (int)AIRG_OK;
   });
 }

@@ -29,6 +29,13 @@ namespace airg {
 
 void launch_zero_bytes(void* p, size_t bytes, hipStream_t s);
 
+// Device bytes the library's buffers hold, and an optional budget on them
+// (a test hook: an allocation that would pass the budget fails as if the
+// device were out of memory; 0 means no budget).
+void account_device_bytes(int64_t delta);
+void check_device_budget(size_t bytes);
+void set_device_budget(int64_t bytes);
+
 // Stream-ordered device buffer (hipMallocAsync / hipFreeAsync).
 template <class T>
 class DBuf {
@@ -50,11 +57,18 @@ class DBuf {
   void alloc(size_t n, hipStream_t s) {
     release();
     s_ = s;
+    if (n) {
+      check_device_budget(n * sizeof(T) + 256);
+      AIRG_HIP(hipMallocAsync((void**)&p_, n * sizeof(T) + 256, s));
+      account_device_bytes((int64_t)(n * sizeof(T) + 256));
+    }
     n_ = n;
-    if (n) AIRG_HIP(hipMallocAsync((void**)&p_, n * sizeof(T) + 256, s));
   }
   void release() {
-    if (p_) (void)hipFreeAsync(p_, s_);
+    if (p_) {
+      (void)hipFreeAsync(p_, s_);
+      account_device_bytes(-(int64_t)(n_ * sizeof(T) + 256));
+    }
     p_ = nullptr;
     n_ = 0;
   }

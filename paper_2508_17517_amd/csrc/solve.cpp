@@ -32,6 +32,11 @@
 
 namespace airg {
 
+// With params.stagnation_check, a restart cycle (Richardson: `restart` steps)
+// must bring the true residual norm below this fraction of its value at the
+// cycle's start, or the process stops as not converged.
+constexpr double kStagnation = 0.99;
+
 Workspace::~Workspace() {
   for (const VcycleGraph& g : graphs) (void)hipGraphExecDestroy(g.exec);
   if (cap) (void)hipStreamDestroy(cap);
@@ -548,8 +553,12 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
   std::vector<double> bn = P.norms(W.bperm.get());
   for (double v : bn)
     if (!std::isfinite(v)) fail(AIRG_ERR_NONFINITE, "right-hand side is not finite");
-  std::vector<int> its(G, 0), rst(G, 0), done(G, 0);
+  std::vector<int> its(G, 0), rst(G, 0), done(G, 0), stag(G, 0);
   std::vector<double> rn(G, 0.0), est(G, 0.0), ref = bn, dh(G), yh((size_t)R * G);
+  // stagnation check: a process whose true residual falls by less than
+  // kStagnation over a restart cycle (Richardson: over `restart` steps) stops
+  const bool stag_check = H.p.stagnation_check != 0;
+  std::vector<double> rwin(G, 0.0);
   auto upload_div = [&]() { W.cdiv.from_host(dh.data(), G); };
   auto residual = [&](double* r) {
     spmv_t<double>(A, H.tpr_top, K, W.xperm.get(), W.w.get(), s);
@@ -565,6 +574,7 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
     for (int c = 0; c < G; ++c) {
       if (ref[c] == 0.0) ref[c] = rn[c];
       done[c] = rn[c] <= tol(ref[c]) || max_it <= 0;
+      rwin[c] = rn[c];
     }
     for (;;) {
       bool any = false;
@@ -581,7 +591,12 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
         if (done[c]) continue;
         ++its[c];
         if (!std::isfinite(rn[c])) fail(AIRG_ERR_BREAKDOWN, "Richardson diverged (non-finite residual)");
-        if (rn[c] <= tol(ref[c]) || its[c] >= max_it) done[c] = 1;
+        if (rn[c] <= tol(ref[c]) || its[c] >= max_it) {
+          done[c] = 1;
+        } else if (stag_check && its[c] % R == 0) {
+          if (rn[c] > kStagnation * rwin[c]) done[c] = stag[c] = 1;
+          rwin[c] = rn[c];
+        }
       }
     }
   } else {
@@ -611,6 +626,11 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
           continue;
         }
         if (!std::isfinite(rn[c])) fail(AIRG_ERR_BREAKDOWN, "FGMRES breakdown (non-finite residual)");
+        if (stag_check && its[c] > 0 && rn[c] > kStagnation * rwin[c]) {
+          done[c] = stag[c] = 1;
+          continue;
+        }
+        rwin[c] = rn[c];
         if (its[c] > 0) ++rst[c];
         act[c] = 1;
         any = true;
@@ -707,6 +727,7 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
     airg_solve_info& o = out[c];
     o.iterations = its[c];
     o.restarts = rst[c];
+    o.stagnated = stag[c];
     o.converged = rn[c] <= tol(ref[c]) ? 1 : 0;
     o.rel_residual = ref[c] > 0.0 ? rn[c] / ref[c] : 0.0;
     o.rel_residual_estimate = H.p.outer == AIRG_OUTER_RICHARDSON
@@ -847,6 +868,9 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
   for (auto& o : out) std::memset(&o, 0, sizeof(o));
   int status = AIRG_OK;
   int its = 0, restarts = 0;
+  int stagnated = 0;
+  const bool stag_check = H.p.stagnation_check != 0;
+  double rwin = 0.0;  // the residual norm the stagnation check compares with
   double est_rel = 0.0;
   std::vector<double> rn(ng, 0.0);
   std::vector<double> ref = bn;  // the norms the relative residuals refer to
@@ -874,12 +898,25 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
     for (size_t q = 0; q < ng; ++q)
       if (ref[q] == 0.0) ref[q] = rn[q];
     converged = done();
+    auto total = [&]() {
+      double t = 0.0;
+      for (double v : rn) t += v * v;
+      return std::sqrt(t);
+    };
+    rwin = total();
     while (!converged && its < max_it) {
       vcycle(H, W, r, e);
       launch_basis_combine(W.xperm.get(), e, W.ld, W.ybuf.get(), 1, n, s);
       ++its;
       residual();
       converged = done();
+      if (!converged && stag_check && its % R == 0) {
+        if (total() > kStagnation * rwin) {
+          stagnated = 1;
+          break;
+        }
+        rwin = total();
+      }
     }
     est_rel = 0.0;
     for (size_t q = 0; q < ng; ++q) est_rel = std::max(est_rel, ref[q] > 0 ? rn[q] / ref[q] : 0.0);
@@ -906,6 +943,11 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
       const double beta = std::sqrt(beta2);
       if (converged || its >= max_it) break;
       if (!std::isfinite(beta)) fail(AIRG_ERR_BREAKDOWN, "FGMRES breakdown (non-finite residual)");
+      if (stag_check && its > 0 && beta > kStagnation * rwin) {
+        stagnated = 1;
+        break;
+      }
+      rwin = beta;
       if (its > 0) ++restarts;
       launch_divide(V, V, beta, n, s, in32);
       std::fill(Hm.begin(), Hm.end(), 0.0);
@@ -986,6 +1028,7 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
   for (size_t q = 0; q < ng; ++q) {
     out[q].iterations = its;
     out[q].restarts = restarts;
+    out[q].stagnated = stagnated;
     out[q].converged = rn[q] <= tol(ref[q]) ? 1 : 0;
     out[q].rel_residual = ref[q] > 0.0 ? rn[q] / ref[q] : 0.0;
     out[q].rel_residual_estimate = est_rel;

@@ -37,7 +37,7 @@ def test_status_strings_and_defaults_without_gpu():
     assert p.coarse_poly_order == 20 and p.trunc_tol == 1e-2 and p.rtol == 1e-10
     assert p.seed == 17517 and p.restart == 30 and p.locality_order == 1 and p.outer == 0
     assert p.smoother == 0 and p.inverse_type == 0 and p.smooth_type == 0
-    assert p.atol == 1e-50 and p.graph == 0 and p.reserved == 0
+    assert p.atol == 1e-50 and p.graph == 0 and p.stagnation_check == 0
 
 
 def test_struct_sizes_match_the_header():
