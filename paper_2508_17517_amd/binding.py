@@ -188,10 +188,13 @@ def default_params(**overrides):
 
 
 def load_host_dense():
-    """Host-only build of the library's dense routines (CPU tests)."""
-    if not os.path.exists(HOST_LIB_PATH):
-        raise ImportError(f"{HOST_LIB_PATH} is missing: run the build")
-    lib = ctypes.CDLL(HOST_LIB_PATH)
+    """Host-only build of the library's dense routines (CPU tests); the
+    environment variable AIRG_HOST_LIB selects another build of them (the
+    sanitizer build)."""
+    path = os.environ.get("AIRG_HOST_LIB", HOST_LIB_PATH)
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: run the build")
+    lib = ctypes.CDLL(path)
     dp, ip = P(c_dbl), ctypes.c_int
     lib.airg_host_gmres_poly.argtypes = [dp, ip, ip, c_dbl, dp]
     lib.airg_host_gmres_poly.restype = ip

@@ -20,6 +20,11 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libairg.so")
 HOST_LIB = os.path.join(HERE, "libairg_dense_host.so")
+# the same host-only routines built with AddressSanitizer and UBSan (g++ only,
+# for the CPU tests that run them under the sanitizers)
+HOST_SAN_LIB = os.path.join(HERE, "libairg_dense_host_san.so")
+GXX_SANITIZE = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                "-fno-sanitize-recover=undefined"]
 
 HIP_SOURCES = ["vec.hip", "spmv.hip", "cf.hip", "spgemm.hip", "order.hip", "fv.hip", "probe.hip",
                "dense.cpp", "hierarchy.cpp", "solve.cpp", "api.cpp"]
@@ -60,6 +65,10 @@ def build(jobs=None, verbose=False):
           "-I", INCLUDE, "-I", CSRC, os.path.join(CSRC, "dense.cpp"),
           os.path.join(CSRC, "dense_host_shim.cpp"), "-o", HOST_LIB + ".tmp"])
     os.replace(HOST_LIB + ".tmp", HOST_LIB)
+    host_sources = [os.path.join(CSRC, "dense.cpp"), os.path.join(CSRC, "dense_host_shim.cpp")]
+    _run([gxx, "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", "-I", INCLUDE, "-I", CSRC]
+         + GXX_SANITIZE + host_sources + ["-o", HOST_SAN_LIB + ".tmp"])
+    os.replace(HOST_SAN_LIB + ".tmp", HOST_SAN_LIB)
     return LIB
 
 
