@@ -120,6 +120,10 @@ struct CSR {
   // in a problem batch: the first of this operator's 64-row groups in the
   // batch's activity masks (-1: not masked)
   int64_t mask_off = -1;
+  // optional stored row order of a solve operator: stored row r is the
+  // operator's row rmap[r], so the products read and write their per-row
+  // vectors at rmap[r] (see spatial_row_order); empty: row r is stored at r
+  DBuf<int32_t> rmap;
   void alloc(int64_t r, int64_t c, int64_t nz, hipStream_t s) {
     rows = r; cols = c; nnz = nz;
     rowptr.alloc(r + 1, s);
@@ -132,6 +136,7 @@ struct CSR {
     rblk.release();
     nrblk = 0;
     mask_off = -1;
+    rmap.release();
   }
 };
 
@@ -159,10 +164,12 @@ struct OpView {
   // zero in this product (its rows then skip the matrix: their sums are 0);
   // null: every row is computed
   const uint8_t* gmask;
+  // stored row r is the operator's row rmap[r] (null: r)
+  const int32_t* rmap;
 };
 inline OpView opview(const CSR& A) {
   return {A.rowptr.get(), A.col.get(), A.val.get(), VT_F64, A.rows, A.nnz, A.col16.get(),
-          A.cbase.get(), A.rblk.get(), A.nrblk, A.cspan.get(), A.max_span, nullptr};
+          A.cbase.get(), A.rblk.get(), A.nrblk, A.cspan.get(), A.max_span, nullptr, A.rmap.get()};
 }
 
 // Read-only view passed to kernels.

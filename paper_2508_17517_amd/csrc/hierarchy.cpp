@@ -626,6 +626,25 @@ void finalize_hierarchy(Hierarchy& H) {
   permute_rows(H.A0, H.levels[0].pos.get(), H.levels[0].pos.get(), H.n0, H.Aperm, s);
   if (order) sort_rows(H.Aperm, s);
   H.tpr_top = pick_tpr(H.Aperm.rows, H.Aperm.nnz);
+  // The rows of the top matrix and of every Z are points of several blocks
+  // of the nested numbering (level l's F points, then level l+1's, ...),
+  // each block in locality order; taken in that order, the rows of each
+  // block sweep the whole domain again and gather the blocks they couple to
+  // once per sweep.  Stored in the order of the points' locality keys
+  // instead, the rows of all blocks that lie together are taken together,
+  // and each gathered element is fetched about once (the epilogues read and
+  // write through the row map, which keeps the blocks' own orders).
+  if (order) {
+    DBuf<int32_t> rkey(H.n0, s);
+    launch_scatter_i32(rkey.get(), key[0].get(), H.levels[0].pos.get(), H.n0, s);
+    spatial_row_order(H.Aperm, rkey.get(), s);
+    for (int l = 0; l + 1 < nl; ++l) {
+      Level& L = H.levels[l];
+      const Level& N = H.levels[l + 1];
+      launch_scatter_i32(rkey.get(), key[l + 1].get(), N.pos.get(), L.nC, s);
+      spatial_row_order(L.Z, rkey.get(), s);
+    }
+  }
   // value copies in the storage precision of the mixed-precision V-cycle
   if (H.p.precision != AIRG_FP64) {
     const bool bf = H.p.precision == AIRG_BF16;
@@ -731,11 +750,15 @@ void finalize_hierarchy(Hierarchy& H) {
       if (A.rows <= 0) return;
       if (first < 0 || first + A.rows > H.n0) fail(AIRG_ERR_INTERNAL, "operator rows outside the numbering");
       A.mask_off = (int64_t)g0.size();
+      // stored row r is the operator's row rm[r]
+      std::vector<int32_t> rm;
+      if (A.rmap.get()) rm = A.rmap.host(A.rows);
+      auto prob = [&](int64_t r) { return pp[first + (rm.empty() ? r : (int64_t)rm[r])]; };
       for (int64_t r0 = 0; r0 < A.rows; r0 += 64) {
-        int32_t lo = pp[first + r0], hi = lo;
+        int32_t lo = prob(r0), hi = lo;
         for (int64_t r = r0 + 1; r < std::min(A.rows, r0 + 64); ++r) {
-          lo = std::min(lo, pp[first + r]);
-          hi = std::max(hi, pp[first + r]);
+          lo = std::min(lo, prob(r));
+          hi = std::max(hi, prob(r));
         }
         g0.push_back(lo);
         g1.push_back(hi);

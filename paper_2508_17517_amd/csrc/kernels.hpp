@@ -138,6 +138,8 @@ void launch_sqrt_inplace(double* v, hipStream_t s);
 
 // Permutations: y[perm[i]] = x[i] (scatter) and y[i] = x[perm[i]] (gather).
 void launch_scatter(double* y, const double* x, const int32_t* perm, int64_t n, hipStream_t s);
+// y[perm[i]] = x[i] for int32 arrays
+void launch_scatter_i32(int32_t* y, const int32_t* x, const int32_t* perm, int64_t n, hipStream_t s);
 void launch_gather(double* y, const double* x, const int32_t* perm, int64_t n, hipStream_t s);
 
 // K interleaved columns: ys[pos[i] K + c] = b[c ldb + i] and x[c ldx + i] = xs[pos[i] K + c];
@@ -402,6 +404,9 @@ bool compress_columns(CSR& A, hipStream_t s);
 void build_row_blocks(CSR& A, hipStream_t s);
 // Sort the entries of every row by column (insertion sort per row).
 void sort_rows(CSR& A, hipStream_t s);
+// Store A's rows in ascending order of rkey[row] (ties by row) and record the
+// order in A.rmap (stored row r is row rmap[r]); columns are unchanged.
+void spatial_row_order(CSR& A, const int32_t* rkey, hipStream_t s);
 // Explicit transpose with ascending columns.
 void transpose(const CSR& A, CSR& At, hipStream_t s);
 // Deep copy of a device CSR.

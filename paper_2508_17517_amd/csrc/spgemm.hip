@@ -724,6 +724,24 @@ __global__ void row_sort_kernel(int64_t rows, const int32_t* rowptr, int32_t* co
   }
 }
 
+__global__ void inverse_perm_kernel(const int32_t* perm, int64_t n, int32_t* inv) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) inv[perm[i]] = (int32_t)i;
+}
+
+void spatial_row_order(CSR& A, const int32_t* rkey, hipStream_t s) {
+  if (A.rows <= 0) return;
+  if (A.rmap.get()) fail(AIRG_ERR_INTERNAL, "operator rows are already reordered");
+  DBuf<int32_t> rank(A.rows, s);
+  rank_points(rkey, A.rows, rank.get(), s);
+  CSR P;
+  permute_rows(A, rank.get(), nullptr, A.cols, P, s);
+  P.rmap.alloc(A.rows, s);
+  inverse_perm_kernel<<<blocks_for(A.rows, kBlock), kBlock, 0, s>>>(rank.get(), A.rows, P.rmap.get());
+  AIRG_CHECK_LAUNCH();
+  A = std::move(P);
+}
+
 void sort_rows(CSR& A, hipStream_t s) {
   if (A.rows <= 0 || A.nnz <= 0) return;
   row_sort_kernel<<<blocks_for(A.rows, kBlock), kBlock, 0, s>>>(A.rows, A.rowptr.get(), A.col.get(),

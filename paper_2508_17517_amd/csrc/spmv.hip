@@ -32,9 +32,14 @@ struct CSRT {
   const MV* __restrict__ val;
   int64_t rows;
   const uint8_t* __restrict__ gmask;  // see OpView::gmask
+  const int32_t* __restrict__ rmap;   // see OpView::rmap
   // false where the row's 64-row group is masked off: its sum is 0
   __device__ __forceinline__ bool computed(int64_t row) const {
     return gmask == nullptr || gmask[row >> kColBlockShift] != 0;
+  }
+  // the operator row of stored row `row`: where its epilogue reads and writes
+  __device__ __forceinline__ int64_t out_row(int64_t row) const {
+    return rmap ? (int64_t)rmap[row] : row;
   }
   __device__ __forceinline__ int base(int64_t row) const {
     if constexpr (C16) return cbase[row >> kColBlockShift];
@@ -49,7 +54,7 @@ struct CSRT {
 
 template <class MV, bool C16>
 static CSRT<MV, C16> csr_t(const OpView& A) {
-  return {A.rowptr, A.col, A.col16, A.cbase, (const MV*)A.val, A.rows, A.gmask};
+  return {A.rowptr, A.col, A.col16, A.cbase, (const MV*)A.val, A.rows, A.gmask, A.rmap};
 }
 
 // Entries in flight per lane: every lane first loads the column indices and
@@ -99,7 +104,7 @@ __device__ __forceinline__ X row_dot(const CSRT<MV, C16>& A, int s, int e, int b
                                      const XI* __restrict__ x, int c, Idx idx, X sum) {
   if constexpr (C16) {
     if (b < 0) {
-      const CSRT<MV, false> W{A.rowptr, A.col, nullptr, nullptr, A.val, A.rows, nullptr};
+      const CSRT<MV, false> W{A.rowptr, A.col, nullptr, nullptr, A.val, A.rows, nullptr, nullptr};
       return row_dot_cols<TPR, U, K>(W, s, e, 0, lane, x, c, idx, sum);
     }
   }
@@ -207,7 +212,7 @@ __device__ __forceinline__ X row_dot_pairs(const CSRT<MV, C16>& A, int s, int e,
                                            const XI* __restrict__ x, X sum) {
   if constexpr (C16) {
     if (b < 0) {
-      const CSRT<MV, false> W{A.rowptr, A.col, nullptr, nullptr, A.val, A.rows, nullptr};
+      const CSRT<MV, false> W{A.rowptr, A.col, nullptr, nullptr, A.val, A.rows, nullptr, nullptr};
       return row_dot_pairs_cols<TPR, U, false>(W, s, e, 0, lane, x, sum);
     }
   }
@@ -239,7 +244,7 @@ __global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV, C16> A, const XI* __
   const int64_t row = row_block_index(xcd) * (256 / TPR) + threadIdx.x / TPR;
   const bool live = row < A.rows;
   typename Epi::Pre pre{};
-  if (live && lane == 0) pre = epi.pre(row);
+  if (live && lane == 0) pre = epi.pre(A.out_row(row));
   X sum = 0;
   if (live) {
     const int rs = A.rowptr[row];
@@ -253,7 +258,7 @@ __global__ __launch_bounds__(256) void spmv_kernel(CSRT<MV, C16> A, const XI* __
 #pragma unroll
     for (int o = TPR / 2; o > 0; o >>= 1) sum = sum + __shfl_down(sum, o, TPR);
   }
-  if (lane == 0 && live) epi(row, sum, pre);
+  if (lane == 0 && live) epi(A.out_row(row), sum, pre);
 }
 
 // column-per-lane kernel (K > 1 interleaved columns): each column's row sum
@@ -264,10 +269,11 @@ __global__ __launch_bounds__(256) void spmm_kernel(CSRT<MV, C16> A, const XI* __
   const int c = threadIdx.x & (K - 1);
   const int64_t row = row_block_index(xcd) * (256 / K) + threadIdx.x / K;
   if (row >= A.rows) return;
-  const typename Epi::Pre pre = epi.pre(row * K + c);
+  const int64_t orow = A.out_row(row);
+  const typename Epi::Pre pre = epi.pre(orow * K + c);
   const X sum = row_dot<1, 4, K>(A, A.rowptr[row], A.rowptr[row + 1], A.base(row), 0, x, c,
                                  IdxPlain{}, X(0));
-  epi(row * K + c, sum, pre);
+  epi(orow * K + c, sum, pre);
 }
 
 // Row-block kernel (K = 1, selected with tpr = 0): a workgroup takes one row
@@ -295,7 +301,7 @@ __global__ __launch_bounds__(256) void spmv_rowblock_kernel(CSRT<MV, C16> A,
   typename Epi::Pre pre{};
   int rs = 0, re = 0;
   if (mine) {
-    pre = epi.pre(row);
+    pre = epi.pre(A.out_row(row));
     rs = A.rowptr[row];
     re = A.rowptr[row + 1];
   }
@@ -326,7 +332,7 @@ __global__ __launch_bounds__(256) void spmv_rowblock_kernel(CSRT<MV, C16> A,
     }
     __syncthreads();
   }
-  if (mine) epi(row, sum, pre);
+  if (mine) epi(A.out_row(row), sum, pre);
 }
 
 // Entry-staged kernel (K = 1, shape bit 10): a workgroup takes 256
@@ -355,7 +361,7 @@ __global__ __launch_bounds__(256) void spmv_entries_kernel(CSRT<MV, C16> A, cons
   typename Epi::Pre pre{};
   int rs = 0, re = 0;
   if (live) {
-    pre = epi.pre(row);
+    pre = epi.pre(A.out_row(row));
     rs = A.rowptr[row];
     re = (!MASK || A.computed(row)) ? A.rowptr[row + 1] : rs;
   }
@@ -401,7 +407,7 @@ __global__ __launch_bounds__(256) void spmv_entries_kernel(CSRT<MV, C16> A, cons
     }
     __syncthreads();
   }
-  if (live) epi(row, sum, pre);
+  if (live) epi(A.out_row(row), sum, pre);
 }
 
 // LDS-staged kernel (K = 1, shape bit 9, operators with compressed columns):
@@ -446,7 +452,7 @@ __global__ __launch_bounds__(64 * TPR) void spmv_lds_kernel(CSRT<MV, true> A,
   // the same for the whole workgroup
   const bool staged = on && base >= 0 && span <= lds_cap;
   typename Epi::Pre pre{};
-  if (live && lane == 0) pre = epi.pre(row);
+  if (live && lane == 0) pre = epi.pre(A.out_row(row));
   int s = 0, e = 0;
   if (live) {
     s = A.rowptr[row];
@@ -476,7 +482,7 @@ __global__ __launch_bounds__(64 * TPR) void spmv_lds_kernel(CSRT<MV, true> A,
 #pragma unroll
     for (int o = TPR / 2; o > 0; o >>= 1) sum = sum + __shfl_down(sum, o, TPR);
   }
-  if (lane == 0 && live) epi(row, sum, pre);
+  if (lane == 0 && live) epi(A.out_row(row), sum, pre);
 }
 
 // shape: lanes per row in bits 0-7 (0: the row-block kernel), the XCD

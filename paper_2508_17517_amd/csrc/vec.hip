@@ -862,6 +862,15 @@ void launch_scatter(double* y, const double* x, const int32_t* perm, int64_t n, 
   scatter_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, perm, n);
   AIRG_CHECK_LAUNCH();
 }
+__global__ void scatter_i32_kernel(int32_t* y, const int32_t* x, const int32_t* perm, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[perm[i]] = x[i];
+}
+void launch_scatter_i32(int32_t* y, const int32_t* x, const int32_t* perm, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  scatter_i32_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, perm, n);
+  AIRG_CHECK_LAUNCH();
+}
 void launch_gather(double* y, const double* x, const int32_t* perm, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   gather_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, perm, n);
