@@ -44,10 +44,13 @@ void launch_basis_combine(double* x, const float* Z, int64_t ldz, const double* 
 size_t dot_work_size(int64_t n, int nv);
 void launch_tree_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
                       double* out, double* work, hipStream_t s);
-// A Gram-Schmidt update fused with the reduction after it (1 <= nv <= 32):
-// w = w - sum_k h[k] V_k, then out[k] = V_k . w (k < nv) or out[0] = w . w,
-// in a fixed order; `work` needs cgs_fused_work_size(n) doubles.
+// A Gram-Schmidt sweep fused with the reduction after it (1 <= nv <= 32):
+// out[k] = V_k . w (launch_cgs_dots), or w = w - sum_k h[k] V_k and then
+// out[k] = V_k . w (k < nv) or out[0] = w . w; every sum in a fixed order.
+// `work` needs cgs_fused_work_size(n) doubles.
 size_t cgs_fused_work_size(int64_t n);
+void launch_cgs_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
+                     double* out, double* work, hipStream_t s);
 void launch_cgs_update_dots(double* w, const double* V, int64_t ldv, const double* h, int nv,
                             int64_t n, double* out, double* work, hipStream_t s);
 void launch_cgs_update_norm2(double* w, const double* V, int64_t ldv, const double* h, int nv,

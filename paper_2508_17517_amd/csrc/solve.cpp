@@ -966,14 +966,15 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
           spmv_t<double>(opview(H.Aperm), H.tpr_top, K, zj, W.w.get(), s);
         }
         ++its;
-        // CGS2: h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; |w|^2, the
-        // second and third sweeps each fused with the reduction after them
-        dots(V, ld, j + 1, W.w.get(), n, hd, W, s);
+        // CGS2: h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; |w|^2, each
+        // sweep fused with the reduction after it
         if (j + 1 <= kFusedVecs) {
+          launch_cgs_dots(V, ld, j + 1, W.w.get(), n, hd, W.fused_work.get(), s);
           launch_cgs_update_dots(W.w.get(), V, ld, hd, j + 1, n, hd + (R + 1), W.fused_work.get(), s);
           launch_cgs_update_norm2(W.w.get(), V, ld, hd + (R + 1), j + 1, n, hd + 2 * (R + 1),
                                   W.fused_work.get(), s);
         } else {
+          dots(V, ld, j + 1, W.w.get(), n, hd, W, s);
           launch_cgs_update(W.w.get(), V, ld, hd, j + 1, n, s);
           dots(V, ld, j + 1, W.w.get(), n, hd + (R + 1), W, s);
           launch_cgs_update(W.w.get(), V, ld, hd + (R + 1), j + 1, n, s);

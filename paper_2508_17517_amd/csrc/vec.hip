@@ -251,99 +251,114 @@ void launch_sqrt_inplace(double* v, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ fused Gram-Schmidt sweeps
-// The update of a classical Gram-Schmidt sweep fused with the reduction that
-// follows it: w = w - sum_k h[k] V_k (k ascending per element, as in
-// cgs_update_kernel), then either out[k] = V_k . w for k < nv (the next
-// sweep's coefficients) or out[0] = w . w (the new norm).  An element's V_k
+// A classical Gram-Schmidt sweep with the reduction that follows it: MODE 0
+// forms out[k] = V_k . w; MODE 1 updates w = w - sum_k h[k] V_k (k ascending
+// per element, as in cgs_update_kernel) and then forms out[k] = V_k . w;
+// MODE 2 updates w the same way and forms out[0] = w . w.  An element's V_k
 // values stay in registers between the update and the products, so the
-// basis is read once instead of twice.  One element per thread: block b
-// reduces elements b * 256 .. b * 256 + 255 by the shuffle tree and its four
-// waves in pairs, and the block partials of each k by the tree sum.
+// basis is read once per sweep.  Block b takes the kFusedSpan elements from
+// b * kFusedSpan, four per thread at stride 256 (coalesced); a thread adds its
+// four products in order, the shuffle tree and the four waves in pairs give
+// the block's partial, and one more launch sums the partials of each k in
+// block order (sum_partials_kernel).  Fixed orders throughout: the result is
+// the same on every run.
+constexpr int kFusedPerThread = 4;
+constexpr int64_t kFusedSpan = 256 * kFusedPerThread;
 
-// w = w - sum_k h[k] V_k, then the products V_k . w (DOTS) or w . w; NV basis
-// vectors, a compile-time count so that every load is issued unconditionally
-template <bool DOTS, int NV>
+template <int MODE, int NV>
 __global__ __launch_bounds__(256) void cgs_fused_kernel(
     double* __restrict__ w, const double* __restrict__ V, int64_t ldv, const double* __restrict__ h,
     int64_t n, double* __restrict__ part, int64_t nb) {
-  constexpr int CNT = DOTS ? NV : 1;
+  constexpr int CNT = MODE == 2 ? 1 : NV;
   __shared__ double red[CNT][4];
   const int t = threadIdx.x;
-  const int64_t i = (int64_t)blockIdx.x * 256 + t;
-  const bool in = i < n;
-  const int64_t ii = in ? i : 0;  // in-range address for the padding lanes
-  double v[NV];
+  double hk[MODE == 0 ? 1 : NV];
+  if constexpr (MODE != 0) {
 #pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = V[(int64_t)k * ldv + ii];
-  double wi = w[ii];
+    for (int k = 0; k < NV; ++k) hk[k] = h[k];
+  }
+  double acc[CNT];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) wi = wi - h[k] * v[k];
-  if (in) w[i] = wi;
+  for (int k = 0; k < CNT; ++k) acc[k] = 0.0;
+  for (int u = 0; u < kFusedPerThread; ++u) {
+    const int64_t i = (int64_t)blockIdx.x * kFusedSpan + u * 256 + t;
+    if (i >= n) break;
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = V[(int64_t)k * ldv + i];
+    double wi = w[i];
+    if constexpr (MODE != 0) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) wi = wi - hk[k] * v[k];
+      w[i] = wi;
+    }
+#pragma unroll
+    for (int k = 0; k < CNT; ++k) acc[k] = acc[k] + (MODE == 2 ? wi * wi : v[k] * wi);
+  }
   const int lane = t & 63, wave = t >> 6;
 #pragma unroll
   for (int k = 0; k < CNT; ++k) {
-    const double s = wave_tree(in ? (DOTS ? v[k] * wi : wi * wi) : 0.0);
+    const double s = wave_tree(acc[k]);
     if (lane == 0) red[k][wave] = s;
   }
   __syncthreads();
   if (t < CNT) part[(int64_t)t * nb + blockIdx.x] = (red[t][0] + red[t][1]) + (red[t][2] + red[t][3]);
 }
 
-template <bool DOTS, int NV>
+// out[k] = sum of part[k * nb + q] over q < nb, block k: thread t adds
+// q = t, t + 256, ... in order, then the shuffle tree and the waves in pairs
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restrict__ part,
+                                                           int64_t nb, double* __restrict__ out) {
+  __shared__ double red[4];
+  const int t = threadIdx.x;
+  const double* p = part + (int64_t)blockIdx.x * nb;
+  double acc = 0.0;
+#pragma unroll 4
+  for (int64_t q = t; q < nb; q += 256) acc = acc + p[q];
+  const double s = wave_tree(acc);
+  if ((t & 63) == 0) red[t >> 6] = s;
+  __syncthreads();
+  if (t == 0) out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+template <int MODE, int NV>
 static void launch_fused_nv(int nv, double* w, const double* V, int64_t ldv, const double* h,
                             int64_t n, double* part, int64_t nb, hipStream_t s) {
   if constexpr (NV > kFusedVecs) {
     fail(AIRG_ERR_INTERNAL, "fused Gram-Schmidt takes 1 to 32 vectors");
   } else {
-    if (nv != NV) return launch_fused_nv<DOTS, NV + 1>(nv, w, V, ldv, h, n, part, nb, s);
-    cgs_fused_kernel<DOTS, NV><<<(unsigned)nb, 256, 0, s>>>(w, V, ldv, h, n, part, nb);
+    if (nv != NV) return launch_fused_nv<MODE, NV + 1>(nv, w, V, ldv, h, n, part, nb, s);
+    cgs_fused_kernel<MODE, NV><<<(unsigned)nb, 256, 0, s>>>(w, V, ldv, h, n, part, nb);
   }
 }
 
-static int64_t fused_blocks(int64_t n) { return n < 256 ? 1 : (n + 255) / 256; }
+static int64_t fused_blocks(int64_t n) { return n < 1 ? 1 : (n + kFusedSpan - 1) / kFusedSpan; }
 
-size_t cgs_fused_work_size(int64_t n) {
-  const int64_t nb = fused_blocks(n);
-  const int64_t nb2 = (nb + kDotChunk - 1) / kDotChunk;
-  return (size_t)kFusedVecs * (size_t)(nb + nb2 + 2);
-}
+size_t cgs_fused_work_size(int64_t n) { return (size_t)kFusedVecs * (size_t)fused_blocks(n); }
 
-// out[k] = sum of the m partials a[k * m ...] by repeated tree stages (b: scratch)
-static void tree_reduce(double* a, int64_t m, int nv, double* out, double* b, hipStream_t s) {
-  int64_t stride = m;
-  for (;;) {
-    const int64_t mb = (m + kDotChunk - 1) / kDotChunk;
-    double* dst = (mb == 1) ? out : b;
-    const int64_t dstride = (mb == 1) ? 1 : mb;
-    tree_sum_stage<<<dim3((unsigned)mb, (unsigned)nv), 256, 0, s>>>(a, m, stride, dst, dstride);
-    AIRG_CHECK_LAUNCH();
-    if (mb == 1) return;
-    std::swap(a, b);
-    m = mb;
-    stride = dstride;
-  }
-}
-
-static void launch_cgs_fused(bool dots, double* w, const double* V, int64_t ldv, const double* h,
-                             int nv, int64_t n, double* out, double* work, hipStream_t s) {
+template <int MODE>
+static void launch_cgs_fused(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                             int64_t n, double* out, double* work, hipStream_t s) {
   if (nv < 1 || nv > kFusedVecs) fail(AIRG_ERR_INTERNAL, "fused Gram-Schmidt takes 1 to 32 vectors");
   if (n <= 0) return;
   const int64_t nb = fused_blocks(n);
-  const int cnt = dots ? nv : 1;
-  double* a = work;
-  double* b = work + (size_t)kFusedVecs * nb;
-  if (dots) launch_fused_nv<true, 1>(nv, w, V, ldv, h, n, a, nb, s);
-  else launch_fused_nv<false, 1>(nv, w, V, ldv, h, n, a, nb, s);
+  launch_fused_nv<MODE, 1>(nv, w, V, ldv, h, n, work, nb, s);
   AIRG_CHECK_LAUNCH();
-  tree_reduce(a, nb, cnt, out, b, s);
+  sum_partials_kernel<<<MODE == 2 ? 1 : nv, 256, 0, s>>>(work, nb, out);
+  AIRG_CHECK_LAUNCH();
+}
+void launch_cgs_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
+                     double* out, double* work, hipStream_t s) {
+  // MODE 0 neither writes w nor reads h
+  launch_cgs_fused<0>(const_cast<double*>(w), V, ldv, nullptr, nv, n, out, work, s);
 }
 void launch_cgs_update_dots(double* w, const double* V, int64_t ldv, const double* h, int nv,
                             int64_t n, double* out, double* work, hipStream_t s) {
-  launch_cgs_fused(true, w, V, ldv, h, nv, n, out, work, s);
+  launch_cgs_fused<1>(w, V, ldv, h, nv, n, out, work, s);
 }
 void launch_cgs_update_norm2(double* w, const double* V, int64_t ldv, const double* h, int nv,
                              int64_t n, double* out, double* work, hipStream_t s) {
-  launch_cgs_fused(false, w, V, ldv, h, nv, n, out, work, s);
+  launch_cgs_fused<2>(w, V, ldv, h, nv, n, out, work, s);
 }
 
 // ------------------------------------------------------------------ per-column Krylov
