@@ -147,8 +147,9 @@ def _timed(fn, warmup, steps):
 def batched_legs(a, p, s64, value64, ip, ix, dv):
     """Batching with FP32 storage in the V-cycle (FP64 FGMRES): many right-hand
     sides of the big matrix as interleaved columns, and many independent
-    problems of uneven sizes in one block-diagonal hierarchy.  Every column and
-    problem must reach the FP64 1e-10 true relative residual."""
+    problems of uneven sizes in one block-diagonal hierarchy (FP32, then BF16
+    storage).  Every column and problem must reach the FP64 1e-10 true
+    relative residual."""
     import torch
     from airg_inputs import workloads
     from paper_2508_17517_amd import BatchSolver, Solver, binding
@@ -177,34 +178,37 @@ def batched_legs(a, p, s64, value64, ip, ix, dv):
     sm.close()
     del B, X
     q = a.batch_problems
-    print(f"bench: batch: {q} problems, FP32 V-cycle (generating)", file=sys.stderr, flush=True)
+    print(f"bench: batch: {q} problems (generating)", file=sys.stderr, flush=True)
     probs = workloads.batch_problems(q)
     ntot = sum(pr.n for pr in probs)
     mats = [(torch.from_numpy(pr.indptr).cuda(), torch.from_numpy(pr.indices).cuda(),
              torch.from_numpy(pr.data).cuda()) for pr in probs]
     bs = [torch.from_numpy(pr.b).cuda() for pr in probs]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sb = BatchSolver(mats, precision=binding.FP32, **SOLVER_OPTS)
-    torch.cuda.synchronize()
-    setup_b = time.perf_counter() - t0
-    _tune(sb)
-    xs = [torch.zeros_like(b_) for b_ in bs]
-    dt, (xs, infos) = _timed(lambda: sb.solve(bs, xs), 1, max(1, min(a.steps, 3)))
-    assert all(i["converged"] == 1 and i["rel_residual"] <= 1e-10 for i in infos), infos
-    st = sb.stats()
-    v = ntot / dt
-    res["problems"] = {"problems": q, "dofs": ntot, "value": v, "unit": "DOF/s",
-                       "ms_per_step": 1e3 * dt,
-                       "iterations": max(i["iterations"] for i in infos),
-                       "iterations_min": min(i["iterations"] for i in infos),
-                       "max_rel_residual": max(i["rel_residual"] for i in infos),
-                       "levels": st["levels"], "setup_s": round(setup_b, 3),
-                       "setup_component_ms": {k: round(v, 1) for k, v in
-                                              st["setup_component_ms"].items()},
-                       "speedup_vs_fp64": v / value64}
-    print(f"bench: problems {res['problems']}", file=sys.stderr, flush=True)
-    sb.close()
+    for key, prec in (("problems", binding.FP32), ("problems_bf16", binding.BF16)):
+        print(f"bench: batch: {q} problems, {key}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sb = BatchSolver(mats, precision=prec, **SOLVER_OPTS)
+        torch.cuda.synchronize()
+        setup_b = time.perf_counter() - t0
+        _tune(sb)
+        xs = [torch.zeros_like(b_) for b_ in bs]
+        dt, (xs, infos) = _timed(lambda: sb.solve(bs, xs), 1, max(1, min(a.steps, 3)))
+        assert all(i["converged"] == 1 and i["rel_residual"] <= 1e-10 for i in infos), infos
+        st = sb.stats()
+        v = ntot / dt
+        res[key] = {"problems": q, "dofs": ntot,
+                    "precision": "fp32" if prec == binding.FP32 else "bf16",
+                    "value": v, "unit": "DOF/s", "ms_per_step": 1e3 * dt,
+                    "iterations": max(i["iterations"] for i in infos),
+                    "iterations_min": min(i["iterations"] for i in infos),
+                    "max_rel_residual": max(i["rel_residual"] for i in infos),
+                    "levels": st["levels"], "setup_s": round(setup_b, 3),
+                    "setup_component_ms": {k: round(v, 1) for k, v in
+                                           st["setup_component_ms"].items()},
+                    "speedup_vs_fp64": v / value64}
+        print(f"bench: {key} {res[key]}", file=sys.stderr, flush=True)
+        sb.close()
     return res
 
 

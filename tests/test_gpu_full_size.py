@@ -6,8 +6,8 @@
 * 64 right-hand sides of the FV 2048 x 2048 matrix (FP32 V-cycle), one outer
   process per column.
 * 48 FV problems with sides drawn from {128, 256, 512, 1024} and angles from
-  U(0, pi/2) in one block-diagonal hierarchy (FP32 V-cycle), one outer process
-  per problem.
+  U(0, pi/2) in one block-diagonal hierarchy (FP32 and BF16 V-cycles), one
+  outer process per problem.
 
 The exact discrete solution comes from the oracle's flow-order sweep (one
 Gauss-Seidel pass in flow order solves an upwind system exactly).  Every
@@ -86,13 +86,14 @@ def test_fv2048_64_columns_against_the_exact_solution():
     s.close()
 
 
-def test_48_problems_against_the_exact_solution():
+@pytest.mark.parametrize("prec,name", [(1, "fp32"), (2, "bf16")])
+def test_48_problems_against_the_exact_solution(prec, name):
     _needs_gpu()
     from paper_2508_17517_amd import BatchSolver
-    print("building the 48 problems", flush=True)
+    print(f"building the 48 problems ({name} V-cycle)", flush=True)
     probs = workloads.batch_problems(48)
     mats = [(q.indptr, q.indices, q.data) for q in probs]
-    sb = BatchSolver(mats, precision=1)
+    sb = BatchSolver(mats, precision=prec)
     xs, infos = sb.solve([torch.from_numpy(q.b).cuda() for q in probs])
     worst = 0.0
     for q, x, i in zip(probs, xs, infos):
@@ -104,7 +105,7 @@ def test_48_problems_against_the_exact_solution():
         emax, e2 = _err(xq, u)
         worst = max(worst, e2)
         assert e2 <= 1e-7
-    print(f"48 problems ({sum(q.n for q in probs)} unknowns, FP32 V-cycle): iterations "
+    print(f"48 problems ({sum(q.n for q in probs)} unknowns, {name} V-cycle): iterations "
           f"{min(i['iterations'] for i in infos)}-{max(i['iterations'] for i in infos)}, worst "
           f"2-norm error vs exact {worst:.2e}", flush=True)
     sb.close()
