@@ -392,6 +392,31 @@ def assembled_leg(a, p, value64, ip, ix, dv, b):
     return res
 
 
+def persistent_coarse_leg(a, p, value64, ip, ix, dv, b, newton_us):
+    """The coarsest level's Newton steps in one persistent launch
+    (coarse_persistent = 1) against the per-step launches of the main solve:
+    same hierarchy and launch shapes, FP64, same tolerance."""
+    import torch
+    from paper_2508_17517_amd import Solver
+    sm = Solver(ip, ix, dv, coarse_persistent=1, **SOLVER_OPTS)
+    kept = os.path.join(ROOT, "paper_2508_17517_amd", "shapes", f"{a.workload}_fp64.json")
+    if TUNE["on"] and os.path.exists(kept):
+        with open(kept) as f:
+            sm.pin_shapes(json.load(f))
+    xm = torch.zeros_like(b)
+    dt, (xm, im) = _timed(lambda: sm.solve(b, xm), a.warmup, a.steps)
+    assert im["converged"] == 1 and im["rel_residual"] <= 1e-10, im
+    kt = sm.time_kernels("newton", reps=a.kernel_reps)
+    res = {"value": p.n / dt, "unit": "DOF/s", "ms_per_step": 1e3 * dt,
+           "iterations": im["iterations"], "rel_residual": im["rel_residual"],
+           "newton_apply_us": 1e3 * kt["avg_launch_ms"] * kt["launches"],
+           "per_step_newton_apply_us": newton_us,
+           "speedup_vs_fp64": (p.n / dt) / value64}
+    print(f"bench: persistent coarse solve: {res}", file=sys.stderr, flush=True)
+    sm.close()
+    return res
+
+
 def optional(name, fn, *args):
     """Run one extra bench leg; a failure is reported and does not lose the
     main result."""
@@ -538,6 +563,9 @@ def main():
         out["mixed"] = optional("mixed", mixed_legs, a, p, x, value, ip, ix, dv, b)
     if not a.no_mixed:
         out["assembled_smoother"] = optional("assembled", assembled_leg, a, p, value, ip, ix, dv, b)
+        nw = classes["newton"]
+        out["persistent_coarse"] = optional("persistent", persistent_coarse_leg, a, p, value, ip, ix,
+                                            dv, b, 1e3 * nw["avg_launch_ms"] * nw["launches"])
     if not a.no_batch:
         out["batched"] = optional("batched", batched_legs, a, p, s, value, ip, ix, dv)
     if not a.no_dg:

@@ -99,6 +99,18 @@ typedef struct {
                                 over `restart` steps) stops there, not converged, with
                                 airg_solve_info.stagnated set; 0: only rtol, atol and max_it
                                 stop it, 0 */
+  int32_t coarse_persistent; /* 1: apply the coarsest level's Newton polynomial (Sec. 2.3) in
+                                one persistent launch that keeps the coarsest matrix in
+                                registers across its steps, with a grid-wide barrier between
+                                steps, where it fits (one right-hand side of a single problem,
+                                at most 65535 coarsest rows, no empty row, 32 entries per
+                                thread of the workgroups the device holds at once); the same
+                                steps as the per-step launches, rows summed in another fixed
+                                order.  Such a launch needs the whole device: solves of other
+                                handles that overlap it on other streams may fail with
+                                AIRG_ERR_INTERNAL.  0: one product launch per step (faster on
+                                the MI355X: a barrier across its XCDs costs about as much as a
+                                launch), 0 */
 } airg_params;
 
 /* The polynomial approximation of A_ff^{-1} in the smoother and in Ahat^{-1}.

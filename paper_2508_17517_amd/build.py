@@ -26,7 +26,7 @@ HOST_SAN_LIB = os.path.join(HERE, "libairg_dense_host_san.so")
 GXX_SANITIZE = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
                 "-fno-sanitize-recover=undefined"]
 
-HIP_SOURCES = ["vec.hip", "spmv.hip", "cf.hip", "spgemm.hip", "order.hip", "fv.hip", "probe.hip",
+HIP_SOURCES = ["vec.hip", "spmv.hip", "cf.hip", "spgemm.hip", "order.hip", "fv.hip", "probe.hip", "coarse.hip",
                "dense.cpp", "hierarchy.cpp", "solve.cpp", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("AIRG_OFFLOAD_ARCH", "gfx950")

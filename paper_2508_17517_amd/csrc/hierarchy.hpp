@@ -109,6 +109,38 @@ struct Hierarchy {
   uint64_t shape_epoch = 0;
 };
 
+// The coarsest level's Newton polynomial in one persistent launch (coarse.hip):
+// the steps of the per-step form, the rows each workgroup owns and the
+// barrier state.  ok is false where the launch does not apply (more than
+// 65535 rows, an empty row, a row map, or entries that do not fit the
+// registers of the workgroups the device holds at once).
+enum { kCoarseReal = 0, kCoarsePair1 = 1, kCoarsePair2 = 2 };
+struct CoarseStep {
+  int32_t kind;   // kCoarseReal (a = 1 / theta, b = a folded final root's 1 / theta or 0),
+                  // kCoarsePair1 (a = 2 Re z / |z|^2, b = 1 / |z|^2),
+                  // kCoarsePair2 (a, b as Pair1, c = a folded final root's 1 / theta or 0)
+  int32_t first;  // x starts here (it is not read)
+  double a, b, c;
+};
+struct CoarsePlan {
+  bool ok = false;
+  int blocks = 0, nsteps = 0;
+  int fin = 0, fin_first = 0;  // a final real root applied without a product
+  double fin_inv = 0.0;
+  int64_t n = 0;
+  DBuf<int32_t> wrows;         // blocks + 1 row bounds
+  DBuf<CoarseStep> steps;
+  DBuf<double> pub;            // two vectors of n (FP64 or FP32 elements)
+  DBuf<unsigned long long> bar;
+  DBuf<int> err;
+};
+bool coarse_plan_build(CoarsePlan& pc, const CSR& A, const std::vector<cplx>& roots, int prec,
+                       hipStream_t s);
+template <class X>
+void coarse_persistent_t(const CoarsePlan& pc, const OpView& A, const X* r, X* x, hipStream_t s);
+// nonzero when a launch's barrier wait gave up (cleared by the call)
+int coarse_plan_error(const CoarsePlan& pc, hipStream_t s);
+
 // Build the hierarchy for A (device CSR, validated) with parameters p.
 void build_hierarchy(Hierarchy& H, CSR&& A);
 // Nested numbering and solve-form operators; frees setup data unless kept.

@@ -135,6 +135,9 @@ void workspace_init(const Hierarchy& H, Workspace& W, int K) {
   W.col_work.alloc(col_sumsq_work_size(H.n0, K), s);
   AIRG_HIP(hipEventCreate(&W.ev0));
   AIRG_HIP(hipEventCreate(&W.ev1));
+  W.pc.ok = false;
+  if (K == 1 && H.seg.empty() && H.p.coarse_persistent)
+    coarse_plan_build(W.pc, H.levels.back().A, H.levels.back().roots, H.p.precision, s);
 }
 
 namespace {
@@ -153,16 +156,18 @@ struct VecSet {
   X* ct;        // Newton scratch
   X* rin;       // stacked level residuals (C-point smoothing), or null
   const uint8_t* gmask;  // activity masks of a problem batch, or null
+  const CoarsePlan* pc;  // the persistent coarse solve, or null (per-step launches)
 };
 
 VecSet<double> vecs64(Workspace& W, const double* in, double* e) {
   return {in,        e,         W.rr.get(), W.sv.get(), W.y0.get(), W.y1.get(),
-          W.cw0.get(), W.cw1.get(), W.ct.get(), W.rin.get(), W.mask_on ? W.gmask.get() : nullptr};
+          W.cw0.get(), W.cw1.get(), W.ct.get(), W.rin.get(), W.mask_on ? W.gmask.get() : nullptr,
+          W.pc.ok ? &W.pc : nullptr};
 }
 VecSet<float> vecs32(Workspace& W, float* e) {
   return {W.in32.get(), e, W.rr32.get(), W.sv32.get(), W.y032.get(), W.y132.get(),
           W.cw032.get(), W.cw132.get(), W.ct32.get(), W.rin32.get(),
-          W.mask_on ? W.gmask.get() : nullptr};
+          W.mask_on ? W.gmask.get() : nullptr, W.pc.ok ? &W.pc : nullptr};
 }
 
 struct LevelOps {
@@ -358,8 +363,11 @@ void vcycle_t(const Hierarchy& H, const VecSet<X>& v, int K, hipStream_t s) {
   }
   const Level& lc = H.levels[L];
   const X* rc = L == 0 ? v.in : input(L);
-  newton_apply_t<X>(ops_of(lc, prec, v.gmask).a, lc.tpr_a, K, lc.roots, rc, v.e + lc.off * K,
-                    v.cw0, v.cw1, v.ct, s);
+  if (v.pc && K == 1)
+    coarse_persistent_t<X>(*v.pc, ops_of(lc, prec, v.gmask).a, rc, v.e + lc.off, s);
+  else
+    newton_apply_t<X>(ops_of(lc, prec, v.gmask).a, lc.tpr_a, K, lc.roots, rc, v.e + lc.off * K,
+                      v.cw0, v.cw1, v.ct, s);
   for (int l = L - 1; l >= 0; --l) {
     const Level& lv = H.levels[l];
     const LevelOps o = ops_of(lv, prec, v.gmask);
@@ -1037,6 +1045,8 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
   }
   if (info)
     for (size_t q = 0; q < ng; ++q) info[q] = out[q];
+  if (coarse_plan_error(W.pc, s) != 0)
+    fail(AIRG_ERR_INTERNAL, "the persistent coarse solve's barrier wait gave up");
   return status;
 }
 
@@ -1058,8 +1068,17 @@ void time_pass(const Hierarchy& H, const VecSet<X>& v, int cls, LaunchTally* t) 
     }
   if (poly || cls == AIRG_K_NEWTON) {
     const Level& lc = H.levels[L];
-    newton_apply_t<X>(ops_of(lc, prec).a, lc.tpr_a, 1, lc.roots, v.rr + lc.off, v.e + lc.off,
-                      v.cw0, v.cw1, v.ct, s, t);
+    if (v.pc) {
+      // one launch: the matrix is read once, each step's vector is written
+      // and gathered once; x and r once
+      coarse_persistent_t<X>(*v.pc, ops_of(lc, prec).a, v.rr + lc.off, v.e + lc.off, s);
+      if (t)
+        t->add(csr_bytes(lc.n, lc.A.nnz, vb) + xb * lc.n * (2.0 + 2.0 * v.pc->nsteps),
+               2.0 * lc.A.nnz * v.pc->nsteps + 6.0 * lc.n * v.pc->nsteps);
+    } else {
+      newton_apply_t<X>(ops_of(lc, prec).a, lc.tpr_a, 1, lc.roots, v.rr + lc.off, v.e + lc.off,
+                        v.cw0, v.cw1, v.ct, s, t);
+    }
   }
   if (cls == AIRG_K_RESIDUAL)
     for (int l = 0; l < L; ++l) {

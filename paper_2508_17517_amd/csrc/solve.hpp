@@ -29,6 +29,9 @@ struct Workspace {
   bool z32 = false;
   DBuf<double> w, rr, sv, y0, y1;
   DBuf<double> cw0, cw1, ct;
+  // the coarsest level's Newton steps in one persistent launch (single
+  // right-hand side, single problem, params.coarse_persistent; ok where it fits)
+  CoarsePlan pc;
   // FP32 vectors of the mixed-precision V-cycle
   DBuf<float> in32, e32, rr32, sv32, y032, y132, cw032, cw132, ct32;
   // each level's residual kept for C-point smoothing (stacked segments)
