@@ -62,7 +62,11 @@ void workspace_init(const Hierarchy& H, Workspace& W, int K) {
   W.graphs.clear();
   const int64_t n = H.n0 * K;
   W.K = K;
-  W.ld = (n + 63) / 64 * 64;
+  // the bases' stride: a multiple of 4 KiB plus 4.5 KiB, so that successive
+  // vectors do not start at the same offset of a power-of-two interleave
+  // (n is often a power of two; a Gram-Schmidt sweep reads up to 32 basis
+  // vectors at the same index)
+  W.ld = (n + 511) / 512 * 512 + 576;
   W.restart = H.p.restart;
   W.V.alloc((size_t)(W.restart + 1) * W.ld, s);
   // the FGMRES Z basis: FP64, or FP32 with lower-precision storage (the
