@@ -403,12 +403,17 @@ def persistent_coarse_leg(a, p, value64, ip, ix, dv, b, newton_us):
     if TUNE["on"] and os.path.exists(kept):
         with open(kept) as f:
             sm.pin_shapes(json.load(f))
+    else:
+        _tune(sm)
     xm = torch.zeros_like(b)
     dt, (xm, im) = _timed(lambda: sm.solve(b, xm), a.warmup, a.steps)
     assert im["converged"] == 1 and im["rel_residual"] <= 1e-10, im
     kt = sm.time_kernels("newton", reps=a.kernel_reps)
     res = {"value": p.n / dt, "unit": "DOF/s", "ms_per_step": 1e3 * dt,
            "iterations": im["iterations"], "rel_residual": im["rel_residual"],
+           # one launch per Newton apply where the coarsest level fits, else
+           # the per-step launches ran
+           "persistent_launch": kt["launches"] == 1,
            "newton_apply_us": 1e3 * kt["avg_launch_ms"] * kt["launches"],
            "per_step_newton_apply_us": newton_us,
            "speedup_vs_fp64": (p.n / dt) / value64}
