@@ -123,13 +123,17 @@ void launch_cols_update_dots(double* w, const double* V, int64_t ldv, const doub
 void launch_cols_update_norm2(double* w, const double* V, int64_t ldv, const double* h, int nv,
                               int64_t n0, int K, double* out, double* work, hipStream_t s);
 // The fused Gram-Schmidt sweeps per problem, on items of at most 256
-// elements (build_group_items with chunk 256): w = w - sum_k h[k, g] V_k,
-// then out[k, g] = V_k . w (update_dots) or out[0, g] = w . w (update_norm2)
-// over problem g, each summed in a fixed order.  1 to 32 basis vectors;
-// `work` needs group_fused_work_size(items) doubles.
+// elements (build_group_items with chunk 256): out[k, g] = V_k . w
+// (fused_dots), or w = w - sum_k h[k, g] V_k and then out[k, g] = V_k . w
+// (update_dots) or out[0, g] = w . w (update_norm2) over problem g, each
+// summed in a fixed order.  1 to 32 basis vectors; `work` needs
+// group_fused_work_size(items) doubles.
 size_t group_fused_work_size(const GroupItems& it);
 // `active` as in launch_group_dots (skipped items leave w unchanged: their
 // w and coefficients are zero).
+void launch_group_fused_dots(const double* V, int64_t ldv, int nv, const double* w,
+                             const GroupItems& it, double* out, double* work, hipStream_t s,
+                             const uint8_t* active = nullptr);
 void launch_group_update_dots(double* w, const double* V, int64_t ldv, const double* h, int nv,
                               const GroupItems& it, double* out, double* work, hipStream_t s,
                               const uint8_t* active = nullptr);

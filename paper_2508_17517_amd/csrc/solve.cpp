@@ -483,6 +483,14 @@ struct Procs {
     if (cols) launch_col_dots(V, ld, nv, w, H.n0, W.K, out, W.cdot_work.get(), H.s);
     else launch_group_dots(V, ld, nv, w, W.gitems, out, W.gdot_work.get(), H.s, act);
   }
+  // the first sweep of an Arnoldi step: V^T w (fused per problem where a
+  // fused kernel exists)
+  void first_dots(const double* V, int64_t ld, int nv, const double* w, double* out) {
+    if (!cols && nv <= kFusedVecs)
+      launch_group_fused_dots(V, ld, nv, w, W.gitems_f, out, W.gfused_work.get(), H.s, act);
+    else
+      dots(V, ld, nv, w, out);
+  }
   void update(double* w, const double* V, int64_t ld, const double* h, int nv) {
     if (cols) launch_cgs_update_cols(w, V, ld, h, nv, H.n0, W.K, H.s);
     else launch_group_update(w, V, ld, h, nv, W.gitems, H.s);
@@ -693,7 +701,7 @@ void solve_processes(const Hierarchy& H, Workspace& W, Procs& P, std::vector<air
         // a stopped problem's basis vector was zero, so its V-cycle output,
         // product and every Gram-Schmidt term are zero: the sweeps skip it
         if (mask) P.act = W.active.get();
-        P.dots(V, ld, j + 1, W.w.get(), h1);
+        P.first_dots(V, ld, j + 1, W.w.get(), h1);
         P.update_dots(W.w.get(), V, ld, h1, j + 1, h2);
         P.update_sumsq(W.w.get(), V, ld, h2, j + 1, hn2);
         P.act = nullptr;

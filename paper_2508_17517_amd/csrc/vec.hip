@@ -766,18 +766,19 @@ void launch_group_divide(double* y, const double* x, const double* d, const Grou
 }
 
 // The fused sweeps of cgs_fused_kernel per problem: block q takes item q (at
-// most 256 elements of problem grp[q], one per thread), updates w with that
-// problem's coefficients, and leaves the item's partial products, which
-// group_sum_kernel adds per problem in list order.  An item of a problem whose
+// most 256 elements of problem grp[q], one per thread) and forms the item's
+// partial products (MODE 0: V_k . w), or first updates w with that problem's
+// coefficients (MODE 1: then V_k . w; MODE 2: then w . w); group_sum_kernel
+// adds the partials per problem in list order.  An item of a problem whose
 // process is not running (active given and active[grp] == 0) has w = 0 and
 // coefficients 0: it leaves w as it is and zero partials, reading nothing.
-template <bool DOTS, int NV>
+template <int MODE, int NV>
 __global__ __launch_bounds__(256) void group_fused_kernel(
     double* __restrict__ w, const double* __restrict__ V, int64_t ldv, const double* __restrict__ h,
     int G, const int64_t* __restrict__ start, const int32_t* __restrict__ len,
     const int32_t* __restrict__ grp, const uint8_t* __restrict__ active, double* __restrict__ part,
     int64_t nq) {
-  constexpr int CNT = DOTS ? NV : 1;
+  constexpr int CNT = MODE == 2 ? 1 : NV;
   __shared__ double red[CNT][4];
   const int t = threadIdx.x;
   const int g = grp[blockIdx.x];
@@ -792,20 +793,22 @@ __global__ __launch_bounds__(256) void group_fused_kernel(
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = V[(int64_t)k * ldv + i];
   double wi = w[i];
+  if constexpr (MODE != 0) {
 #pragma unroll
-  for (int k = 0; k < NV; ++k) wi = wi - h[(int64_t)k * G + g] * v[k];
-  if (in) w[i] = wi;
+    for (int k = 0; k < NV; ++k) wi = wi - h[(int64_t)k * G + g] * v[k];
+    if (in) w[i] = wi;
+  }
   const int lane = t & 63, wave = t >> 6;
 #pragma unroll
   for (int k = 0; k < CNT; ++k) {
-    const double s = wave_tree(in ? (DOTS ? v[k] * wi : wi * wi) : 0.0);
+    const double s = wave_tree(in ? (MODE == 2 ? wi * wi : v[k] * wi) : 0.0);
     if (lane == 0) red[k][wave] = s;
   }
   __syncthreads();
   if (t < CNT) part[(int64_t)t * nq + blockIdx.x] = (red[t][0] + red[t][1]) + (red[t][2] + red[t][3]);
 }
 
-template <bool DOTS, int NV>
+template <int MODE, int NV>
 static void launch_group_fused_nv(int nv, double* w, const double* V, int64_t ldv, const double* h,
                                   const GroupItems& it, const uint8_t* active, double* part,
                                   hipStream_t s) {
@@ -813,8 +816,8 @@ static void launch_group_fused_nv(int nv, double* w, const double* V, int64_t ld
     fail(AIRG_ERR_INTERNAL, "fused Gram-Schmidt takes 1 to 32 vectors");
   } else {
     if (nv != NV)
-      return launch_group_fused_nv<DOTS, NV + 1>(nv, w, V, ldv, h, it, active, part, s);
-    group_fused_kernel<DOTS, NV><<<(unsigned)it.n, 256, 0, s>>>(
+      return launch_group_fused_nv<MODE, NV + 1>(nv, w, V, ldv, h, it, active, part, s);
+    group_fused_kernel<MODE, NV><<<(unsigned)it.n, 256, 0, s>>>(
         w, V, ldv, h, it.G, it.start.get(), it.len.get(), it.grp.get(), active, part, it.n);
   }
 }
@@ -823,27 +826,33 @@ size_t group_fused_work_size(const GroupItems& it) {
   return (size_t)kFusedVecs * (size_t)std::max<int64_t>(it.n, 1);
 }
 
-static void launch_group_fused(bool dots, double* w, const double* V, int64_t ldv, const double* h,
-                               int nv, const GroupItems& it, double* out, double* work,
-                               hipStream_t s, const uint8_t* active) {
+template <int MODE>
+static void launch_group_fused(double* w, const double* V, int64_t ldv, const double* h, int nv,
+                               const GroupItems& it, double* out, double* work, hipStream_t s,
+                               const uint8_t* active) {
   if (nv < 1 || nv > kFusedVecs) fail(AIRG_ERR_INTERNAL, "fused Gram-Schmidt takes 1 to 32 vectors");
   if (it.n <= 0) return;
-  if (dots) launch_group_fused_nv<true, 1>(nv, w, V, ldv, h, it, active, work, s);
-  else launch_group_fused_nv<false, 1>(nv, w, V, ldv, h, it, active, work, s);
+  launch_group_fused_nv<MODE, 1>(nv, w, V, ldv, h, it, active, work, s);
   AIRG_CHECK_LAUNCH();
-  group_sum_kernel<<<dim3((unsigned)it.G, (unsigned)(dots ? nv : 1)), 256, 0, s>>>(
+  group_sum_kernel<<<dim3((unsigned)it.G, (unsigned)(MODE == 2 ? 1 : nv)), 256, 0, s>>>(
       work, it.n, it.gptr.get(), it.glist.get(), it.G, out);
   AIRG_CHECK_LAUNCH();
+}
+void launch_group_fused_dots(const double* V, int64_t ldv, int nv, const double* w,
+                             const GroupItems& it, double* out, double* work, hipStream_t s,
+                             const uint8_t* active) {
+  // MODE 0 neither writes w nor reads h
+  launch_group_fused<0>(const_cast<double*>(w), V, ldv, nullptr, nv, it, out, work, s, active);
 }
 void launch_group_update_dots(double* w, const double* V, int64_t ldv, const double* h, int nv,
                               const GroupItems& it, double* out, double* work, hipStream_t s,
                               const uint8_t* active) {
-  launch_group_fused(true, w, V, ldv, h, nv, it, out, work, s, active);
+  launch_group_fused<1>(w, V, ldv, h, nv, it, out, work, s, active);
 }
 void launch_group_update_norm2(double* w, const double* V, int64_t ldv, const double* h, int nv,
                                const GroupItems& it, double* out, double* work, hipStream_t s,
                                const uint8_t* active) {
-  launch_group_fused(false, w, V, ldv, h, nv, it, out, work, s, active);
+  launch_group_fused<2>(w, V, ldv, h, nv, it, out, work, s, active);
 }
 
 // mask[i] = 1 where any problem g0[i] .. g1[i] of 64-row group i is active
