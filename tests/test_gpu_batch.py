@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from airg_inputs import workloads
-from parity import assert_elementwise
+from parity import assert_elementwise, mmatrix_inverse_inf_norm
 
 pytestmark = pytest.mark.gpu
 
@@ -204,6 +204,45 @@ def test_problem_batch_runs_one_process_per_problem(outer):
         assert np.linalg.norm(x.cpu().numpy() - xo[k]) <= 1e-10 * np.linalg.norm(xo[k]), k
         assert_elementwise(x.cpu().numpy(), xo[k])
     assert len(set(its)) >= 2
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_problem_batch_low_precision_with_the_assembled_smoother(prec):
+    # FP32 / BF16 storage and the assembled fixed-sparsity smoother on a
+    # problem batch: each problem lies within the bound the two FP64
+    # residuals give, |A^-1|_inf |r_o - r_g|_inf (A^-1 >= 0 for these upwind
+    # M-matrices, so |A^-1|_inf is one sweep of ones), against the FP64
+    # oracle with the assembled smoother on the same block-diagonal
+    # hierarchy.  FP32 (6e-8 relative perturbation of the V-cycle) takes the
+    # oracle's count; BF16 (4e-3) may cross the tolerance one outer step
+    # earlier or later, as it does on the smallest problem here
+    _needs_gpu()
+    import scipy.sparse as sp
+    from paper_2508_17517_amd import BatchSolver
+    probs = _problems()
+    A = sp.csr_matrix(sp.block_diag([q.scipy() for q in probs]))
+    A.sort_indices()
+    pr = oracle.Params(smoother="assembled")
+    levels = oracle.setup(A, pr)
+    seg = np.concatenate([[0], np.cumsum([q.n for q in probs])])
+    s = BatchSolver([(q.indptr, q.indices, q.data) for q in probs], precision=prec, smoother=1)
+    xs, infos = s.solve([torch.from_numpy(q.b).cuda() for q in probs])
+    for k, q in enumerate(probs):
+        b = np.zeros(A.shape[0])
+        b[seg[k]:seg[k + 1]] = q.b
+        xo, ik, rel, _, _ = oracle.solve(A, b, pr, levels)
+        xo = xo[seg[k]:seg[k + 1]]
+        Aq = q.scipy()
+        xg = xs[k].cpu().numpy()
+        assert infos[k]["converged"] == 1, k
+        if prec == 1:
+            assert infos[k]["iterations"] == ik, k
+        else:
+            assert abs(infos[k]["iterations"] - ik) <= 1, k
+        assert np.linalg.norm(q.b - Aq @ xg) <= 1e-10 * (1 + 1e-6) * np.linalg.norm(q.b), k
+        bound = mmatrix_inverse_inf_norm(Aq, q.level) * np.abs((q.b - Aq @ xo) - (q.b - Aq @ xg)).max()
+        assert np.abs(xg - xo).max() <= 1.01 * bound + 1e-14 * np.abs(xo).max(), k
     s.close()
 
 
