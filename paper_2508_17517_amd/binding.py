@@ -146,7 +146,9 @@ _lib = None
 
 
 def load(path=None):
-    """Load libairg.so; raises if it has not been built (no fallback exists)."""
+    """Load libairg.so, or the build at `path`, which then serves every later
+    call (Solver, BatchSolver, ...); raises if it has not been built (no
+    fallback exists)."""
     global _lib
     if _lib is not None and path is None:
         return _lib
@@ -159,8 +161,7 @@ def load(path=None):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    if path == LIB_PATH:
-        _lib = lib
+    _lib = lib
     return lib
 
 

@@ -153,3 +153,10 @@ def test_library_rank_of_singular_block():
     S = np.ones((3, 3))
     r = host.airg_host_numerical_rank(np.ascontiguousarray(S).ctypes.data_as(dp), 3, 3, 1e-12)
     assert r == 1
+
+
+def test_loading_a_build_by_path_serves_later_calls():
+    # a build loaded by path is the one every later load() returns (and so
+    # the one Solver and BatchSolver call)
+    lib = binding.load(binding.LIB_PATH)
+    assert binding.load() is lib
