@@ -137,6 +137,7 @@ SYMBOLS = {
     "airg_stream_probe": (c_i32, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, c_i64, ctypes.c_int,
                                   ctypes.c_int, P(c_dbl), ctypes.c_void_p]),
     "airg_set_alloc_budget": (c_i32, [c_i64, P(c_i64)]),
+    "airg_set_spin_limit": (c_i32, [c_i64]),
     "airg_destroy": (None, [ctypes.c_void_p]),
     "airg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "airg_last_error": (ctypes.c_char_p, []),

@@ -143,8 +143,17 @@ int solve_columns(Hierarchy& H, Workspace& W, std::map<int, std::unique_ptr<Work
       }
       ws = it->second.get();
     }
-    int st = fgmres_solve(H, *ws, b + (int64_t)k0 * ldb, ldb, x + (int64_t)k0 * ldx, ldx, cnt,
-                          guess != 0, info ? info + k0 : nullptr);
+    int st;
+    try {
+      st = fgmres_solve(H, *ws, b + (int64_t)k0 * ldb, ldb, x + (int64_t)k0 * ldx, ldx, cnt,
+                        guess != 0, info ? info + k0 : nullptr);
+    } catch (const Error&) {
+      // a persistent coarse solve whose barrier gave up leaves garbage that
+      // can also break the outer loop down: report the cause
+      if (coarse_plan_error(ws->pc, H.s) != 0)
+        fail(AIRG_ERR_INTERNAL, "the persistent coarse solve's barrier wait gave up");
+      throw;
+    }
     if (st != AIRG_OK) status = st;
     k0 += cnt;
   }
@@ -550,6 +559,13 @@ int airg_set_alloc_budget(int64_t bytes, int64_t* in_use) {
   return guard([&]() {
     set_device_budget(bytes);
     if (in_use) *in_use = g_device_bytes.load();
+    return (int)AIRG_OK;
+  });
+}
+
+int airg_set_spin_limit(int64_t polls) {
+  return guard([&]() {
+    set_coarse_spin_limit(polls);
     return (int)AIRG_OK;
   });
 }

@@ -23,6 +23,7 @@
 // t = A w and x += (2a w - t) / (a^2 + b^2), then w -= (2a t - A t) / (a^2 +
 // b^2); a final real root adds w / theta without a product; a real root that
 // directly follows the last product is folded into it.
+#include <atomic>
 #include <type_traits>
 #include <vector>
 
@@ -38,8 +39,6 @@ constexpr int kPcEntries = 32;
 constexpr int kPcCapacity = kPcThreads * kPcEntries;
 // values staged per round of the initial load (32 KB in FP64)
 constexpr int kPcStage = 4096;
-// polls of the barrier counter before a wait gives up (about a second)
-constexpr int64_t kPcSpinLimit = int64_t(1) << 20;
 
 __device__ __forceinline__ double to_x(double v, double) { return v; }
 __device__ __forceinline__ float to_x(float v, float) { return v; }
@@ -52,7 +51,7 @@ __device__ __forceinline__ float to_x(bf16 v, float) { return __uint_as_float((u
 // barrier that completes at the next multiple of the grid size.  A wait that
 // exceeds the poll limit, or sees another workgroup's failure, stops waiting
 // and sets *err, so every workgroup always finishes.
-__device__ void grid_barrier(unsigned long long* bar, int* err) {
+__device__ void grid_barrier(unsigned long long* bar, int* err, int64_t spin_limit) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
@@ -63,7 +62,7 @@ __device__ void grid_barrier(unsigned long long* bar, int* err) {
     for (;;) {
       if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
       if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-      if (++polls > kPcSpinLimit) {
+      if (++polls > spin_limit) {
         atomicOr(err, 1);
         break;
       }
@@ -79,7 +78,8 @@ __global__ __launch_bounds__(kPcThreads) void newton_persistent_kernel(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const MV* __restrict__ val, const int32_t* __restrict__ wrows,
     const CoarseStep* __restrict__ steps, int nsteps, int fin, double fin_inv, int fin_first,
-    const X* r, X* __restrict__ x, X* pub, int64_t n, unsigned long long* bar, int* err) {
+    const X* r, X* __restrict__ x, X* pub, int64_t n, unsigned long long* bar, int* err,
+    int64_t spin_limit) {
   // the workgroup's 16-bit columns (thread t's at t * 32 ..), its row starts,
   // the row pieces' sums (each thread's first and last piece, and the rows
   // that lie inside one thread's entries), and a staging area for the values
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kPcThreads) void newton_persistent_kernel(
       if (k + 1 < nsteps) pub[(int64_t)(k & 1) * n + row] = out;
     }
     if (k + 1 < nsteps) {
-      grid_barrier(bar, err);
+      grid_barrier(bar, err, spin_limit);
       src = pub + (int64_t)(k & 1) * n;
     }
   }
@@ -266,6 +266,13 @@ int max_resident_blocks() {
 }
 
 }  // namespace
+
+// polls of the barrier counter before a wait gives up (about a second)
+constexpr int64_t kPcSpinDefault = int64_t(1) << 20;
+static std::atomic<int64_t> g_coarse_spin_limit{kPcSpinDefault};
+void set_coarse_spin_limit(int64_t polls) {
+  g_coarse_spin_limit.store(polls > 0 ? polls : kPcSpinDefault);
+}
 
 bool coarse_plan_build(CoarsePlan& pc, const CSR& A, const std::vector<cplx>& roots, int prec,
                        hipStream_t s) {
@@ -357,20 +364,21 @@ template <class X>
 void coarse_persistent_t(const CoarsePlan& pc, const OpView& A, const X* r, X* x, hipStream_t s) {
   if (!pc.ok || A.rows != pc.n) fail(AIRG_ERR_INTERNAL, "persistent coarse solve without a plan");
   X* pub = reinterpret_cast<X*>(pc.pub.get());
+  const int64_t lim = g_coarse_spin_limit.load();
   if constexpr (std::is_same<X, double>::value) {
     if (A.vt != VT_F64) fail(AIRG_ERR_INTERNAL, "FP64 coarse solve needs FP64 values");
     newton_persistent_kernel<double, double><<<pc.blocks, kPcThreads, 0, s>>>(
         A.rowptr, A.col, (const double*)A.val, pc.wrows.get(), pc.steps.get(), pc.nsteps, pc.fin,
-        pc.fin_inv, pc.fin_first, r, x, pub, pc.n, pc.bar.get(), pc.err.get());
+        pc.fin_inv, pc.fin_first, r, x, pub, pc.n, pc.bar.get(), pc.err.get(), lim);
   } else {
     if (A.vt == VT_F32)
       newton_persistent_kernel<float, float><<<pc.blocks, kPcThreads, 0, s>>>(
           A.rowptr, A.col, (const float*)A.val, pc.wrows.get(), pc.steps.get(), pc.nsteps, pc.fin,
-          pc.fin_inv, pc.fin_first, r, x, pub, pc.n, pc.bar.get(), pc.err.get());
+          pc.fin_inv, pc.fin_first, r, x, pub, pc.n, pc.bar.get(), pc.err.get(), lim);
     else if (A.vt == VT_BF16)
       newton_persistent_kernel<bf16, float><<<pc.blocks, kPcThreads, 0, s>>>(
           A.rowptr, A.col, (const bf16*)A.val, pc.wrows.get(), pc.steps.get(), pc.nsteps, pc.fin,
-          pc.fin_inv, pc.fin_first, r, x, pub, pc.n, pc.bar.get(), pc.err.get());
+          pc.fin_inv, pc.fin_first, r, x, pub, pc.n, pc.bar.get(), pc.err.get(), lim);
     else
       fail(AIRG_ERR_INTERNAL, "FP32 coarse solve needs FP32 or BF16 values");
   }

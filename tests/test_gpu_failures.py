@@ -1,6 +1,7 @@
 """Failure handling forced from the host: an allocation budget that makes
-the library's device allocations fail as out-of-memory, and the stagnation
-check of the outer loop on a system where FGMRES(1) cannot make progress."""
+the library's device allocations fail as out-of-memory, the stagnation
+check of the outer loop on a system where FGMRES(1) cannot make progress,
+and a poll limit that makes the persistent coarse solve's barrier give up."""
 import ctypes
 
 import numpy as np
@@ -14,6 +15,7 @@ torch = pytest.importorskip("torch")
 
 AIRG_ERR_NOMEM = -5
 AIRG_NOT_CONVERGED = 1
+AIRG_ERR_INTERNAL = -7
 
 
 def _needs_gpu():
@@ -94,3 +96,31 @@ def test_stagnation_check_stops_a_stagnating_solve():
             assert i["converged"] == 0 and i["stagnated"] == stag
             assert (i["iterations"] < 10) if stag else (i["iterations"] == 60)
         s.close()
+
+
+def test_persistent_coarse_barrier_that_gives_up_fails_the_solve():
+    # the persistent coarse solve's grid barrier waits a bounded number of
+    # polls; with one poll allowed, the waits give up, every workgroup still
+    # finishes, and the solve reports AIRG_ERR_INTERNAL instead of hanging;
+    # with the default limit the same handle then solves as before
+    _needs_gpu()
+    from paper_2508_17517_amd import AirgError, Solver, binding
+    lib = binding.load()
+    p = workloads.fv_random(160, 0.4, True)  # one level: 25 workgroups
+    s = Solver(p.indptr, p.indices, p.data, max_levels=1, coarse_poly_order=8, restart=40,
+               coarse_persistent=1)
+    b = torch.from_numpy(p.b).cuda()
+    x0, i0 = s.solve(b)
+    assert i0["converged"] == 1
+    try:
+        assert lib.airg_set_spin_limit(1) == 0
+        with pytest.raises(AirgError) as e:
+            s.solve(b)
+        assert e.value.code == AIRG_ERR_INTERNAL
+        assert "barrier" in str(e.value)
+    finally:
+        assert lib.airg_set_spin_limit(0) == 0
+    x1, i1 = s.solve(b)
+    assert i1["iterations"] == i0["iterations"]
+    assert torch.equal(x1, x0)
+    s.close()
