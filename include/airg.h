@@ -111,6 +111,13 @@ typedef struct {
                                 AIRG_ERR_INTERNAL.  0: one product launch per step (faster on
                                 the MI355X: a barrier across its XCDs costs about as much as a
                                 launch), 0 */
+  int32_t lookahead;         /* 1: the outer FGMRES of one right-hand side of a single problem
+                                queues Arnoldi step j + 1 on the device before it reads step
+                                j's coefficients back, when the residual estimates predict
+                                that step j does not converge (the GPU then works while the
+                                host updates the least-squares problem); the same results bit
+                                for bit, a wrong prediction costs one step's work; 0: every
+                                step waits for the host, 1 */
 } airg_params;
 
 /* The polynomial approximation of A_ff^{-1} in the smoother and in Ahat^{-1}.

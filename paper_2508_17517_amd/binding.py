@@ -29,7 +29,7 @@ class Params(ctypes.Structure):
                 ("max_it", c_i32), ("restart", c_i32), ("keep_setup_data", c_i32),
                 ("locality_order", c_i32), ("outer", c_i32), ("smoother", c_i32),
                 ("inverse_type", c_i32), ("smooth_type", c_i32), ("atol", c_dbl), ("graph", c_i32),
-                ("stagnation_check", c_i32), ("coarse_persistent", c_i32)]
+                ("stagnation_check", c_i32), ("coarse_persistent", c_i32), ("lookahead", c_i32)]
 
 
 class SolveInfo(ctypes.Structure):

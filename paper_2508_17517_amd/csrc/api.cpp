@@ -85,6 +85,7 @@ void check_params(const airg_params& p) {
   if (p.graph != 0 && p.graph != 1) bad("graph");
   if (p.stagnation_check != 0 && p.stagnation_check != 1) bad("stagnation_check");
   if (p.coarse_persistent != 0 && p.coarse_persistent != 1) bad("coarse_persistent");
+  if (p.lookahead != 0 && p.lookahead != 1) bad("lookahead");
   if (p.max_it < 0) bad("max_it");
   if (p.restart < 1 || p.restart > 512) bad("restart");
   if (p.outer != AIRG_OUTER_FGMRES && p.outer != AIRG_OUTER_RICHARDSON) bad("outer");
@@ -223,6 +224,7 @@ int airg_params_default(airg_params* p) {
   p->graph = 0;
   p->stagnation_check = 0;
   p->coarse_persistent = 0;
+  p->lookahead = 1;
   return AIRG_OK;
 }
 

@@ -28,6 +28,9 @@ void launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t s
 void launch_divide(double* y, const double* x, double d, int64_t n, hipStream_t s,
                    float* y32 = nullptr);
 void launch_divide_dev(double* y, const double* x, const double* d, int64_t n, hipStream_t s);
+// y = x / sqrt(d2[0]) with the norm's square on the device (y32 as above)
+void launch_divide_norm2(double* y, const double* x, const double* d2, int64_t n, hipStream_t s,
+                         float* y32 = nullptr);
 void launch_sub(double* z, const double* x, const double* y, int64_t n, hipStream_t s);  // z = x - y
 // w = w - h[0] V_0 - h[1] V_1 - ... (k sequential per element; V_k = V + k ldv)
 void launch_cgs_update(double* w, const double* V, int64_t ldv, const double* h, int nv,

@@ -42,6 +42,8 @@ Workspace::~Workspace() {
   if (cap) (void)hipStreamDestroy(cap);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
+  for (hipEvent_t e : evh)
+    if (e) (void)hipEventDestroy(e);
   if (pin) (void)hipHostFree(pin);
 }
 
@@ -131,14 +133,17 @@ void workspace_init(const Hierarchy& H, Workspace& W, int K) {
   }
   const size_t ng = std::max<size_t>((size_t)K, H.seg.empty() ? 1 : H.seg.size());
   W.gbuf.alloc(ng + 1, s);
-  W.pin_n = std::max((2 * (size_t)(W.restart + 1) + 2) * G, ng + 1);
+  W.pin_slot = (2 * (size_t)(W.restart + 1) + 2) * G;
+  W.pin_n = std::max(2 * W.pin_slot, ng + 1);
   if (W.pin) (void)hipHostFree(W.pin);
   W.pin = nullptr;
   AIRG_HIP(hipHostMalloc((void**)&W.pin, W.pin_n * sizeof(double), hipHostMallocDefault));
   W.dot_work.alloc(dot_work_size(n, 64), s);
   W.col_work.alloc(col_sumsq_work_size(H.n0, K), s);
-  AIRG_HIP(hipEventCreate(&W.ev0));
-  AIRG_HIP(hipEventCreate(&W.ev1));
+  if (!W.ev0) AIRG_HIP(hipEventCreate(&W.ev0));
+  if (!W.ev1) AIRG_HIP(hipEventCreate(&W.ev1));
+  for (hipEvent_t& e : W.evh)
+    if (!e) AIRG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   W.pc.ok = false;
   if (K == 1 && H.seg.empty() && H.p.coarse_persistent)
     coarse_plan_build(W.pc, H.levels.back().A, H.levels.back().roots, H.p.precision, s);
@@ -974,7 +979,12 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
       std::fill(g.begin(), g.end(), 0.0);
       g[0] = beta;
       int k = 0;
-      for (int j = 0; j < R; ++j) {
+      // Arnoldi step j on the device: V-cycle, product, CGS2 (h1 = V^T w;
+      // w -= V h1; h2 = V^T w; w -= V h2; |w|^2, each sweep fused with the
+      // reduction after it), and the copy of its coefficients to pinned
+      // slot `slot`, marked by that slot's event
+      const size_t nh = 2 * (size_t)(R + 1) + 1;
+      auto enqueue_step = [&](int j, int slot) {
         double* vj = V + (int64_t)j * ld;
         if (Zb32) {
           float* zj32 = Zb32 + (int64_t)j * ld;
@@ -985,9 +995,6 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
           vcycle(H, W, vj, zj);
           spmv_t<double>(opview(H.Aperm), H.tpr_top, K, zj, W.w.get(), s);
         }
-        ++its;
-        // CGS2: h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; |w|^2, each
-        // sweep fused with the reduction after it
         if (j + 1 <= kFusedVecs) {
           launch_cgs_dots(V, ld, j + 1, W.w.get(), n, hd, W.fused_work.get(), s);
           launch_cgs_update_dots(W.w.get(), V, ld, hd, j + 1, n, hd + (R + 1), W.fused_work.get(), s);
@@ -1000,7 +1007,36 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
           launch_cgs_update(W.w.get(), V, ld, hd + (R + 1), j + 1, n, s);
           launch_tree_dots(W.w.get(), 0, 1, W.w.get(), n, hd + 2 * (R + 1), W.dot_work.get(), s);
         }
-        read_small(W, W.hbuf.get(), hh.data(), 2 * (R + 1) + 1, s);
+        AIRG_HIP(hipMemcpyAsync(W.pin + slot * W.pin_slot, hd, nh * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+        AIRG_HIP(hipEventRecord(W.evh[slot], s));
+      };
+      // Look-ahead: step j + 1 (its basis vector divided by the device's own
+      // square root of |w|^2, the same value the host would pass) is queued
+      // before the host reads step j's coefficients, when the residual
+      // estimates predict that step j does not converge: the estimate has
+      // fallen by r per step lately, and est_{j-1} r must stay above four
+      // times the threshold.  A wrong prediction costs one step's work,
+      // never the results, which are the same bits either way.
+      const bool look = H.p.lookahead != 0;
+      double est_m1 = beta, est_m2 = 0.0;  // the estimates of steps j-1 and j-2
+      bool ahead = false;
+      int slot = 0;
+      for (int j = 0; j < R; ++j) {
+        if (!ahead) enqueue_step(j, slot);
+        ++its;
+        ahead = false;
+        if (look && j + 1 < R && its < max_it) {
+          const double r = est_m2 > 0.0 ? std::min(1.0, est_m1 / est_m2) : 0.5;
+          if (est_m1 * r > 4.0 * thr) {
+            launch_divide_norm2(V + (int64_t)(j + 1) * ld, W.w.get(), hd + 2 * (R + 1), n, s,
+                                in32);
+            enqueue_step(j + 1, slot ^ 1);
+            ahead = true;
+          }
+        }
+        AIRG_HIP(hipEventSynchronize(W.evh[slot]));
+        std::memcpy(hh.data(), W.pin + slot * W.pin_slot, nh * sizeof(double));
         for (int i = 0; i <= j; ++i) Hm[(size_t)i * R + j] = hh[i] + hh[(R + 1) + i];
         const double hn = std::sqrt(hh[2 * (R + 1)]);
         Hm[(size_t)(j + 1) * R + j] = hn;
@@ -1028,7 +1064,10 @@ int fgmres_solve(const Hierarchy& H, Workspace& W, const double* b, int64_t ldb,
         if (!std::isfinite(est)) fail(AIRG_ERR_BREAKDOWN, "FGMRES breakdown (non-finite residual)");
         if (est <= thr || its >= max_it) break;
         if (hn == 0.0) break;
-        launch_divide(V + (int64_t)(j + 1) * ld, W.w.get(), hn, n, s, in32);
+        est_m2 = est_m1;
+        est_m1 = est;
+        if (!ahead) launch_divide(V + (int64_t)(j + 1) * ld, W.w.get(), hn, n, s, in32);
+        slot ^= 1;
       }
       for (int i = k - 1; i >= 0; --i) {
         double t = g[i];

@@ -51,9 +51,13 @@ struct Workspace {
   DBuf<uint8_t> active, gmask;
   bool mask_on = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  // pinned host staging for the small per-iteration reads of the outer loop
+  // pinned host staging for the small per-iteration reads of the outer loop;
+  // the single-process FGMRES uses two slots of pin_slot doubles at pin,
+  // each with the event that marks its copy (evh), so that the next Arnoldi
+  // step can be queued while the host reads the last one's coefficients
   double* pin = nullptr;
-  size_t pin_n = 0;
+  size_t pin_n = 0, pin_slot = 0;
+  hipEvent_t evh[2] = {nullptr, nullptr};
   // captured V-cycles (params.graph) and the stream they are captured on
   std::vector<VcycleGraph> graphs;
   hipStream_t cap = nullptr;

@@ -59,6 +59,16 @@ __global__ void divide_kernel(double* y, const double* x, double d, int64_t n, f
   y[i] = v;
   if (y32) y32[i] = (float)v;
 }
+// y = x / sqrt(d2[0]) (the square root taken here, correctly rounded like
+// the host's), and y32 = (float) y when given
+__global__ void divide_norm2_kernel(double* y, const double* x, const double* d2, int64_t n,
+                                    float* y32) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = x[i] / sqrt(d2[0]);
+  y[i] = v;
+  if (y32) y32[i] = (float)v;
+}
 __global__ void divide_dev_kernel(double* y, const double* x, const double* d, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = x[i] / d[0];
@@ -96,6 +106,12 @@ void launch_scale(double* y, const double* x, double a, int64_t n, hipStream_t s
 void launch_divide(double* y, const double* x, double d, int64_t n, hipStream_t s, float* y32) {
   if (n <= 0) return;
   divide_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, d, n, y32);
+  AIRG_CHECK_LAUNCH();
+}
+void launch_divide_norm2(double* y, const double* x, const double* d2, int64_t n, hipStream_t s,
+                         float* y32) {
+  if (n <= 0) return;
+  divide_norm2_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(y, x, d2, n, y32);
   AIRG_CHECK_LAUNCH();
 }
 void launch_divide_dev(double* y, const double* x, const double* d, int64_t n, hipStream_t s) {

@@ -38,13 +38,12 @@ def test_status_strings_and_defaults_without_gpu():
     assert p.seed == 17517 and p.restart == 30 and p.locality_order == 1 and p.outer == 0
     assert p.smoother == 0 and p.inverse_type == 0 and p.smooth_type == 0
     assert p.atol == 1e-50 and p.graph == 0 and p.stagnation_check == 0
-    assert p.coarse_persistent == 0
+    assert p.coarse_persistent == 0 and p.lookahead == 1
 
 
 def test_struct_sizes_match_the_header():
     # the ctypes mirrors must have the C layout (fields are naturally aligned)
-    # (the last int32 is followed by 4 bytes of padding to the double alignment)
-    assert ctypes.sizeof(binding.Params) == 6 * 8 + 8 + 8 + 16 * 4 + 8 + 4 + 4 + 4 + 4
+    assert ctypes.sizeof(binding.Params) == 6 * 8 + 8 + 8 + 16 * 4 + 8 + 4 * 4
     assert ctypes.sizeof(binding.SolveInfo) == 4 * 4 + 3 * 8
     assert ctypes.sizeof(binding.LevelInfo) == 7 * 8 + 4 * 4
     assert ctypes.sizeof(binding.LevelArrays) == 18 * 8
