@@ -74,11 +74,15 @@ TRAFFIC_SOURCES = ["spmv.hip", "hierarchy.cpp", "solve.cpp", "order.hip", "spgem
 
 
 def kernel_source_digest():
+    """Digest of the sources that decide the poly-SpMV launches, and of the
+    launch shapes the counter runs pin."""
     import hashlib
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, "paper_2508_17517_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_2508_17517_amd", "shapes", "fv2048_fp64.json"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()
 
 
