@@ -451,11 +451,13 @@ int airg_fv_gradients_noalloc(int64_t nx, int64_t ny, double theta, const int32_
  * over every handle of the process. */
 int airg_set_alloc_budget(int64_t bytes, int64_t* in_use);
 
-/* Failure-handling hook (for tests): a grid-wide barrier wait of the
- * persistent coarse solve (airg_params.coarse_persistent) gives up after
- * `polls` polls of its counter (polls <= 0: the default, about a second) and
- * the solve then fails with AIRG_ERR_INTERNAL; every workgroup still
- * finishes.  Applies to launches enqueued after the call. */
+/* Failure-handling hook (for tests): a grid-wide barrier wait of a
+ * persistent launch gives up after `polls` polls of its counter (polls <= 0:
+ * the default, about a second); every workgroup still finishes.  In the
+ * persistent coarse solve (airg_params.coarse_persistent) the solve then
+ * fails with AIRG_ERR_INTERNAL; in the breadth-first passes of the locality
+ * order (setup) the pass runs again with one launch per step, with the same
+ * result.  Applies to launches enqueued after the call. */
 int airg_set_spin_limit(int64_t polls);
 
 /* Release the handle and all its device memory (NULL is a no-op). */

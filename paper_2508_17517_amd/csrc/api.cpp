@@ -567,7 +567,7 @@ int airg_set_alloc_budget(int64_t bytes, int64_t* in_use) {
 
 int airg_set_spin_limit(int64_t polls) {
   return guard([&]() {
-    set_coarse_spin_limit(polls);
+    set_grid_spin_limit(polls);
     return (int)AIRG_OK;
   });
 }

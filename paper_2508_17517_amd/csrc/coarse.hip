@@ -27,6 +27,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "grid_sync.hpp"
 #include "hierarchy.hpp"
 #include "kernels.hpp"
 
@@ -43,35 +44,6 @@ constexpr int kPcStage = 4096;
 __device__ __forceinline__ double to_x(double v, double) { return v; }
 __device__ __forceinline__ float to_x(float v, float) { return v; }
 __device__ __forceinline__ float to_x(bf16 v, float) { return __uint_as_float((uint32_t)v.bits << 16); }
-
-// Wait until every workgroup has arrived: the workgroup's writes are
-// published by a device-scope fence before its arrival is counted, and a
-// device-scope fence after the wait makes the other workgroups' writes
-// visible to it.  The counter only grows: arrival number k belongs to the
-// barrier that completes at the next multiple of the grid size.  A wait that
-// exceeds the poll limit, or sees another workgroup's failure, stops waiting
-// and sets *err, so every workgroup always finishes.
-__device__ void grid_barrier(unsigned long long* bar, int* err, int64_t spin_limit) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned long long g = gridDim.x;
-    const unsigned long long k = atomicAdd(bar, 1ull);
-    const unsigned long long target = k - k % g + g;
-    int64_t polls = 0;
-    for (;;) {
-      if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
-      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-      if (++polls > spin_limit) {
-        atomicOr(err, 1);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(2);
-    }
-    __threadfence();
-  }
-  __syncthreads();
-}
 
 template <class MV, class X>
 __global__ __launch_bounds__(kPcThreads) void newton_persistent_kernel(
@@ -268,11 +240,10 @@ int max_resident_blocks() {
 }  // namespace
 
 // polls of the barrier counter before a wait gives up (about a second)
-constexpr int64_t kPcSpinDefault = int64_t(1) << 20;
-static std::atomic<int64_t> g_coarse_spin_limit{kPcSpinDefault};
-void set_coarse_spin_limit(int64_t polls) {
-  g_coarse_spin_limit.store(polls > 0 ? polls : kPcSpinDefault);
-}
+constexpr int64_t kSpinDefault = int64_t(1) << 20;
+static std::atomic<int64_t> g_grid_spin_limit{kSpinDefault};
+void set_grid_spin_limit(int64_t polls) { g_grid_spin_limit.store(polls > 0 ? polls : kSpinDefault); }
+int64_t grid_spin_limit() { return g_grid_spin_limit.load(); }
 
 bool coarse_plan_build(CoarsePlan& pc, const CSR& A, const std::vector<cplx>& roots, int prec,
                        hipStream_t s) {
@@ -364,7 +335,7 @@ template <class X>
 void coarse_persistent_t(const CoarsePlan& pc, const OpView& A, const X* r, X* x, hipStream_t s) {
   if (!pc.ok || A.rows != pc.n) fail(AIRG_ERR_INTERNAL, "persistent coarse solve without a plan");
   X* pub = reinterpret_cast<X*>(pc.pub.get());
-  const int64_t lim = g_coarse_spin_limit.load();
+  const int64_t lim = grid_spin_limit();
   if constexpr (std::is_same<X, double>::value) {
     if (A.vt != VT_F64) fail(AIRG_ERR_INTERNAL, "FP64 coarse solve needs FP64 values");
     newton_persistent_kernel<double, double><<<pc.blocks, kPcThreads, 0, s>>>(

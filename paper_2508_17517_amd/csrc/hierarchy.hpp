@@ -140,8 +140,6 @@ template <class X>
 void coarse_persistent_t(const CoarsePlan& pc, const OpView& A, const X* r, X* x, hipStream_t s);
 // nonzero when a launch's barrier wait gave up (cleared by the call)
 int coarse_plan_error(const CoarsePlan& pc, hipStream_t s);
-// polls of a barrier wait before it gives up (<= 0: the default)
-void set_coarse_spin_limit(int64_t polls);
 
 // Build the hierarchy for A (device CSR, validated) with parameters p.
 void build_hierarchy(Hierarchy& H, CSR&& A);

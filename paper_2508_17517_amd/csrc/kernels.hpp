@@ -302,6 +302,13 @@ void launch_iota(int32_t* x, int64_t n, hipStream_t s);
 void launch_one_point(const CSR& A, const int8_t* state, const int64_t* fidx,
                       const int64_t* cidx, int32_t* cmap, hipStream_t s);
 
+// ---------------------------------------------------------------- grid barrier
+// Polls of a persistent launch's grid-barrier wait before it gives up (<= 0
+// restores the default, about a second of waiting); read when such a launch
+// is enqueued.
+void set_grid_spin_limit(int64_t polls);
+int64_t grid_spin_limit();
+
 // ---------------------------------------------------------------- order.hip
 // Breadth-first levels of the graph of A + A^T from src (level[i] >= 0 for
 // every i; unreached components restart at the next level).

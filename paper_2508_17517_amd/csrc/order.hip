@@ -15,33 +15,170 @@
 // each.  The coarsest level, ordered by its own graph for its LDS-staged
 // products, takes the anti-diagonal key, whose 64-row groups span one
 // narrow window of columns.
+#include <algorithm>
 #include <functional>
 
+#include "grid_sync.hpp"
 #include "kernels.hpp"
 
 namespace airg {
 
-// One breadth-first step over the frontier q_in (count cnt[d % 3]): every
-// unreached neighbour (in A or A^T) of a frontier node gets level d + 1 and
-// joins q_out (count cnt[(d + 1) % 3]).  Which thread claims a node does not
-// matter: the levels are the breadth-first distances either way.  The
-// counter for step d + 2 is cleared here.
+// Expand one frontier: every unreached neighbour (in A or A^T) of a node
+// q_in[t], t < n_in, gets level dn and joins q_out (count *n_out).  Waves
+// take 64 consecutive frontier nodes from wave_first on, in steps of stride.
+// A lane takes its node's neighbours 8 at a time: it loads their indices,
+// then tries to claim each of them (a compare-and-swap from -1; a neighbour
+// already reached keeps its level), all 8 in flight at once, and one atomic
+// per wave then reserves the queue slots of the nodes the wave claimed.  So
+// that no branch separates the 8 swaps, a slot with no neighbour (and a lane
+// past the frontier's end) swaps on the level of a frontier node instead,
+// which is never -1 and so never changes.  Which lane claims a node does not
+// matter: the levels are the breadth-first distances either way.
+constexpr int kExpandChunk = 8;
+__device__ __forceinline__ void expand_frontier(const CSRView& A, const CSRView& At, int32_t* level,
+                                                int32_t dn, const int32_t* q_in, int64_t n_in,
+                                                int32_t* q_out, int32_t* n_out, int64_t wave_first,
+                                                int64_t stride) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t b = wave_first; b < n_in; b += stride) {
+    const int64_t t = b + lane;
+    const bool live = t < n_in;
+    const int u = q_in[live ? t : t % n_in];
+    int a0 = 0, na = 0, t0 = 0, deg = 0;
+    if (live) {
+      a0 = A.rowptr[u];
+      na = A.rowptr[u + 1] - a0;
+      t0 = At.rowptr[u];
+      deg = na + (At.rowptr[u + 1] - t0);
+    }
+    int dmax = deg;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, 64));
+    for (int j0 = 0; j0 < dmax; j0 += kExpandChunk) {
+      int v[kExpandChunk];
+#pragma unroll
+      for (int c = 0; c < kExpandChunk; ++c) {
+        const int j = j0 + c;
+        v[c] = j < deg ? (j < na ? A.col[a0 + j] : At.col[t0 + j - na]) : u;
+      }
+      bool got[kExpandChunk];
+#pragma unroll
+      for (int c = 0; c < kExpandChunk; ++c) got[c] = atomicCAS(&level[v[c]], -1, dn) == -1;
+      unsigned long long m[kExpandChunk];
+      int total = 0;
+#pragma unroll
+      for (int c = 0; c < kExpandChunk; ++c) {
+        m[c] = __ballot(got[c]);
+        total += (int)__popcll(m[c]);
+      }
+      if (total == 0) continue;
+      int base = 0;
+      if (lane == 0) base = atomicAdd(n_out, total);
+      base = __shfl(base, 0, 64);
+#pragma unroll
+      for (int c = 0; c < kExpandChunk; ++c) {
+        const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m[c] >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m[c], 0u));
+        if (got[c]) q_out[base + below] = v[c];
+        base += (int)__popcll(m[c]);
+      }
+    }
+  }
+}
+
+// One breadth-first step over the frontier of step d (q_in, count
+// cnt[d % 3]) into q_out (count cnt[(d + 1) % 3]).  The counter for step
+// d + 2 is cleared here.
 __global__ void bfs_frontier_kernel(CSRView A, CSRView At, int32_t* level, int32_t d,
                                     const int32_t* q_in, int32_t* q_out, int32_t* cnt) {
   const int32_t n_in = cnt[d % 3];
-  int32_t* n_out = cnt + (d + 1) % 3;
   if (blockIdx.x == 0 && threadIdx.x == 0) cnt[(d + 2) % 3] = 0;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_in;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int u = q_in[t];
-    for (int p = A.rowptr[u]; p < A.rowptr[u + 1]; ++p) {
-      const int v = A.col[p];
-      if (level[v] < 0 && atomicCAS(&level[v], -1, d + 1) == -1) q_out[atomicAdd(n_out, 1)] = v;
+  expand_frontier(A, At, level, d + 1, q_in, n_in, q_out, cnt + (d + 1) % 3,
+                  (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63), (int64_t)gridDim.x * blockDim.x);
+}
+
+constexpr int kBfsThreads = 256;
+
+// Steps d0, d0 + 1, .. of bfs_frontier_kernel in one launch, with a grid
+// barrier after each, until a step finds its frontier empty or `steps` steps
+// have run; ctl[0] receives the step it stopped at (d0 + steps when none was
+// empty).  The frontier of step d is qa for even d and qb for odd d.  Every
+// workgroup reads the same count after a barrier, so all leave together; a
+// barrier wait that gives up sets *err and every workgroup leaves.
+__global__ __launch_bounds__(kBfsThreads) void bfs_persistent_kernel(CSRView A, CSRView At, int32_t* level,
+                                                                int32_t d0, int32_t steps, int32_t* qa,
+                                                                int32_t* qb, int32_t* cnt, int32_t* ctl,
+                                                                unsigned long long* bar, int* err,
+                                                                int64_t spin_limit) {
+  __shared__ int s_n;
+  const int64_t wave_first = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int32_t d = d0;
+  for (int k = 0; k < steps; ++k, ++d) {
+    if (threadIdx.x == 0) s_n = __hip_atomic_load(cnt + d % 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int n_in = s_n;
+    if (n_in == 0) break;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+      __hip_atomic_store(cnt + (d + 2) % 3, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    expand_frontier(A, At, level, d + 1, (d & 1) ? qb : qa, n_in, (d & 1) ? qa : qb,
+                    cnt + (d + 1) % 3, wave_first, stride);
+    grid_barrier(bar, err, spin_limit);
+    if (grid_failed(err)) break;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl[0] = d;
+}
+
+// Workgroups of a persistent breadth-first launch: enough for the wide
+// frontiers, few enough that a barrier stays cheap, never more than the
+// device holds at once (0 when that cannot be found out).
+constexpr int kBfsBlocks = 64;
+// steps per persistent launch (the host reads the state back once per launch)
+constexpr int32_t kBfsSteps = 4096;
+
+static int bfs_blocks() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bfs_persistent_kernel, kBfsThreads, 0) != hipSuccess)
+    return 0;
+  return std::min(kBfsBlocks, cus * per);
+}
+
+// Steps from d on until a frontier is empty; d becomes the first step whose
+// frontier is empty.  Persistent launches when `persistent` (false when a
+// barrier wait gave up: the levels are then incomplete), else one launch per
+// step, 32 steps between reads of the count (steps past the end do nothing).
+static bool bfs_steps(const CSR& A, const CSR& At, int32_t* level, int32_t& d, int32_t* const q[2],
+                      int32_t* cnt, bool persistent, hipStream_t s) {
+  const int64_t n = A.rows;
+  if (persistent) {
+    const int g = bfs_blocks();
+    if (g <= 0) return false;
+    DBuf<int32_t> ctl(2, s);
+    DBuf<unsigned long long> bar(1, s);
+    const int64_t lim = grid_spin_limit();
+    for (;;) {
+      bar.zero();
+      ctl.zero();
+      bfs_persistent_kernel<<<g, kBfsThreads, 0, s>>>(view(A), view(At), level, d, kBfsSteps, q[0], q[1],
+                                                 cnt, ctl.get(), bar.get(), ctl.get() + 1, lim);
+      AIRG_CHECK_LAUNCH();
+      const std::vector<int32_t> h = ctl.host(2);
+      if (h[1] != 0) return false;
+      const bool done = h[0] < d + kBfsSteps;
+      d = h[0];
+      if (done) return true;
     }
-    for (int p = At.rowptr[u]; p < At.rowptr[u + 1]; ++p) {
-      const int v = At.col[p];
-      if (level[v] < 0 && atomicCAS(&level[v], -1, d + 1) == -1) q_out[atomicAdd(n_out, 1)] = v;
+  }
+  const unsigned nb = blocks_for(std::min<int64_t>(n, 256 * 1024), kBlock);
+  for (;;) {
+    for (int k = 0; k < 32; ++k, ++d) {
+      bfs_frontier_kernel<<<nb, kBlock, 0, s>>>(view(A), view(At), level, d, q[d & 1], q[(d + 1) & 1],
+                                                cnt);
+      AIRG_CHECK_LAUNCH();
     }
+    if (fetch(cnt + d % 3, s) == 0) return true;
   }
 }
 
@@ -72,32 +209,25 @@ __global__ void seed_frontier_kernel(int32_t* level, int64_t i, int32_t v, int32
 
 // Breadth-first levels of the graph of A + A^T from src; unreached
 // components restart from their smallest index at the next level.
-void bfs_levels(const CSR& A, const CSR& At, int64_t src, int32_t* level, hipStream_t s) {
+static bool bfs_levels_pass(const CSR& A, const CSR& At, int64_t src, int32_t* level, bool persistent,
+                            hipStream_t s) {
   const int64_t n = A.rows;
   launch_fill_i32(level, n, -1, s);
   DBuf<int32_t> qa(n, s), qb(n, s), cnt(3, s);
   DBuf<unsigned long long> red(1, s);
-  const unsigned nb = blocks_for(std::min<int64_t>(n, 256 * 1024), kBlock);
   int32_t d = 0;
   seed_frontier_kernel<<<1, 1, 0, s>>>(level, src, 0, qa.get(), cnt.get(), 0);
   AIRG_CHECK_LAUNCH();
-  int32_t* q[2] = {qa.get(), qb.get()};
+  int32_t* const q[2] = {qa.get(), qb.get()};
   for (;;) {
-    // a batch of steps between host checks; steps past the end do nothing
-    const int batch = 32;
-    for (int k = 0; k < batch; ++k, ++d) {
-      bfs_frontier_kernel<<<nb, kBlock, 0, s>>>(view(A), view(At), level, d, q[d & 1],
-                                                q[(d + 1) & 1], cnt.get());
-      AIRG_CHECK_LAUNCH();
-    }
-    if (fetch(cnt.get() + d % 3, s) > 0) continue;
+    if (!bfs_steps(A, At, level, d, q, cnt.get(), persistent, s)) return false;
     // the frontier is empty: every component reached so far is done
     unsigned long long first = ~0ull;
     red.from_host(&first, 1);
     first_unvisited_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(level, n, red.get());
     AIRG_CHECK_LAUNCH();
     first = fetch(red.get(), s);
-    if (first == ~0ull) break;
+    if (first == ~0ull) return true;
     unsigned long long zero = 0;
     red.from_host(&zero, 1);
     far_node_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(level, n, red.get());
@@ -107,6 +237,12 @@ void bfs_levels(const CSR& A, const CSR& At, int64_t src, int32_t* level, hipStr
     seed_frontier_kernel<<<1, 1, 0, s>>>(level, (int64_t)first, d, q[d & 1], cnt.get(), d % 3);
     AIRG_CHECK_LAUNCH();
   }
+}
+
+// The persistent steps first; where a barrier wait gives up, the pass runs
+// again with one launch per step.
+void bfs_levels(const CSR& A, const CSR& At, int64_t src, int32_t* level, hipStream_t s) {
+  if (!bfs_levels_pass(A, At, src, level, true, s)) bfs_levels_pass(A, At, src, level, false, s);
 }
 
 int64_t far_node(const int32_t* level, int64_t n, hipStream_t s) {
@@ -487,32 +623,24 @@ static std::vector<unsigned long long> seg_reduce(int nseg, unsigned long long i
 // breadth-first levels from one start node per segment (none where -1);
 // unreached parts restart, every segment at once, from their smallest
 // index at the next step
-static void bfs_levels_seg(const CSR& A, const CSR& At, const std::vector<int32_t>& start,
-                           const int32_t* sid, int nseg, int32_t* level, hipStream_t s) {
+static bool bfs_levels_seg_pass(const CSR& A, const CSR& At, const std::vector<int32_t>& start,
+                                const int32_t* sid, int nseg, int32_t* level, bool persistent,
+                                hipStream_t s) {
   const int64_t n = A.rows;
   launch_fill_i32(level, n, -1, s);
   DBuf<int32_t> qa(n, s), qb(n, s), cnt(3, s), sd(std::max(nseg, 1), s);
-  const unsigned nb = blocks_for(std::min<int64_t>(n, 256 * 1024), kBlock);
-  int32_t* q[2] = {qa.get(), qb.get()};
+  int32_t* const q[2] = {qa.get(), qb.get()};
   std::vector<int32_t> seeds;
   for (int32_t v : start)
     if (v >= 0) seeds.push_back(v);
   int32_t d = 0;
   for (;;) {
-    if (seeds.empty()) break;
+    if (seeds.empty()) return true;
     sd.from_host(seeds.data(), seeds.size());
     seed_list_kernel<<<1, 256, 0, s>>>(level, sd.get(), (int)seeds.size(), d, q[d & 1], cnt.get(),
                                        d % 3);
     AIRG_CHECK_LAUNCH();
-    for (;;) {
-      const int batch = 32;
-      for (int k = 0; k < batch; ++k, ++d) {
-        bfs_frontier_kernel<<<nb, kBlock, 0, s>>>(view(A), view(At), level, d, q[d & 1],
-                                                  q[(d + 1) & 1], cnt.get());
-        AIRG_CHECK_LAUNCH();
-      }
-      if (fetch(cnt.get() + d % 3, s) == 0) break;
-    }
+    if (!bfs_steps(A, At, level, d, q, cnt.get(), persistent, s)) return false;
     // the frontier is empty: restart every segment that has unreached nodes
     const std::vector<unsigned long long> first = seg_reduce(nseg, kNone, [&](unsigned long long* sl) {
       seg_first_kernel<<<blocks_for(n, kBlock), kBlock, 0, s>>>(level, sid, n, 0, sl);
@@ -522,6 +650,12 @@ static void bfs_levels_seg(const CSR& A, const CSR& At, const std::vector<int32_
     for (unsigned long long f : first)
       if (f != kNone) seeds.push_back((int32_t)f);
   }
+}
+
+static void bfs_levels_seg(const CSR& A, const CSR& At, const std::vector<int32_t>& start,
+                           const int32_t* sid, int nseg, int32_t* level, hipStream_t s) {
+  if (!bfs_levels_seg_pass(A, At, start, sid, nseg, level, true, s))
+    bfs_levels_seg_pass(A, At, start, sid, nseg, level, false, s);
 }
 
 void locality_keys_seg(const CSR& A, const int32_t* sid, int nseg, int32_t* key, hipStream_t s,

@@ -1,7 +1,9 @@
 """Failure handling forced from the host: an allocation budget that makes
 the library's device allocations fail as out-of-memory, the stagnation
 check of the outer loop on a system where FGMRES(1) cannot make progress,
-and a poll limit that makes the persistent coarse solve's barrier give up."""
+and a poll limit that makes the grid barriers of persistent launches give up
+(the persistent coarse solve fails; the breadth-first passes of the locality
+order run again with one launch per step)."""
 import ctypes
 
 import numpy as np
@@ -124,3 +126,51 @@ def test_persistent_coarse_barrier_that_gives_up_fails_the_solve():
     assert i1["iterations"] == i0["iterations"]
     assert torch.equal(x1, x0)
     s.close()
+
+
+BFS_CASES = {
+    # one connected graph: the two-distance key of one component
+    "fv256_perm": lambda: [workloads.fv_random(256, 0.3, True)],
+    # a flow along the grid lines: 96 components, keyed all at once
+    "fv96_theta0_perm": lambda: [workloads.fv_random(96, 0.0, True, seed=301)],
+    # a block-diagonal batch: every problem's passes at once
+    "batch3": lambda: [workloads.fv_random(96, 0.0, True, seed=301),
+                       workloads.fv_random(48, 0.5, True, seed=302),
+                       workloads.fv_random(64, 0.3, True, seed=303)],
+}
+
+
+@pytest.mark.parametrize("case", list(BFS_CASES))
+def test_breadth_first_barrier_that_gives_up_falls_back_to_per_step_launches(case):
+    # the locality order's breadth-first passes run many steps per launch
+    # behind a grid barrier; with one poll allowed the barrier gives up and
+    # the pass runs again with one launch per step.  Breadth-first distances
+    # are unique, so both give the same order: the same iteration counts and
+    # bit-for-bit the same solutions
+    _needs_gpu()
+    from paper_2508_17517_amd import BatchSolver, Solver, binding
+    lib = binding.load()
+    probs = BFS_CASES[case]()
+    print(f"breadth-first fallback: {case}, n = {[q.n for q in probs]}", flush=True)
+
+    def run():
+        if len(probs) == 1:
+            q = probs[0]
+            s = Solver(q.indptr, q.indices, q.data)
+            x, info = s.solve(torch.from_numpy(q.b).cuda())
+            s.close()
+            return [x], [info]
+        s = BatchSolver([(q.indptr, q.indices, q.data) for q in probs])
+        xs, infos = s.solve([torch.from_numpy(q.b).cuda() for q in probs])
+        s.close()
+        return xs, infos
+
+    x0, i0 = run()
+    try:
+        assert lib.airg_set_spin_limit(1) == 0
+        x1, i1 = run()
+    finally:
+        assert lib.airg_set_spin_limit(0) == 0
+    for a, b, ia, ib in zip(x0, x1, i0, i1):
+        assert ia["converged"] == 1 and ia["iterations"] == ib["iterations"]
+        assert torch.equal(a, b)
