@@ -145,8 +145,9 @@ static int bfs_blocks() {
   return std::min(kBfsBlocks, cus * per);
 }
 
-// Steps from d on until a frontier is empty; d becomes the first step whose
-// frontier is empty.  Persistent launches when `persistent` (false when a
+// Steps from d on until a frontier is empty; d becomes a step at or after
+// the first one whose frontier is empty (the callers restart from the
+// levels, not from d).  Persistent launches when `persistent` (false when a
 // barrier wait gave up: the levels are then incomplete), else one launch per
 // step, 32 steps between reads of the count (steps past the end do nothing).
 static bool bfs_steps(const CSR& A, const CSR& At, int32_t* level, int32_t& d, int32_t* const q[2],
@@ -649,6 +650,8 @@ static bool bfs_levels_seg_pass(const CSR& A, const CSR& At, const std::vector<i
     seeds.clear();
     for (unsigned long long f : first)
       if (f != kNone) seeds.push_back((int32_t)f);
+    // the restarted parts begin one level past the deepest level so far
+    if (!seeds.empty()) d = fetch(level + far_node(level, n, s), s) + 1;
   }
 }
 
