@@ -6,8 +6,6 @@
 
 #include <hip/hip_runtime.h>
 
-#include "kernels.hpp"
-
 namespace airg {
 
 // Wait until every workgroup has arrived: a device-scope release fence
